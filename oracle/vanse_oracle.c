@@ -1,0 +1,495 @@
+/*
+ * vanse_oracle.c -- plain FP64 CPU reference for one time step of the
+ * consistent multiple-relaxation-time lattice Boltzmann method for the
+ * volume-averaged Navier-Stokes equations (MRTLB-VANSE) on a D2Q9 lattice,
+ * after Liu, Zhang, Min & Wu, arXiv:2409.02964.
+ *
+ * TEST INFRASTRUCTURE.  This file is the oracle that the GPU path is checked
+ * against.  Only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark load it.  It shares no code, header, table or helper with the
+ * GPU library, and the product never calls it.
+ *
+ * Style: slow and literal on purpose.  Whole-field passes in the order the
+ * paper states the scheme (Sec. 2.3), the 9x9 matrices of Eq. (A1) applied as
+ * plain matrix-vector products, push streaming into a fresh array, no fusion,
+ * no blocking.  Build with -O3 -ffp-contract=off and without -ffast-math,
+ * so there is no FMA contraction and no reassociation.
+ *
+ * Layout: every field is row-major [ny][nx], index y*nx + x.  Populations
+ * are nine such planes, plane i at f + i*nx*ny.  The state held between
+ * steps is the post-streaming (pre-collision) population f_i(x, t).
+ *
+ * Readings of the paper taken here (each one is listed in the design notes):
+ *  - the paper's tau_* are relaxation RATES (Sec. 2.2: tau^-1 = nu/cs^2+1/2
+ *    for SRT; Eq. (A11) for MRT); they are called s_* here;
+ *  - gradients of Eq. (13) and Eq. (20) use fields of the same time level,
+ *    computed from the current populations, neighbour velocities included;
+ *  - derivatives of products (e.g. d_x(rho u_x)) apply Eq. (10) to the
+ *    node-wise product field; phi*rho*u is formed as (sum_i f_i) * u, since
+ *    Eq. (7) defines phi*rho as the zeroth moment;
+ *  - d_t phi is the forward difference phi(t+1) - phi(t) (Sec. 2.3, below
+ *    Eq. (20)); it is zero when no next field is given;
+ *  - Eq. (10) next to a domain wall uses the mirror image across the wall
+ *    (scalars copied, velocity-like fields negated, i.e. zero at the
+ *    half-way wall); next to a solid node of the mask it uses the centre
+ *    node's own value (velocity-like fields negated);
+ *  - walls are half-way bounce-back (Sec. 3.1) on the domain faces, so every
+ *    stored row/column is fluid unless the mask says otherwise;
+ *  - the body force is F^B = phi*G + F_ext when scale_by_phi is set (the
+ *    paper's F^B = phi(G - ...) form, Sec. 3.1 and Eq. (23)), else G + F_ext.
+ *  - Eq. (16) is taken with a minus sign on the relaxation term (Eq. (A2)
+ *    prints a plus, at odds with Eq. (16) and Eq. (A3)).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- lattice constants, Eq. (5) ------------------------------------------ */
+static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double WT[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                             1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#define CS2 (1.0 / 3.0) /* lattice sound speed squared, c = 1 */
+
+/* ---- transformation matrix and its inverse, Eq. (A1) ---------------------- */
+/* moment order (Eq. 17): (phi*rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy) */
+static const double MM[9][9] = {
+    {1, 1, 1, 1, 1, 1, 1, 1, 1},
+    {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+    {4, -2, -2, -2, -2, 1, 1, 1, 1},
+    {0, 1, 0, -1, 0, 1, -1, -1, 1},
+    {0, -2, 0, 2, 0, 1, -1, -1, 1},
+    {0, 0, 1, 0, -1, 1, 1, -1, -1},
+    {0, 0, -2, 0, 2, 1, 1, -1, -1},
+    {0, 1, -1, 1, -1, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+/* M^-1 = (1/36) * MINV36, as printed in Eq. (A1) */
+static const double MINV36[9][9] = {
+    {4, -4, 4, 0, 0, 0, 0, 0, 0},   {4, -1, -2, 6, -6, 0, 0, 9, 0},
+    {4, -1, -2, 0, 0, 6, -6, -9, 0}, {4, -1, -2, -6, 6, 0, 0, 9, 0},
+    {4, -1, -2, 0, 0, -6, 6, -9, 0}, {4, 2, 1, 6, 3, 6, 3, 0, 9},
+    {4, 2, 1, -6, -3, 6, 3, 0, -9}, {4, 2, 1, -6, -3, -6, -3, 0, 9},
+    {4, 2, 1, 6, 3, -6, -3, 0, -9}};
+
+typedef struct {
+  int nx, ny;
+  int bc_x, bc_y;  /* 0 periodic, 1 half-way bounce-back walls on both faces */
+  double kappa;    /* provisional equation-of-state constant, Eq. (13) */
+  double s_c, s_e, s_eps, s_q, s_nu; /* diagonal of Gamma, Eq. (16) */
+  double gx, gy;   /* uniform external acceleration G */
+  int scale_by_phi;/* 1: F^B = phi*G (+F_ext); 0: F^B = G (+F_ext) */
+  int use_penalty; /* 1: penalty source C of Eq. (20); 0: ablation (tests) */
+} vo_params;
+
+/* ---- small exported helpers (used by the identity tests) ----------------- */
+
+void vo_tables(double *M, double *Minv36, int *ex, int *ey, double *w,
+               int *opp) {
+  for (int i = 0; i < 9; ++i) {
+    for (int j = 0; j < 9; ++j) {
+      M[i * 9 + j] = MM[i][j];
+      Minv36[i * 9 + j] = MINV36[i][j];
+    }
+    ex[i] = EX[i];
+    ey[i] = EY[i];
+    w[i] = WT[i];
+    opp[i] = OPP[i];
+  }
+}
+
+/* Adjusted density equilibrium with the provisional equation of state,
+ * third-order Hermite form, Eq. (14).  X = kappa/phi. */
+void vo_feq(double phi, double rho, double ux, double uy, double kappa,
+            double *feq) {
+  const double X = kappa / phi;
+  const double uu = ux * ux + uy * uy;
+  double sum_w_nonzero = 0.0;
+  for (int i = 1; i < 9; ++i) sum_w_nonzero += WT[i];
+  feq[0] = phi * rho - sum_w_nonzero * kappa * rho -
+           WT[0] * phi * rho * uu / (2.0 * CS2);
+  for (int i = 1; i < 9; ++i) {
+    const double eu = EX[i] * ux + EY[i] * uy;
+    const double ee = (double)(EX[i] * EX[i] + EY[i] * EY[i]);
+    const double third = 1.0 + 0.5 * (X - 1.0) * (ee / CS2 - 4.0);
+    feq[i] = WT[i] * (kappa * rho +
+                      phi * rho *
+                          (eu / CS2 * third + eu * eu / (2.0 * CS2 * CS2) -
+                           uu / (2.0 * CS2)));
+  }
+}
+
+/* Equilibrium moments, Eq. (18). */
+void vo_meq(double phi, double rho, double ux, double uy, double kappa,
+            double *meq) {
+  const double X = kappa / phi;
+  const double pr = phi * rho;
+  const double uu = ux * ux + uy * uy;
+  meq[0] = pr * 1.0;
+  meq[1] = pr * (-4.0 + 3.0 * uu + 2.0 * X);
+  meq[2] = pr * (4.0 - 3.0 * uu - 3.0 * X);
+  meq[3] = pr * ux;
+  meq[4] = pr * (X - 2.0) * ux;
+  meq[5] = pr * uy;
+  meq[6] = pr * (X - 2.0) * uy;
+  meq[7] = pr * (ux * ux - uy * uy);
+  meq[8] = pr * (ux * uy);
+}
+
+/* Force moments S = M F of Guo's forcing, Eq. (19). */
+void vo_force_moments(double ux, double uy, double Fx, double Fy, double *S) {
+  const double uF = ux * Fx + uy * Fy;
+  S[0] = 0.0;
+  S[1] = 6.0 * uF;
+  S[2] = -6.0 * uF;
+  S[3] = Fx;
+  S[4] = -Fx;
+  S[5] = Fy;
+  S[6] = -Fy;
+  S[7] = 2.0 * (ux * Fx - uy * Fy);
+  S[8] = ux * Fy + uy * Fx;
+}
+
+/* Penalty source components (C_a, C_b, C_c) of Eq. (20). d[] holds
+ * d_x(rho u_x), d_y(rho u_y), d_x u_x, d_y u_y, d_x u_y, d_y u_x,
+ * d_x(phi rho u_x), d_y(phi rho u_y) at the node. */
+void vo_penalty(double phi, double rho, double kappa, double dt_phi,
+                const double *d, double *Cabc) {
+  const double X = kappa / phi;
+  const double drux_x = d[0], druy_y = d[1], dux_x = d[2], duy_y = d[3];
+  const double duy_x = d[4], dux_y = d[5], dmux_x = d[6], dmuy_y = d[7];
+  Cabc[0] = -kappa * (drux_x + druy_y) +
+            2.0 * (kappa - phi) * rho * (dux_x + duy_y) +
+            (3.0 - 2.0 * X) * (dmux_x + dmuy_y) - 2.0 * X * rho * dt_phi;
+  Cabc[1] = -kappa * (drux_x - druy_y) +
+            2.0 / 3.0 * (kappa - phi) * rho * (dux_x - duy_y) +
+            (dmux_x - dmuy_y);
+  Cabc[2] = 1.0 / 3.0 * (kappa - phi) * rho * (duy_x + dux_y);
+}
+
+/* ---- neighbour lookup with the boundary/ghost rules ------------------------
+ * Resolve the neighbour (x+dx, y+dy) of fluid node (x, y).  Returns the index
+ * of the node whose value stands in for it, and sets *sign to -1 when the
+ * stand-in is a reflection (velocity-like fields change sign there). */
+static int is_solid(const unsigned char *mask, int idx) {
+  return mask != NULL && mask[idx] != 0;
+}
+
+static int neighbour(const vo_params *P, const unsigned char *mask, int x,
+                     int y, int dx, int dy, int *sign) {
+  int xn = x + dx, yn = y + dy;
+  int reflected = 0;
+  if (xn < 0 || xn >= P->nx) {
+    if (P->bc_x == 0) {
+      xn = (xn + P->nx) % P->nx;
+    } else {
+      xn = (xn < 0) ? -1 - xn : 2 * P->nx - 1 - xn; /* image across the face */
+      reflected = 1;
+    }
+  }
+  if (yn < 0 || yn >= P->ny) {
+    if (P->bc_y == 0) {
+      yn = (yn + P->ny) % P->ny;
+    } else {
+      yn = (yn < 0) ? -1 - yn : 2 * P->ny - 1 - yn;
+      reflected = 1;
+    }
+  }
+  int idx = yn * P->nx + xn;
+  if (is_solid(mask, idx)) { /* solid neighbour: centre value */
+    idx = y * P->nx + x;
+    reflected = 1;
+  }
+  *sign = reflected ? -1 : 1;
+  return idx;
+}
+
+/* Neighbour table: for every node c and direction i, the index standing in
+ * for x+e_i and the sign for velocity-like fields (built once per step). */
+typedef struct {
+  int *idx;         /* [9][N] */
+  signed char *sgn; /* [9][N] */
+} vo_nbr;
+
+static int nbr_build(const vo_params *P, const unsigned char *mask, vo_nbr *T) {
+  const int N = P->nx * P->ny;
+  T->idx = malloc((size_t)9 * N * sizeof(int));
+  T->sgn = malloc((size_t)9 * N);
+  if (!T->idx || !T->sgn) return -1;
+  for (int y = 0; y < P->ny; ++y)
+    for (int x = 0; x < P->nx; ++x)
+      for (int i = 0; i < 9; ++i) {
+        int sign;
+        const int c = y * P->nx + x;
+        T->idx[(size_t)i * N + c] = neighbour(P, mask, x, y, EX[i], EY[i], &sign);
+        T->sgn[(size_t)i * N + c] = (signed char)sign;
+      }
+  return 0;
+}
+
+static void nbr_free(vo_nbr *T) {
+  free(T->idx);
+  free(T->sgn);
+}
+
+/* Isotropic gradient, Eq. (10): d_a psi = 1/(cs^2 dt) sum_i w_i psi(x+e_i) e_ia.
+ * odd = 1 for velocity-like fields (negated at reflected stand-ins). */
+static void gradient_tab(const vo_params *P, const unsigned char *mask,
+                         const vo_nbr *T, const double *psi, int odd,
+                         double *gx, double *gy) {
+  const int N = P->nx * P->ny;
+  for (int c = 0; c < N; ++c) {
+    if (is_solid(mask, c)) {
+      gx[c] = 0.0;
+      gy[c] = 0.0;
+      continue;
+    }
+    double sx = 0.0, sy = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      const int n = T->idx[(size_t)i * N + c];
+      const double v = (odd && T->sgn[(size_t)i * N + c] < 0) ? -psi[n] : psi[n];
+      sx += WT[i] * v * EX[i];
+      sy += WT[i] * v * EY[i];
+    }
+    gx[c] = sx / CS2;
+    gy[c] = sy / CS2;
+  }
+}
+
+void vo_gradient(const vo_params *P, const unsigned char *mask,
+                 const double *psi, int odd, double *gx, double *gy) {
+  vo_nbr T;
+  if (nbr_build(P, mask, &T) == 0) gradient_tab(P, mask, &T, psi, odd, gx, gy);
+  nbr_free(&T);
+}
+
+/* ---- macroscopic fields, Eq. (7) with the force of Eq. (13) ---------------
+ * rho = sum f / phi; grad rho by Eq. (10); F = (kappa - phi) cs^2 grad rho +
+ * F^B; u = (sum e f + F/2) / sum f; p = rho cs^2.  Any output may be NULL. */
+static void macroscopic_tab(const vo_params *P, const vo_nbr *T,
+                            const double *phi, const unsigned char *mask,
+                            const double *fext_x, const double *fext_y,
+                            const double *f, double *m0_out, double *rho_out,
+                            double *ux_out, double *uy_out, double *Fx_out,
+                            double *Fy_out, double *p_out) {
+  const int N = P->nx * P->ny;
+  double *m0 = calloc(N, sizeof(double)), *rho = calloc(N, sizeof(double));
+  double *jx = calloc(N, sizeof(double)), *jy = calloc(N, sizeof(double));
+  double *grx = calloc(N, sizeof(double)), *gry = calloc(N, sizeof(double));
+  for (int c = 0; c < N; ++c) {
+    if (is_solid(mask, c)) continue;
+    double s = 0.0, sx = 0.0, sy = 0.0;
+    for (int i = 0; i < 9; ++i) {
+      const double fi = f[(size_t)i * N + c];
+      s += fi;
+      sx += EX[i] * fi;
+      sy += EY[i] * fi;
+    }
+    m0[c] = s;
+    jx[c] = sx;
+    jy[c] = sy;
+    rho[c] = s / phi[c];
+  }
+  gradient_tab(P, mask, T, rho, 0, grx, gry);
+  for (int c = 0; c < N; ++c) {
+    double ux = 0.0, uy = 0.0, Fx = 0.0, Fy = 0.0;
+    if (!is_solid(mask, c)) {
+      const double Fpx = (P->kappa - phi[c]) * CS2 * grx[c];
+      const double Fpy = (P->kappa - phi[c]) * CS2 * gry[c];
+      const double sc = P->scale_by_phi ? phi[c] : 1.0;
+      double FBx = sc * P->gx, FBy = sc * P->gy;
+      if (fext_x) FBx += fext_x[c];
+      if (fext_y) FBy += fext_y[c];
+      Fx = Fpx + FBx;
+      Fy = Fpy + FBy;
+      ux = (jx[c] + 0.5 * Fx) / m0[c];
+      uy = (jy[c] + 0.5 * Fy) / m0[c];
+    }
+    if (m0_out) m0_out[c] = m0[c];
+    if (rho_out) rho_out[c] = rho[c];
+    if (ux_out) ux_out[c] = ux;
+    if (uy_out) uy_out[c] = uy;
+    if (Fx_out) Fx_out[c] = Fx;
+    if (Fy_out) Fy_out[c] = Fy;
+    if (p_out) p_out[c] = rho[c] * CS2;
+  }
+  free(m0); free(rho); free(jx); free(jy); free(grx); free(gry);
+}
+
+void vo_macroscopic(const vo_params *P, const double *phi,
+                    const unsigned char *mask, const double *fext_x,
+                    const double *fext_y, const double *f, double *m0_out,
+                    double *rho_out, double *ux_out, double *uy_out,
+                    double *Fx_out, double *Fy_out, double *p_out) {
+  vo_nbr T;
+  if (nbr_build(P, mask, &T) == 0)
+    macroscopic_tab(P, &T, phi, mask, fext_x, fext_y, f, m0_out, rho_out,
+                    ux_out, uy_out, Fx_out, Fy_out, p_out);
+  nbr_free(&T);
+}
+
+/* ---- one time step, Eq. (16) followed by streaming ------------------------
+ * f: post-stream populations at t; fout receives those at t+1.  phi_next,
+ * mask, fext_x, fext_y may be NULL.  Returns 0, or -1 on allocation failure. */
+static int step_tab(const vo_params *P, const vo_nbr *Tp, const double *phi,
+                    const double *phi_next, const unsigned char *mask,
+                    const double *fext_x, const double *fext_y,
+                    const double *f, double *fout) {
+  const int nx = P->nx, ny = P->ny, N = nx * ny;
+  double *m0 = malloc(N * sizeof(double)), *rho = malloc(N * sizeof(double));
+  double *ux = malloc(N * sizeof(double)), *uy = malloc(N * sizeof(double));
+  double *Fx = malloc(N * sizeof(double)), *Fy = malloc(N * sizeof(double));
+  /* product fields and their eight derivatives (O4-O5) */
+  double *rux = malloc(N * sizeof(double)), *ruy = malloc(N * sizeof(double));
+  double *mux = malloc(N * sizeof(double)), *muy = malloc(N * sizeof(double));
+  double *d = malloc((size_t)8 * N * sizeof(double));
+  double *tmp = malloc(N * sizeof(double));
+  if (!m0 || !rho || !ux || !uy || !Fx || !Fy || !rux || !ruy || !mux ||
+      !muy || !d || !tmp)
+    return -1;
+  double *d_rux_x = d, *d_ruy_y = d + N, *d_ux_x = d + 2 * (size_t)N,
+         *d_uy_y = d + 3 * (size_t)N, *d_uy_x = d + 4 * (size_t)N,
+         *d_ux_y = d + 5 * (size_t)N, *d_mux_x = d + 6 * (size_t)N,
+         *d_muy_y = d + 7 * (size_t)N;
+
+  const vo_nbr T = *Tp;
+
+  /* O1-O3: rho, F = F^p + F^B, u (Eq. 7, Eq. 13) */
+  macroscopic_tab(P, &T, phi, mask, fext_x, fext_y, f, m0, rho, ux, uy, Fx,
+                  Fy, NULL);
+
+  /* O4: node-wise product fields */
+  for (int c = 0; c < N; ++c) {
+    rux[c] = rho[c] * ux[c];
+    ruy[c] = rho[c] * uy[c];
+    mux[c] = m0[c] * ux[c]; /* phi*rho*u_x with phi*rho = sum_i f_i */
+    muy[c] = m0[c] * uy[c];
+  }
+
+  /* O5: the eight derivatives of Eq. (20), each by Eq. (10) */
+  gradient_tab(P, mask, &T, rux, 1, d_rux_x, tmp);
+  gradient_tab(P, mask, &T, ruy, 1, tmp, d_ruy_y);
+  gradient_tab(P, mask, &T, ux, 1, d_ux_x, d_ux_y);
+  gradient_tab(P, mask, &T, uy, 1, d_uy_x, d_uy_y);
+  gradient_tab(P, mask, &T, mux, 1, d_mux_x, tmp);
+  gradient_tab(P, mask, &T, muy, 1, tmp, d_muy_y);
+
+  const double s[9] = {P->s_c, P->s_e, P->s_eps, P->s_c, P->s_q,
+                       P->s_c, P->s_q, P->s_nu, P->s_nu};
+
+  for (size_t k = 0; k < (size_t)9 * N; ++k) fout[k] = 0.0;
+
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const int c = y * nx + x;
+      if (is_solid(mask, c)) continue;
+
+      /* O6: penalty source C = (0, C_a, 0, 0, 0, 0, 0, C_b, C_c), Eq. (20) */
+      const double dt_phi = phi_next ? (phi_next[c] - phi[c]) : 0.0;
+      const double dd[8] = {d_rux_x[c], d_ruy_y[c], d_ux_x[c], d_uy_y[c],
+                            d_uy_x[c],  d_ux_y[c],  d_mux_x[c], d_muy_y[c]};
+      double Cabc[3];
+      vo_penalty(phi[c], rho[c], P->kappa, dt_phi, dd, Cabc);
+      double C[9] = {0, Cabc[0], 0, 0, 0, 0, 0, Cabc[1], Cabc[2]};
+      if (!P->use_penalty)
+        for (int k = 0; k < 9; ++k) C[k] = 0.0;
+
+      /* O7: m = M f (Eq. 17), m^eq (Eq. 18), S (Eq. 19) */
+      double fl[9], m[9], meq[9], S[9], mp[9];
+      for (int i = 0; i < 9; ++i) fl[i] = f[(size_t)i * N + c];
+      for (int k = 0; k < 9; ++k) {
+        double acc = 0.0;
+        for (int i = 0; i < 9; ++i) acc += MM[k][i] * fl[i];
+        m[k] = acc;
+      }
+      vo_meq(phi[c], rho[c], ux[c], uy[c], P->kappa, meq);
+      vo_force_moments(ux[c], uy[c], Fx[c], Fy[c], S);
+
+      /* O8: m+ = m - Gamma (m - m^eq) + (I - Gamma/2)(S + C), Eq. (16) */
+      for (int k = 0; k < 9; ++k)
+        mp[k] = m[k] - s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * s[k]) * (S[k] + C[k]);
+
+      /* O9: f+ = M^-1 m+ (Eq. A1) */
+      double fp[9];
+      for (int i = 0; i < 9; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < 9; ++k) acc += MINV36[i][k] * mp[k];
+        fp[i] = acc / 36.0;
+      }
+
+      /* O10: push streaming f_i(x+e_i, t+1) = f+_i(x, t); half-way bounce-back
+       * off walls and solid nodes: f_opp(i)(x, t+1) = f+_i(x, t). */
+      for (int i = 0; i < 9; ++i) {
+        int xn = x + EX[i], yn = y + EY[i];
+        int blocked = 0;
+        if (xn < 0 || xn >= nx) {
+          if (P->bc_x == 0) xn = (xn + nx) % nx; else blocked = 1;
+        }
+        if (yn < 0 || yn >= ny) {
+          if (P->bc_y == 0) yn = (yn + ny) % ny; else blocked = 1;
+        }
+        if (!blocked && is_solid(mask, yn * nx + xn)) blocked = 1;
+        if (blocked)
+          fout[(size_t)OPP[i] * N + c] = fp[i];
+        else
+          fout[(size_t)i * N + (yn * nx + xn)] = fp[i];
+      }
+    }
+
+  free(m0); free(rho); free(ux); free(uy); free(Fx); free(Fy);
+  free(rux); free(ruy); free(mux); free(muy); free(d); free(tmp);
+  return 0;
+}
+
+int vo_step(const vo_params *P, const double *phi, const double *phi_next,
+            const unsigned char *mask, const double *fext_x,
+            const double *fext_y, const double *f, double *fout) {
+  vo_nbr T;
+  if (nbr_build(P, mask, &T) != 0) return -1;
+  const int rc = step_tab(P, &T, phi, phi_next, mask, fext_x, fext_y, f, fout);
+  nbr_free(&T);
+  return rc;
+}
+
+/* Initial populations f(0) = f^eq(rho0, u0) of Eq. (14) at every fluid node. */
+void vo_init_equilibrium(const vo_params *P, const double *phi,
+                         const unsigned char *mask, double rho0, double ux0,
+                         double uy0, double *f) {
+  const int N = P->nx * P->ny;
+  for (int c = 0; c < N; ++c) {
+    double feq[9] = {0};
+    if (!is_solid(mask, c)) vo_feq(phi[c], rho0, ux0, uy0, P->kappa, feq);
+    for (int i = 0; i < 9; ++i) f[(size_t)i * N + c] = feq[i];
+  }
+}
+
+/* Same with a per-node density and velocity (used to start shear waves,
+ * manufactured solutions and random states). */
+void vo_init_fields(const vo_params *P, const double *phi,
+                    const unsigned char *mask, const double *rho,
+                    const double *ux, const double *uy, double *f) {
+  const int N = P->nx * P->ny;
+  for (int c = 0; c < N; ++c) {
+    double feq[9] = {0};
+    if (!is_solid(mask, c)) vo_feq(phi[c], rho[c], ux[c], uy[c], P->kappa, feq);
+    for (int i = 0; i < 9; ++i) f[(size_t)i * N + c] = feq[i];
+  }
+}
+
+/* n steps in a row with static phi and forcing; f is updated in place. */
+int vo_run(const vo_params *P, const double *phi, const unsigned char *mask,
+           const double *fext_x, const double *fext_y, double *f, long nsteps) {
+  const size_t n9 = (size_t)9 * P->nx * P->ny;
+  double *g = malloc(n9 * sizeof(double));
+  vo_nbr T;
+  if (!g || nbr_build(P, mask, &T) != 0) return -1;
+  int rc = 0;
+  for (long t = 0; t < nsteps && rc == 0; ++t) {
+    rc = step_tab(P, &T, phi, NULL, mask, fext_x, fext_y, f, g);
+    if (rc == 0) memcpy(f, g, n9 * sizeof(double));
+  }
+  nbr_free(&T);
+  free(g);
+  return rc;
+}
