@@ -1,0 +1,166 @@
+"""Benchmark of the fused MRTLB-VANSE step on one MI355X.
+
+Workload (the channel configuration the throughput metric is quoted on):
+a single 4096 x 4096 D2Q9 channel, half-way bounce-back walls at y = 0 and
+y = H, periodic in x, body force G = 1e-7 along x (F^B = phi G), phi a tanh
+step from 0.4 to 1.0 (width 2 cells) at mid-channel plus seeded smoothed
+noise of amplitude 0.05 (sigma = 8 cells), kappa = 0.5, s_nu = 0.8 and the
+other rates 1.2, FP32 arithmetic and storage.  A "step" is one launch of the
+fused kernel over the whole lattice.
+
+Prints ONE JSON line (rank 0).  `value` is MLUPS (million lattice-node
+updates per second) over the timed steps, inputs resident in HBM.  The
+`roofline` object prices the step kernel against the 8 TB/s HBM peak with
+the algorithmic bytes per node update (9 population reads + 9 writes + phi);
+its duration comes from HIP events recorded on the stream the kernel is
+launched on.  `cpu_baseline` times the FP64 CPU oracle on a bounded sample
+of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NX = NY = 4096
+G = 1e-7
+KAPPA = 0.5
+RATES = dict(s_c=1.2, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=0.8)
+PRECISION = "f32"
+TILING = (256, 64)  # threads per workgroup, rows swept per workgroup
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS + %HBM peak (D2Q9 MRT-VANSE); batched solves/s + p99 latency"
+BYTES_PER_NODE = {"f64": 9 * 8 * 2 + 8, "f32": 9 * 4 * 2 + 4, "f32s": 9 * 4 * 2 + 4,
+                  "f16s": 9 * 2 * 2 + 4}
+KERNEL_SOURCES = ["paper_2409_02964_amd/csrc/step_kernel.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_f32_channel4096_traffic.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, when
+    they were taken on the current kernel source; else None."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(steps: int):
+    """The FP64 oracle on the same channel: `steps` full-lattice steps."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2409_02964_amd import workloads as W
+    phi = W.channel_phi(NX, NY, seed=2409)
+    o = O.Oracle(NX, NY, phi, kappa=KAPPA, rates=RATES, g=(G, 0.0), bc_y="wall")
+    o.init_equilibrium()
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(o.f[:, ::512, ::512]).all()
+    return dict(value=NX * NY * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{steps} full steps of the {NX}x{NY} channel, FP64, single thread "
+                       f"({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--precision", default=PRECISION, choices=sorted(BYTES_PER_NODE))
+    ap.add_argument("--threads", type=int, default=TILING[0])
+    ap.add_argument("--rows", type=int, default=TILING[1])
+    ap.add_argument("--cpu-steps", type=int, default=3,
+                    help="oracle steps for the CPU baseline (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2409_02964_amd import workloads as W
+    from paper_2409_02964_amd.vanse import Lattice
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    phi = W.channel_phi(NX, NY, seed=2409)
+    lat = Lattice(NX, NY, precision=args.precision, bc_y="wall", device=dev)
+    lat.set_params(KAPPA, RATES).set_body_force(G, 0.0, True)
+    lat.set_void_fraction(phi)
+    lat.set_tiling(args.threads, args.rows)
+    lat.init_equilibrium(1.0)
+    stream = torch.cuda.current_stream(dev)
+
+    lat.step(args.warmup, stream)
+    torch.cuda.synchronize(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    lat.step(args.steps, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    obs = lat.observe(stream, raise_on_diverged=False)
+
+    nodes = NX * NY
+    sec = gpu_ms / 1e3
+    mlups = nodes * args.steps / sec / 1e6
+    per_launch_ms = gpu_ms / max(args.steps, 1)
+    bpn = BYTES_PER_NODE[args.precision]
+    achieved = bpn * nodes / (per_launch_ms / 1e3) / 1e9
+    traffic = measured_traffic() if args.precision == PRECISION else None
+    tl = lat.tiling()
+
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(per_launch_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"D2Q9 MRT-VANSE channel {NX}x{NY}, walls in y, G=1e-7, "
+                               "phi tanh 0.4->1.0 + smoothed noise 0.05 (seed 2409), kappa=0.5, "
+                               "s_nu=0.8, other rates 1.2",
+                   "nx": NX, "ny": NY, "precision": args.precision,
+                   "threads": tl["threads"], "rows": tl["rows"],
+                   "workgroups": tl["workgroups"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bpn * nodes},
+        "wall_s": round(wall, 3),
+        "final_umax": obs["umax"],
+        "nonfinite": obs["nonfinite"],
+    }
+    if args.cpu_steps > 0:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

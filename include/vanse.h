@@ -1,0 +1,165 @@
+/*
+ * vanse.h -- C ABI of libvanse, the MI355X (gfx950) implementation of the
+ * D2Q9 time step of the consistent multiple-relaxation-time lattice
+ * Boltzmann method for the volume-averaged Navier-Stokes equations
+ * (MRTLB-VANSE) of Liu, Zhang, Min & Wu, arXiv:2409.02964.
+ *
+ * Problem statement (Sec. 2.1-2.3): given a void-fraction field phi(x) in
+ * (0, 1], a body force F^B, relaxation rates (the paper's tau_*, which are
+ * RATES: Sec. 2.2, Eq. A11), the provisional equation-of-state constant
+ * kappa (Eq. 13) and boundary conditions, advance Eq. (16) -- moment-space
+ * MRT relaxation with the adjusted equilibrium (Eq. 14/18), Guo forcing
+ * (Eq. 6/19) carrying F = F^p (Eq. 13) + F^B and the penalty source C
+ * (Eq. 20) -- followed by streaming, and report rho, u, p (Eq. 7).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns VANSE_OK (0) or a negative VANSE_ERR_* code and
+ *    never throws; vanse_last_error() returns a thread-local detail string.
+ *  - Field arrays passed in or out are DEVICE pointers to dense row-major
+ *    float64 arrays of shape [ny][nx] (index y*nx + x).  Populations are
+ *    [9][ny][nx] in the D2Q9 order of Eq. (5): e_0 = (0,0), e_1..4 =
+ *    (1,0),(0,1),(-1,0),(0,-1), e_5..8 = (1,1),(-1,1),(-1,-1),(1,-1).
+ *    Inputs are borrowed for the duration of the call only (copied into the
+ *    workspace); outputs are written by the call.
+ *  - `stream` is a hipStream_t (NULL: the legacy default stream).  All work
+ *    is enqueued on it; calls returning host data synchronize it.
+ *  - A handle must not be used by two host threads at once.
+ *  - The library allocates no device memory: all device state lives in a
+ *    caller-owned workspace of vanse_workspace_bytes() bytes that must
+ *    outlive the handle.
+ */
+#ifndef VANSE_H
+#define VANSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define VANSE_OK 0
+#define VANSE_ERR_INVALID_ARG (-1) /* bad size, rate, kappa, phi, pointer */
+#define VANSE_ERR_WORKSPACE (-2)   /* workspace missing, too small, misaligned */
+#define VANSE_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define VANSE_ERR_STATE (-4)       /* step/read before phi, params and init */
+#define VANSE_ERR_DIVERGED (-5)    /* non-finite populations were observed */
+#define VANSE_ERR_UNSUPPORTED (-6) /* a variant that is not built */
+
+/* ---- precision of arithmetic and of the stored populations --------------
+ * The step always works on deviations g_i = f_i - f_i^rest from the rest
+ * state f^rest = f^eq(rho0, u = 0) of Eq. (14) (rest_0 = (phi - 5 kappa/9)
+ * rho0, rest_i = w_i kappa rho0).  "Shifted" storage keeps g in memory, the
+ * others keep f. */
+#define VANSE_F64 0         /* FP64 arithmetic, FP64 f                 152 B/node */
+#define VANSE_F32 1         /* FP32 arithmetic, FP32 f                  76 B/node */
+#define VANSE_F32_SHIFTED 2 /* FP32 arithmetic, FP32 g                  76 B/node */
+#define VANSE_F16_SHIFTED 3 /* FP32 arithmetic, FP16 g * 2^storage_exp  40 B/node */
+
+/* ---- boundaries ---------------------------------------------------------- */
+#define VANSE_PERIODIC 0
+#define VANSE_WALL 1 /* half-way bounce-back walls on both faces (Sec. 3.1) */
+
+typedef struct vanse_lattice vanse_lattice;
+
+typedef struct {
+  int32_t nx, ny;          /* nodes; nx >= 2, ny >= 2 */
+  int32_t precision;       /* VANSE_F64 | VANSE_F32 | ..._SHIFTED */
+  int32_t bc_x;            /* VANSE_PERIODIC (walls in x: VANSE_ERR_UNSUPPORTED) */
+  int32_t bc_y;            /* VANSE_PERIODIC | VANSE_WALL */
+  int32_t has_force_field; /* 1: a per-node force field is added to F^B */
+} vanse_desc;
+
+/* Diagonal of Gamma in Eq. (16), each in (0, 2):
+ * Gamma = diag(s_c, s_e, s_eps, s_c, s_q, s_c, s_q, s_nu, s_nu).
+ * nu = (1/s_nu - 1/2)/3 and nu_e = (1/s_e - 1/2)/3 (Eq. A11).  s_c acts on
+ * conserved moments only and drops out of the update (their relaxation
+ * leaves phi*rho and j + F unchanged, Eq. 17). */
+typedef struct {
+  double s_c, s_e, s_eps, s_q, s_nu;
+} vanse_rates;
+
+/* Bytes of device workspace the lattice described by *d needs (256-byte
+ * aligned).  Layout: two population buffers, phi, optional force planes, a
+ * density scratch plane and reduction space. */
+int vanse_workspace_bytes(const vanse_desc *d, size_t *bytes);
+
+/* Create a lattice whose device state lives in `workspace` (device pointer,
+ * 256-byte aligned, >= vanse_workspace_bytes).  The caller keeps ownership
+ * of the workspace; the handle is host memory freed by vanse_destroy. */
+int vanse_create(const vanse_desc *d, void *workspace, size_t bytes,
+                 vanse_lattice **out);
+int vanse_destroy(vanse_lattice *h);
+
+/* kappa in [0, 1] (Eq. 13: constant of the provisional equation of state,
+ * best close to the minimum of phi) and the relaxation rates. */
+int vanse_set_params(vanse_lattice *h, double kappa, const vanse_rates *r);
+
+/* Uniform external acceleration G: F^B = phi*G (scale_by_phi = 1, the form
+ * F^B = phi(G - ...) of Sec. 3.1 and Eq. 23) or F^B = G (scale_by_phi = 0).
+ * Defaults: G = 0, scale_by_phi = 1. */
+int vanse_set_body_force(vanse_lattice *h, double gx, double gy,
+                         int scale_by_phi);
+
+/* Void fraction phi: device float64 [ny][nx], each value in (0, 1]
+ * (checked; VANSE_ERR_INVALID_ARG otherwise).  Synchronizes the stream. */
+int vanse_set_void_fraction(vanse_lattice *h, const double *phi, void *stream);
+
+/* Per-node force added to F^B (e.g. the manufactured-solution forces of
+ * Appendix C): device float64 [ny][nx] each.  Needs has_force_field. */
+int vanse_set_force_field(vanse_lattice *h, const double *fx, const double *fy,
+                          void *stream);
+
+/* t = 0 with f(0) = f^eq(rho0, u0) of Eq. (14) at every node.  rho0 is also
+ * the reference density of the rest state used by the deviation form. */
+int vanse_init_equilibrium(vanse_lattice *h, double rho0, double ux0,
+                           double uy0, void *stream);
+
+/* t = 0 with the given post-streaming populations f(0): device float64
+ * [9][ny][nx].  The rest-state reference density is rho0. */
+int vanse_set_populations(vanse_lattice *h, const double *f, double rho0,
+                          void *stream);
+
+/* Advance nsteps >= 0 time steps (collision of Eq. 16, then streaming with
+ * bounce-back).  Enqueued only; does not synchronize. */
+int vanse_step(vanse_lattice *h, int64_t nsteps, void *stream);
+
+/* rho = sum f / phi, u = (sum e f + F/2) / sum f, p = rho/3 (Eq. 7, with
+ * F = F^p + F^B of Eq. 13) of the populations at the current t.  Device
+ * float64 [ny][nx] outputs; any of ux, uy, p may be NULL. */
+int vanse_read_moments(vanse_lattice *h, double *rho, double *ux, double *uy,
+                       double *p, void *stream);
+
+/* Post-streaming populations f_i(x, t) at the current t: device float64
+ * [9][ny][nx]. */
+int vanse_read_populations(vanse_lattice *h, double *f, void *stream);
+
+/* Observables of the current state, reduced in FP64 on the device in a
+ * fixed order: out[0] = total mass sum_x sum_i f_i, out[1] = sum_x |u|^2,
+ * out[2] = max_x |u|, out[3] = number of nodes with a non-finite value.
+ * `out` is HOST memory (4 doubles); synchronizes the stream.  Returns
+ * VANSE_ERR_DIVERGED (after filling out) when out[3] > 0. */
+int vanse_observe(vanse_lattice *h, double *out, void *stream);
+
+/* Launch shape of the step kernel: threads per workgroup (64, 128, 256 or
+ * 512; a workgroup owns threads-4 columns) and rows swept per workgroup
+ * (>= 1).  threads = 0 or rows = 0 restores the size-based default. */
+int vanse_set_tiling(vanse_lattice *h, int threads, int rows);
+int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
+                     int *workgroups);
+
+/* Exponent e of the storage scale 2^e of VANSE_F16_SHIFTED (default 12):
+ * memory holds g * 2^e in FP16.  Only before init. */
+int vanse_set_storage_exponent(vanse_lattice *h, int e);
+
+/* Current time step t. */
+int64_t vanse_time(const vanse_lattice *h);
+
+const char *vanse_error_string(int code);
+const char *vanse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VANSE_H */

@@ -1,0 +1,285 @@
+// aux_kernels.hpp -- set-up and read-out kernels around the fused step:
+// field uploads, initial populations, population I/O, macroscopic fields and
+// FP64 observables.  None of these is on the per-step path.
+//
+// Storage convention (see step_kernel.hpp): buffer slot s_i(y) holds the
+// post-collision population that the next pull delivers to node y + e_i as
+// f_i, or -- when y + e_i lies beyond a wall -- back to node y as f_opp(i).
+// Values are f (plain storage) or deviations g = f - f^rest (shifted storage,
+// times a power-of-two scale).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "step_kernel.hpp"
+
+namespace vanse_dev {
+
+__constant__ int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__constant__ int kOPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+struct Geo {
+  int nx, ny, pitch, walls;
+  long long plane;
+};
+
+// Rest-state population f^rest_i = f^eq_i(rho0, 0) of Eq. (14) at a node
+// of void fraction phi.
+template <typename T>
+__device__ __forceinline__ T rest_pop(int i, T phi, const StepPhys<T>& ph) {
+  if (i == 0) return phi * ph.rho0 - ph.rest0_k;
+  return (i < 5) ? ph.rest_axis : ph.rest_diag;
+}
+
+// Adjusted equilibrium of Eq. (14), written with cs^2 = 1/3 and X = kappa/phi:
+// the third-order factor is (3 - X)/2 on the axes and X on the diagonals.
+__device__ inline double feq_pop(int i, double phi, double rho, double ux, double uy,
+                                 double kappa) {
+  const double uu = ux * ux + uy * uy;
+  if (i == 0) return phi * rho - 5.0 / 9.0 * kappa * rho - 2.0 / 3.0 * phi * rho * uu;
+  const double X = kappa / phi;
+  const double eu = kEX[i] * ux + kEY[i] * uy;
+  const bool axis = i < 5;
+  const double w = axis ? 1.0 / 9.0 : 1.0 / 36.0;
+  const double h3 = axis ? 0.5 * (3.0 - X) : X;
+  return w * (kappa * rho + phi * rho * (3.0 * eu * h3 + 4.5 * eu * eu - 1.5 * uu));
+}
+
+template <typename S, typename T, bool SHIFT>
+__device__ __forceinline__ S encode(double f, T phi, int i, const StepPhys<T>& ph) {
+  if (SHIFT) return static_cast<S>((static_cast<T>(f - double(rest_pop(i, phi, ph)))) * ph.scale);
+  return static_cast<S>(f);
+}
+
+template <typename S, typename T, bool SHIFT>
+__device__ __forceinline__ double decode(S s, T phi, int i, const StepPhys<T>& ph) {
+  if (SHIFT) return double(static_cast<T>(s) * ph.inv_scale) + double(rest_pop(i, phi, ph));
+  return double(static_cast<T>(s));
+}
+
+// Receiving node of stored slot (x, y, i): (x + e_i, y + e_i) or, across a
+// wall, (x, y) with direction opp(i).  Returns false for the wall case.
+__device__ __forceinline__ bool receiver(const Geo& G, int x, int y, int i, int* xr, int* yr) {
+  int xn = x + kEX[i];
+  int yn = y + kEY[i];
+  xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
+  if (G.walls) {
+    if (yn < 0 || yn >= G.ny) { *xr = x; *yr = y; return false; }
+  } else {
+    yn = yn < 0 ? yn + G.ny : (yn >= G.ny ? yn - G.ny : yn);
+  }
+  *xr = xn; *yr = yn;
+  return true;
+}
+
+// Convert a dense float64 field to a pitched plane of T.
+template <typename T>
+__global__ void convert_field(const double* __restrict__ in, T* __restrict__ out, int nx, int ny,
+                              int pitch) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x < nx && y < ny) out[y * pitch + x] = static_cast<T>(in[y * nx + x]);
+}
+
+// Count entries of a dense field outside (0, 1] (or non-finite).
+__global__ void count_bad_phi(const double* __restrict__ in, long long n,
+                              unsigned long long* __restrict__ bad) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  unsigned long long cnt = 0;
+  for (; i < n; i += stride) {
+    const double v = in[i];
+    if (!(v > 0.0 && v <= 1.0)) ++cnt;
+  }
+  if (cnt) atomicAdd(bad, cnt);
+}
+
+// Fill the stored slots so that the next pull yields f(0): either the
+// equilibrium of Eq. (14) at (rho0, u0), or given dense populations.
+template <typename S, typename T, bool SHIFT>
+__global__ void fill_state(Geo G, S* __restrict__ buf, const T* __restrict__ phi, StepPhys<T> ph,
+                           const double* __restrict__ fin, double rho_init, double ux0, double uy0,
+                           double kappa) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const long long N = (long long)G.nx * G.ny;
+  for (int i = 0; i < 9; ++i) {
+    int xr, yr;
+    const bool through = receiver(G, x, y, i, &xr, &yr);
+    const int j = through ? i : kOPP[i];  // population index at the receiver
+    const T phr = phi[yr * G.pitch + xr];
+    double f;
+    if (fin) {
+      f = fin[j * N + (long long)yr * G.nx + xr];
+    } else {
+      f = feq_pop(j, double(phr), rho_init, ux0, uy0, kappa);
+    }
+    buf[i * G.plane + (long long)y * G.pitch + x] = encode<S, T, SHIFT>(f, phr, j, ph);
+  }
+}
+
+// Pull the populations of the current time: f_i(x) = slot_i(x - e_i), or
+// slot_opp(i)(x) when x - e_i is beyond a wall.
+template <typename S, typename T, bool SHIFT>
+__device__ __forceinline__ double pull_one(const Geo& G, const S* __restrict__ buf, T phi_x,
+                                           const StepPhys<T>& ph, int x, int y, int i) {
+  int xs = x - kEX[i];
+  int ys = y - kEY[i];
+  int slot = i;
+  xs = xs < 0 ? xs + G.nx : (xs >= G.nx ? xs - G.nx : xs);
+  if (G.walls && (ys < 0 || ys >= G.ny)) {
+    xs = x; ys = y; slot = kOPP[i];
+  } else {
+    ys = ys < 0 ? ys + G.ny : (ys >= G.ny ? ys - G.ny : ys);
+  }
+  const S s = buf[slot * G.plane + (long long)ys * G.pitch + xs];
+  return decode<S, T, SHIFT>(s, phi_x, i, ph);  // rest_i depends on phi only for i = 0
+}
+
+template <typename S, typename T, bool SHIFT>
+__global__ void read_pops(Geo G, const S* __restrict__ buf, const T* __restrict__ phi,
+                          StepPhys<T> ph, double* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const long long N = (long long)G.nx * G.ny;
+  const T ph_x = phi[y * G.pitch + x];
+  for (int i = 0; i < 9; ++i)
+    out[i * N + (long long)y * G.nx + x] = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i);
+}
+
+// Pass 1 of the macroscopic read-out: delta rho (in T) to a scratch plane.
+template <typename S, typename T, bool SHIFT>
+__global__ void moments_rho(Geo G, const S* __restrict__ buf, const T* __restrict__ phi,
+                            StepPhys<T> ph, T* __restrict__ drho_out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const T ph_x = phi[y * G.pitch + x];
+  T dm0 = 0;
+  for (int i = 0; i < 9; ++i) {
+    const double f = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i);
+    dm0 += static_cast<T>(f - double(rest_pop(i, ph_x, ph)));
+  }
+  drho_out[y * G.pitch + x] = dm0 / ph_x;
+}
+
+// Pass 2: grad rho (Eq. 10 with mirror images at walls), F, u, p; optional
+// FP64 block partials of the observables.
+template <typename S, typename T, bool SHIFT, bool FFIELD>
+__global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restrict__ phi,
+                            StepPhys<T> ph, const T* __restrict__ drho, const T* __restrict__ fxf,
+                            const T* __restrict__ fyf, double* __restrict__ rho_o,
+                            double* __restrict__ ux_o, double* __restrict__ uy_o,
+                            double* __restrict__ p_o, double* __restrict__ partials) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  double mass = 0.0, u2 = 0.0, umax = 0.0, bad = 0.0;
+  if (x < G.nx && y < G.ny) {
+    const T ph_x = phi[y * G.pitch + x];
+    double m0 = 0.0, jx = 0.0, jy = 0.0;
+    T dm0 = 0;
+    T f[9];
+    for (int i = 0; i < 9; ++i) {
+      const double fi = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i);
+      f[i] = static_cast<T>(fi - double(rest_pop(i, ph_x, ph)));
+      m0 += fi;
+    }
+    for (int i = 0; i < 9; ++i) dm0 += f[i];
+    T tjx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+    T tjy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+    jx = tjx; jy = tjy;
+    // neighbours of delta-rho; mirror image across walls
+    auto R = [&](int dx, int dy) -> T {
+      int xn = x + dx, yn = y + dy;
+      xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
+      if (G.walls) {
+        yn = yn < 0 ? 0 : (yn >= G.ny ? G.ny - 1 : yn);
+      } else {
+        yn = yn < 0 ? yn + G.ny : (yn >= G.ny ? yn - G.ny : yn);
+      }
+      return drho[yn * G.pitch + xn];
+    };
+    const T grx = stencil_dx(R(1, 0), R(-1, 0), R(1, 1), R(1, -1), R(-1, 1), R(-1, -1));
+    const T gry = stencil_dy(R(0, 1), R(0, -1), R(1, 1), R(-1, 1), R(1, -1), R(-1, -1));
+    const T kp = (ph.kappa - ph_x) * T(1.0 / 3.0);
+    const T sg = ph.scale_by_phi ? ph_x : T(1);
+    T Fx = kp * grx + sg * ph.gx;
+    T Fy = kp * gry + sg * ph.gy;
+    if (FFIELD) {
+      Fx += fxf[y * G.pitch + x];
+      Fy += fyf[y * G.pitch + x];
+    }
+    const T tm0 = ph_x * ph.rho0 + dm0;
+    const T ux = (tjx + T(0.5) * Fx) / tm0;
+    const T uy = (tjy + T(0.5) * Fy) / tm0;
+    const T rho = ph.rho0 + dm0 / ph_x;
+    const long long o = (long long)y * G.nx + x;
+    if (rho_o) rho_o[o] = double(rho);
+    if (ux_o) ux_o[o] = double(ux);
+    if (uy_o) uy_o[o] = double(uy);
+    if (p_o) p_o[o] = double(rho) / 3.0;
+    mass = m0;
+    u2 = double(ux) * double(ux) + double(uy) * double(uy);
+    umax = sqrt(u2);
+    const bool finite = isfinite(m0) && isfinite(double(ux)) && isfinite(double(uy)) &&
+                        isfinite(jx) && isfinite(jy);
+    bad = finite ? 0.0 : 1.0;
+    if (!finite) { mass = 0.0; u2 = 0.0; umax = 0.0; }
+  }
+  if (partials) {
+    // block reduction in a fixed order: wavefront shuffles, then LDS
+    __shared__ double red[4][16];
+    for (int off = 32; off > 0; off >>= 1) {
+      mass += __shfl_down(mass, off, 64);
+      u2 += __shfl_down(u2, off, 64);
+      umax = fmax(umax, __shfl_down(umax, off, 64));
+      bad += __shfl_down(bad, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) { red[0][wv] = mass; red[1][wv] = u2; red[2][wv] = umax; red[3][wv] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int nw = blockDim.x >> 6;
+      double a = 0, b = 0, c = 0, d = 0;
+      for (int k = 0; k < nw; ++k) { a += red[0][k]; b += red[1][k]; c = fmax(c, red[2][k]); d += red[3][k]; }
+      const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
+      partials[blk * 4 + 0] = a;
+      partials[blk * 4 + 1] = b;
+      partials[blk * 4 + 2] = c;
+      partials[blk * 4 + 3] = d;
+    }
+  }
+}
+
+// Final fixed-order reduction of the block partials (one workgroup).
+__global__ void reduce_partials(const double* __restrict__ partials, long long nblk,
+                                double* __restrict__ out) {
+  __shared__ double red[4][256];
+  double a = 0, b = 0, c = 0, d = 0;
+  for (long long k = threadIdx.x; k < nblk; k += blockDim.x) {
+    a += partials[k * 4 + 0];
+    b += partials[k * 4 + 1];
+    c = fmax(c, partials[k * 4 + 2]);
+    d += partials[k * 4 + 3];
+  }
+  red[0][threadIdx.x] = a; red[1][threadIdx.x] = b; red[2][threadIdx.x] = c; red[3][threadIdx.x] = d;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + s]);
+      red[3][threadIdx.x] += red[3][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = red[0][0]; out[1] = red[1][0]; out[2] = red[2][0]; out[3] = red[3][0];
+  }
+}
+
+}  // namespace vanse_dev

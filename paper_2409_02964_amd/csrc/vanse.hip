@@ -1,0 +1,522 @@
+// vanse.hip -- libvanse: host side of the C ABI declared in include/vanse.h.
+//
+// The handle validates arguments, carves all device state out of the
+// caller's workspace, picks the template instance of the fused step kernel
+// (precision x boundary x force field x workgroup width) and enqueues work on
+// the caller's stream.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <type_traits>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "aux_kernels.hpp"
+#include "step_kernel.hpp"
+#include "vanse.h"
+
+using namespace vanse_dev;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(VANSE_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int storage_bytes(int precision) {
+  switch (precision) {
+    case VANSE_F64: return 8;
+    case VANSE_F32: return 4;
+    case VANSE_F32_SHIFTED: return 4;
+    case VANSE_F16_SHIFTED: return 2;
+    default: return 0;
+  }
+}
+int compute_bytes(int precision) { return precision == VANSE_F64 ? 8 : 4; }
+
+int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
+
+struct Layout {
+  size_t pop[2], phi, fx, fy, drho, partials, result, badcount, total;
+  long long plane;
+  int pitch;
+  long long max_partials;
+};
+
+int make_layout(const vanse_desc* d, Layout* L) {
+  if (!d) return fail(VANSE_ERR_INVALID_ARG, "desc is NULL");
+  if (d->nx < 2 || d->ny < 2) return fail(VANSE_ERR_INVALID_ARG, "nx, ny must be >= 2 (got %d, %d)", d->nx, d->ny);
+  if (storage_bytes(d->precision) == 0) return fail(VANSE_ERR_INVALID_ARG, "unknown precision %d", d->precision);
+  if (d->bc_x != VANSE_PERIODIC) {
+    if (d->bc_x == VANSE_WALL) return fail(VANSE_ERR_UNSUPPORTED, "walls in x are not built");
+    return fail(VANSE_ERR_INVALID_ARG, "unknown bc_x %d", d->bc_x);
+  }
+  if (d->bc_y != VANSE_PERIODIC && d->bc_y != VANSE_WALL) return fail(VANSE_ERR_INVALID_ARG, "unknown bc_y %d", d->bc_y);
+  if (d->has_force_field != 0 && d->has_force_field != 1) return fail(VANSE_ERR_INVALID_ARG, "has_force_field must be 0 or 1");
+  const long long pitch = pitch_of(d->nx);
+  const long long plane = pitch * d->ny;
+  if (plane * 9 > (1LL << 31) - 1) return fail(VANSE_ERR_INVALID_ARG, "lattice too large (%d x %d)", d->nx, d->ny);
+  const size_t sb = storage_bytes(d->precision), cb = compute_bytes(d->precision);
+  size_t off = 0;
+  L->pitch = (int)pitch;
+  L->plane = plane;
+  for (int b = 0; b < 2; ++b) { L->pop[b] = off; off = align256(off + 9 * plane * sb); }
+  L->phi = off; off = align256(off + plane * cb);
+  if (d->has_force_field) {
+    L->fx = off; off = align256(off + plane * cb);
+    L->fy = off; off = align256(off + plane * cb);
+  } else {
+    L->fx = L->fy = 0;
+  }
+  L->drho = off; off = align256(off + plane * cb);
+  L->max_partials = (long long)((d->nx + 255) / 256) * d->ny;
+  L->partials = off; off = align256(off + L->max_partials * 4 * sizeof(double));
+  L->result = off; off = align256(off + 4 * sizeof(double));
+  L->badcount = off; off = align256(off + sizeof(unsigned long long));
+  L->total = off;
+  return VANSE_OK;
+}
+
+}  // namespace
+
+struct vanse_lattice {
+  vanse_desc d;
+  Layout L;
+  char* ws;
+  int cur;  // buffer holding the current state
+  int64_t t;
+  bool phi_set, params_set, state_set, ff_set;
+  double kappa, rho0, gx, gy;
+  int scale_by_phi;
+  vanse_rates rates;
+  int threads, rows;  // launch shape of the step kernel
+  bool tiling_default;
+  int storage_exp;
+};
+
+namespace {
+
+void default_tiling(vanse_lattice* h) {
+  const int nx = h->d.nx, ny = h->d.ny;
+  int threads = nx >= 200 ? 256 : (nx >= 100 ? 128 : 64);
+  const int strips = (nx + threads - 5) / (threads - 4);
+  long long r = (long long)ny * strips / 1024;
+  if (r < 4) r = 4;
+  if (r > 64) r = 64;
+  h->threads = threads;
+  h->rows = (int)r;
+}
+
+template <typename T>
+StepPhys<T> make_phys(const vanse_lattice* h) {
+  StepPhys<T> p;
+  p.kappa = T(h->kappa);
+  p.rho0 = T(h->rho0);
+  p.gx = T(h->gx);
+  p.gy = T(h->gy);
+  p.s_e = T(h->rates.s_e);
+  p.s_eps = T(h->rates.s_eps);
+  p.s_q = T(h->rates.s_q);
+  p.s_nu = T(h->rates.s_nu);
+  p.rest_axis = T(h->kappa * h->rho0 / 9.0);
+  p.rest_diag = T(h->kappa * h->rho0 / 36.0);
+  p.rest0_k = T(5.0 * h->kappa * h->rho0 / 9.0);
+  const bool half = h->d.precision == VANSE_F16_SHIFTED;
+  p.scale = T(half ? std::ldexp(1.0, h->storage_exp) : 1.0);
+  p.inv_scale = T(half ? std::ldexp(1.0, -h->storage_exp) : 1.0);
+  p.scale_by_phi = h->scale_by_phi;
+  return p;
+}
+
+Geo make_geo(const vanse_lattice* h) {
+  Geo G;
+  G.nx = h->d.nx;
+  G.ny = h->d.ny;
+  G.pitch = h->L.pitch;
+  G.walls = h->d.bc_y == VANSE_WALL;
+  G.plane = h->L.plane;
+  return G;
+}
+
+template <typename S, typename T, bool SHIFT, bool WALLS, bool FF, int NT>
+void launch_step_nt(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& ph, int blocks,
+                    hipStream_t st) {
+  hipLaunchKernelGGL((vanse_step_kernel<S, T, SHIFT, WALLS, FF, NT>), dim3(blocks), dim3(NT), 0, st, g,
+                     ph);
+}
+
+template <typename S, typename T, bool SHIFT, bool WALLS, bool FF>
+int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& ph, int blocks,
+                  hipStream_t st) {
+  switch (h->threads) {
+    case 64: launch_step_nt<S, T, SHIFT, WALLS, FF, 64>(h, g, ph, blocks, st); break;
+    case 128: launch_step_nt<S, T, SHIFT, WALLS, FF, 128>(h, g, ph, blocks, st); break;
+    case 256: launch_step_nt<S, T, SHIFT, WALLS, FF, 256>(h, g, ph, blocks, st); break;
+    case 512: launch_step_nt<S, T, SHIFT, WALLS, FF, 512>(h, g, ph, blocks, st); break;
+    default: return fail(VANSE_ERR_INVALID_ARG, "unsupported workgroup width %d", h->threads);
+  }
+  return VANSE_OK;
+}
+
+template <typename S, typename T, bool SHIFT>
+int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
+  const StepPhys<T> ph = make_phys<T>(h);
+  StepGeom g;
+  g.phi = h->ws + h->L.phi;
+  g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
+  g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
+  g.plane = h->L.plane;
+  g.nx = h->d.nx;
+  g.ny = h->d.ny;
+  g.pitch = h->L.pitch;
+  g.out_w = h->threads - 4;
+  g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
+  g.rows = h->rows;
+  const int nby = (h->d.ny + g.rows - 1) / g.rows;
+  const int blocks = g.strips * nby;
+  const bool walls = h->d.bc_y == VANSE_WALL;
+  const bool ff = h->d.has_force_field != 0;
+  for (int64_t s = 0; s < n; ++s) {
+    g.src = h->ws + h->L.pop[h->cur];
+    g.dst = h->ws + h->L.pop[h->cur ^ 1];
+    int rc;
+    if (walls)
+      rc = ff ? launch_step_w<S, T, SHIFT, true, true>(h, g, ph, blocks, st)
+              : launch_step_w<S, T, SHIFT, true, false>(h, g, ph, blocks, st);
+    else
+      rc = ff ? launch_step_w<S, T, SHIFT, false, true>(h, g, ph, blocks, st)
+              : launch_step_w<S, T, SHIFT, false, false>(h, g, ph, blocks, st);
+    if (rc != VANSE_OK) return rc;
+    h->cur ^= 1;
+    h->t += 1;
+    if (s == 0) HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipGetLastError());
+  return VANSE_OK;
+}
+
+// Dispatch on the storage precision: F(S, T, SHIFT) is a generic lambda.
+template <typename Fn>
+int by_precision(const vanse_lattice* h, Fn&& fn) {
+  switch (h->d.precision) {
+    case VANSE_F64: return fn((double*)nullptr, (double*)nullptr, std::false_type{});
+    case VANSE_F32: return fn((float*)nullptr, (float*)nullptr, std::false_type{});
+    case VANSE_F32_SHIFTED: return fn((float*)nullptr, (float*)nullptr, std::true_type{});
+    case VANSE_F16_SHIFTED: return fn((_Float16*)nullptr, (float*)nullptr, std::true_type{});
+  }
+  return fail(VANSE_ERR_INVALID_ARG, "unknown precision");
+}
+
+int check_handle(const vanse_lattice* h) {
+  if (!h) return fail(VANSE_ERR_INVALID_ARG, "handle is NULL");
+  return VANSE_OK;
+}
+
+int check_ready(const vanse_lattice* h) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->phi_set) return fail(VANSE_ERR_STATE, "void fraction not set");
+  if (!h->params_set) return fail(VANSE_ERR_STATE, "kappa and rates not set");
+  if (h->d.has_force_field && !h->ff_set) return fail(VANSE_ERR_STATE, "force field not set");
+  return VANSE_OK;
+}
+
+dim3 field_grid(const vanse_lattice* h) { return dim3((h->d.nx + 255) / 256, h->d.ny); }
+
+}  // namespace
+
+extern "C" {
+
+int vanse_workspace_bytes(const vanse_desc* d, size_t* bytes) {
+  if (!bytes) return fail(VANSE_ERR_INVALID_ARG, "bytes is NULL");
+  Layout L;
+  if (int rc = make_layout(d, &L)) return rc;
+  *bytes = L.total;
+  return VANSE_OK;
+}
+
+int vanse_create(const vanse_desc* d, void* workspace, size_t bytes, vanse_lattice** out) {
+  if (!out) return fail(VANSE_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  Layout L;
+  if (int rc = make_layout(d, &L)) return rc;
+  if (!workspace) return fail(VANSE_ERR_WORKSPACE, "workspace is NULL");
+  if (((uintptr_t)workspace) & 255) return fail(VANSE_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (bytes < L.total) return fail(VANSE_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", bytes, L.total);
+  vanse_lattice* h = new (std::nothrow) vanse_lattice();
+  if (!h) return fail(VANSE_ERR_INVALID_ARG, "out of host memory");
+  h->d = *d;
+  h->L = L;
+  h->ws = static_cast<char*>(workspace);
+  h->cur = 0;
+  h->t = 0;
+  h->phi_set = h->params_set = h->state_set = h->ff_set = false;
+  h->kappa = 0.5;
+  h->rho0 = 1.0;
+  h->gx = h->gy = 0.0;
+  h->scale_by_phi = 1;
+  h->rates = vanse_rates{1.0, 1.2, 1.2, 1.2, 1.2};
+  h->storage_exp = 12;
+  h->tiling_default = true;
+  default_tiling(h);
+  *out = h;
+  return VANSE_OK;
+}
+
+int vanse_destroy(vanse_lattice* h) {
+  delete h;
+  return VANSE_OK;
+}
+
+int vanse_set_params(vanse_lattice* h, double kappa, const vanse_rates* r) {
+  if (int rc = check_handle(h)) return rc;
+  if (!r) return fail(VANSE_ERR_INVALID_ARG, "rates is NULL");
+  if (!(kappa >= 0.0 && kappa <= 1.0)) return fail(VANSE_ERR_INVALID_ARG, "kappa must be in [0, 1] (got %g)", kappa);
+  const double s[5] = {r->s_c, r->s_e, r->s_eps, r->s_q, r->s_nu};
+  for (double v : s)
+    if (!(v > 0.0 && v < 2.0)) return fail(VANSE_ERR_INVALID_ARG, "relaxation rates must be in (0, 2) (got %g)", v);
+  h->kappa = kappa;
+  h->rates = *r;
+  h->params_set = true;
+  return VANSE_OK;
+}
+
+int vanse_set_body_force(vanse_lattice* h, double gx, double gy, int scale_by_phi) {
+  if (int rc = check_handle(h)) return rc;
+  if (!std::isfinite(gx) || !std::isfinite(gy)) return fail(VANSE_ERR_INVALID_ARG, "G must be finite");
+  if (scale_by_phi != 0 && scale_by_phi != 1) return fail(VANSE_ERR_INVALID_ARG, "scale_by_phi must be 0 or 1");
+  h->gx = gx;
+  h->gy = gy;
+  h->scale_by_phi = scale_by_phi;
+  return VANSE_OK;
+}
+
+int vanse_set_void_fraction(vanse_lattice* h, const double* phi, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!phi) return fail(VANSE_ERR_INVALID_ARG, "phi is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned long long* bad = reinterpret_cast<unsigned long long*>(h->ws + h->L.badcount);
+  HIP_TRY(hipMemsetAsync(bad, 0, sizeof(*bad), st));
+  const long long n = (long long)h->d.nx * h->d.ny;
+  hipLaunchKernelGGL(count_bad_phi, dim3(256), dim3(256), 0, st, phi, n, bad);
+  HIP_TRY(hipGetLastError());
+  unsigned long long nbad = 0;
+  HIP_TRY(hipMemcpyAsync(&nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (nbad) return fail(VANSE_ERR_INVALID_ARG, "%llu void-fraction values outside (0, 1]", nbad);
+  void* dst = h->ws + h->L.phi;
+  if (h->d.precision == VANSE_F64)
+    hipLaunchKernelGGL(convert_field<double>, field_grid(h), dim3(256), 0, st, phi, (double*)dst, h->d.nx, h->d.ny, h->L.pitch);
+  else
+    hipLaunchKernelGGL(convert_field<float>, field_grid(h), dim3(256), 0, st, phi, (float*)dst, h->d.nx, h->d.ny, h->L.pitch);
+  HIP_TRY(hipGetLastError());
+  h->phi_set = true;
+  return VANSE_OK;
+}
+
+int vanse_set_force_field(vanse_lattice* h, const double* fx, const double* fy, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->d.has_force_field) return fail(VANSE_ERR_STATE, "lattice was created without a force field");
+  if (!fx || !fy) return fail(VANSE_ERR_INVALID_ARG, "force planes are NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double* in[2] = {fx, fy};
+  const size_t off[2] = {h->L.fx, h->L.fy};
+  for (int k = 0; k < 2; ++k) {
+    void* dst = h->ws + off[k];
+    if (h->d.precision == VANSE_F64)
+      hipLaunchKernelGGL(convert_field<double>, field_grid(h), dim3(256), 0, st, in[k], (double*)dst, h->d.nx, h->d.ny, h->L.pitch);
+    else
+      hipLaunchKernelGGL(convert_field<float>, field_grid(h), dim3(256), 0, st, in[k], (float*)dst, h->d.nx, h->d.ny, h->L.pitch);
+  }
+  HIP_TRY(hipGetLastError());
+  h->ff_set = true;
+  return VANSE_OK;
+}
+
+static int fill(vanse_lattice* h, const double* fin, double rho0, double ux0, double uy0, void* stream) {
+  if (int rc = check_ready(h)) return rc;
+  if (!(rho0 > 0.0) || !std::isfinite(rho0)) return fail(VANSE_ERR_INVALID_ARG, "rho0 must be positive");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  h->rho0 = rho0;
+  const Geo G = make_geo(h);
+  const int rc = by_precision(h, [&](auto* s_tag, auto* t_tag, auto shift) -> int {
+    using S = std::remove_pointer_t<decltype(s_tag)>;
+    using T = std::remove_pointer_t<decltype(t_tag)>;
+    constexpr bool SH = decltype(shift)::value;
+    const StepPhys<T> ph = make_phys<T>(h);
+    hipLaunchKernelGGL((fill_state<S, T, SH>), field_grid(h), dim3(256), 0, st, G,
+                       (S*)(h->ws + h->L.pop[0]), (const T*)(h->ws + h->L.phi), ph, fin, rho0, ux0,
+                       uy0, h->kappa);
+    return VANSE_OK;
+  });
+  if (rc) return rc;
+  HIP_TRY(hipGetLastError());
+  h->cur = 0;
+  h->t = 0;
+  h->state_set = true;
+  return VANSE_OK;
+}
+
+int vanse_init_equilibrium(vanse_lattice* h, double rho0, double ux0, double uy0, void* stream) {
+  if (!std::isfinite(ux0) || !std::isfinite(uy0)) return fail(VANSE_ERR_INVALID_ARG, "u0 must be finite");
+  return fill(h, nullptr, rho0, ux0, uy0, stream);
+}
+
+int vanse_set_populations(vanse_lattice* h, const double* f, double rho0, void* stream) {
+  if (!f) return fail(VANSE_ERR_INVALID_ARG, "populations are NULL");
+  return fill(h, f, rho0, 0.0, 0.0, stream);
+}
+
+int vanse_step(vanse_lattice* h, int64_t nsteps, void* stream) {
+  if (int rc = check_ready(h)) return rc;
+  if (!h->state_set) return fail(VANSE_ERR_STATE, "populations not initialised");
+  if (nsteps < 0) return fail(VANSE_ERR_INVALID_ARG, "nsteps must be >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return by_precision(h, [&](auto* s_tag, auto* t_tag, auto shift) -> int {
+    using S = std::remove_pointer_t<decltype(s_tag)>;
+    using T = std::remove_pointer_t<decltype(t_tag)>;
+    return run_steps<S, T, decltype(shift)::value>(h, nsteps, st);
+  });
+}
+
+static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double* p, bool partials,
+                   void* stream) {
+  if (int rc = check_ready(h)) return rc;
+  if (!h->state_set) return fail(VANSE_ERR_STATE, "populations not initialised");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Geo G = make_geo(h);
+  const int rc = by_precision(h, [&](auto* s_tag, auto* t_tag, auto shift) -> int {
+    using S = std::remove_pointer_t<decltype(s_tag)>;
+    using T = std::remove_pointer_t<decltype(t_tag)>;
+    constexpr bool SH = decltype(shift)::value;
+    const StepPhys<T> ph = make_phys<T>(h);
+    const S* buf = (const S*)(h->ws + h->L.pop[h->cur]);
+    const T* phi = (const T*)(h->ws + h->L.phi);
+    T* drho = (T*)(h->ws + h->L.drho);
+    hipLaunchKernelGGL((moments_rho<S, T, SH>), field_grid(h), dim3(256), 0, st, G, buf, phi, ph, drho);
+    double* part = partials ? (double*)(h->ws + h->L.partials) : nullptr;
+    const T* fx = h->d.has_force_field ? (const T*)(h->ws + h->L.fx) : nullptr;
+    const T* fy = h->d.has_force_field ? (const T*)(h->ws + h->L.fy) : nullptr;
+    if (h->d.has_force_field)
+      hipLaunchKernelGGL((moments_out<S, T, SH, true>), field_grid(h), dim3(256), 0, st, G, buf, phi, ph,
+                         drho, fx, fy, rho, ux, uy, p, part);
+    else
+      hipLaunchKernelGGL((moments_out<S, T, SH, false>), field_grid(h), dim3(256), 0, st, G, buf, phi,
+                         ph, drho, fx, fy, rho, ux, uy, p, part);
+    return VANSE_OK;
+  });
+  if (rc) return rc;
+  HIP_TRY(hipGetLastError());
+  return VANSE_OK;
+}
+
+int vanse_read_moments(vanse_lattice* h, double* rho, double* ux, double* uy, double* p, void* stream) {
+  if (!rho) return fail(VANSE_ERR_INVALID_ARG, "rho output is NULL");
+  return moments(h, rho, ux, uy, p, false, stream);
+}
+
+int vanse_read_populations(vanse_lattice* h, double* f, void* stream) {
+  if (int rc = check_ready(h)) return rc;
+  if (!h->state_set) return fail(VANSE_ERR_STATE, "populations not initialised");
+  if (!f) return fail(VANSE_ERR_INVALID_ARG, "output is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Geo G = make_geo(h);
+  const int rc = by_precision(h, [&](auto* s_tag, auto* t_tag, auto shift) -> int {
+    using S = std::remove_pointer_t<decltype(s_tag)>;
+    using T = std::remove_pointer_t<decltype(t_tag)>;
+    constexpr bool SH = decltype(shift)::value;
+    const StepPhys<T> ph = make_phys<T>(h);
+    hipLaunchKernelGGL((read_pops<S, T, SH>), field_grid(h), dim3(256), 0, st, G,
+                       (const S*)(h->ws + h->L.pop[h->cur]), (const T*)(h->ws + h->L.phi), ph, f);
+    return VANSE_OK;
+  });
+  if (rc) return rc;
+  HIP_TRY(hipGetLastError());
+  return VANSE_OK;
+}
+
+int vanse_observe(vanse_lattice* h, double* out, void* stream) {
+  if (!out) return fail(VANSE_ERR_INVALID_ARG, "out is NULL");
+  if (int rc = moments(h, nullptr, nullptr, nullptr, nullptr, true, stream)) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const long long nblk = (long long)((h->d.nx + 255) / 256) * h->d.ny;
+  double* res = (double*)(h->ws + h->L.result);
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, (const double*)(h->ws + h->L.partials), nblk, res);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (out[3] > 0) return fail(VANSE_ERR_DIVERGED, "%.0f nodes hold non-finite values at t = %lld", out[3], (long long)h->t);
+  return VANSE_OK;
+}
+
+int vanse_set_tiling(vanse_lattice* h, int threads, int rows) {
+  if (int rc = check_handle(h)) return rc;
+  if (threads == 0 || rows == 0) {
+    h->tiling_default = true;
+    default_tiling(h);
+    return VANSE_OK;
+  }
+  if (threads != 64 && threads != 128 && threads != 256 && threads != 512)
+    return fail(VANSE_ERR_INVALID_ARG, "threads must be 64, 128, 256 or 512 (got %d)", threads);
+  if (rows < 1) return fail(VANSE_ERR_INVALID_ARG, "rows must be >= 1 (got %d)", rows);
+  h->threads = threads;
+  h->rows = rows;
+  h->tiling_default = false;
+  return VANSE_OK;
+}
+
+int vanse_get_tiling(const vanse_lattice* h, int* threads, int* rows, int* workgroups) {
+  if (int rc = check_handle(h)) return rc;
+  const int out_w = h->threads - 4;
+  const int strips = (h->d.nx + out_w - 1) / out_w;
+  const int nby = (h->d.ny + h->rows - 1) / h->rows;
+  if (threads) *threads = h->threads;
+  if (rows) *rows = h->rows;
+  if (workgroups) *workgroups = strips * nby;
+  return VANSE_OK;
+}
+
+int vanse_set_storage_exponent(vanse_lattice* h, int e) {
+  if (int rc = check_handle(h)) return rc;
+  if (e < -24 || e > 24) return fail(VANSE_ERR_INVALID_ARG, "storage exponent out of range (got %d)", e);
+  if (h->state_set) return fail(VANSE_ERR_STATE, "storage exponent must be set before the populations");
+  h->storage_exp = e;
+  return VANSE_OK;
+}
+
+int64_t vanse_time(const vanse_lattice* h) { return h ? h->t : -1; }
+
+const char* vanse_error_string(int code) {
+  switch (code) {
+    case VANSE_OK: return "ok";
+    case VANSE_ERR_INVALID_ARG: return "invalid argument";
+    case VANSE_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case VANSE_ERR_HIP: return "HIP runtime error";
+    case VANSE_ERR_STATE: return "lattice not ready";
+    case VANSE_ERR_DIVERGED: return "non-finite values observed";
+    case VANSE_ERR_UNSUPPORTED: return "unsupported variant";
+  }
+  return "unknown error";
+}
+
+const char* vanse_last_error(void) { return g_err; }
+
+}  // extern "C"

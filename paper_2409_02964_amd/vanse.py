@@ -1,0 +1,250 @@
+"""Python binding of libvanse (the C ABI in include/vanse.h).
+
+Argument marshalling only: torch supplies the device workspace, the field
+tensors and the stream; every step of the method runs in the library's HIP
+kernels.  If ``libvanse.so`` is missing or cannot be loaded, every entry point
+raises -- there is no fallback path.
+
+    lat = Lattice(4096, 4096, precision="f32", bc_y="wall")
+    lat.set_params(kappa=0.5, rates=dict(s_nu=0.8, s_e=1.2, s_eps=1.2, s_q=1.2))
+    lat.set_void_fraction(phi)              # (ny, nx) float64, any device
+    lat.set_body_force(1e-7, 0.0)
+    lat.init_equilibrium(rho0=1.0)
+    lat.step(10000)
+    m = lat.read_moments()                  # dict of (ny, nx) float64 cuda tensors
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvanse.so")
+
+PRECISION = {"f64": 0, "f32": 1, "f32s": 2, "f16s": 3}
+BC = {"periodic": 0, "wall": 1}
+ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4: "state",
+          -5: "diverged", -6: "unsupported"}
+
+EXPORTS = [
+    "vanse_workspace_bytes", "vanse_create", "vanse_destroy", "vanse_set_params",
+    "vanse_set_body_force", "vanse_set_void_fraction", "vanse_set_force_field",
+    "vanse_init_equilibrium", "vanse_set_populations", "vanse_step", "vanse_read_moments",
+    "vanse_read_populations", "vanse_observe", "vanse_set_tiling", "vanse_get_tiling",
+    "vanse_set_storage_exponent", "vanse_time", "vanse_error_string", "vanse_last_error",
+]
+
+
+class VanseError(RuntimeError):
+    def __init__(self, code, detail):
+        super().__init__(f"{ERRORS.get(code, code)} ({code}): {detail}")
+        self.code = code
+
+
+class Diverged(VanseError):
+    pass
+
+
+class Desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32),
+                ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("has_force_field", C.c_int32)]
+
+
+class Rates(C.Structure):
+    _fields_ = [("s_c", C.c_double), ("s_e", C.c_double), ("s_eps", C.c_double),
+                ("s_q", C.c_double), ("s_nu", C.c_double)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib():
+    """Load libvanse.so (raises if it is not built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+            L = C.CDLL(LIB_PATH)
+            vp, d, i32, i64 = C.c_void_p, C.c_double, C.c_int, C.c_int64
+            pd = C.POINTER(C.c_double)
+            sig = {
+                "vanse_workspace_bytes": [C.POINTER(Desc), C.POINTER(C.c_size_t)],
+                "vanse_create": [C.POINTER(Desc), vp, C.c_size_t, C.POINTER(vp)],
+                "vanse_destroy": [vp],
+                "vanse_set_params": [vp, d, C.POINTER(Rates)],
+                "vanse_set_body_force": [vp, d, d, i32],
+                "vanse_set_void_fraction": [vp, vp, vp],
+                "vanse_set_force_field": [vp, vp, vp, vp],
+                "vanse_init_equilibrium": [vp, d, d, d, vp],
+                "vanse_set_populations": [vp, vp, d, vp],
+                "vanse_step": [vp, i64, vp],
+                "vanse_read_moments": [vp, vp, vp, vp, vp, vp],
+                "vanse_read_populations": [vp, vp, vp],
+                "vanse_observe": [vp, pd, vp],
+                "vanse_set_tiling": [vp, i32, i32],
+                "vanse_get_tiling": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+                "vanse_set_storage_exponent": [vp, i32],
+                "vanse_time": [vp],
+                "vanse_error_string": [i32],
+                "vanse_last_error": [],
+            }
+            for name, args in sig.items():
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = C.c_int
+            L.vanse_time.restype = C.c_int64
+            L.vanse_error_string.restype = C.c_char_p
+            L.vanse_last_error.restype = C.c_char_p
+            _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != 0:
+        detail = lib().vanse_last_error().decode(errors="replace")
+        raise (Diverged if rc == -5 else VanseError)(rc, detail)
+    return rc
+
+
+def workspace_bytes(nx, ny, precision="f64", bc_y="periodic", force_field=False) -> int:
+    desc = Desc(int(nx), int(ny), PRECISION[precision], 0, BC[bc_y], int(bool(force_field)))
+    n = C.c_size_t()
+    check(lib().vanse_workspace_bytes(C.byref(desc), C.byref(n)))
+    return n.value
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Lattice:
+    """One lattice whose device state lives in a torch-allocated workspace."""
+
+    def __init__(self, nx, ny, precision="f64", bc_y="periodic", force_field=False,
+                 device=None, workspace=None):
+        import torch
+        self.nx, self.ny = int(nx), int(ny)
+        self.precision = precision
+        self.device = torch.device(device or "cuda")
+        self.desc = Desc(self.nx, self.ny, PRECISION[precision], 0, BC[bc_y],
+                         int(bool(force_field)))
+        nbytes = C.c_size_t()
+        check(lib().vanse_workspace_bytes(C.byref(self.desc), C.byref(nbytes)))
+        if workspace is None:
+            workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.workspace = workspace  # must outlive the handle
+        self.handle = C.c_void_p()
+        check(lib().vanse_create(C.byref(self.desc), C.c_void_p(workspace.data_ptr()),
+                                 workspace.numel(), C.byref(self.handle)))
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().vanse_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- inputs ----
+    def _field(self, a, shape):
+        import torch
+        t = torch.as_tensor(a, dtype=torch.float64).to(self.device).contiguous()
+        if tuple(t.shape) != shape:
+            raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+        return t
+
+    def set_params(self, kappa=0.5, rates=None):
+        r = dict(s_c=1.0, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=1.2)
+        r.update(rates or {})
+        rr = Rates(r["s_c"], r["s_e"], r["s_eps"], r["s_q"], r["s_nu"])
+        check(lib().vanse_set_params(self.handle, float(kappa), C.byref(rr)))
+        return self
+
+    def set_body_force(self, gx, gy=0.0, scale_by_phi=True):
+        check(lib().vanse_set_body_force(self.handle, float(gx), float(gy),
+                                         1 if scale_by_phi else 0))
+        return self
+
+    def set_void_fraction(self, phi, stream=None):
+        t = self._field(phi, (self.ny, self.nx))
+        check(lib().vanse_set_void_fraction(self.handle, C.c_void_p(t.data_ptr()),
+                                            _stream(stream)))
+        return self
+
+    def set_force_field(self, fx, fy, stream=None):
+        a = self._field(fx, (self.ny, self.nx))
+        b = self._field(fy, (self.ny, self.nx))
+        check(lib().vanse_set_force_field(self.handle, C.c_void_p(a.data_ptr()),
+                                          C.c_void_p(b.data_ptr()), _stream(stream)))
+        self._keep = (a, b)
+        return self
+
+    def init_equilibrium(self, rho0=1.0, ux0=0.0, uy0=0.0, stream=None):
+        check(lib().vanse_init_equilibrium(self.handle, float(rho0), float(ux0), float(uy0),
+                                           _stream(stream)))
+        return self
+
+    def set_populations(self, f, rho0=1.0, stream=None):
+        t = self._field(f, (9, self.ny, self.nx))
+        check(lib().vanse_set_populations(self.handle, C.c_void_p(t.data_ptr()), float(rho0),
+                                          _stream(stream)))
+        self._keep_f = t
+        return self
+
+    def set_tiling(self, threads=0, rows=0):
+        check(lib().vanse_set_tiling(self.handle, int(threads), int(rows)))
+        return self
+
+    def tiling(self):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        check(lib().vanse_get_tiling(self.handle, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(threads=a.value, rows=b.value, workgroups=c.value)
+
+    def set_storage_exponent(self, e):
+        check(lib().vanse_set_storage_exponent(self.handle, int(e)))
+        return self
+
+    # ---- stepping ----
+    def step(self, n=1, stream=None):
+        check(lib().vanse_step(self.handle, int(n), _stream(stream)))
+        return self
+
+    @property
+    def t(self):
+        return int(lib().vanse_time(self.handle))
+
+    # ---- outputs ----
+    def read_moments(self, stream=None):
+        import torch
+        out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+               for k in ("rho", "ux", "uy", "p")}
+        check(lib().vanse_read_moments(self.handle, *[C.c_void_p(out[k].data_ptr())
+                                                      for k in ("rho", "ux", "uy", "p")],
+                                       _stream(stream)))
+        return out
+
+    def read_populations(self, stream=None):
+        import torch
+        out = torch.empty((9, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        check(lib().vanse_read_populations(self.handle, C.c_void_p(out.data_ptr()),
+                                           _stream(stream)))
+        return out
+
+    def observe(self, stream=None, raise_on_diverged=True):
+        """dict(mass, u2, umax, nonfinite) reduced in FP64 on the device."""
+        buf = (C.c_double * 4)()
+        rc = lib().vanse_observe(self.handle, buf, _stream(stream))
+        res = dict(mass=buf[0], u2=buf[1], umax=buf[2], nonfinite=int(buf[3]))
+        if rc == -5 and not raise_on_diverged:
+            return res
+        check(rc)
+        return res

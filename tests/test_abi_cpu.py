@@ -1,0 +1,118 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, sizes workspaces, and validates arguments on the host."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2409_02964_amd import vanse as V
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vanse.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vanse_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = V.lib()
+    names = declared_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(V.EXPORTS) == names
+
+
+def test_workspace_bytes_scales_with_precision():
+    b64 = V.workspace_bytes(4096, 4096, "f64", "wall")
+    b32 = V.workspace_bytes(4096, 4096, "f32", "wall")
+    b16 = V.workspace_bytes(4096, 4096, "f16s", "wall")
+    plane = 4096 * 4096
+    # two population buffers dominate: 2 x 9 planes
+    assert b64 >= 18 * plane * 8 and b64 < 18 * plane * 8 + 4 * plane * 8 + (1 << 24)
+    assert b32 >= 18 * plane * 4 and b32 < 18 * plane * 4 + 4 * plane * 4 + (1 << 24)
+    assert b16 >= 18 * plane * 2 and b16 < b32
+    assert V.workspace_bytes(64, 64, "f64", force_field=True) > V.workspace_bytes(64, 64, "f64")
+
+
+@pytest.mark.parametrize("nx,ny,prec,bcx,bcy,ff,code", [
+    (1, 64, 0, 0, 0, 0, -1),
+    (64, 1, 0, 0, 0, 0, -1),
+    (64, 64, 7, 0, 0, 0, -1),
+    (64, 64, 0, 1, 0, 0, -6),
+    (64, 64, 0, 0, 5, 0, -1),
+    (64, 64, 0, 0, 0, 2, -1),
+    (60000, 60000, 1, 0, 0, 0, -1),
+])
+def test_bad_descriptors_are_rejected(nx, ny, prec, bcx, bcy, ff, code):
+    d = V.Desc(nx, ny, prec, bcx, bcy, ff)
+    n = C.c_size_t()
+    assert V.lib().vanse_workspace_bytes(C.byref(d), C.byref(n)) == code
+    assert V.lib().vanse_last_error()
+
+
+def _fake_handle(nx=64, ny=48, prec=0, bcy=0):
+    """A handle over a fake, aligned device address: only host-side calls
+    (no HIP work) may be made on it."""
+    d = V.Desc(nx, ny, prec, 0, bcy, 0)
+    n = C.c_size_t()
+    V.check(V.lib().vanse_workspace_bytes(C.byref(d), C.byref(n)))
+    h = C.c_void_p()
+    assert V.lib().vanse_create(C.byref(d), C.c_void_p(1 << 40), n.value - 1, C.byref(h)) == -2
+    assert V.lib().vanse_create(C.byref(d), C.c_void_p((1 << 40) + 8), n.value, C.byref(h)) == -2
+    assert V.lib().vanse_create(C.byref(d), None, n.value, C.byref(h)) == -2
+    V.check(V.lib().vanse_create(C.byref(d), C.c_void_p(1 << 40), n.value, C.byref(h)))
+    return h
+
+
+def test_host_side_validation():
+    L = V.lib()
+    h = _fake_handle()
+    good = V.Rates(1.0, 1.2, 1.2, 1.4, 1.25)
+    assert L.vanse_set_params(h, 0.5, C.byref(good)) == 0
+    assert L.vanse_set_params(h, 1.5, C.byref(good)) == -1
+    assert L.vanse_set_params(h, -0.1, C.byref(good)) == -1
+    for k in range(5):
+        vals = [1.0, 1.2, 1.2, 1.4, 1.25]
+        vals[k] = 2.0
+        assert L.vanse_set_params(h, 0.5, C.byref(V.Rates(*vals))) == -1
+        vals[k] = 0.0
+        assert L.vanse_set_params(h, 0.5, C.byref(V.Rates(*vals))) == -1
+    assert L.vanse_set_body_force(h, 1e-6, 0.0, 1) == 0
+    assert L.vanse_set_body_force(h, float("nan"), 0.0, 1) == -1
+    assert L.vanse_set_body_force(h, 1e-6, 0.0, 3) == -1
+    # stepping or reading before phi and populations: state errors, no GPU work
+    assert L.vanse_step(h, 1, None) == -4
+    assert L.vanse_read_populations(h, C.c_void_p(1 << 40), None) == -4
+    assert L.vanse_init_equilibrium(h, 1.0, 0.0, 0.0, None) == -4
+    assert L.vanse_time(h) == 0
+    assert L.vanse_set_force_field(h, C.c_void_p(1 << 40), C.c_void_p(1 << 40), None) == -4
+    assert L.vanse_set_storage_exponent(h, 40) == -1
+    assert L.vanse_set_storage_exponent(h, 10) == 0
+    assert L.vanse_destroy(h) == 0
+
+
+def test_tiling_choices():
+    L = V.lib()
+    h = _fake_handle(4096, 4096, 1, 1)
+    t, r, w = C.c_int(), C.c_int(), C.c_int()
+    V.check(L.vanse_get_tiling(h, C.byref(t), C.byref(r), C.byref(w)))
+    assert t.value in (64, 128, 256, 512) and r.value >= 1
+    strips = -(-4096 // (t.value - 4))
+    assert w.value == strips * -(-4096 // r.value)
+    assert L.vanse_set_tiling(h, 96, 8) == -1
+    assert L.vanse_set_tiling(h, 128, 0) == 0  # back to the default
+    assert L.vanse_set_tiling(h, 512, 3) == 0
+    V.check(L.vanse_get_tiling(h, C.byref(t), C.byref(r), C.byref(w)))
+    assert (t.value, r.value, w.value) == (512, 3, 9 * 1366)
+    assert L.vanse_destroy(h) == 0
+
+
+def test_error_strings():
+    L = V.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.vanse_error_string(code)

@@ -1,0 +1,273 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Every case feeds both sides the same seeded inputs from the workloads module
+and compares element by element.  Tolerances:
+  * FP64 path, one step from a random non-equilibrium state:
+      max |f_gpu - f_oracle| <= 1e-14 * max |f|
+  * FP64 path after many steps: rel-L2(u) <= 1e-12 (Eq. 26 form),
+      rel-L2(p) <= 1e-14
+  * FP32 paths: the error against the oracle is reported and bounded by the
+    storage rounding it must come from (see the individual tests).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_2409_02964_amd import workloads as W  # noqa: E402
+
+C1_RATES = dict(s_c=1.2, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=0.8)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_lattice(nx, ny, phi, precision="f64", bc_y="periodic", kappa=0.5, rates=C1_RATES,
+                g=(0.0, 0.0), scale_by_phi=True, force=None, tiling=None):
+    from paper_2409_02964_amd.vanse import Lattice
+    lat = Lattice(nx, ny, precision=precision, bc_y=bc_y, force_field=force is not None)
+    lat.set_params(kappa, rates).set_body_force(g[0], g[1], scale_by_phi)
+    lat.set_void_fraction(phi)
+    if force is not None:
+        lat.set_force_field(force[0], force[1])
+    if tiling:
+        lat.set_tiling(*tiling)
+    return lat
+
+
+def oracle_lattice(oracle, nx, ny, phi, bc_y="periodic", kappa=0.5, rates=C1_RATES,
+                   g=(0.0, 0.0), scale_by_phi=True, force=None):
+    return oracle.Oracle(nx, ny, phi, kappa=kappa, rates=rates, g=g, scale_by_phi=scale_by_phi,
+                         bc_y=bc_y, force=force)
+
+
+def rel_l2(a, b):
+    return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b ** 2)))
+
+
+def rel_l2_u(m, ref):
+    num = np.sum((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2)
+    den = np.sum(ref["ux"] ** 2 + ref["uy"] ** 2)
+    return math.sqrt(num / den)
+
+
+def to_np(d):
+    return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+# ---- one step from random states: every population, many shapes ------------
+
+SHAPES = [
+    (64, 64, "periodic", None),
+    (61, 37, "wall", None),        # ragged strip and block tails
+    (253, 9, "periodic", (256, 4)),  # just past one 256-lane strip
+    (252, 11, "wall", (256, 3)),
+    (125, 130, "wall", (128, 7)),
+    (60, 5, "periodic", (64, 1)),
+    (2, 3, "periodic", (64, 2)),   # smaller than the halo: everything wraps
+    (97, 2, "wall", (64, 64)),     # both walls on every row
+    (300, 70, "periodic", (512, 16)),
+]
+
+
+@pytest.mark.parametrize("nx,ny,bc,tiling", SHAPES)
+def test_one_step_populations_fp64(oracle, nx, ny, bc, tiling):
+    torch = _torch()
+    _say(f"one-step fp64 {nx}x{ny} {bc} tiling={tiling}")
+    phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 2.0, seed=nx * 1000 + ny) ** 2
+    f0 = W.random_populations(nx, ny, seed=11 + nx + ny)
+    g = (2e-5, -1e-5)
+    ora = oracle_lattice(oracle, nx, ny, phi, bc, g=g)
+    ora.set_populations(f0)
+    ora.step(1)
+    lat = gpu_lattice(nx, ny, phi, "f64", bc, g=g, tiling=tiling)
+    lat.set_populations(torch.from_numpy(f0))
+    back = lat.read_populations().cpu().numpy()
+    assert np.max(np.abs(back - f0)) <= 1e-15 * np.max(np.abs(f0))  # storage round trip
+    lat.step(1)
+    fg = lat.read_populations().cpu().numpy()
+    err = np.max(np.abs(fg - ora.f)) / np.max(np.abs(ora.f))
+    _say(f"   max rel err {err:.3e}")
+    assert err <= 1e-14
+
+
+def test_one_step_force_field_fp64(oracle):
+    torch = _torch()
+    n = 48
+    m = W.mms_case("II", n, 0.5, 0.3, 0.8, 0.1)
+    f0 = W.random_populations(n, n, seed=5)
+    ora = oracle_lattice(oracle, n, n, m["phi"], scale_by_phi=False, force=(m["fx"], m["fy"]),
+                         g=(1e-6, 0))
+    ora.set_populations(f0)
+    ora.step(1)
+    lat = gpu_lattice(n, n, m["phi"], "f64", scale_by_phi=False, force=(m["fx"], m["fy"]),
+                      g=(1e-6, 0))
+    lat.set_populations(torch.from_numpy(f0)).step(1)
+    fg = lat.read_populations().cpu().numpy()
+    assert np.max(np.abs(fg - ora.f)) <= 1e-14 * np.max(np.abs(ora.f))
+
+
+# ---- many steps: the periodic wave workload and a walled channel --------------
+
+def test_periodic_wave_1000_steps_fp64(oracle):
+    """64x64 periodic, phi = 0.75 + 0.2 sin cos, G = 1e-6, s_nu = 0.8, other
+    rates 1.2, kappa = 0.5, 1000 steps."""
+    _torch()
+    phi = W.periodic_wave()
+    ora = oracle_lattice(oracle, 64, 64, phi, g=(1e-6, 0)).init_equilibrium()
+    ora.step(1000)
+    ref = ora.macroscopic()
+    lat = gpu_lattice(64, 64, phi, "f64", g=(1e-6, 0)).init_equilibrium().step(1000)
+    m = to_np(lat.read_moments())
+    eu = rel_l2_u(m, ref)
+    ep = rel_l2(m["p"], ref["p"])
+    epd = rel_l2(m["p"] - m["p"].mean(), ref["p"] - ref["p"].mean())
+    _say(f"periodic wave t=1000: rel-L2 u {eu:.3e}  p {ep:.3e}  p-<p> {epd:.3e}")
+    assert eu <= 1e-12 and ep <= 1e-14
+    assert lat.t == 1000
+
+
+def test_channel_walls_fp64(oracle):
+    _torch()
+    nx, ny = 90, 41
+    phi = W.channel_phi(nx, ny, seed=3)
+    ora = oracle_lattice(oracle, nx, ny, phi, "wall", g=(1e-5, 0)).init_equilibrium()
+    ora.step(400)
+    ref = ora.macroscopic()
+    lat = gpu_lattice(nx, ny, phi, "f64", "wall", g=(1e-5, 0), tiling=(64, 6))
+    lat.init_equilibrium().step(400)
+    m = to_np(lat.read_moments())
+    eu = rel_l2_u(m, ref)
+    _say(f"channel t=400: rel-L2 u {eu:.3e}")
+    assert eu <= 1e-12 and rel_l2(m["p"], ref["p"]) <= 1e-14
+
+
+def test_manufactured_forcing_fp64(oracle):
+    _torch()
+    n = 32
+    m = W.mms_case("I", n, 0.5, 0.4, 0.8, 0.1)
+    rates = dict(s_c=1.0, s_e=1 / 0.6, s_eps=1.2, s_q=1.4, s_nu=1.25)
+    ora = oracle_lattice(oracle, n, n, m["phi"], kappa=0.1, rates=rates, scale_by_phi=False,
+                         force=(m["fx"], m["fy"]))
+    ora.init_fields(np.ones((n, n)), m["ux"], m["uy"])
+    f0 = ora.f.copy()
+    ora.step(500)
+    ref = ora.macroscopic()
+    lat = gpu_lattice(n, n, m["phi"], "f64", kappa=0.1, rates=rates, scale_by_phi=False,
+                      force=(m["fx"], m["fy"]))
+    import torch
+    lat.set_populations(torch.from_numpy(f0)).step(500)
+    g = to_np(lat.read_moments())
+    eu = rel_l2_u(g, ref)
+    _say(f"manufactured case I t=500: rel-L2 u {eu:.3e}")
+    assert eu <= 1e-12
+
+
+# ---- invariants on the GPU -----------------------------------------------------
+
+def test_mass_conservation_and_observables_fp64():
+    _torch()
+    phi = W.channel_phi(128, 96, seed=1)
+    lat = gpu_lattice(128, 96, phi, "f64", "wall", g=(1e-5, 1e-6)).init_equilibrium()
+    o0 = lat.observe()
+    lat.step(1000)
+    o1 = lat.observe()
+    _say(f"mass {o0['mass']!r} -> {o1['mass']!r}")
+    assert abs(o1["mass"] - o0["mass"]) / o0["mass"] <= 1e-13
+    m = to_np(lat.read_moments())
+    u = np.hypot(m["ux"], m["uy"])
+    assert o1["nonfinite"] == 0
+    assert abs(o1["umax"] - u.max()) <= 1e-15
+    assert abs(o1["u2"] - np.sum(u ** 2)) <= 1e-12 * np.sum(u ** 2)
+
+
+def test_tilings_are_bitwise_identical():
+    """Each node's arithmetic does not depend on the launch shape."""
+    _torch()
+    nx, ny = 300, 77
+    phi = W.channel_phi(nx, ny, seed=9)
+    outs = []
+    for tiling in [(64, 1), (128, 5), (256, 64), (512, 13)]:
+        lat = gpu_lattice(nx, ny, phi, "f32", "wall", g=(1e-5, 0), tiling=tiling)
+        lat.init_equilibrium().step(20)
+        outs.append(lat.read_populations().cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_determinism_two_runs():
+    _torch()
+    phi = W.channel_phi(256, 128, seed=4)
+    res = []
+    for _ in range(2):
+        lat = gpu_lattice(256, 128, phi, "f32", "wall", g=(1e-5, 0)).init_equilibrium().step(50)
+        res.append(lat.read_populations().cpu().numpy())
+    assert np.array_equal(res[0], res[1])
+
+
+def test_rest_state_stays_at_rest_gpu():
+    _torch()
+    phi = W.discontinuous_block(100, 0.3)
+    for prec in ("f64", "f32s"):
+        lat = gpu_lattice(100, 100, phi, prec, kappa=0.3,
+                          rates=dict(s_c=1.0, s_e=1 / 0.6, s_eps=1.2, s_q=1.4, s_nu=1.25))
+        lat.init_equilibrium().step(500)
+        o = lat.observe()
+        _say(f"rest state {prec}: max |u| = {o['umax']:.3e}")
+        assert o["umax"] <= (1e-14 if prec == "f64" else 1e-9)
+
+
+# ---- reduced precision: errors against the FP64 oracle --------------------------
+
+@pytest.mark.parametrize("prec,bound", [("f32", 5e-2), ("f32s", 1e-4), ("f16s", 5e-2)])
+def test_reduced_precision_errors(oracle, prec, bound):
+    _torch()
+    phi = W.periodic_wave()
+    ora = oracle_lattice(oracle, 64, 64, phi, g=(1e-6, 0)).init_equilibrium()
+    ora.step(1000)
+    ref = ora.macroscopic()
+    lat = gpu_lattice(64, 64, phi, prec, g=(1e-6, 0)).init_equilibrium().step(1000)
+    m = to_np(lat.read_moments())
+    eu = rel_l2_u(m, ref)
+    epd = rel_l2(m["p"] - m["p"].mean(), ref["p"] - ref["p"].mean())
+    _say(f"{prec}: periodic wave t=1000 rel-L2 u {eu:.3e}  p-<p> {epd:.3e}")
+    assert eu <= bound
+
+
+# ---- the full-size channel in the benchmark's launch configuration ------------
+
+def test_full_size_channel_one_step_fp32(oracle):
+    """4096 x 4096 channel (walls, tanh step + smoothed noise in phi), FP32
+    storage and arithmetic, the benchmark's launch shape: one step from a
+    random state against the FP64 oracle on every population."""
+    torch = _torch()
+    n = 4096
+    phi = W.channel_phi(n, n, seed=2409)
+    f0 = W.random_populations(n, n, seed=77)
+    _say("full-size: oracle step ...")
+    ora = oracle_lattice(oracle, n, n, phi, "wall", g=(1e-7, 0))
+    ora.set_populations(f0)
+    ora.step(1)
+    _say("full-size: gpu step ...")
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    lat = gpu_lattice(n, n, phi, "f32", "wall", g=(1e-7, 0), tiling=bench.TILING)
+    lat.set_populations(torch.from_numpy(f0)).step(1)
+    fg = lat.read_populations().cpu().numpy()
+    err = np.max(np.abs(fg - ora.f)) / np.max(np.abs(ora.f))
+    _say(f"full-size fp32 one step: max rel err {err:.3e}")
+    # FP32 storage of f ~ 0.5 and FP32 arithmetic: a few units of 2^-24
+    assert err <= 2e-6
