@@ -33,7 +33,7 @@ G = 1e-7
 KAPPA = 0.5
 RATES = dict(s_c=1.2, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=0.8)
 PRECISION = "f32"
-TILING = (256, 64)  # threads per workgroup, rows swept per workgroup
+TILING = (256, 69)  # threads per workgroup, rows swept per workgroup (one full round)
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + %HBM peak (D2Q9 MRT-VANSE); batched solves/s + p99 latency"
 BYTES_PER_NODE = {"f64": 9 * 8 * 2 + 8, "f32": 9 * 4 * 2 + 4, "f32s": 9 * 4 * 2 + 4,
@@ -78,6 +78,78 @@ def cpu_baseline(steps: int):
                        f"({dt:.1f} s)")
 
 
+def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
+    """Turn rocprofv3 CSV output (a kernel-trace --stats run in prof_dir/trace,
+    --pmc FETCH_SIZE in prof_dir/fetch, --pmc WRITE_SIZE in prof_dir/write)
+    into a short text summary and the traffic record this benchmark reports.
+
+    The counters are scaled by what they read for the same-pattern copy
+    kernel, whose bytes are known exactly (9 planes read, 9 written)."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def one(pattern):
+        hits = glob.glob(os.path.join(prof_dir, pattern), recursive=True)
+        if not hits:
+            raise SystemExit(f"no {pattern} under {prof_dir}")
+        return hits[0]
+
+    stats = list(csv.DictReader(open(one("trace/**/*kernel_stats.csv"))))
+    counters = {}
+    for kind, name in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        per = defaultdict(list)
+        for r in csv.DictReader(open(one(f"{kind}/**/*counter_collection.csv"))):
+            if r["Counter_Name"] == name:
+                per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        counters[name] = {k: sum(v) / len(v) for k, v in per.items()}
+
+    def pick(d, key):
+        ks = [k for k in d if key in k]
+        if not ks:
+            raise SystemExit(f"kernel {key} not in profile")
+        return d[ks[0]]
+
+    nodes = NX * NY
+    copy_bytes = 9 * 4 * nodes  # per direction, FP32
+    f_copy = pick(counters["FETCH_SIZE"], "stream_copy") * 1024
+    w_copy = pick(counters["WRITE_SIZE"], "stream_copy") * 1024
+    f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
+    f_step = pick(counters["FETCH_SIZE"], "vanse_step_kernel") * 1024 * f_scale
+    w_step = pick(counters["WRITE_SIZE"], "vanse_step_kernel") * 1024 * w_scale
+    alg = BYTES_PER_NODE[PRECISION] * nodes
+    step_ns = float(pick({r["Name"]: r["AverageNs"] for r in stats}, "vanse_step_kernel"))
+    copy_ns = float(pick({r["Name"]: r["AverageNs"] for r in stats}, "stream_copy"))
+    rec = {"kernel_hash": kernel_hash(), "bytes_per_launch": int(f_step + w_step),
+           "fetch_bytes": int(f_step), "write_bytes": int(w_step),
+           "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
+           "algorithmic_bytes": alg, "step_avg_ns": step_ns, "copy_avg_ns": copy_ns}
+    json.dump(rec, open(prefix + "_traffic.json", "w"), indent=1)
+    lines = [f"# rocprofv3: fused step, {NX}x{NY} FP32 channel (walls), tiling {TILING}", "",
+             "Commands (from the repository root; outputs under gpurun_out/prof):", "",
+             "```", commands.strip(), "```", "",
+             "## Kernel statistics (--kernel-trace --stats)", "",
+             "| kernel | calls | average ns | min ns | max ns |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:8]:
+        lines.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']):.0f} | "
+                     f"{r['MinNs']} | {r['MaxNs']} |")
+    lines += ["", "## HBM traffic per dispatch (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", "",
+              "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|"]
+    for k in sorted(counters["FETCH_SIZE"]):
+        if "step_kernel" in k or "stream_copy" in k:
+            lines.append(f"| {k[:90]} | {counters['FETCH_SIZE'][k]:.0f} | "
+                         f"{counters['WRITE_SIZE'].get(k, float('nan')):.0f} |")
+    lines += ["", f"Calibration with the same-pattern copy ({copy_bytes} B read and written per "
+              f"dispatch): FETCH x {f_scale:.4f}, WRITE x {w_scale:.4f}.", "",
+              f"Step kernel: {f_step / 1e6:.1f} MB read + {w_step / 1e6:.1f} MB written = "
+              f"{(f_step + w_step) / 1e6:.1f} MB per launch; algorithmic {alg / 1e6:.1f} MB "
+              f"({(f_step + w_step) / alg:.3f}x).  Average duration {step_ns / 1e3:.1f} us -> "
+              f"{alg / step_ns:.0f} GB/s algorithmic, {(f_step + w_step) / step_ns:.0f} GB/s "
+              f"measured; copy {copy_bytes * 2 / copy_ns:.0f} GB/s."]
+    open(prefix + "_rocprof.md", "w").write("\n".join(lines) + "\n")
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,9 +158,18 @@ def main():
     ap.add_argument("--precision", default=PRECISION, choices=sorted(BYTES_PER_NODE))
     ap.add_argument("--threads", type=int, default=TILING[0])
     ap.add_argument("--rows", type=int, default=TILING[1])
+    ap.add_argument("--sol-steps", type=int, default=200,
+                    help="launches of the same-pattern copy kernel (0: skip)")
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--summarize-profile", metavar="DIR",
+                    help="summarize rocprofv3 CSVs in DIR/{trace,fetch,write} into profiles/")
     args = ap.parse_args()
+    if args.summarize_profile:
+        cmds = open(os.path.join(args.summarize_profile, "commands.txt")).read()
+        summarize_profile(args.summarize_profile,
+                          os.path.join(ROOT, "profiles", "step_f32_channel4096"), cmds)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -121,6 +202,19 @@ def main():
     gpu_ms = ev0.elapsed_time(ev1)
     obs = lat.observe(stream, raise_on_diverged=False)
 
+    # speed-of-light reference: the step's memory pattern without arithmetic
+    sol = None
+    if args.sol_steps > 0:
+        lat.stream_copy(10, stream)
+        torch.cuda.synchronize(dev)
+        ev0.record(stream)
+        lat.stream_copy(args.sol_steps, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize(dev)
+        copy_ms = ev0.elapsed_time(ev1) / args.sol_steps
+        sol_bytes = (BYTES_PER_NODE[args.precision] - (8 if args.precision == "f64" else 4))
+        sol = round(sol_bytes * NX * NY / (copy_ms / 1e3) / 1e9, 1)
+
     nodes = NX * NY
     sec = gpu_ms / 1e3
     mlups = nodes * args.steps / sec / 1e6
@@ -152,7 +246,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "algorithmic_bytes_per_launch": bpn * nodes},
+                     "algorithmic_bytes_per_launch": bpn * nodes,
+                     "same_pattern_copy_gbs": sol},
         "wall_s": round(wall, 3),
         "final_umax": obs["umax"],
         "nonfinite": obs["nonfinite"],

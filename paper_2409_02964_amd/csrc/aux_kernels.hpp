@@ -282,4 +282,38 @@ __global__ void reduce_partials(const double* __restrict__ partials, long long n
   }
 }
 
+// Speed-of-light reference with the step's memory pattern: every node pulls
+// its nine populations from the same shifted positions (with the same
+// bounce-back at walls) and writes them back unchanged to the other buffer.
+// No arithmetic: 9 reads + 9 writes per node, the step's HBM traffic minus
+// the phi plane.
+template <typename S>
+__global__ void __launch_bounds__(256) stream_copy(Geo G, const S* __restrict__ src,
+                                                   S* __restrict__ dst) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  const long long P = G.plane;
+  const int xm = x == 0 ? G.nx - 1 : x - 1, xp = x == G.nx - 1 ? 0 : x + 1;
+  const int o = y * G.pitch;
+  S f[9];
+  f[0] = src[o + x];
+  f[1] = src[P + o + xm];
+  f[3] = src[3 * P + o + xp];
+  if (G.walls && y == 0) {
+    f[2] = src[4 * P + o + x]; f[5] = src[7 * P + o + x]; f[6] = src[8 * P + o + x];
+  } else {
+    const int os = (y == 0 ? G.ny - 1 : y - 1) * G.pitch;
+    f[2] = src[2 * P + os + x]; f[5] = src[5 * P + os + xm]; f[6] = src[6 * P + os + xp];
+  }
+  if (G.walls && y == G.ny - 1) {
+    f[4] = src[2 * P + o + x]; f[7] = src[5 * P + o + x]; f[8] = src[6 * P + o + x];
+  } else {
+    const int on = (y == G.ny - 1 ? 0 : y + 1) * G.pitch;
+    f[4] = src[4 * P + on + x]; f[7] = src[7 * P + on + xp]; f[8] = src[8 * P + on + xm];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dst[i * P + o + x] = f[i];
+}
+
 }  // namespace vanse_dev

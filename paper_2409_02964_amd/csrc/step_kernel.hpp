@@ -14,10 +14,10 @@
 // Work layout: one workgroup owns a strip of `out_w` columns plus two halo
 // columns on each side (one lane per column) and sweeps a block of rows
 // bottom-up.  Per sweep iteration three stages run on three consecutive rows:
-//   A  row yn   : pull the 9 populations, moments, delta-rho -> LDS ring(5)
-//   B  row yn-1 : grad rho from the ring, F and u -> LDS ring(3)
-//   C  row yn-2 : the eight derivatives from the rings, collision, store.
-// Populations of rows yn-1, yn-2 stay in registers between stages, so each
+//   A  row yn   : pull the 9 populations, moments, delta-rho -> LDS ring
+//   B  row yn-1 : grad rho from the ring, F, u, rho u, phi rho u -> LDS ring
+//   C  row yn-2 : the eight derivatives from the ring, collision, store.
+// Moments of rows yn-1, yn-2 stay in registers between stages, so each
 // stored population is read from HBM once (plus the strip/block halos), and
 // the step needs no second pass over memory.  All arithmetic is vector ALU:
 // the 9x9 transforms are integer-coefficient sums (no MFMA -- the step is
@@ -34,9 +34,17 @@
 
 namespace vanse_dev {
 
+// Per-node velocity data shared with the neighbours through LDS: u, the
+// products rho u and (phi rho) u that the penalty derivatives of Eq. (20)
+// act on.  Split in a 4-vector read by every neighbour and a 2-vector read by
+// the north/south and diagonal neighbours only.
 template <typename T>
 struct alignas(4 * sizeof(T)) U4 {
-  T ux, uy, mux, muy;  // u and (phi rho) u at one node
+  T ux, uy, mux, rux;  // u_x, u_y, (phi rho) u_x, rho u_x
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) U2 {
+  T muy, ruy;  // (phi rho) u_y, rho u_y
 };
 
 template <typename T>
@@ -66,12 +74,45 @@ __device__ __forceinline__ int wrap_index(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
-__device__ __forceinline__ int slot5(int y) { return (y + 10) % 5; }
-__device__ __forceinline__ int slot3(int y) { return (y + 9) % 3; }
+// LDS ring slot of a (possibly negative) row index: four rows per ring
+__device__ __forceinline__ int slot4(int y) { return y & 3; }
 
-template <typename S, typename T>
-__device__ __forceinline__ T load_pop(const S* p) {
-  return static_cast<T>(*p);
+// Reciprocal: the hardware v_rcp_f32 (1 ulp) in FP32, a correctly rounded
+// division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// Buffer-resource memory access: a scalar descriptor per plane (base and
+// size in bytes), a per-lane byte offset (the column, loop-invariant) and a
+// uniform byte offset (the row).  Address arithmetic then costs no vector
+// instructions, and an offset beyond the plane reads 0 instead of faulting.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
+}
+template <typename S>
+__device__ __forceinline__ S bload(rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float bload<float>(rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ _Float16 bload<_Float16>(rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, rsrc_t r, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, rsrc_t r, unsigned voff, unsigned soff) {
+  using u2 = unsigned __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(_Float16 v, rsrc_t r, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, voff, soff, 0);
 }
 
 // Eq. (10): d_x psi = (psi_E - psi_W)/3 + (psi_NE + psi_SE - psi_NW - psi_SW)/12
@@ -84,6 +125,14 @@ __device__ __forceinline__ T stencil_dy(T n, T s, T ne, T nw, T se, T sw) {
   return (n - s) * T(1.0 / 3.0) + ((ne + nw) - (se + sw)) * T(1.0 / 12.0);
 }
 
+// Moments of one row carried from stage A to stages B and C (deviations from
+// the rest state): dm0 = sum g, j, and the six non-conserved moments of
+// Eq. (17), plus phi and delta-rho of the node.
+template <typename T>
+struct RowState {
+  T dm0, jx, jy, me, mep, mqx, mqy, mpxx, mpxy, phi, drho;
+};
+
 // S: storage type of populations (double, float, _Float16)
 // T: arithmetic type (double, float)
 // SHIFT: memory holds deviations g (scaled by ph.scale) instead of f
@@ -91,9 +140,15 @@ __device__ __forceinline__ T stencil_dy(T n, T s, T ne, T nw, T se, T sw) {
 // FFIELD: add the per-node force planes to F^B
 // NT: threads per workgroup (= out_w + 4 active lanes at most)
 template <typename S, typename T, bool SHIFT, bool WALLS, bool FFIELD, int NT>
-__global__ void __launch_bounds__(NT) vanse_step_kernel(StepGeom g, StepPhys<T> ph) {
-  __shared__ T s_rho[5][NT];     // delta-rho of the last five pulled rows
-  __shared__ U4<T> s_u[3][NT];   // u, (phi rho) u of the last three rows
+__global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
+vanse_step_kernel(StepGeom g, StepPhys<T> ph) {
+  // LDS rings over the last four rows.  Next to a wall the row beyond it is
+  // filled with the mirror image (scalars copied, velocities negated), so the
+  // stencils below never test for walls.
+  __shared__ T s_rho[4][NT];      // delta-rho (stage A -> stage B)
+  __shared__ U4<T> s_u4[4][NT];   // (stage B -> stage C)
+  __shared__ U2<T> s_u2[4][NT];
 
   const int t = threadIdx.x;
   const int strip = blockIdx.x % g.strips;
@@ -108,11 +163,18 @@ __global__ void __launch_bounds__(NT) vanse_step_kernel(StepGeom g, StepPhys<T> 
   const int cm = (c == 0) ? nx - 1 : c - 1;
   const int cp = (c == nx - 1) ? 0 : c + 1;
   const int tl = max(t - 1, 0), tr = min(t + 1, NT - 1);
+  constexpr unsigned SB = sizeof(S);
+  constexpr unsigned TB = sizeof(T);
 
-  const S* __restrict__ src = static_cast<const S*>(g.src);
-  S* __restrict__ dst = static_cast<S*>(g.dst);
-  const T* __restrict__ phif = static_cast<const T*>(g.phi);
-  const long long P = g.plane;
+  // one buffer descriptor per array; the plane and the row go into the
+  // uniform offset, the column into the per-lane offset (each population
+  // buffer is below 4 GiB, which the host checks)
+  const unsigned plane_bytes = unsigned(g.plane) * SB;
+  const unsigned row_bytes = unsigned(pitch) * SB;
+  const rsrc_t srcr = make_rsrc(g.src, 9u * plane_bytes);
+  const rsrc_t dstr = make_rsrc(g.dst, 9u * plane_bytes);
+  const rsrc_t phir = make_rsrc(g.phi, unsigned(g.plane) * TB);
+  auto poff = [&](int i, int r) { return unsigned(i) * plane_bytes + unsigned(r) * row_bytes; };
 
   const int y0 = by * g.rows;
   const int y1 = min(y0 + g.rows, ny);
@@ -120,157 +182,157 @@ __global__ void __launch_bounds__(NT) vanse_step_kernel(StepGeom g, StepPhys<T> 
 
   const T kappa = ph.kappa, rho0 = ph.rho0;
   const T third = T(1.0 / 3.0);
+  // loop-invariant per-lane byte offsets of the own and neighbour columns
+  const unsigned xcb = unsigned(c) * SB, xmb = unsigned(cm) * SB, xpb = unsigned(cp) * SB;
+  const unsigned xcT = unsigned(c) * TB;
 
-  T gB[9], gC[9];                  // deviations of rows yn-1, yn-2
-  T sB[5], sC[5];                  // dm0, jx, jy, phi, drho of rows yn-1, yn-2
-  T bC[4] = {0, 0, 0, 0};          // ux, uy, Fx, Fy of row yn-2
-#pragma unroll
-  for (int i = 0; i < 9; ++i) { gB[i] = T(0); gC[i] = T(0); }
-#pragma unroll
-  for (int i = 0; i < 5; ++i) { sB[i] = T(0); sC[i] = T(0); }
+  // Issue the ten loads (nine pulled populations and phi) of row yn.  Rows
+  // outside a walled domain are clamped to a valid row and never used, so
+  // every load is unconditional and in bounds.
+  auto load_row = [&](int yn, S (&f)[9], T& phi) {
+    int r, rs, rn;
+    bool bl = false, bh = false;
+    if (WALLS) {
+      r = min(max(yn, 0), ny - 1);
+      bl = (yn == 0);
+      bh = (yn == ny - 1);
+      rs = max(r - 1, 0);
+      rn = min(r + 1, ny - 1);
+    } else {
+      r = wrap_index(yn, ny);
+      rs = (r == 0) ? ny - 1 : r - 1;
+      rn = (r == ny - 1) ? 0 : r + 1;
+    }
+    phi = bload<T>(phir, xcT, unsigned(r) * unsigned(pitch) * TB);
+    f[0] = bload<S>(srcr, xcb, poff(0, r));
+    f[1] = bload<S>(srcr, xmb, poff(1, r));
+    f[3] = bload<S>(srcr, xpb, poff(3, r));
+    // sources below the lower wall bounce back: f2,f5,f6 <- f4,f7,f8 at x
+    f[2] = bload<S>(srcr, xcb, bl ? poff(4, r) : poff(2, rs));
+    f[5] = bload<S>(srcr, bl ? xcb : xmb, bl ? poff(7, r) : poff(5, rs));
+    f[6] = bload<S>(srcr, bl ? xcb : xpb, bl ? poff(8, r) : poff(6, rs));
+    // sources above the upper wall: f4,f7,f8 <- f2,f5,f6 at x
+    f[4] = bload<S>(srcr, xcb, bh ? poff(2, r) : poff(4, rn));
+    f[7] = bload<S>(srcr, bh ? xcb : xpb, bh ? poff(5, r) : poff(7, rn));
+    f[8] = bload<S>(srcr, bh ? xcb : xmb, bh ? poff(6, r) : poff(8, rn));
+  };
 
-  for (int k = 0; k < nit; ++k) {
+  // One sweep iteration.  A: row yn, B: row yn-1, C: row yn-2.  rA is
+  // written, rB/rC are read; bNew is written by B, bOld (row yn-2) read by C.
+  auto body = [&](int k, const S (&f)[9], const T phi_in, RowState<T>& rA,
+                  const RowState<T>& rB, const RowState<T>& rC, T (&bNew)[2],
+                  const T (&bOld)[2]) {
     const int yn = y0 - 2 + k;
-    T gA[9];
-    T sA[5];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) gA[i] = T(0);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) sA[i] = T(0);
 
-    // ---------------- stage A: pull row yn ----------------
+    // ---------------- stage A: moments of row yn ----------------
     const bool rowA = WALLS ? (yn >= 0 && yn < ny) : true;
     if (rowA && live) {
-      const int r = WALLS ? yn : wrap_index(yn, ny);
-      const int rs = WALLS ? yn - 1 : wrap_index(yn - 1, ny);
-      const int rn = WALLS ? yn + 1 : wrap_index(yn + 1, ny);
-      const int o = r * pitch;
-      const T phi = phif[o + c];
-      T f[9];
-      f[0] = load_pop<S, T>(src + 0 * P + o + c);
-      f[1] = load_pop<S, T>(src + 1 * P + o + cm);
-      f[3] = load_pop<S, T>(src + 3 * P + o + cp);
-      if (WALLS && yn == 0) {  // sources below the lower wall: bounce back
-        f[2] = load_pop<S, T>(src + 4 * P + o + c);
-        f[5] = load_pop<S, T>(src + 7 * P + o + c);
-        f[6] = load_pop<S, T>(src + 8 * P + o + c);
-      } else {
-        const int os = rs * pitch;
-        f[2] = load_pop<S, T>(src + 2 * P + os + c);
-        f[5] = load_pop<S, T>(src + 5 * P + os + cm);
-        f[6] = load_pop<S, T>(src + 6 * P + os + cp);
-      }
-      if (WALLS && yn == ny - 1) {  // sources above the upper wall
-        f[4] = load_pop<S, T>(src + 2 * P + o + c);
-        f[7] = load_pop<S, T>(src + 5 * P + o + c);
-        f[8] = load_pop<S, T>(src + 6 * P + o + c);
-      } else {
-        const int on = rn * pitch;
-        f[4] = load_pop<S, T>(src + 4 * P + on + c);
-        f[7] = load_pop<S, T>(src + 7 * P + on + cp);
-        f[8] = load_pop<S, T>(src + 8 * P + on + cm);
-      }
+      const T phi = phi_in;
+      T q[9];
       if (SHIFT) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) gA[i] = f[i] * ph.inv_scale;
+        for (int i = 0; i < 9; ++i) q[i] = static_cast<T>(f[i]) * ph.inv_scale;
       } else {
-        gA[0] = f[0] - (phi * rho0 - ph.rest0_k);
+        q[0] = static_cast<T>(f[0]) - (phi * rho0 - ph.rest0_k);
 #pragma unroll
-        for (int i = 1; i < 5; ++i) gA[i] = f[i] - ph.rest_axis;
+        for (int i = 1; i < 5; ++i) q[i] = static_cast<T>(f[i]) - ph.rest_axis;
 #pragma unroll
-        for (int i = 5; i < 9; ++i) gA[i] = f[i] - ph.rest_diag;
+        for (int i = 5; i < 9; ++i) q[i] = static_cast<T>(f[i]) - ph.rest_diag;
       }
-      const T dm0 = gA[0] + ((gA[1] + gA[2]) + (gA[3] + gA[4])) +
-                    ((gA[5] + gA[6]) + (gA[7] + gA[8]));
-      const T jx = (gA[1] - gA[3]) + ((gA[5] - gA[6]) + (gA[8] - gA[7]));
-      const T jy = (gA[2] - gA[4]) + ((gA[5] + gA[6]) - (gA[7] + gA[8]));
-      const T drho = dm0 / phi;
-      sA[0] = dm0; sA[1] = jx; sA[2] = jy; sA[3] = phi; sA[4] = drho;
-      s_rho[slot5(yn)][t] = drho;
+      // rows of M (Eq. A1) applied to the deviations
+      const T sa = (q[1] + q[2]) + (q[3] + q[4]);
+      const T sd = (q[5] + q[6]) + (q[7] + q[8]);
+      rA.dm0 = q[0] + (sa + sd);
+      rA.jx = (q[1] - q[3]) + ((q[5] - q[6]) + (q[8] - q[7]));
+      rA.jy = (q[2] - q[4]) + ((q[5] + q[6]) - (q[7] + q[8]));
+      rA.me = T(-4) * q[0] - sa + T(2) * sd;
+      rA.mep = T(4) * q[0] - T(2) * sa + sd;
+      rA.mqx = T(-2) * (q[1] - q[3]) + ((q[5] - q[6]) + (q[8] - q[7]));
+      rA.mqy = T(-2) * (q[2] - q[4]) + ((q[5] + q[6]) - (q[7] + q[8]));
+      rA.mpxx = (q[1] + q[3]) - (q[2] + q[4]);
+      rA.mpxy = (q[5] + q[7]) - (q[6] + q[8]);
+      rA.phi = phi;
+      rA.drho = rA.dm0 * recip(phi);
+      s_rho[slot4(yn)][t] = rA.drho;
+      if (WALLS && yn == 0) s_rho[slot4(-1)][t] = rA.drho;      // image below
+      if (WALLS && yn == ny - 1) s_rho[slot4(ny)][t] = rA.drho; // image above
     }
     __syncthreads();
 
     // ---------------- stage B: velocity of row yn-1 ----------------
     const int yb = yn - 1;
-    T bN[4] = {0, 0, 0, 0};
     const bool rowB = (yb >= y0 - 1) && (WALLS ? (yb >= 0 && yb < ny) : true);
     if (rowB && ulane) {
-      const int sc = slot5(yb);
-      const int ss = (WALLS && yb == 0) ? sc : slot5(yb - 1);       // mirror image
-      const int sn = (WALLS && yb == ny - 1) ? sc : slot5(yb + 1);
+      const int sc = slot4(yb), ss = slot4(yb - 1), sn = slot4(yb + 1);
       const T rE = s_rho[sc][tr], rW = s_rho[sc][tl];
       const T rN = s_rho[sn][t], rS = s_rho[ss][t];
       const T rNE = s_rho[sn][tr], rNW = s_rho[sn][tl];
       const T rSE = s_rho[ss][tr], rSW = s_rho[ss][tl];
       const T grx = stencil_dx(rE, rW, rNE, rSE, rNW, rSW);
       const T gry = stencil_dy(rN, rS, rNE, rNW, rSE, rSW);
-      const T phi = sB[3];
+      const T phi = rB.phi;
       const T kp = (kappa - phi) * third;
       const T sg = ph.scale_by_phi ? phi : T(1);
       T Fx = kp * grx + sg * ph.gx;
       T Fy = kp * gry + sg * ph.gy;
       if (FFIELD) {
-        const int r = WALLS ? yb : wrap_index(yb, ny);
-        Fx += static_cast<const T*>(g.fxf)[r * pitch + c];
-        Fy += static_cast<const T*>(g.fyf)[r * pitch + c];
+        const unsigned ro = unsigned(WALLS ? yb : wrap_index(yb, ny)) * unsigned(pitch) * TB;
+        Fx += bload<T>(make_rsrc(g.fxf, unsigned(g.plane) * TB), xcT, ro);
+        Fy += bload<T>(make_rsrc(g.fyf, unsigned(g.plane) * TB), xcT, ro);
       }
-      const T m0 = phi * rho0 + sB[0];
-      const T inv_m0 = T(1) / m0;
-      const T ux = (sB[1] + T(0.5) * Fx) * inv_m0;
-      const T uy = (sB[2] + T(0.5) * Fy) * inv_m0;
-      U4<T> uu;
-      uu.ux = ux; uu.uy = uy; uu.mux = m0 * ux; uu.muy = m0 * uy;
-      s_u[slot3(yb)][t] = uu;
-      bN[0] = ux; bN[1] = uy; bN[2] = Fx; bN[3] = Fy;
+      const T m0 = phi * rho0 + rB.dm0;
+      const T inv_m0 = recip(m0);
+      const T ux = (rB.jx + T(0.5) * Fx) * inv_m0;
+      const T uy = (rB.jy + T(0.5) * Fy) * inv_m0;
+      const T rho = rho0 + rB.drho;
+      U4<T> a;
+      U2<T> b;
+      a.ux = ux; a.uy = uy; a.mux = m0 * ux; a.rux = rho * ux;
+      b.muy = m0 * uy; b.ruy = rho * uy;
+      s_u4[slot4(yb)][t] = a;
+      s_u2[slot4(yb)][t] = b;
+      if (WALLS && (yb == 0 || yb == ny - 1)) {  // mirror image beyond the wall
+        const int sg2 = slot4(yb == 0 ? -1 : ny);
+        U4<T> am;
+        U2<T> bm;
+        am.ux = -a.ux; am.uy = -a.uy; am.mux = -a.mux; am.rux = -a.rux;
+        bm.muy = -b.muy; bm.ruy = -b.ruy;
+        s_u4[sg2][t] = am;
+        s_u2[sg2][t] = bm;
+      }
+      bNew[0] = Fx;
+      bNew[1] = Fy;
     }
     __syncthreads();
 
     // ---------------- stage C: collide row yn-2 ----------------
     const int yo = yn - 2;
     if (yo >= y0 && olane) {
-      const bool lo_wall = WALLS && yo == 0;
-      const bool hi_wall = WALLS && yo == ny - 1;
-      const int uo = slot3(yo);
-      const int us = lo_wall ? uo : slot3(yo - 1);
-      const int un = hi_wall ? uo : slot3(yo + 1);
-      const int ro = slot5(yo);
-      const int rs = lo_wall ? ro : slot5(yo - 1);
-      const int rn = hi_wall ? ro : slot5(yo + 1);
-      const T sgs = lo_wall ? T(-1) : T(1);  // velocity images change sign
-      const T sgn = hi_wall ? T(-1) : T(1);
-
-      const U4<T> qE = s_u[uo][tr], qW = s_u[uo][tl];
-      U4<T> qN = s_u[un][t], qS = s_u[us][t];
-      U4<T> qNE = s_u[un][tr], qNW = s_u[un][tl];
-      U4<T> qSE = s_u[us][tr], qSW = s_u[us][tl];
-      const T pE = rho0 + s_rho[ro][tr], pW = rho0 + s_rho[ro][tl];
-      const T pN = rho0 + s_rho[rn][t], pS = rho0 + s_rho[rs][t];
-      const T pNE = rho0 + s_rho[rn][tr], pNW = rho0 + s_rho[rn][tl];
-      const T pSE = rho0 + s_rho[rs][tr], pSW = rho0 + s_rho[rs][tl];
-      qN.ux *= sgn; qN.uy *= sgn; qN.mux *= sgn; qN.muy *= sgn;
-      qNE.ux *= sgn; qNE.uy *= sgn; qNE.mux *= sgn; qNE.muy *= sgn;
-      qNW.ux *= sgn; qNW.uy *= sgn; qNW.mux *= sgn; qNW.muy *= sgn;
-      qS.ux *= sgs; qS.uy *= sgs; qS.mux *= sgs; qS.muy *= sgs;
-      qSE.ux *= sgs; qSE.uy *= sgs; qSE.mux *= sgs; qSE.muy *= sgs;
-      qSW.ux *= sgs; qSW.uy *= sgs; qSW.mux *= sgs; qSW.muy *= sgs;
+      const int uo = slot4(yo), us = slot4(yo - 1), un = slot4(yo + 1);
+      const U4<T> aC = s_u4[uo][t];
+      const U4<T> aE = s_u4[uo][tr], aW = s_u4[uo][tl];
+      const U4<T> aN = s_u4[un][t], aS = s_u4[us][t];
+      const U4<T> aNE = s_u4[un][tr], aNW = s_u4[un][tl];
+      const U4<T> aSE = s_u4[us][tr], aSW = s_u4[us][tl];
+      const U2<T> bN = s_u2[un][t], bS = s_u2[us][t];
+      const U2<T> bNE = s_u2[un][tr], bNW = s_u2[un][tl];
+      const U2<T> bSE = s_u2[us][tr], bSW = s_u2[us][tl];
 
       // the eight derivatives of Eq. (20), each by Eq. (10)
-      const T d_rux_x = stencil_dx(pE * qE.ux, pW * qW.ux, pNE * qNE.ux, pSE * qSE.ux,
-                                   pNW * qNW.ux, pSW * qSW.ux);
-      const T d_ruy_y = stencil_dy(pN * qN.uy, pS * qS.uy, pNE * qNE.uy, pNW * qNW.uy,
-                                   pSE * qSE.uy, pSW * qSW.uy);
-      const T d_ux_x = stencil_dx(qE.ux, qW.ux, qNE.ux, qSE.ux, qNW.ux, qSW.ux);
-      const T d_uy_y = stencil_dy(qN.uy, qS.uy, qNE.uy, qNW.uy, qSE.uy, qSW.uy);
-      const T d_uy_x = stencil_dx(qE.uy, qW.uy, qNE.uy, qSE.uy, qNW.uy, qSW.uy);
-      const T d_ux_y = stencil_dy(qN.ux, qS.ux, qNE.ux, qNW.ux, qSE.ux, qSW.ux);
-      const T d_mux_x = stencil_dx(qE.mux, qW.mux, qNE.mux, qSE.mux, qNW.mux, qSW.mux);
-      const T d_muy_y = stencil_dy(qN.muy, qS.muy, qNE.muy, qNW.muy, qSE.muy, qSW.muy);
+      const T d_rux_x = stencil_dx(aE.rux, aW.rux, aNE.rux, aSE.rux, aNW.rux, aSW.rux);
+      const T d_ruy_y = stencil_dy(bN.ruy, bS.ruy, bNE.ruy, bNW.ruy, bSE.ruy, bSW.ruy);
+      const T d_ux_x = stencil_dx(aE.ux, aW.ux, aNE.ux, aSE.ux, aNW.ux, aSW.ux);
+      const T d_uy_y = stencil_dy(aN.uy, aS.uy, aNE.uy, aNW.uy, aSE.uy, aSW.uy);
+      const T d_uy_x = stencil_dx(aE.uy, aW.uy, aNE.uy, aSE.uy, aNW.uy, aSW.uy);
+      const T d_ux_y = stencil_dy(aN.ux, aS.ux, aNE.ux, aNW.ux, aSE.ux, aSW.ux);
+      const T d_mux_x = stencil_dx(aE.mux, aW.mux, aNE.mux, aSE.mux, aNW.mux, aSW.mux);
+      const T d_muy_y = stencil_dy(bN.muy, bS.muy, bNE.muy, bNW.muy, bSE.muy, bSW.muy);
 
-      const T phi = sC[3];
-      const T rho = rho0 + sC[4];
-      const T X = kappa / phi;
+      const T phi = rC.phi;
+      const T rho = rho0 + rC.drho;
+      const T X = kappa * recip(phi);
       const T kmp = kappa - phi;
-      const T ux = bC[0], uy = bC[1], Fx = bC[2], Fy = bC[3];
+      const T ux = aC.ux, uy = aC.uy, Fx = bOld[0], Fy = bOld[1];
 
       // penalty source (Eq. 20); d_t phi = 0 for a static void fraction
       const T Ca = -kappa * (d_rux_x + d_ruy_y) + T(2) * kmp * rho * (d_ux_x + d_uy_y) +
@@ -279,20 +341,9 @@ __global__ void __launch_bounds__(NT) vanse_step_kernel(StepGeom g, StepPhys<T> 
                    (d_mux_x - d_muy_y);
       const T Cc = third * kmp * rho * (d_uy_x + d_ux_y);
 
-      // non-conserved moments of the deviations (rows of M, Eq. A1)
-      const T* q = gC;
-      const T sa = (q[1] + q[2]) + (q[3] + q[4]);
-      const T sd = (q[5] + q[6]) + (q[7] + q[8]);
-      const T me = T(-4) * q[0] - sa + T(2) * sd;
-      const T mep = T(4) * q[0] - T(2) * sa + sd;
-      const T mqx = T(-2) * (q[1] - q[3]) + ((q[5] - q[6]) + (q[8] - q[7]));
-      const T mqy = T(-2) * (q[2] - q[4]) + ((q[5] + q[6]) - (q[7] + q[8]));
-      const T mpxx = (q[1] + q[3]) - (q[2] + q[4]);
-      const T mpxy = (q[5] + q[7]) - (q[6] + q[8]);
-
       // equilibria (Eq. 18) minus those of the rest state
-      const T m0 = phi * rho0 + sC[0];  // phi rho
-      const T drho = sC[4];
+      const T m0 = phi * rho0 + rC.dm0;  // phi rho
+      const T drho = rC.drho;
       const T uu = ux * ux + uy * uy;
       const T eq_e = (T(2) * kappa - T(4) * phi) * drho + T(3) * m0 * uu;
       const T eq_ep = (T(4) * phi - T(3) * kappa) * drho - T(3) * m0 * uu;
@@ -310,15 +361,15 @@ __global__ void __launch_bounds__(NT) vanse_step_kernel(StepGeom g, StepPhys<T> 
       // relaxation (Eq. 16); conserved moments: m0+ = m0, j+ = j + F
       const T he = T(1) - T(0.5) * ph.s_e, hep = T(1) - T(0.5) * ph.s_eps;
       const T hq = T(1) - T(0.5) * ph.s_q, hn = T(1) - T(0.5) * ph.s_nu;
-      const T pe = me - ph.s_e * (me - eq_e) + he * (S1 + Ca);
-      const T pep = mep - ph.s_eps * (mep - eq_ep) - hep * S1;
-      const T pqx = mqx - ph.s_q * (mqx - eq_qx) - hq * Fx;
-      const T pqy = mqy - ph.s_q * (mqy - eq_qy) - hq * Fy;
-      const T ppxx = mpxx - ph.s_nu * (mpxx - eq_pxx) + hn * (S7 + Cb);
-      const T ppxy = mpxy - ph.s_nu * (mpxy - eq_pxy) + hn * (S8 + Cc);
-      const T pm0 = sC[0];
-      const T pjx = sC[1] + Fx;
-      const T pjy = sC[2] + Fy;
+      const T pe = rC.me - ph.s_e * (rC.me - eq_e) + he * (S1 + Ca);
+      const T pep = rC.mep - ph.s_eps * (rC.mep - eq_ep) - hep * S1;
+      const T pqx = rC.mqx - ph.s_q * (rC.mqx - eq_qx) - hq * Fx;
+      const T pqy = rC.mqy - ph.s_q * (rC.mqy - eq_qy) - hq * Fy;
+      const T ppxx = rC.mpxx - ph.s_nu * (rC.mpxx - eq_pxx) + hn * (S7 + Cb);
+      const T ppxy = rC.mpxy - ph.s_nu * (rC.mpxy - eq_pxy) + hn * (S8 + Cc);
+      const T pm0 = rC.dm0;
+      const T pjx = rC.jx + Fx;
+      const T pjy = rC.jy + Fy;
 
       // back-transform f+ = M^-1 m+ (Eq. A1)
       const T a = (T(4) * pm0 - pe - T(2) * pep) * T(1.0 / 36.0);
@@ -337,25 +388,45 @@ __global__ void __launch_bounds__(NT) vanse_step_kernel(StepGeom g, StepPhys<T> 
       o9[7] = b - X2 - Y2 + Qd;
       o9[8] = b + X2 - Y2 - Qd;
 
-      const int oo = yo * pitch + c;
       if (SHIFT) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) dst[i * P + oo] = static_cast<S>(o9[i] * ph.scale);
+        for (int i = 0; i < 9; ++i) bstore(static_cast<S>(o9[i] * ph.scale), dstr, xcb, poff(i, yo));
       } else {
-        dst[0 * P + oo] = static_cast<S>(o9[0] + (phi * rho0 - ph.rest0_k));
+        bstore(static_cast<S>(o9[0] + (phi * rho0 - ph.rest0_k)), dstr, xcb, poff(0, yo));
 #pragma unroll
-        for (int i = 1; i < 5; ++i) dst[i * P + oo] = static_cast<S>(o9[i] + ph.rest_axis);
+        for (int i = 1; i < 5; ++i) bstore(static_cast<S>(o9[i] + ph.rest_axis), dstr, xcb, poff(i, yo));
 #pragma unroll
-        for (int i = 5; i < 9; ++i) dst[i * P + oo] = static_cast<S>(o9[i] + ph.rest_diag);
+        for (int i = 5; i < 9; ++i) bstore(static_cast<S>(o9[i] + ph.rest_diag), dstr, xcb, poff(i, yo));
       }
     }
+  };
 
-#pragma unroll
-    for (int i = 0; i < 9; ++i) { gC[i] = gB[i]; gB[i] = gA[i]; }
-#pragma unroll
-    for (int i = 0; i < 5; ++i) { sC[i] = sB[i]; sB[i] = sA[i]; }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) bC[i] = bN[i];
+  // Software pipeline: the loads of row yn+1 are in flight while row yn is
+  // processed.  Unrolled by six so that the two load buffers (period 2) and
+  // the three row states (period 3) are renamed instead of copied.
+  S fa[9], fb[9];
+  T pa, pb;
+  RowState<T> R0{}, R1{}, R2{};
+  T b0[2] = {0, 0}, b1[2] = {0, 0};
+  load_row(y0 - 2, fa, pa);
+  for (int k = 0; k < nit; k += 6) {
+    load_row(y0 - 1 + k, fb, pb);
+    body(k + 0, fa, pa, R0, R2, R1, b0, b1);
+    if (k + 1 >= nit) break;
+    load_row(y0 + k, fa, pa);
+    body(k + 1, fb, pb, R1, R0, R2, b1, b0);
+    if (k + 2 >= nit) break;
+    load_row(y0 + 1 + k, fb, pb);
+    body(k + 2, fa, pa, R2, R1, R0, b0, b1);
+    if (k + 3 >= nit) break;
+    load_row(y0 + 2 + k, fa, pa);
+    body(k + 3, fb, pb, R0, R2, R1, b1, b0);
+    if (k + 4 >= nit) break;
+    load_row(y0 + 3 + k, fb, pb);
+    body(k + 4, fa, pa, R1, R0, R2, b0, b1);
+    if (k + 5 >= nit) break;
+    load_row(y0 + 4 + k, fa, pa);
+    body(k + 5, fb, pb, R2, R1, R0, b1, b0);
   }
 }
 

@@ -76,6 +76,10 @@ int make_layout(const vanse_desc* d, Layout* L) {
   const long long plane = pitch * d->ny;
   if (plane * 9 > (1LL << 31) - 1) return fail(VANSE_ERR_INVALID_ARG, "lattice too large (%d x %d)", d->nx, d->ny);
   const size_t sb = storage_bytes(d->precision), cb = compute_bytes(d->precision);
+  // the step kernel addresses each population buffer with 32-bit offsets
+  if ((unsigned long long)plane * 9ULL * sb >= (1ULL << 32))
+    return fail(VANSE_ERR_INVALID_ARG, "lattice too large: one population buffer must stay below 4 GiB "
+                "(%d x %d at %zu bytes per population)", d->nx, d->ny, sb);
   size_t off = 0;
   L->pitch = (int)pitch;
   L->plane = plane;
@@ -115,13 +119,31 @@ struct vanse_lattice {
 
 namespace {
 
+// Compute units of the current device (256 on MI355X when no device is
+// visible, so that host-only use of the ABI still gets a tiling).
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+    return cus;
+  (void)hipGetLastError();
+  return 256;
+}
+
+// Default launch shape: 256-lane workgroups on wide lattices, and rows per
+// workgroup chosen so that the grid is one full round of resident
+// workgroups (4 per CU for the FP32 kernels, 2 for FP64): every workgroup
+// then sweeps the same number of rows and none waits in a second round.
 void default_tiling(vanse_lattice* h) {
   const int nx = h->d.nx, ny = h->d.ny;
-  int threads = nx >= 200 ? 256 : (nx >= 100 ? 128 : 64);
+  const int threads = nx >= 200 ? 256 : (nx >= 100 ? 128 : 64);
   const int strips = (nx + threads - 5) / (threads - 4);
-  long long r = (long long)ny * strips / 1024;
+  const int per_cu = (h->d.precision == VANSE_F64 ? 2 : 4) * (256 / threads);
+  const long long slots = (long long)device_cus() * per_cu;
+  long long nby = slots / strips;
+  if (nby < 1) nby = 1;
+  long long r = (ny + nby - 1) / nby;
   if (r < 4) r = 4;
-  if (r > 64) r = 64;
   h->threads = threads;
   h->rows = (int)r;
 }
@@ -499,6 +521,27 @@ int vanse_set_storage_exponent(vanse_lattice* h, int e) {
   if (e < -24 || e > 24) return fail(VANSE_ERR_INVALID_ARG, "storage exponent out of range (got %d)", e);
   if (h->state_set) return fail(VANSE_ERR_STATE, "storage exponent must be set before the populations");
   h->storage_exp = e;
+  return VANSE_OK;
+}
+
+int vanse_stream_copy(vanse_lattice* h, int64_t n, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (n < 0) return fail(VANSE_ERR_INVALID_ARG, "n must be >= 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Geo G = make_geo(h);
+  const int sb = storage_bytes(h->d.precision);
+  for (int64_t s = 0; s < n; ++s) {
+    const void* src = h->ws + h->L.pop[h->cur];
+    void* dst = h->ws + h->L.pop[h->cur ^ 1];
+    if (sb == 8)
+      hipLaunchKernelGGL(stream_copy<double>, field_grid(h), dim3(256), 0, st, G, (const double*)src, (double*)dst);
+    else if (sb == 4)
+      hipLaunchKernelGGL(stream_copy<float>, field_grid(h), dim3(256), 0, st, G, (const float*)src, (float*)dst);
+    else
+      hipLaunchKernelGGL(stream_copy<_Float16>, field_grid(h), dim3(256), 0, st, G, (const _Float16*)src, (_Float16*)dst);
+    h->cur ^= 1;
+  }
+  HIP_TRY(hipGetLastError());
   return VANSE_OK;
 }
 

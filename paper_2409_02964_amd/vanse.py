@@ -32,7 +32,7 @@ EXPORTS = [
     "vanse_set_body_force", "vanse_set_void_fraction", "vanse_set_force_field",
     "vanse_init_equilibrium", "vanse_set_populations", "vanse_step", "vanse_read_moments",
     "vanse_read_populations", "vanse_observe", "vanse_set_tiling", "vanse_get_tiling",
-    "vanse_set_storage_exponent", "vanse_time", "vanse_error_string", "vanse_last_error",
+    "vanse_set_storage_exponent", "vanse_stream_copy", "vanse_time", "vanse_error_string", "vanse_last_error",
 ]
 
 
@@ -87,6 +87,7 @@ def lib():
                 "vanse_set_tiling": [vp, i32, i32],
                 "vanse_get_tiling": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
                 "vanse_set_storage_exponent": [vp, i32],
+                "vanse_stream_copy": [vp, i64, vp],
                 "vanse_time": [vp],
                 "vanse_error_string": [i32],
                 "vanse_last_error": [],
@@ -216,6 +217,12 @@ class Lattice:
     # ---- stepping ----
     def step(self, n=1, stream=None):
         check(lib().vanse_step(self.handle, int(n), _stream(stream)))
+        return self
+
+    def stream_copy(self, n=1, stream=None):
+        """Speed-of-light reference: n launches of the step's memory pattern
+        without arithmetic (permutes the stored state)."""
+        check(lib().vanse_stream_copy(self.handle, int(n), _stream(stream)))
         return self
 
     @property
