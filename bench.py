@@ -78,6 +78,67 @@ def cpu_baseline(steps: int):
                        f"({dt:.1f} s)")
 
 
+def batched_bench(steps: int, baseline_steps: int, graph_steps: int = 100):
+    """Batched workload: 256 independent periodic lattices, sides log-uniform
+    in [32, 512] (seed 4), phi = 0.6 + 0.3 sin(2 pi kx x/L) sin(2 pi ky y/L),
+    |G| ~ U[1e-7, 1e-5] along x, FP32, `steps` steps, one launch per step
+    over all lattices (autotuned tile shape, hipGraph-captured loop).  The
+    comparison is the plain path with one launch per lattice per step."""
+    import torch
+    from paper_2409_02964_amd import workloads as W
+    from paper_2409_02964_amd.vanse import Batch, Lattice, autotune_batch
+
+    specs = W.batch_lattices(256, seed=4)
+
+    def build():
+        lats = []
+        for sp in specs:
+            lat = Lattice(sp["L"], sp["L"], precision=PRECISION)
+            lat.set_params(KAPPA, RATES).set_body_force(sp["g"], 0.0).set_void_fraction(sp["phi"])
+            lat.init_equilibrium(1.0)
+            lats.append(lat)
+        return lats
+
+    nodes = sum(sp["L"] ** 2 for sp in specs)
+    lats = build()
+    best, _ = autotune_batch(lats, candidates=[(64, 0), (128, 0), (128, 16), (256, 0), (64, 16)],
+                             steps=10)
+    for lat in lats:
+        lat.init_equilibrium(1.0)
+    b = Batch(lats, threads=best[0], rows=best[1], graph_steps=graph_steps)
+    b.step(graph_steps)
+    torch.cuda.synchronize()
+    for lat in lats:
+        lat.init_equilibrium(1.0)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    b.step(steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_batch = ev0.elapsed_time(ev1) / 1e3
+    # plain path: one launch per lattice per step (timed on fewer steps)
+    for lat in lats:
+        lat.init_equilibrium(1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(baseline_steps):
+        for lat in lats:
+            lat.step(1)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) * steps / baseline_steps
+    return {"workload": "256 periodic lattices, L log-uniform 32..512 (seed 4), FP32, "
+                        f"{steps} steps", "lattices": len(specs), "nodes": nodes,
+            "steps": steps, "threads": best[0], "rows": b.tiles()["rows"],
+            "tiles": b.tiles()["tiles"], "graph_steps": graph_steps,
+            "solves_per_s": round(len(specs) / t_batch, 2),
+            "mlups": round(nodes * steps / t_batch / 1e6, 1),
+            "plain_one_launch_per_lattice_solves_per_s": round(len(specs) / t_plain, 2),
+            "plain_mlups": round(nodes * steps / t_plain / 1e6, 1),
+            "speedup": round(t_plain / t_batch, 2)}
+
+
 def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
     """Turn rocprofv3 CSV output (a kernel-trace --stats run in prof_dir/trace,
     --pmc FETCH_SIZE in prof_dir/fetch, --pmc WRITE_SIZE in prof_dir/write)
@@ -162,6 +223,8 @@ def main():
                     help="launches of the same-pattern copy kernel (0: skip)")
     ap.add_argument("--cpu-steps", type=int, default=3,
                     help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=2000,
+                    help="steps of the batched 256-lattice workload (0: skip)")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="summarize rocprofv3 CSVs in DIR/{trace,fetch,write} into profiles/")
     args = ap.parse_args()
@@ -252,6 +315,8 @@ def main():
         "final_umax": obs["umax"],
         "nonfinite": obs["nonfinite"],
     }
+    if args.batch_steps > 0:
+        line["batched"] = batched_bench(args.batch_steps, max(1, args.batch_steps // 10))
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -161,6 +161,39 @@ int vanse_set_storage_exponent(vanse_lattice *h, int e);
  * memory counters.  It permutes the stored state; t is not advanced. */
 int vanse_stream_copy(vanse_lattice *h, int64_t n, void *stream);
 
+/* ---- batches -------------------------------------------------------------
+ * Many independent lattices advanced together: every call to
+ * vanse_batch_step launches ONE kernel per time step whose workgroups cover
+ * the tiles of all member lattices (tile = strip of threads-4 columns x
+ * `rows` rows of one lattice).  Each member's arithmetic is exactly that of
+ * vanse_step (results are bitwise identical).  Members must share precision,
+ * boundary type and the force-field flag, be fully set up, and stay alive
+ * while the batch exists.  The batch keeps a table of the members'
+ * parameters and buffer parity in a caller-owned device workspace; it is
+ * written again automatically when a member changed or was stepped on its
+ * own.  Member handles stay usable (vanse_time, vanse_read_*). */
+typedef struct vanse_batch vanse_batch;
+
+/* Workspace bytes for a batch of n lattices with the given workgroup width
+ * (64, 128 or 256) and rows per workgroup (0: about two rounds of resident
+ * workgroups over the batch). */
+int vanse_batch_workspace_bytes(vanse_lattice *const *lats, int n, int threads,
+                                int rows, size_t *bytes);
+int vanse_batch_create(vanse_lattice *const *lats, int n, int threads, int rows,
+                       void *workspace, size_t bytes, vanse_batch **out);
+int vanse_batch_destroy(vanse_batch *b);
+
+/* Capture the step loop in a hipGraph of this many launches (even, > 0;
+ * 0 turns graphs off).  Graph launches run on a stream owned by the batch,
+ * ordered after and before the caller's stream with events. */
+int vanse_batch_set_graph(vanse_batch *b, int steps_per_graph);
+
+/* Advance every member nsteps time steps.  Enqueued on `stream`. */
+int vanse_batch_step(vanse_batch *b, int64_t nsteps, void *stream);
+
+/* Tiles (workgroups per launch) and rows per workgroup of the batch. */
+int vanse_batch_tiles(const vanse_batch *b, int *tiles, int *rows);
+
 /* Current time step t. */
 int64_t vanse_time(const vanse_lattice *h);
 

@@ -139,20 +139,26 @@ struct RowState {
 // WALLS: half-way bounce-back walls at y = -1/2 and y = ny - 1/2
 // FFIELD: add the per-node force planes to F^B
 // NT: threads per workgroup (= out_w + 4 active lanes at most)
-template <typename S, typename T, bool SHIFT, bool WALLS, bool FFIELD, int NT>
-__global__ void __launch_bounds__(NT)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2)))
-vanse_step_kernel(StepGeom g, StepPhys<T> ph) {
-  // LDS rings over the last four rows.  Next to a wall the row beyond it is
-  // filled with the mirror image (scalars copied, velocities negated), so the
-  // stencils below never test for walls.
-  __shared__ T s_rho[4][NT];      // delta-rho (stage A -> stage B)
-  __shared__ U4<T> s_u4[4][NT];   // (stage B -> stage C)
-  __shared__ U2<T> s_u2[4][NT];
+// LDS rings over the last four rows.  Next to a wall the row beyond it is
+// filled with the mirror image (scalars copied, velocities negated), so the
+// stencils never test for walls.
+template <typename T, int NT>
+struct StepLds {
+  T rho[4][NT];      // delta-rho (stage A -> stage B)
+  U4<T> u4[4][NT];   // (stage B -> stage C)
+  U2<T> u2[4][NT];
+};
 
+// One workgroup's tile: strip `strip` (columns strip*out_w .. +out_w-1) and
+// row block `by` (rows by*rows .. +rows-1) of the lattice described by g.
+// PD: prefetch distance in rows (1 or 2).
+template <typename S, typename T, bool SHIFT, bool WALLS, bool FFIELD, int NT, int PD>
+__device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& ph, int strip,
+                                          int by, StepLds<T, NT>& L) {
+  auto& s_rho = L.rho;
+  auto& s_u4 = L.u4;
+  auto& s_u2 = L.u2;
   const int t = threadIdx.x;
-  const int strip = blockIdx.x % g.strips;
-  const int by = blockIdx.x / g.strips;
   const int nx = g.nx, ny = g.ny, pitch = g.pitch;
   const int x0 = strip * g.out_w;
   const int w = min(g.out_w, nx - x0);
@@ -401,33 +407,102 @@ vanse_step_kernel(StepGeom g, StepPhys<T> ph) {
     }
   };
 
-  // Software pipeline: the loads of row yn+1 are in flight while row yn is
-  // processed.  Unrolled by six so that the two load buffers (period 2) and
+  // Software pipeline: the loads of row yn+PD are in flight while row yn is
+  // processed.  Unrolled by six so that the load buffers (period PD+1) and
   // the three row states (period 3) are renamed instead of copied.
-  S fa[9], fb[9];
-  T pa, pb;
   RowState<T> R0{}, R1{}, R2{};
   T b0[2] = {0, 0}, b1[2] = {0, 0};
-  load_row(y0 - 2, fa, pa);
-  for (int k = 0; k < nit; k += 6) {
-    load_row(y0 - 1 + k, fb, pb);
-    body(k + 0, fa, pa, R0, R2, R1, b0, b1);
-    if (k + 1 >= nit) break;
-    load_row(y0 + k, fa, pa);
-    body(k + 1, fb, pb, R1, R0, R2, b1, b0);
-    if (k + 2 >= nit) break;
-    load_row(y0 + 1 + k, fb, pb);
-    body(k + 2, fa, pa, R2, R1, R0, b0, b1);
-    if (k + 3 >= nit) break;
-    load_row(y0 + 2 + k, fa, pa);
-    body(k + 3, fb, pb, R0, R2, R1, b1, b0);
-    if (k + 4 >= nit) break;
-    load_row(y0 + 3 + k, fb, pb);
-    body(k + 4, fa, pa, R1, R0, R2, b0, b1);
-    if (k + 5 >= nit) break;
-    load_row(y0 + 4 + k, fa, pa);
-    body(k + 5, fb, pb, R2, R1, R0, b1, b0);
+  if constexpr (PD == 1) {
+    S fa[9], fb[9];
+    T pa, pb;
+    load_row(y0 - 2, fa, pa);
+    for (int k = 0; k < nit; k += 6) {
+      load_row(y0 - 1 + k, fb, pb);
+      body(k + 0, fa, pa, R0, R2, R1, b0, b1);
+      if (k + 1 >= nit) break;
+      load_row(y0 + k, fa, pa);
+      body(k + 1, fb, pb, R1, R0, R2, b1, b0);
+      if (k + 2 >= nit) break;
+      load_row(y0 + 1 + k, fb, pb);
+      body(k + 2, fa, pa, R2, R1, R0, b0, b1);
+      if (k + 3 >= nit) break;
+      load_row(y0 + 2 + k, fa, pa);
+      body(k + 3, fb, pb, R0, R2, R1, b1, b0);
+      if (k + 4 >= nit) break;
+      load_row(y0 + 3 + k, fb, pb);
+      body(k + 4, fa, pa, R1, R0, R2, b0, b1);
+      if (k + 5 >= nit) break;
+      load_row(y0 + 4 + k, fa, pa);
+      body(k + 5, fb, pb, R2, R1, R0, b1, b0);
+    }
+  } else {
+    static_assert(PD == 2, "prefetch distance 1 or 2");
+    S fa[9], fb[9], fc[9];
+    T pa, pb, pc;
+    load_row(y0 - 2, fa, pa);
+    load_row(y0 - 1, fb, pb);
+    for (int k = 0; k < nit; k += 6) {
+      load_row(y0 + k, fc, pc);
+      body(k + 0, fa, pa, R0, R2, R1, b0, b1);
+      if (k + 1 >= nit) break;
+      load_row(y0 + 1 + k, fa, pa);
+      body(k + 1, fb, pb, R1, R0, R2, b1, b0);
+      if (k + 2 >= nit) break;
+      load_row(y0 + 2 + k, fb, pb);
+      body(k + 2, fc, pc, R2, R1, R0, b0, b1);
+      if (k + 3 >= nit) break;
+      load_row(y0 + 3 + k, fc, pc);
+      body(k + 3, fa, pa, R0, R2, R1, b1, b0);
+      if (k + 4 >= nit) break;
+      load_row(y0 + 4 + k, fa, pa);
+      body(k + 4, fb, pb, R1, R0, R2, b0, b1);
+      if (k + 5 >= nit) break;
+      load_row(y0 + 5 + k, fb, pb);
+      body(k + 5, fc, pc, R2, R1, R0, b1, b0);
+    }
   }
+}
+
+// One lattice per launch: workgroup b takes strip b % strips, row block
+// b / strips.  WPE: minimum waves per SIMD the register allocation allows.
+template <typename S, typename T, bool SHIFT, bool WALLS, bool FFIELD, int NT, int PD = 1,
+          int WPE = (sizeof(T) == 4 ? 4 : 2)>
+__global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(WPE)))
+vanse_step_kernel(StepGeom g, StepPhys<T> ph) {
+  __shared__ StepLds<T, NT> lds;
+  step_tile<S, T, SHIFT, WALLS, FFIELD, NT, PD>(g, ph, int(blockIdx.x) % g.strips,
+                                                 int(blockIdx.x) / g.strips, lds);
+}
+
+// Many independent lattices per launch.  Lattice k owns tiles
+// [first_tile_k, first_tile_k + strips_k * row_blocks_k); its two population
+// buffers alternate with parity (cur0_k + launch) & 1.
+template <typename T>
+struct BatchEntry {
+  StepGeom g;          // src/dst hold buffer 0 and buffer 1
+  StepPhys<T> ph;
+  int first_tile;
+  int cur0;            // buffer holding the state before launch 0
+};
+
+template <typename S, typename T, bool SHIFT, bool WALLS, bool FFIELD, int NT,
+          int WPE = (sizeof(T) == 4 ? 4 : 2)>
+__global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(WPE)))
+vanse_batch_step_kernel(const BatchEntry<T>* __restrict__ entries,
+                        const int* __restrict__ tile_lattice, int launch) {
+  __shared__ StepLds<T, NT> lds;
+  const int k = tile_lattice[blockIdx.x];
+  const BatchEntry<T>& e = entries[k];
+  StepGeom g = e.g;
+  const int par = (e.cur0 + launch) & 1;
+  void* const b0 = const_cast<void*>(e.g.src);
+  void* const b1 = e.g.dst;
+  g.src = par ? b1 : b0;
+  g.dst = par ? b0 : b1;
+  const int local = int(blockIdx.x) - e.first_tile;
+  step_tile<S, T, SHIFT, WALLS, FFIELD, NT, 1>(g, e.ph, local % g.strips, local / g.strips, lds);
 }
 
 }  // namespace vanse_dev

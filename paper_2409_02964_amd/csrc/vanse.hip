@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "aux_kernels.hpp"
 #include "step_kernel.hpp"
@@ -115,6 +116,7 @@ struct vanse_lattice {
   int threads, rows;  // launch shape of the step kernel
   bool tiling_default;
   int storage_exp;
+  long long version;  // bumped by every call that changes what the step reads
 };
 
 namespace {
@@ -297,6 +299,7 @@ int vanse_create(const vanse_desc* d, void* workspace, size_t bytes, vanse_latti
   h->scale_by_phi = 1;
   h->rates = vanse_rates{1.0, 1.2, 1.2, 1.2, 1.2};
   h->storage_exp = 12;
+  h->version = 0;
   h->tiling_default = true;
   default_tiling(h);
   *out = h;
@@ -318,6 +321,7 @@ int vanse_set_params(vanse_lattice* h, double kappa, const vanse_rates* r) {
   h->kappa = kappa;
   h->rates = *r;
   h->params_set = true;
+  h->version += 1;
   return VANSE_OK;
 }
 
@@ -328,6 +332,7 @@ int vanse_set_body_force(vanse_lattice* h, double gx, double gy, int scale_by_ph
   h->gx = gx;
   h->gy = gy;
   h->scale_by_phi = scale_by_phi;
+  h->version += 1;
   return VANSE_OK;
 }
 
@@ -394,6 +399,7 @@ static int fill(vanse_lattice* h, const double* fin, double rho0, double ux0, do
   h->cur = 0;
   h->t = 0;
   h->state_set = true;
+  h->version += 1;
   return VANSE_OK;
 }
 
@@ -521,6 +527,7 @@ int vanse_set_storage_exponent(vanse_lattice* h, int e) {
   if (e < -24 || e > 24) return fail(VANSE_ERR_INVALID_ARG, "storage exponent out of range (got %d)", e);
   if (h->state_set) return fail(VANSE_ERR_STATE, "storage exponent must be set before the populations");
   h->storage_exp = e;
+  h->version += 1;
   return VANSE_OK;
 }
 
@@ -546,6 +553,289 @@ int vanse_stream_copy(vanse_lattice* h, int64_t n, void* stream) {
 }
 
 int64_t vanse_time(const vanse_lattice* h) { return h ? h->t : -1; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: many independent lattices advanced by one launch per time step.
+// ---------------------------------------------------------------------------
+struct vanse_batch {
+  std::vector<vanse_lattice*> lats;
+  std::vector<int> rows;     // rows per workgroup, per lattice
+  std::vector<int> first;    // first tile of each lattice
+  int threads = 256;
+  int total_tiles = 0;
+  char* ws = nullptr;
+  size_t entries_off = 0, tiles_off = 0;
+  bool table_ready = false;
+  long long launched = 0;    // launches since the table was written
+  std::vector<long long> versions;  // member versions at the last upload
+  std::vector<int> cur0;            // member buffer parity at the last upload
+  int graph_steps = 0;
+  hipGraphExec_t graph = nullptr;
+  hipStream_t own = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+int batch_per_cu(int precision, int threads) { return (precision == VANSE_F64 ? 2 : 4) * (256 / threads); }
+
+int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, std::vector<int>* rows_out,
+                 std::vector<int>* first_out, int* total_tiles, size_t* entries_off, size_t* tiles_off,
+                 size_t* bytes) {
+  if (!lats || n < 1) return fail(VANSE_ERR_INVALID_ARG, "a batch needs at least one lattice");
+  if (threads != 64 && threads != 128 && threads != 256)
+    return fail(VANSE_ERR_INVALID_ARG, "batch threads must be 64, 128 or 256 (got %d)", threads);
+  if (rows < 0) return fail(VANSE_ERR_INVALID_ARG, "rows must be >= 0");
+  const vanse_desc& d0 = lats[0] ? lats[0]->d : vanse_desc{};
+  const int out_w = threads - 4;
+  long long strip_rows = 0;
+  for (int k = 0; k < n; ++k) {
+    if (!lats[k]) return fail(VANSE_ERR_INVALID_ARG, "lattice %d is NULL", k);
+    const vanse_desc& d = lats[k]->d;
+    if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field)
+      return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary or force field", k);
+    strip_rows += (long long)((d.nx + out_w - 1) / out_w) * d.ny;
+  }
+  int r = rows;
+  if (r == 0) {  // about two rounds of resident workgroups over the whole batch
+    const long long slots = (long long)device_cus() * batch_per_cu(d0.precision, threads);
+    r = (int)((strip_rows + 2 * slots - 1) / (2 * slots));
+    if (r < 8) r = 8;
+  }
+  rows_out->assign(n, r);
+  first_out->assign(n, 0);
+  long long tiles = 0;
+  for (int k = 0; k < n; ++k) {
+    const vanse_desc& d = lats[k]->d;
+    (*first_out)[k] = (int)tiles;
+    tiles += (long long)((d.nx + out_w - 1) / out_w) * ((d.ny + r - 1) / r);
+  }
+  if (tiles > (1LL << 30)) return fail(VANSE_ERR_INVALID_ARG, "too many tiles");
+  *total_tiles = (int)tiles;
+  const size_t esz = sizeof(BatchEntry<double>) > sizeof(BatchEntry<float>) ? sizeof(BatchEntry<double>)
+                                                                            : sizeof(BatchEntry<float>);
+  *entries_off = 0;
+  *tiles_off = align256((size_t)n * esz);
+  *bytes = align256(*tiles_off + (size_t)tiles * sizeof(int));
+  return VANSE_OK;
+}
+
+template <typename T>
+void fill_entries(vanse_batch* b, std::vector<char>* blob) {
+  const int n = (int)b->lats.size();
+  blob->assign((size_t)n * sizeof(BatchEntry<T>), 0);
+  BatchEntry<T>* E = reinterpret_cast<BatchEntry<T>*>(blob->data());
+  for (int k = 0; k < n; ++k) {
+    vanse_lattice* h = b->lats[k];
+    StepGeom g;
+    g.src = h->ws + h->L.pop[0];
+    g.dst = h->ws + h->L.pop[1];
+    g.phi = h->ws + h->L.phi;
+    g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
+    g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
+    g.plane = h->L.plane;
+    g.nx = h->d.nx;
+    g.ny = h->d.ny;
+    g.pitch = h->L.pitch;
+    g.out_w = b->threads - 4;
+    g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
+    g.rows = b->rows[k];
+    E[k].g = g;
+    E[k].ph = make_phys<T>(h);
+    E[k].first_tile = b->first[k];
+    E[k].cur0 = h->cur;
+  }
+}
+
+// Upload the lattice table and the tile -> lattice map (host pageable copies,
+// synchronized: only when parameters or buffer parity change).
+int batch_upload(vanse_batch* b, hipStream_t st) {
+  std::vector<char> blob;
+  if (b->lats[0]->d.precision == VANSE_F64) fill_entries<double>(b, &blob);
+  else fill_entries<float>(b, &blob);
+  std::vector<int> tl((size_t)b->total_tiles);
+  for (size_t k = 0; k < b->lats.size(); ++k) {
+    const int end = (k + 1 < b->lats.size()) ? b->first[k + 1] : b->total_tiles;
+    for (int i = b->first[k]; i < end; ++i) tl[(size_t)i] = (int)k;
+  }
+  HIP_TRY(hipMemcpyAsync(b->ws + b->entries_off, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b->ws + b->tiles_off, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  b->versions.resize(b->lats.size());
+  b->cur0.resize(b->lats.size());
+  for (size_t k = 0; k < b->lats.size(); ++k) {
+    b->versions[k] = b->lats[k]->version;
+    b->cur0[k] = b->lats[k]->cur;
+  }
+  b->table_ready = true;
+  b->launched = 0;
+  return VANSE_OK;
+}
+
+template <typename S, typename T, bool SHIFT, bool WALLS, bool FF>
+void batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
+  const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
+  const int* TL = reinterpret_cast<const int*>(b->ws + b->tiles_off);
+  switch (b->threads) {
+    case 64:
+      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FF, 64>), dim3(b->total_tiles), dim3(64), 0, st, E, TL, launch);
+      break;
+    case 128:
+      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FF, 128>), dim3(b->total_tiles), dim3(128), 0, st, E, TL, launch);
+      break;
+    default:
+      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FF, 256>), dim3(b->total_tiles), dim3(256), 0, st, E, TL, launch);
+  }
+}
+
+int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
+  const vanse_desc& d = b->lats[0]->d;
+  const bool walls = d.bc_y == VANSE_WALL, ff = d.has_force_field != 0;
+  return by_precision(b->lats[0], [&](auto* s_tag, auto* t_tag, auto shift) -> int {
+    using S = std::remove_pointer_t<decltype(s_tag)>;
+    using T = std::remove_pointer_t<decltype(t_tag)>;
+    constexpr bool SH = decltype(shift)::value;
+    if (walls) {
+      if (ff) batch_launch_t<S, T, SH, true, true>(b, launch, st);
+      else batch_launch_t<S, T, SH, true, false>(b, launch, st);
+    } else {
+      if (ff) batch_launch_t<S, T, SH, false, true>(b, launch, st);
+      else batch_launch_t<S, T, SH, false, false>(b, launch, st);
+    }
+    return VANSE_OK;
+  });
+}
+
+}  // namespace
+
+extern "C" {
+
+int vanse_batch_workspace_bytes(vanse_lattice* const* lats, int n, int threads, int rows, size_t* bytes) {
+  if (!bytes) return fail(VANSE_ERR_INVALID_ARG, "bytes is NULL");
+  std::vector<int> r, f;
+  int tiles;
+  size_t eo, to;
+  return batch_layout(lats, n, threads, rows, &r, &f, &tiles, &eo, &to, bytes);
+}
+
+int vanse_batch_create(vanse_lattice* const* lats, int n, int threads, int rows, void* workspace,
+                       size_t bytes, vanse_batch** out) {
+  if (!out) return fail(VANSE_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  std::vector<int> r, f;
+  int tiles;
+  size_t eo, to, need;
+  if (int rc = batch_layout(lats, n, threads, rows, &r, &f, &tiles, &eo, &to, &need)) return rc;
+  if (!workspace || (((uintptr_t)workspace) & 255)) return fail(VANSE_ERR_WORKSPACE, "batch workspace missing or not 256-byte aligned");
+  if (bytes < need) return fail(VANSE_ERR_WORKSPACE, "batch workspace too small: %zu < %zu", bytes, need);
+  vanse_batch* b = new (std::nothrow) vanse_batch();
+  if (!b) return fail(VANSE_ERR_INVALID_ARG, "out of host memory");
+  b->lats.assign(lats, lats + n);
+  b->rows = r;
+  b->first = f;
+  b->threads = threads;
+  b->total_tiles = tiles;
+  b->ws = static_cast<char*>(workspace);
+  b->entries_off = eo;
+  b->tiles_off = to;
+  *out = b;
+  return VANSE_OK;
+}
+
+int vanse_batch_destroy(vanse_batch* b) {
+  if (!b) return VANSE_OK;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->own) (void)hipStreamDestroy(b->own);
+  delete b;
+  return VANSE_OK;
+}
+
+int vanse_batch_set_graph(vanse_batch* b, int steps_per_graph) {
+  if (!b) return fail(VANSE_ERR_INVALID_ARG, "batch is NULL");
+  if (steps_per_graph < 0 || (steps_per_graph & 1))
+    return fail(VANSE_ERR_INVALID_ARG, "steps per graph must be 0 or a positive even number (got %d)", steps_per_graph);
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  b->graph_steps = steps_per_graph;
+  return VANSE_OK;
+}
+
+int vanse_batch_tiles(const vanse_batch* b, int* tiles, int* rows) {
+  if (!b) return fail(VANSE_ERR_INVALID_ARG, "batch is NULL");
+  if (tiles) *tiles = b->total_tiles;
+  if (rows) *rows = b->rows.empty() ? 0 : b->rows[0];
+  return VANSE_OK;
+}
+
+int vanse_batch_step(vanse_batch* b, int64_t nsteps, void* stream) {
+  if (!b) return fail(VANSE_ERR_INVALID_ARG, "batch is NULL");
+  if (nsteps < 0) return fail(VANSE_ERR_INVALID_ARG, "nsteps must be >= 0");
+  for (vanse_lattice* h : b->lats) {
+    if (int rc = check_ready(h)) return rc;
+    if (!h->state_set) return fail(VANSE_ERR_STATE, "a lattice of the batch has no populations");
+  }
+  if (nsteps == 0) return VANSE_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the table snapshots each lattice's buffer parity and parameters: upload
+  // again if a member changed or was stepped on its own since
+  bool stale = !b->table_ready || b->launched > (1LL << 40);
+  for (size_t k = 0; !stale && k < b->lats.size(); ++k)
+    stale = b->lats[k]->version != b->versions[k] ||
+            b->lats[k]->cur != ((b->cur0[k] + (int)(b->launched & 1)) & 1);
+  if (stale) {
+    if (int rc = batch_upload(b, st)) return rc;
+  }
+  int64_t left = nsteps;
+  if (b->graph_steps > 0 && left >= b->graph_steps) {
+    if (!b->own) {
+      HIP_TRY(hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    }
+    // graph replays assume an even launch count at their start
+    if (b->launched & 1) {
+      if (int rc = batch_launch(b, (int)(b->launched & 1), st)) return rc;
+      b->launched += 1;
+      left -= 1;
+    }
+    HIP_TRY(hipEventRecord(b->ev_in, st));
+    HIP_TRY(hipStreamWaitEvent(b->own, b->ev_in, 0));
+    if (!b->graph && left >= b->graph_steps) {
+      hipGraph_t graph;
+      HIP_TRY(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
+      for (int s = 0; s < b->graph_steps; ++s) batch_launch(b, s, b->own);
+      HIP_TRY(hipStreamEndCapture(b->own, &graph));
+      const hipError_t e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return fail(VANSE_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    while (left >= b->graph_steps) {
+      HIP_TRY(hipGraphLaunch(b->graph, b->own));
+      b->launched += b->graph_steps;
+      left -= b->graph_steps;
+    }
+    HIP_TRY(hipEventRecord(b->ev_out, b->own));
+    HIP_TRY(hipStreamWaitEvent(st, b->ev_out, 0));
+  }
+  for (int64_t s = 0; s < left; ++s) {
+    if (int rc = batch_launch(b, (int)(b->launched & 1), st)) return rc;
+    b->launched += 1;
+  }
+  HIP_TRY(hipGetLastError());
+  // keep every member handle consistent with the batch
+  for (size_t k = 0; k < b->lats.size(); ++k) {
+    vanse_lattice* h = b->lats[k];
+    h->t += nsteps;
+    h->cur = (h->cur + (int)(nsteps & 1)) & 1;
+  }
+  return VANSE_OK;
+}
 
 const char* vanse_error_string(int code) {
   switch (code) {

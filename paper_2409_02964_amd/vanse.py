@@ -32,7 +32,9 @@ EXPORTS = [
     "vanse_set_body_force", "vanse_set_void_fraction", "vanse_set_force_field",
     "vanse_init_equilibrium", "vanse_set_populations", "vanse_step", "vanse_read_moments",
     "vanse_read_populations", "vanse_observe", "vanse_set_tiling", "vanse_get_tiling",
-    "vanse_set_storage_exponent", "vanse_stream_copy", "vanse_time", "vanse_error_string", "vanse_last_error",
+    "vanse_set_storage_exponent", "vanse_stream_copy", "vanse_time", "vanse_error_string",
+    "vanse_last_error", "vanse_batch_workspace_bytes", "vanse_batch_create", "vanse_batch_destroy",
+    "vanse_batch_set_graph", "vanse_batch_step", "vanse_batch_tiles",
 ]
 
 
@@ -89,6 +91,14 @@ def lib():
                 "vanse_set_storage_exponent": [vp, i32],
                 "vanse_stream_copy": [vp, i64, vp],
                 "vanse_time": [vp],
+                "vanse_batch_workspace_bytes": [C.POINTER(vp), i32, i32, i32,
+                                                C.POINTER(C.c_size_t)],
+                "vanse_batch_create": [C.POINTER(vp), i32, i32, i32, vp, C.c_size_t,
+                                       C.POINTER(vp)],
+                "vanse_batch_destroy": [vp],
+                "vanse_batch_set_graph": [vp, i32],
+                "vanse_batch_step": [vp, i64, vp],
+                "vanse_batch_tiles": [vp, C.POINTER(i32), C.POINTER(i32)],
                 "vanse_error_string": [i32],
                 "vanse_last_error": [],
             }
@@ -255,3 +265,81 @@ class Lattice:
             return res
         check(rc)
         return res
+
+
+class Batch:
+    """Independent lattices advanced by one kernel launch per time step.
+
+    Members must share precision, boundary type and the force-field flag and
+    be fully set up; they stay usable individually (read_moments, t).  With
+    ``graph_steps`` > 0 step loops are captured in hipGraphs of that many
+    launches."""
+
+    def __init__(self, lattices, threads=128, rows=0, graph_steps=0, device=None):
+        import torch
+        self.lattices = list(lattices)
+        n = len(self.lattices)
+        self._arr = (C.c_void_p * n)(*[l.handle.value for l in self.lattices])
+        nbytes = C.c_size_t()
+        check(lib().vanse_batch_workspace_bytes(self._arr, n, int(threads), int(rows),
+                                                C.byref(nbytes)))
+        dev = device or self.lattices[0].device
+        self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
+        self.handle = C.c_void_p()
+        check(lib().vanse_batch_create(self._arr, n, int(threads), int(rows),
+                                       C.c_void_p(self.workspace.data_ptr()),
+                                       self.workspace.numel(), C.byref(self.handle)))
+        self.threads = int(threads)
+        if graph_steps:
+            self.set_graph(graph_steps)
+
+    def set_graph(self, steps_per_graph):
+        check(lib().vanse_batch_set_graph(self.handle, int(steps_per_graph)))
+        return self
+
+    def step(self, n=1, stream=None):
+        check(lib().vanse_batch_step(self.handle, int(n), _stream(stream)))
+        return self
+
+    def tiles(self):
+        a, b = C.c_int(), C.c_int()
+        check(lib().vanse_batch_tiles(self.handle, C.byref(a), C.byref(b)))
+        return dict(tiles=a.value, rows=b.value)
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().vanse_batch_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_batch(lattices, candidates=None, steps=20, repeats=2):
+    """Pick the (threads, rows) of a batch by timing a few launches of each
+    candidate on the real batch (the members are advanced by the trials).
+    Returns (best, timings) with timings in ms per launch."""
+    import torch
+    if candidates is None:
+        candidates = [(t, r) for t in (64, 128, 256) for r in (0, 8, 16, 32, 64)]
+    times = {}
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    for th, rows in candidates:
+        b = Batch(lattices, threads=th, rows=rows)
+        b.step(2)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(repeats):
+            ev0.record()
+            b.step(steps)
+            ev1.record()
+            torch.cuda.synchronize()
+            best = min(best, ev0.elapsed_time(ev1) / steps)
+        times[(th, b.tiles()["rows"])] = best
+        b.close()
+    best = min(times, key=times.get)
+    return best, times
