@@ -139,6 +139,30 @@ def batched_bench(steps: int, baseline_steps: int, graph_steps: int = 100):
             "speedup": round(t_plain / t_batch, 2)}
 
 
+def served_bench(count: int, rate: float, budget_gib: float):
+    """Served workload: `count` solve requests with Poisson arrivals at `rate`
+    per second, periodic lattices with sides log-uniform in [64, 2048] and
+    tanh-edged inclusions (phi in [0.35, 1]), G = 1e-6, drag 2e-3 + 1e-2 (1 -
+    phi), FP32 arithmetic with FP16 shifted storage, run to a residual of 1e-8
+    or 20000 steps, admitted by device memory within `budget_gib`.  Compared
+    with the same server restricted to one solve at a time (FIFO, one lattice
+    per launch)."""
+    from paper_2409_02964_amd import workloads as W
+    from paper_2409_02964_amd.serve import SolveServer, summarize
+    reqs = W.served_requests(count, rate, seed=5)
+    budget = int(budget_gib * (1 << 30))
+    out = {"workload": f"{count} requests, Poisson {rate}/s, L log-uniform 64..2048, inclusions, "
+                       "FP16 shifted storage, residual 1e-8 or 20000 steps",
+           "memory_budget_gib": budget_gib}
+    for name, kw in (("continuous_batching", {}), ("one_at_a_time", {"max_active": 1})):
+        srv = SolveServer(budget, precision="f16s", chunk=500, max_steps=20000, tol=1e-8, **kw)
+        t0 = time.perf_counter()
+        done = srv.run(reqs)
+        out[name] = summarize(done, time.perf_counter() - t0)
+        out[name]["max_active"] = max(a for _, a, _, _ in srv.log)
+    return out
+
+
 def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
     """Turn rocprofv3 CSV output (a kernel-trace --stats run in prof_dir/trace,
     --pmc FETCH_SIZE in prof_dir/fetch, --pmc WRITE_SIZE in prof_dir/write)
@@ -225,6 +249,10 @@ def main():
                     help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2000,
                     help="steps of the batched 256-lattice workload (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests of the served workload (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=2.0)
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="summarize rocprofv3 CSVs in DIR/{trace,fetch,write} into profiles/")
     args = ap.parse_args()
@@ -317,6 +345,8 @@ def main():
     }
     if args.batch_steps > 0:
         line["batched"] = batched_bench(args.batch_steps, max(1, args.batch_steps // 10))
+    if args.serve_requests > 0:
+        line["served"] = served_bench(args.serve_requests, args.serve_rate, args.serve_budget_gib)
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(line), flush=True)

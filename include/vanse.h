@@ -69,6 +69,7 @@ typedef struct {
   int32_t bc_x;            /* VANSE_PERIODIC (walls in x: VANSE_ERR_UNSUPPORTED) */
   int32_t bc_y;            /* VANSE_PERIODIC | VANSE_WALL */
   int32_t has_force_field; /* 1: a per-node force field is added to F^B */
+  int32_t has_drag;        /* 1: a per-node linear drag acts (vanse_set_drag) */
 } vanse_desc;
 
 /* Diagonal of Gamma in Eq. (16), each in (0, 2):
@@ -111,6 +112,14 @@ int vanse_set_void_fraction(vanse_lattice *h, const double *phi, void *stream);
 int vanse_set_force_field(vanse_lattice *h, const double *fx, const double *fy,
                           void *stream);
 
+/* Linear drag towards a solid velocity u_s: F^B gains -phi*beta*(u - u_s),
+ * and u of Eq. (7) is solved in closed form from
+ * u = (j + F/2)/(phi rho).  This is the Darcy term of Eq. (21) (beta =
+ * phi nu / k0) and the particle drag of Eq. (23) (beta = phi (1 - phi)).
+ * beta: device float64 [ny][nx].  Needs has_drag. */
+int vanse_set_drag(vanse_lattice *h, const double *beta, double usx, double usy,
+                   void *stream);
+
 /* t = 0 with f(0) = f^eq(rho0, u0) of Eq. (14) at every node.  rho0 is also
  * the reference density of the rest state used by the deviation form. */
 int vanse_init_equilibrium(vanse_lattice *h, double rho0, double ux0,
@@ -141,6 +150,14 @@ int vanse_read_populations(vanse_lattice *h, double *f, void *stream);
  * `out` is HOST memory (4 doubles); synchronizes the stream.  Returns
  * VANSE_ERR_DIVERGED (after filling out) when out[3] > 0. */
 int vanse_observe(vanse_lattice *h, double *out, void *stream);
+
+/* Steady-state residual support: out[0] = sum_x |u(t) - u(t')|^2 where t'
+ * is the time of the previous vanse_residual call on this lattice (-1 on
+ * the first call after initialisation), out[1] = sum_x |u(t)|^2, out[2] =
+ * number of non-finite nodes.  u(t) is kept for the next call.  The
+ * relative residual of two consecutive steps is sqrt(out[0] / out[1]).
+ * `out` is HOST memory (3 doubles); synchronizes the stream. */
+int vanse_residual(vanse_lattice *h, double *out, void *stream);
 
 /* Launch shape of the step kernel: threads per workgroup (64, 128, 256 or
  * 512; a workgroup owns threads-4 columns) and rows swept per workgroup

@@ -41,7 +41,8 @@ class _Params(C.Structure):
                 ("bc_y", C.c_int), ("kappa", C.c_double), ("s_c", C.c_double),
                 ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double),
                 ("s_nu", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
-                ("scale_by_phi", C.c_int), ("use_penalty", C.c_int)]
+                ("scale_by_phi", C.c_int), ("use_penalty", C.c_int),
+                ("beta", C.POINTER(C.c_double)), ("usx", C.c_double), ("usy", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -138,7 +139,7 @@ class Oracle:
 
     def __init__(self, nx, ny, phi, kappa=0.5, rates=None, g=(0.0, 0.0),
                  scale_by_phi=True, bc_x="periodic", bc_y="periodic", mask=None,
-                 force=None, penalty=True):
+                 force=None, penalty=True, drag=None):
         r = dict(s_c=1.0, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=1.2)
         if rates:
             r.update(rates)
@@ -148,6 +149,10 @@ class Oracle:
                          float(g[1]), 1 if scale_by_phi else 0, 1 if penalty else 0)
         shp = (self.ny, self.nx)
         self.phi = _f64(phi, shp)
+        if drag is not None:  # (beta field, (usx, usy)): F^B -= phi beta (u - u_s)
+            self.beta = _f64(drag[0], shp)
+            self.p.beta = _dp(self.beta)
+            self.p.usx, self.p.usy = float(drag[1][0]), float(drag[1][1])
         self.mask = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
         if force is None:
             self.fx = self.fy = None

@@ -81,6 +81,11 @@ typedef struct {
   double gx, gy;   /* uniform external acceleration G */
   int scale_by_phi;/* 1: F^B = phi*G (+F_ext); 0: F^B = G (+F_ext) */
   int use_penalty; /* 1: penalty source C of Eq. (20); 0: ablation (tests) */
+  /* Linear drag towards a solid velocity u_s: F^B gains -phi*beta*(u - u_s)
+   * (the Darcy term of Eq. (21), beta = phi*nu/k0, and the particle drag of
+   * Eq. (23), beta = phi*(1 - phi)).  NULL: no drag. */
+  const double *beta;
+  double usx, usy;
 } vo_params;
 
 /* ---- small exported helpers (used by the identity tests) ----------------- */
@@ -301,10 +306,20 @@ static void macroscopic_tab(const vo_params *P, const vo_nbr *T,
       double FBx = sc * P->gx, FBy = sc * P->gy;
       if (fext_x) FBx += fext_x[c];
       if (fext_y) FBy += fext_y[c];
-      Fx = Fpx + FBx;
-      Fy = Fpy + FBy;
-      ux = (jx[c] + 0.5 * Fx) / m0[c];
-      uy = (jy[c] + 0.5 * Fy) / m0[c];
+      if (P->beta) {
+        /* F depends on u through the drag: u = (j + F/2)/m0 with
+         * F = F^p + F^B - phi beta (u - u_s), solved for u in closed form */
+        const double d = phi[c] * P->beta[c];
+        ux = (jx[c] + 0.5 * (Fpx + FBx + d * P->usx)) / (m0[c] + 0.5 * d);
+        uy = (jy[c] + 0.5 * (Fpy + FBy + d * P->usy)) / (m0[c] + 0.5 * d);
+        Fx = Fpx + FBx - d * (ux - P->usx);
+        Fy = Fpy + FBy - d * (uy - P->usy);
+      } else {
+        Fx = Fpx + FBx;
+        Fy = Fpy + FBy;
+        ux = (jx[c] + 0.5 * Fx) / m0[c];
+        uy = (jy[c] + 0.5 * Fy) / m0[c];
+      }
     }
     if (m0_out) m0_out[c] = m0[c];
     if (rho_out) rho_out[c] = rho[c];

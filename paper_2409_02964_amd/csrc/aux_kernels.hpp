@@ -25,6 +25,8 @@ struct Geo {
   long long plane;
 };
 
+constexpr int NOBS = 5;  // observables per reduction record
+
 // Rest-state population f^rest_i = f^eq_i(rho0, 0) of Eq. (14) at a node
 // of void fraction phi.
 template <typename T>
@@ -169,15 +171,17 @@ __global__ void moments_rho(Geo G, const S* __restrict__ buf, const T* __restric
 
 // Pass 2: grad rho (Eq. 10 with mirror images at walls), F, u, p; optional
 // FP64 block partials of the observables.
-template <typename S, typename T, bool SHIFT, bool FFIELD>
+template <typename S, typename T, bool SHIFT, int FEAT>
 __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restrict__ phi,
                             StepPhys<T> ph, const T* __restrict__ drho, const T* __restrict__ fxf,
-                            const T* __restrict__ fyf, double* __restrict__ rho_o,
+                            const T* __restrict__ fyf, const T* __restrict__ beta,
+                            double* __restrict__ rho_o,
                             double* __restrict__ ux_o, double* __restrict__ uy_o,
-                            double* __restrict__ p_o, double* __restrict__ partials) {
+                            double* __restrict__ p_o, double* __restrict__ partials,
+                            T* __restrict__ uprev, int uprev_valid) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  double mass = 0.0, u2 = 0.0, umax = 0.0, bad = 0.0;
+  double mass = 0.0, u2 = 0.0, umax = 0.0, bad = 0.0, du2 = 0.0;
   if (x < G.nx && y < G.ny) {
     const T ph_x = phi[y * G.pitch + x];
     double m0 = 0.0, jx = 0.0, jy = 0.0;
@@ -209,64 +213,90 @@ __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restric
     const T sg = ph.scale_by_phi ? ph_x : T(1);
     T Fx = kp * grx + sg * ph.gx;
     T Fy = kp * gry + sg * ph.gy;
-    if (FFIELD) {
+    if (FEAT & FEAT_FORCE) {
       Fx += fxf[y * G.pitch + x];
       Fy += fyf[y * G.pitch + x];
     }
     const T tm0 = ph_x * ph.rho0 + dm0;
-    const T ux = (tjx + T(0.5) * Fx) / tm0;
-    const T uy = (tjy + T(0.5) * Fy) / tm0;
+    T ux, uy;
+    if (FEAT & FEAT_DRAG) {  // u of Eq. (7) with the drag solved in closed form
+      const T d = ph_x * beta[y * G.pitch + x];
+      ux = (tjx + T(0.5) * (Fx + d * ph.usx)) / (tm0 + T(0.5) * d);
+      uy = (tjy + T(0.5) * (Fy + d * ph.usy)) / (tm0 + T(0.5) * d);
+    } else {
+      ux = (tjx + T(0.5) * Fx) / tm0;
+      uy = (tjy + T(0.5) * Fy) / tm0;
+    }
     const T rho = ph.rho0 + dm0 / ph_x;
     const long long o = (long long)y * G.nx + x;
     if (rho_o) rho_o[o] = double(rho);
     if (ux_o) ux_o[o] = double(ux);
     if (uy_o) uy_o[o] = double(uy);
     if (p_o) p_o[o] = double(rho) / 3.0;
+    if (uprev) {  // |u(t) - u(t')|^2 against the velocity kept at the last call
+      T* px = uprev + (long long)y * G.pitch + x;
+      T* py = px + G.plane;
+      if (uprev_valid) {
+        const double dx = double(ux) - double(*px), dy = double(uy) - double(*py);
+        du2 = dx * dx + dy * dy;
+      }
+      *px = ux;
+      *py = uy;
+    }
     mass = m0;
     u2 = double(ux) * double(ux) + double(uy) * double(uy);
     umax = sqrt(u2);
     const bool finite = isfinite(m0) && isfinite(double(ux)) && isfinite(double(uy)) &&
                         isfinite(jx) && isfinite(jy);
     bad = finite ? 0.0 : 1.0;
-    if (!finite) { mass = 0.0; u2 = 0.0; umax = 0.0; }
+    if (!finite) { mass = 0.0; u2 = 0.0; umax = 0.0; du2 = 0.0; }
   }
   if (partials) {
     // block reduction in a fixed order: wavefront shuffles, then LDS
-    __shared__ double red[4][16];
+    __shared__ double red[NOBS][16];
     for (int off = 32; off > 0; off >>= 1) {
       mass += __shfl_down(mass, off, 64);
       u2 += __shfl_down(u2, off, 64);
       umax = fmax(umax, __shfl_down(umax, off, 64));
       bad += __shfl_down(bad, off, 64);
+      du2 += __shfl_down(du2, off, 64);
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) { red[0][wv] = mass; red[1][wv] = u2; red[2][wv] = umax; red[3][wv] = bad; }
+    if (lane == 0) {
+      red[0][wv] = mass; red[1][wv] = u2; red[2][wv] = umax; red[3][wv] = bad; red[4][wv] = du2;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       const int nw = blockDim.x >> 6;
-      double a = 0, b = 0, c = 0, d = 0;
-      for (int k = 0; k < nw; ++k) { a += red[0][k]; b += red[1][k]; c = fmax(c, red[2][k]); d += red[3][k]; }
+      double a[NOBS] = {0, 0, 0, 0, 0};
+      for (int k = 0; k < nw; ++k) {
+        a[0] += red[0][k]; a[1] += red[1][k]; a[2] = fmax(a[2], red[2][k]); a[3] += red[3][k];
+        a[4] += red[4][k];
+      }
       const long long blk = (long long)blockIdx.y * gridDim.x + blockIdx.x;
-      partials[blk * 4 + 0] = a;
-      partials[blk * 4 + 1] = b;
-      partials[blk * 4 + 2] = c;
-      partials[blk * 4 + 3] = d;
+      for (int q = 0; q < NOBS; ++q) partials[blk * NOBS + q] = a[q];
     }
   }
 }
 
-// Final fixed-order reduction of the block partials (one workgroup).
+// Fixed-order reduction of block partials, in two levels: reduce_partials
+// folds contiguous chunks (one workgroup per chunk) and is applied again to
+// the chunk results until one record is left.  Record fields: mass, sum |u|^2,
+// max |u|, non-finite count, sum |u - u_prev|^2.
 __global__ void reduce_partials(const double* __restrict__ partials, long long nblk,
-                                double* __restrict__ out) {
-  __shared__ double red[4][256];
-  double a = 0, b = 0, c = 0, d = 0;
-  for (long long k = threadIdx.x; k < nblk; k += blockDim.x) {
-    a += partials[k * 4 + 0];
-    b += partials[k * 4 + 1];
-    c = fmax(c, partials[k * 4 + 2]);
-    d += partials[k * 4 + 3];
+                                long long chunk, double* __restrict__ out) {
+  __shared__ double red[NOBS][256];
+  const long long beg = (long long)blockIdx.x * chunk;
+  const long long end = min(beg + chunk, nblk);
+  double a[NOBS] = {0, 0, 0, 0, 0};
+  for (long long k = beg + threadIdx.x; k < end; k += blockDim.x) {
+    a[0] += partials[k * NOBS + 0];
+    a[1] += partials[k * NOBS + 1];
+    a[2] = fmax(a[2], partials[k * NOBS + 2]);
+    a[3] += partials[k * NOBS + 3];
+    a[4] += partials[k * NOBS + 4];
   }
-  red[0][threadIdx.x] = a; red[1][threadIdx.x] = b; red[2][threadIdx.x] = c; red[3][threadIdx.x] = d;
+  for (int q = 0; q < NOBS; ++q) red[q][threadIdx.x] = a[q];
   __syncthreads();
   for (int s = blockDim.x / 2; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) {
@@ -274,12 +304,12 @@ __global__ void reduce_partials(const double* __restrict__ partials, long long n
       red[1][threadIdx.x] += red[1][threadIdx.x + s];
       red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + s]);
       red[3][threadIdx.x] += red[3][threadIdx.x + s];
+      red[4][threadIdx.x] += red[4][threadIdx.x + s];
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    out[0] = red[0][0]; out[1] = red[1][0]; out[2] = red[2][0]; out[3] = red[3][0];
-  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < NOBS; ++q) out[(long long)blockIdx.x * NOBS + q] = red[q][0];
 }
 
 // Speed-of-light reference with the step's memory pattern: every node pulls

@@ -55,6 +55,7 @@ struct StepPhys {
   T rest_axis, rest_diag;   // w_i kappa rho0 for |e|=1 and |e|=sqrt2
   T rest0_k;                // 5 kappa rho0 / 9 : rest_0 = phi rho0 - rest0_k
   T scale, inv_scale;       // storage scale of shifted half storage
+  T usx, usy;               // solid velocity of the linear drag
   int scale_by_phi;
 };
 
@@ -64,6 +65,7 @@ struct StepGeom {
   const void* phi;
   const void* fxf;
   const void* fyf;
+  const void* beta;  // per-node drag coefficient (F^B -= phi beta (u - u_s))
   long long plane;  // elements per population plane (= pitch * ny)
   int nx, ny, pitch;
   int strips, out_w, rows;
@@ -130,14 +132,18 @@ __device__ __forceinline__ T stencil_dy(T n, T s, T ne, T nw, T se, T sw) {
 // Eq. (17), plus phi and delta-rho of the node.
 template <typename T>
 struct RowState {
-  T dm0, jx, jy, me, mep, mqx, mqy, mpxx, mpxy, phi, drho;
+  T dm0, jx, jy, me, mep, mqx, mqy, mpxx, mpxy, phi, drho, beta;
 };
+
+// Optional features of the step (bit mask)
+enum : int { FEAT_FORCE = 1, FEAT_DRAG = 2 };
 
 // S: storage type of populations (double, float, _Float16)
 // T: arithmetic type (double, float)
 // SHIFT: memory holds deviations g (scaled by ph.scale) instead of f
 // WALLS: half-way bounce-back walls at y = -1/2 and y = ny - 1/2
-// FFIELD: add the per-node force planes to F^B
+// FEAT: FEAT_FORCE adds the per-node force planes to F^B; FEAT_DRAG adds
+//       the linear drag -phi beta (u - u_s) with u solved in closed form
 // NT: threads per workgroup (= out_w + 4 active lanes at most)
 // LDS rings over the last four rows.  Next to a wall the row beyond it is
 // filled with the mirror image (scalars copied, velocities negated), so the
@@ -152,7 +158,7 @@ struct StepLds {
 // One workgroup's tile: strip `strip` (columns strip*out_w .. +out_w-1) and
 // row block `by` (rows by*rows .. +rows-1) of the lattice described by g.
 // PD: prefetch distance in rows (1 or 2).
-template <typename S, typename T, bool SHIFT, bool WALLS, bool FFIELD, int NT, int PD>
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT, int PD>
 __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& ph, int strip,
                                           int by, StepLds<T, NT>& L) {
   auto& s_rho = L.rho;
@@ -195,7 +201,8 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
   // Issue the ten loads (nine pulled populations and phi) of row yn.  Rows
   // outside a walled domain are clamped to a valid row and never used, so
   // every load is unconditional and in bounds.
-  auto load_row = [&](int yn, S (&f)[9], T& phi) {
+  const rsrc_t betar = make_rsrc(g.beta, (FEAT & FEAT_DRAG) ? unsigned(g.plane) * TB : 0u);
+  auto load_row = [&](int yn, S (&f)[9], T& phi, T& beta) {
     int r, rs, rn;
     bool bl = false, bh = false;
     if (WALLS) {
@@ -210,6 +217,7 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       rn = (r == ny - 1) ? 0 : r + 1;
     }
     phi = bload<T>(phir, xcT, unsigned(r) * unsigned(pitch) * TB);
+    if (FEAT & FEAT_DRAG) beta = bload<T>(betar, xcT, unsigned(r) * unsigned(pitch) * TB);
     f[0] = bload<S>(srcr, xcb, poff(0, r));
     f[1] = bload<S>(srcr, xmb, poff(1, r));
     f[3] = bload<S>(srcr, xpb, poff(3, r));
@@ -225,7 +233,7 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
 
   // One sweep iteration.  A: row yn, B: row yn-1, C: row yn-2.  rA is
   // written, rB/rC are read; bNew is written by B, bOld (row yn-2) read by C.
-  auto body = [&](int k, const S (&f)[9], const T phi_in, RowState<T>& rA,
+  auto body = [&](int k, const S (&f)[9], const T phi_in, const T beta_in, RowState<T>& rA,
                   const RowState<T>& rB, const RowState<T>& rC, T (&bNew)[2],
                   const T (&bOld)[2]) {
     const int yn = y0 - 2 + k;
@@ -258,6 +266,7 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       rA.mpxx = (q[1] + q[3]) - (q[2] + q[4]);
       rA.mpxy = (q[5] + q[7]) - (q[6] + q[8]);
       rA.phi = phi;
+      rA.beta = beta_in;
       rA.drho = rA.dm0 * recip(phi);
       s_rho[slot4(yn)][t] = rA.drho;
       if (WALLS && yn == 0) s_rho[slot4(-1)][t] = rA.drho;      // image below
@@ -281,15 +290,26 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       const T sg = ph.scale_by_phi ? phi : T(1);
       T Fx = kp * grx + sg * ph.gx;
       T Fy = kp * gry + sg * ph.gy;
-      if (FFIELD) {
+      if (FEAT & FEAT_FORCE) {
         const unsigned ro = unsigned(WALLS ? yb : wrap_index(yb, ny)) * unsigned(pitch) * TB;
         Fx += bload<T>(make_rsrc(g.fxf, unsigned(g.plane) * TB), xcT, ro);
         Fy += bload<T>(make_rsrc(g.fyf, unsigned(g.plane) * TB), xcT, ro);
       }
       const T m0 = phi * rho0 + rB.dm0;
-      const T inv_m0 = recip(m0);
-      const T ux = (rB.jx + T(0.5) * Fx) * inv_m0;
-      const T uy = (rB.jy + T(0.5) * Fy) * inv_m0;
+      T ux, uy;
+      if (FEAT & FEAT_DRAG) {
+        // F = F' - phi beta (u - u_s) with u = (j + F/2)/m0: solved for u
+        const T d = phi * rB.beta;
+        const T inv = recip(m0 + T(0.5) * d);
+        ux = (rB.jx + T(0.5) * (Fx + d * ph.usx)) * inv;
+        uy = (rB.jy + T(0.5) * (Fy + d * ph.usy)) * inv;
+        Fx -= d * (ux - ph.usx);
+        Fy -= d * (uy - ph.usy);
+      } else {
+        const T inv_m0 = recip(m0);
+        ux = (rB.jx + T(0.5) * Fx) * inv_m0;
+        uy = (rB.jy + T(0.5) * Fy) * inv_m0;
+      }
       const T rho = rho0 + rB.drho;
       U4<T> a;
       U2<T> b;
@@ -414,64 +434,64 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
   T b0[2] = {0, 0}, b1[2] = {0, 0};
   if constexpr (PD == 1) {
     S fa[9], fb[9];
-    T pa, pb;
-    load_row(y0 - 2, fa, pa);
+    T pa, pb, qa = T(0), qb = T(0);
+    load_row(y0 - 2, fa, pa, qa);
     for (int k = 0; k < nit; k += 6) {
-      load_row(y0 - 1 + k, fb, pb);
-      body(k + 0, fa, pa, R0, R2, R1, b0, b1);
+      load_row(y0 - 1 + k, fb, pb, qb);
+      body(k + 0, fa, pa, qa, R0, R2, R1, b0, b1);
       if (k + 1 >= nit) break;
-      load_row(y0 + k, fa, pa);
-      body(k + 1, fb, pb, R1, R0, R2, b1, b0);
+      load_row(y0 + k, fa, pa, qa);
+      body(k + 1, fb, pb, qb, R1, R0, R2, b1, b0);
       if (k + 2 >= nit) break;
-      load_row(y0 + 1 + k, fb, pb);
-      body(k + 2, fa, pa, R2, R1, R0, b0, b1);
+      load_row(y0 + 1 + k, fb, pb, qb);
+      body(k + 2, fa, pa, qa, R2, R1, R0, b0, b1);
       if (k + 3 >= nit) break;
-      load_row(y0 + 2 + k, fa, pa);
-      body(k + 3, fb, pb, R0, R2, R1, b1, b0);
+      load_row(y0 + 2 + k, fa, pa, qa);
+      body(k + 3, fb, pb, qb, R0, R2, R1, b1, b0);
       if (k + 4 >= nit) break;
-      load_row(y0 + 3 + k, fb, pb);
-      body(k + 4, fa, pa, R1, R0, R2, b0, b1);
+      load_row(y0 + 3 + k, fb, pb, qb);
+      body(k + 4, fa, pa, qa, R1, R0, R2, b0, b1);
       if (k + 5 >= nit) break;
-      load_row(y0 + 4 + k, fa, pa);
-      body(k + 5, fb, pb, R2, R1, R0, b1, b0);
+      load_row(y0 + 4 + k, fa, pa, qa);
+      body(k + 5, fb, pb, qb, R2, R1, R0, b1, b0);
     }
   } else {
     static_assert(PD == 2, "prefetch distance 1 or 2");
     S fa[9], fb[9], fc[9];
-    T pa, pb, pc;
-    load_row(y0 - 2, fa, pa);
-    load_row(y0 - 1, fb, pb);
+    T pa, pb, pc, qa = T(0), qb = T(0), qc = T(0);
+    load_row(y0 - 2, fa, pa, qa);
+    load_row(y0 - 1, fb, pb, qb);
     for (int k = 0; k < nit; k += 6) {
-      load_row(y0 + k, fc, pc);
-      body(k + 0, fa, pa, R0, R2, R1, b0, b1);
+      load_row(y0 + k, fc, pc, qc);
+      body(k + 0, fa, pa, qa, R0, R2, R1, b0, b1);
       if (k + 1 >= nit) break;
-      load_row(y0 + 1 + k, fa, pa);
-      body(k + 1, fb, pb, R1, R0, R2, b1, b0);
+      load_row(y0 + 1 + k, fa, pa, qa);
+      body(k + 1, fb, pb, qb, R1, R0, R2, b1, b0);
       if (k + 2 >= nit) break;
-      load_row(y0 + 2 + k, fb, pb);
-      body(k + 2, fc, pc, R2, R1, R0, b0, b1);
+      load_row(y0 + 2 + k, fb, pb, qb);
+      body(k + 2, fc, pc, qc, R2, R1, R0, b0, b1);
       if (k + 3 >= nit) break;
-      load_row(y0 + 3 + k, fc, pc);
-      body(k + 3, fa, pa, R0, R2, R1, b1, b0);
+      load_row(y0 + 3 + k, fc, pc, qc);
+      body(k + 3, fa, pa, qa, R0, R2, R1, b1, b0);
       if (k + 4 >= nit) break;
-      load_row(y0 + 4 + k, fa, pa);
-      body(k + 4, fb, pb, R1, R0, R2, b0, b1);
+      load_row(y0 + 4 + k, fa, pa, qa);
+      body(k + 4, fb, pb, qb, R1, R0, R2, b0, b1);
       if (k + 5 >= nit) break;
-      load_row(y0 + 5 + k, fb, pb);
-      body(k + 5, fc, pc, R2, R1, R0, b1, b0);
+      load_row(y0 + 5 + k, fb, pb, qb);
+      body(k + 5, fc, pc, qc, R2, R1, R0, b1, b0);
     }
   }
 }
 
 // One lattice per launch: workgroup b takes strip b % strips, row block
 // b / strips.  WPE: minimum waves per SIMD the register allocation allows.
-template <typename S, typename T, bool SHIFT, bool WALLS, bool FFIELD, int NT, int PD = 1,
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT, int PD = 1,
           int WPE = (sizeof(T) == 4 ? 4 : 2)>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(WPE)))
 vanse_step_kernel(StepGeom g, StepPhys<T> ph) {
   __shared__ StepLds<T, NT> lds;
-  step_tile<S, T, SHIFT, WALLS, FFIELD, NT, PD>(g, ph, int(blockIdx.x) % g.strips,
+  step_tile<S, T, SHIFT, WALLS, FEAT, NT, PD>(g, ph, int(blockIdx.x) % g.strips,
                                                  int(blockIdx.x) / g.strips, lds);
 }
 
@@ -486,7 +506,7 @@ struct BatchEntry {
   int cur0;            // buffer holding the state before launch 0
 };
 
-template <typename S, typename T, bool SHIFT, bool WALLS, bool FFIELD, int NT,
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT,
           int WPE = (sizeof(T) == 4 ? 4 : 2)>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(WPE)))
@@ -502,7 +522,7 @@ vanse_batch_step_kernel(const BatchEntry<T>* __restrict__ entries,
   g.src = par ? b1 : b0;
   g.dst = par ? b0 : b1;
   const int local = int(blockIdx.x) - e.first_tile;
-  step_tile<S, T, SHIFT, WALLS, FFIELD, NT, 1>(g, e.ph, local % g.strips, local / g.strips, lds);
+  step_tile<S, T, SHIFT, WALLS, FEAT, NT, 1>(g, e.ph, local % g.strips, local / g.strips, lds);
 }
 
 }  // namespace vanse_dev

@@ -57,7 +57,7 @@ int compute_bytes(int precision) { return precision == VANSE_F64 ? 8 : 4; }
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
 struct Layout {
-  size_t pop[2], phi, fx, fy, drho, partials, result, badcount, total;
+  size_t pop[2], phi, fx, fy, beta, drho, uprev, partials, partials2, result, badcount, total;
   long long plane;
   int pitch;
   long long max_partials;
@@ -73,6 +73,7 @@ int make_layout(const vanse_desc* d, Layout* L) {
   }
   if (d->bc_y != VANSE_PERIODIC && d->bc_y != VANSE_WALL) return fail(VANSE_ERR_INVALID_ARG, "unknown bc_y %d", d->bc_y);
   if (d->has_force_field != 0 && d->has_force_field != 1) return fail(VANSE_ERR_INVALID_ARG, "has_force_field must be 0 or 1");
+  if (d->has_drag != 0 && d->has_drag != 1) return fail(VANSE_ERR_INVALID_ARG, "has_drag must be 0 or 1");
   const long long pitch = pitch_of(d->nx);
   const long long plane = pitch * d->ny;
   if (plane * 9 > (1LL << 31) - 1) return fail(VANSE_ERR_INVALID_ARG, "lattice too large (%d x %d)", d->nx, d->ny);
@@ -92,10 +93,14 @@ int make_layout(const vanse_desc* d, Layout* L) {
   } else {
     L->fx = L->fy = 0;
   }
+  L->beta = 0;
+  if (d->has_drag) { L->beta = off; off = align256(off + plane * cb); }
   L->drho = off; off = align256(off + plane * cb);
+  L->uprev = off; off = align256(off + 2 * plane * cb);
   L->max_partials = (long long)((d->nx + 255) / 256) * d->ny;
-  L->partials = off; off = align256(off + L->max_partials * 4 * sizeof(double));
-  L->result = off; off = align256(off + 4 * sizeof(double));
+  L->partials = off; off = align256(off + L->max_partials * NOBS * sizeof(double));
+  L->partials2 = off; off = align256(off + 1024 * NOBS * sizeof(double));
+  L->result = off; off = align256(off + NOBS * sizeof(double));
   L->badcount = off; off = align256(off + sizeof(unsigned long long));
   L->total = off;
   return VANSE_OK;
@@ -109,7 +114,8 @@ struct vanse_lattice {
   char* ws;
   int cur;  // buffer holding the current state
   int64_t t;
-  bool phi_set, params_set, state_set, ff_set;
+  bool phi_set, params_set, state_set, ff_set, drag_set, uprev_valid;
+  double usx, usy;  // solid velocity of the linear drag
   double kappa, rho0, gx, gy;
   int scale_by_phi;
   vanse_rates rates;
@@ -167,6 +173,8 @@ StepPhys<T> make_phys(const vanse_lattice* h) {
   const bool half = h->d.precision == VANSE_F16_SHIFTED;
   p.scale = T(half ? std::ldexp(1.0, h->storage_exp) : 1.0);
   p.inv_scale = T(half ? std::ldexp(1.0, -h->storage_exp) : 1.0);
+  p.usx = T(h->usx);
+  p.usy = T(h->usy);
   p.scale_by_phi = h->scale_by_phi;
   return p;
 }
@@ -181,24 +189,41 @@ Geo make_geo(const vanse_lattice* h) {
   return G;
 }
 
-template <typename S, typename T, bool SHIFT, bool WALLS, bool FF, int NT>
-void launch_step_nt(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& ph, int blocks,
-                    hipStream_t st) {
-  hipLaunchKernelGGL((vanse_step_kernel<S, T, SHIFT, WALLS, FF, NT>), dim3(blocks), dim3(NT), 0, st, g,
-                     ph);
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
+void launch_step_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((vanse_step_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(blocks), dim3(NT), 0, st, g, ph);
 }
 
-template <typename S, typename T, bool SHIFT, bool WALLS, bool FF>
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
 int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& ph, int blocks,
                   hipStream_t st) {
   switch (h->threads) {
-    case 64: launch_step_nt<S, T, SHIFT, WALLS, FF, 64>(h, g, ph, blocks, st); break;
-    case 128: launch_step_nt<S, T, SHIFT, WALLS, FF, 128>(h, g, ph, blocks, st); break;
-    case 256: launch_step_nt<S, T, SHIFT, WALLS, FF, 256>(h, g, ph, blocks, st); break;
-    case 512: launch_step_nt<S, T, SHIFT, WALLS, FF, 512>(h, g, ph, blocks, st); break;
+    case 64: launch_step_nt<S, T, SHIFT, WALLS, FEAT, 64>(g, ph, blocks, st); break;
+    case 128: launch_step_nt<S, T, SHIFT, WALLS, FEAT, 128>(g, ph, blocks, st); break;
+    case 256: launch_step_nt<S, T, SHIFT, WALLS, FEAT, 256>(g, ph, blocks, st); break;
+    case 512:
+      if constexpr (FEAT == 0) {
+        launch_step_nt<S, T, SHIFT, WALLS, FEAT, 512>(g, ph, blocks, st);
+        break;
+      }
+      return fail(VANSE_ERR_UNSUPPORTED, "512-lane workgroups are built for the plain step only");
     default: return fail(VANSE_ERR_INVALID_ARG, "unsupported workgroup width %d", h->threads);
   }
   return VANSE_OK;
+}
+
+int feat_of(const vanse_desc& d) { return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0); }
+
+// Call fn(std::integral_constant<bool, WALLS>, std::integral_constant<int, FEAT>).
+template <typename Fn>
+int by_variant(const vanse_desc& d, Fn&& fn) {
+  const bool walls = d.bc_y == VANSE_WALL;
+  switch (feat_of(d)) {
+    case 0: return walls ? fn(std::true_type{}, std::integral_constant<int, 0>{}) : fn(std::false_type{}, std::integral_constant<int, 0>{});
+    case 1: return walls ? fn(std::true_type{}, std::integral_constant<int, 1>{}) : fn(std::false_type{}, std::integral_constant<int, 1>{});
+    case 2: return walls ? fn(std::true_type{}, std::integral_constant<int, 2>{}) : fn(std::false_type{}, std::integral_constant<int, 2>{});
+    default: return walls ? fn(std::true_type{}, std::integral_constant<int, 3>{}) : fn(std::false_type{}, std::integral_constant<int, 3>{});
+  }
 }
 
 template <typename S, typename T, bool SHIFT>
@@ -208,6 +233,7 @@ int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
   g.phi = h->ws + h->L.phi;
   g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
   g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
+  g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
   g.plane = h->L.plane;
   g.nx = h->d.nx;
   g.ny = h->d.ny;
@@ -217,18 +243,12 @@ int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
   g.rows = h->rows;
   const int nby = (h->d.ny + g.rows - 1) / g.rows;
   const int blocks = g.strips * nby;
-  const bool walls = h->d.bc_y == VANSE_WALL;
-  const bool ff = h->d.has_force_field != 0;
   for (int64_t s = 0; s < n; ++s) {
     g.src = h->ws + h->L.pop[h->cur];
     g.dst = h->ws + h->L.pop[h->cur ^ 1];
-    int rc;
-    if (walls)
-      rc = ff ? launch_step_w<S, T, SHIFT, true, true>(h, g, ph, blocks, st)
-              : launch_step_w<S, T, SHIFT, true, false>(h, g, ph, blocks, st);
-    else
-      rc = ff ? launch_step_w<S, T, SHIFT, false, true>(h, g, ph, blocks, st)
-              : launch_step_w<S, T, SHIFT, false, false>(h, g, ph, blocks, st);
+    const int rc = by_variant(h->d, [&](auto walls, auto feat) -> int {
+      return launch_step_w<S, T, SHIFT, decltype(walls)::value, decltype(feat)::value>(h, g, ph, blocks, st);
+    });
     if (rc != VANSE_OK) return rc;
     h->cur ^= 1;
     h->t += 1;
@@ -260,6 +280,7 @@ int check_ready(const vanse_lattice* h) {
   if (!h->phi_set) return fail(VANSE_ERR_STATE, "void fraction not set");
   if (!h->params_set) return fail(VANSE_ERR_STATE, "kappa and rates not set");
   if (h->d.has_force_field && !h->ff_set) return fail(VANSE_ERR_STATE, "force field not set");
+  if (h->d.has_drag && !h->drag_set) return fail(VANSE_ERR_STATE, "drag field not set");
   return VANSE_OK;
 }
 
@@ -292,7 +313,8 @@ int vanse_create(const vanse_desc* d, void* workspace, size_t bytes, vanse_latti
   h->ws = static_cast<char*>(workspace);
   h->cur = 0;
   h->t = 0;
-  h->phi_set = h->params_set = h->state_set = h->ff_set = false;
+  h->phi_set = h->params_set = h->state_set = h->ff_set = h->drag_set = h->uprev_valid = false;
+  h->usx = h->usy = 0.0;
   h->kappa = 0.5;
   h->rho0 = 1.0;
   h->gx = h->gy = 0.0;
@@ -378,6 +400,25 @@ int vanse_set_force_field(vanse_lattice* h, const double* fx, const double* fy, 
   return VANSE_OK;
 }
 
+int vanse_set_drag(vanse_lattice* h, const double* beta, double usx, double usy, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->d.has_drag) return fail(VANSE_ERR_STATE, "lattice was created without drag");
+  if (!beta) return fail(VANSE_ERR_INVALID_ARG, "beta is NULL");
+  if (!std::isfinite(usx) || !std::isfinite(usy)) return fail(VANSE_ERR_INVALID_ARG, "u_s must be finite");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  void* dst = h->ws + h->L.beta;
+  if (h->d.precision == VANSE_F64)
+    hipLaunchKernelGGL(convert_field<double>, field_grid(h), dim3(256), 0, st, beta, (double*)dst, h->d.nx, h->d.ny, h->L.pitch);
+  else
+    hipLaunchKernelGGL(convert_field<float>, field_grid(h), dim3(256), 0, st, beta, (float*)dst, h->d.nx, h->d.ny, h->L.pitch);
+  HIP_TRY(hipGetLastError());
+  h->usx = usx;
+  h->usy = usy;
+  h->drag_set = true;
+  h->version += 1;
+  return VANSE_OK;
+}
+
 static int fill(vanse_lattice* h, const double* fin, double rho0, double ux0, double uy0, void* stream) {
   if (int rc = check_ready(h)) return rc;
   if (!(rho0 > 0.0) || !std::isfinite(rho0)) return fail(VANSE_ERR_INVALID_ARG, "rho0 must be positive");
@@ -399,6 +440,7 @@ static int fill(vanse_lattice* h, const double* fin, double rho0, double ux0, do
   h->cur = 0;
   h->t = 0;
   h->state_set = true;
+  h->uprev_valid = false;
   h->version += 1;
   return VANSE_OK;
 }
@@ -426,7 +468,7 @@ int vanse_step(vanse_lattice* h, int64_t nsteps, void* stream) {
 }
 
 static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double* p, bool partials,
-                   void* stream) {
+                   void* stream, bool keep_u = false) {
   if (int rc = check_ready(h)) return rc;
   if (!h->state_set) return fail(VANSE_ERR_STATE, "populations not initialised");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -443,13 +485,15 @@ static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double
     double* part = partials ? (double*)(h->ws + h->L.partials) : nullptr;
     const T* fx = h->d.has_force_field ? (const T*)(h->ws + h->L.fx) : nullptr;
     const T* fy = h->d.has_force_field ? (const T*)(h->ws + h->L.fy) : nullptr;
-    if (h->d.has_force_field)
-      hipLaunchKernelGGL((moments_out<S, T, SH, true>), field_grid(h), dim3(256), 0, st, G, buf, phi, ph,
-                         drho, fx, fy, rho, ux, uy, p, part);
-    else
-      hipLaunchKernelGGL((moments_out<S, T, SH, false>), field_grid(h), dim3(256), 0, st, G, buf, phi,
-                         ph, drho, fx, fy, rho, ux, uy, p, part);
-    return VANSE_OK;
+    const T* beta = h->d.has_drag ? (const T*)(h->ws + h->L.beta) : nullptr;
+    return by_variant(h->d, [&](auto walls, auto feat) -> int {
+      (void)walls;
+      T* up = keep_u ? (T*)(h->ws + h->L.uprev) : nullptr;
+      hipLaunchKernelGGL((moments_out<S, T, SH, decltype(feat)::value>), field_grid(h), dim3(256), 0, st, G,
+                         buf, phi, ph, drho, fx, fy, beta, rho, ux, uy, p, part, up,
+                         (int)(keep_u && h->uprev_valid));
+      return VANSE_OK;
+    });
   });
   if (rc) return rc;
   HIP_TRY(hipGetLastError());
@@ -481,17 +525,47 @@ int vanse_read_populations(vanse_lattice* h, double* f, void* stream) {
   return VANSE_OK;
 }
 
+// Reduce the block partials of the last moments pass to one record and copy
+// it to the host (synchronizes the stream).
+static int reduce_to_host(vanse_lattice* h, double* rec, hipStream_t st) {
+  long long n = (long long)((h->d.nx + 255) / 256) * h->d.ny;
+  const double* in = (const double*)(h->ws + h->L.partials);
+  double* mid = (double*)(h->ws + h->L.partials2);
+  double* res = (double*)(h->ws + h->L.result);
+  // level 1: at most 1024 chunks; level 2: one workgroup
+  const long long chunk = (n + 1023) / 1024;
+  const long long nchunks = (n + chunk - 1) / chunk;
+  hipLaunchKernelGGL(reduce_partials, dim3((unsigned)nchunks), dim3(256), 0, st, in, n, chunk, mid);
+  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, (const double*)mid, nchunks, nchunks, res);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(rec, res, NOBS * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return VANSE_OK;
+}
+
 int vanse_observe(vanse_lattice* h, double* out, void* stream) {
   if (!out) return fail(VANSE_ERR_INVALID_ARG, "out is NULL");
   if (int rc = moments(h, nullptr, nullptr, nullptr, nullptr, true, stream)) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const long long nblk = (long long)((h->d.nx + 255) / 256) * h->d.ny;
-  double* res = (double*)(h->ws + h->L.result);
-  hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, (const double*)(h->ws + h->L.partials), nblk, res);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(out, res, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
+  double rec[NOBS];
+  if (int rc = reduce_to_host(h, rec, st)) return rc;
+  for (int q = 0; q < 4; ++q) out[q] = rec[q];
   if (out[3] > 0) return fail(VANSE_ERR_DIVERGED, "%.0f nodes hold non-finite values at t = %lld", out[3], (long long)h->t);
+  return VANSE_OK;
+}
+
+int vanse_residual(vanse_lattice* h, double* out, void* stream) {
+  if (!out) return fail(VANSE_ERR_INVALID_ARG, "out is NULL");
+  const bool had_prev = h && h->uprev_valid;
+  if (int rc = moments(h, nullptr, nullptr, nullptr, nullptr, true, stream, true)) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double rec[NOBS];
+  if (int rc = reduce_to_host(h, rec, st)) return rc;
+  h->uprev_valid = true;
+  out[0] = had_prev ? rec[4] : -1.0;
+  out[1] = rec[1];
+  out[2] = rec[3];
+  if (rec[3] > 0) return fail(VANSE_ERR_DIVERGED, "%.0f nodes hold non-finite values at t = %lld", rec[3], (long long)h->t);
   return VANSE_OK;
 }
 
@@ -594,8 +668,9 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, std::
   for (int k = 0; k < n; ++k) {
     if (!lats[k]) return fail(VANSE_ERR_INVALID_ARG, "lattice %d is NULL", k);
     const vanse_desc& d = lats[k]->d;
-    if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field)
-      return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary or force field", k);
+    if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field ||
+        d.has_drag != d0.has_drag)
+      return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary, force field or drag", k);
     strip_rows += (long long)((d.nx + out_w - 1) / out_w) * d.ny;
   }
   int r = rows;
@@ -635,6 +710,7 @@ void fill_entries(vanse_batch* b, std::vector<char>* blob) {
     g.phi = h->ws + h->L.phi;
     g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
     g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
+    g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
     g.plane = h->L.plane;
     g.nx = h->d.nx;
     g.ny = h->d.ny;
@@ -674,37 +750,31 @@ int batch_upload(vanse_batch* b, hipStream_t st) {
   return VANSE_OK;
 }
 
-template <typename S, typename T, bool SHIFT, bool WALLS, bool FF>
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
 void batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
   const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
   const int* TL = reinterpret_cast<const int*>(b->ws + b->tiles_off);
   switch (b->threads) {
     case 64:
-      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FF, 64>), dim3(b->total_tiles), dim3(64), 0, st, E, TL, launch);
+      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FEAT, 64>), dim3(b->total_tiles), dim3(64), 0, st, E, TL, launch);
       break;
     case 128:
-      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FF, 128>), dim3(b->total_tiles), dim3(128), 0, st, E, TL, launch);
+      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FEAT, 128>), dim3(b->total_tiles), dim3(128), 0, st, E, TL, launch);
       break;
     default:
-      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FF, 256>), dim3(b->total_tiles), dim3(256), 0, st, E, TL, launch);
+      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FEAT, 256>), dim3(b->total_tiles), dim3(256), 0, st, E, TL, launch);
   }
 }
 
 int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
-  const vanse_desc& d = b->lats[0]->d;
-  const bool walls = d.bc_y == VANSE_WALL, ff = d.has_force_field != 0;
   return by_precision(b->lats[0], [&](auto* s_tag, auto* t_tag, auto shift) -> int {
     using S = std::remove_pointer_t<decltype(s_tag)>;
     using T = std::remove_pointer_t<decltype(t_tag)>;
     constexpr bool SH = decltype(shift)::value;
-    if (walls) {
-      if (ff) batch_launch_t<S, T, SH, true, true>(b, launch, st);
-      else batch_launch_t<S, T, SH, true, false>(b, launch, st);
-    } else {
-      if (ff) batch_launch_t<S, T, SH, false, true>(b, launch, st);
-      else batch_launch_t<S, T, SH, false, false>(b, launch, st);
-    }
-    return VANSE_OK;
+    return by_variant(b->lats[0]->d, [&](auto walls, auto feat) -> int {
+      batch_launch_t<S, T, SH, decltype(walls)::value, decltype(feat)::value>(b, launch, st);
+      return VANSE_OK;
+    });
   });
 }
 

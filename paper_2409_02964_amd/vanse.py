@@ -29,9 +29,10 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4:
 
 EXPORTS = [
     "vanse_workspace_bytes", "vanse_create", "vanse_destroy", "vanse_set_params",
-    "vanse_set_body_force", "vanse_set_void_fraction", "vanse_set_force_field",
+    "vanse_set_body_force", "vanse_set_void_fraction", "vanse_set_force_field", "vanse_set_drag",
     "vanse_init_equilibrium", "vanse_set_populations", "vanse_step", "vanse_read_moments",
-    "vanse_read_populations", "vanse_observe", "vanse_set_tiling", "vanse_get_tiling",
+    "vanse_read_populations", "vanse_observe", "vanse_residual", "vanse_set_tiling",
+    "vanse_get_tiling",
     "vanse_set_storage_exponent", "vanse_stream_copy", "vanse_time", "vanse_error_string",
     "vanse_last_error", "vanse_batch_workspace_bytes", "vanse_batch_create", "vanse_batch_destroy",
     "vanse_batch_set_graph", "vanse_batch_step", "vanse_batch_tiles",
@@ -50,7 +51,8 @@ class Diverged(VanseError):
 
 class Desc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32),
-                ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("has_force_field", C.c_int32)]
+                ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("has_force_field", C.c_int32),
+                ("has_drag", C.c_int32)]
 
 
 class Rates(C.Structure):
@@ -80,12 +82,14 @@ def lib():
                 "vanse_set_body_force": [vp, d, d, i32],
                 "vanse_set_void_fraction": [vp, vp, vp],
                 "vanse_set_force_field": [vp, vp, vp, vp],
+                "vanse_set_drag": [vp, vp, d, d, vp],
                 "vanse_init_equilibrium": [vp, d, d, d, vp],
                 "vanse_set_populations": [vp, vp, d, vp],
                 "vanse_step": [vp, i64, vp],
                 "vanse_read_moments": [vp, vp, vp, vp, vp, vp],
                 "vanse_read_populations": [vp, vp, vp],
                 "vanse_observe": [vp, pd, vp],
+                "vanse_residual": [vp, pd, vp],
                 "vanse_set_tiling": [vp, i32, i32],
                 "vanse_get_tiling": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
                 "vanse_set_storage_exponent": [vp, i32],
@@ -120,8 +124,10 @@ def check(rc):
     return rc
 
 
-def workspace_bytes(nx, ny, precision="f64", bc_y="periodic", force_field=False) -> int:
-    desc = Desc(int(nx), int(ny), PRECISION[precision], 0, BC[bc_y], int(bool(force_field)))
+def workspace_bytes(nx, ny, precision="f64", bc_y="periodic", force_field=False,
+                    drag=False) -> int:
+    desc = Desc(int(nx), int(ny), PRECISION[precision], 0, BC[bc_y], int(bool(force_field)),
+                int(bool(drag)))
     n = C.c_size_t()
     check(lib().vanse_workspace_bytes(C.byref(desc), C.byref(n)))
     return n.value
@@ -138,13 +144,13 @@ class Lattice:
     """One lattice whose device state lives in a torch-allocated workspace."""
 
     def __init__(self, nx, ny, precision="f64", bc_y="periodic", force_field=False,
-                 device=None, workspace=None):
+                 device=None, workspace=None, drag=False):
         import torch
         self.nx, self.ny = int(nx), int(ny)
         self.precision = precision
         self.device = torch.device(device or "cuda")
         self.desc = Desc(self.nx, self.ny, PRECISION[precision], 0, BC[bc_y],
-                         int(bool(force_field)))
+                         int(bool(force_field)), int(bool(drag)))
         nbytes = C.c_size_t()
         check(lib().vanse_workspace_bytes(C.byref(self.desc), C.byref(nbytes)))
         if workspace is None:
@@ -197,6 +203,14 @@ class Lattice:
         check(lib().vanse_set_force_field(self.handle, C.c_void_p(a.data_ptr()),
                                           C.c_void_p(b.data_ptr()), _stream(stream)))
         self._keep = (a, b)
+        return self
+
+    def set_drag(self, beta, us=(0.0, 0.0), stream=None):
+        """F^B -= phi beta (u - u_s) with a per-node beta (ny, nx)."""
+        b = self._field(beta, (self.ny, self.nx))
+        check(lib().vanse_set_drag(self.handle, C.c_void_p(b.data_ptr()), float(us[0]),
+                                   float(us[1]), _stream(stream)))
+        self._keep_beta = b
         return self
 
     def init_equilibrium(self, rho0=1.0, ux0=0.0, uy0=0.0, stream=None):
@@ -255,6 +269,13 @@ class Lattice:
         check(lib().vanse_read_populations(self.handle, C.c_void_p(out.data_ptr()),
                                            _stream(stream)))
         return out
+
+    def residual(self, stream=None):
+        """(sum |u - u_prev|^2 or None on the first call, sum |u|^2, nonfinite):
+        u_prev is the velocity at the previous call."""
+        buf = (C.c_double * 3)()
+        check(lib().vanse_residual(self.handle, buf, _stream(stream)))
+        return (None if buf[0] < 0 else buf[0]), buf[1], int(buf[2])
 
     def observe(self, stream=None, raise_on_diverged=True):
         """dict(mass, u2, umax, nonfinite) reduced in FP64 on the device."""

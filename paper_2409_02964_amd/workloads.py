@@ -150,3 +150,51 @@ def mms_case(case: str, n: int, a: float, b: float, us: float, nu: float, t: flo
     else:
         raise ValueError(f"unknown manufactured case {case!r}")
     return dict(phi=phi, ux=ux, uy=uy, fx=fx, fy=fy)
+
+
+def inclusion_phi(L: int, rng, rmin: float = 5.0, rmax: float = 50.0, fill: float = 0.15,
+                  lo: float = 0.35, width: float = 2.0):
+    """Periodic L x L void fraction with tanh-edged circular inclusions:
+    phi = 1 - (1 - lo) max_k 1/2 (1 - tanh((d_k - r_k)/width)), radii
+    r_k ~ U[rmin, rmax], count ceil(fill L^2 / (pi rbar^2)), uniform centres,
+    periodic distance d_k.  Each inclusion is evaluated on a window around it."""
+    rbar = 0.5 * (rmin + rmax)
+    count = int(math.ceil(fill * L * L / (math.pi * rbar * rbar)))
+    m = np.zeros((L, L))
+    for _ in range(count):
+        r = rng.uniform(rmin, rmax)
+        cx, cy = rng.uniform(0, L, 2)
+        h = int(min(L // 2, math.ceil(r + 10 * width)))
+        xs = np.arange(int(cx) - h, int(cx) + h + 1)
+        ys = np.arange(int(cy) - h, int(cy) + h + 1)
+        if len(xs) > L:
+            xs = np.arange(L)
+        if len(ys) > L:
+            ys = np.arange(L)
+        dx = xs[None, :] - cx
+        dy = ys[:, None] - cy
+        dx = dx - L * np.round(dx / L)
+        dy = dy - L * np.round(dy / L)
+        v = 0.5 * (1 - np.tanh((np.sqrt(dx * dx + dy * dy) - r) / width))
+        iy = np.mod(ys, L)[:, None]
+        ix = np.mod(xs, L)[None, :]
+        m[iy, ix] = np.maximum(m[iy, ix], v)
+    return 1.0 - (1.0 - lo) * m
+
+
+def served_requests(count: int = 40, rate: float = 4.0, seed: int = 5, lmin: int = 64,
+                    lmax: int = 2048, beta0: float = 2e-3, beta1: float = 1e-2, g: float = 1e-6):
+    """Solve requests for the serving loop: Poisson arrivals at `rate` per
+    second; each a periodic L x L lattice, L = round(exp U(ln lmin, ln lmax)),
+    with an inclusion void fraction (inclusion_phi), body force G = g along x
+    and a linear drag beta = beta0 + beta1 (1 - phi) (background drag keeps a
+    steady state reachable on a periodic domain)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += rng.exponential(1.0 / rate)
+        L = int(round(math.exp(rng.uniform(math.log(lmin), math.log(lmax)))))
+        phi = inclusion_phi(L, rng)
+        out.append(dict(rid=k, L=L, arrival=t, phi=phi, beta=beta0 + beta1 * (1.0 - phi), g=g))
+    return out

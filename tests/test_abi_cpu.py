@@ -49,7 +49,7 @@ def test_workspace_bytes_scales_with_precision():
     (60000, 60000, 1, 0, 0, 0, -1),
 ])
 def test_bad_descriptors_are_rejected(nx, ny, prec, bcx, bcy, ff, code):
-    d = V.Desc(nx, ny, prec, bcx, bcy, ff)
+    d = V.Desc(nx, ny, prec, bcx, bcy, ff, 0)
     n = C.c_size_t()
     assert V.lib().vanse_workspace_bytes(C.byref(d), C.byref(n)) == code
     assert V.lib().vanse_last_error()
@@ -58,7 +58,7 @@ def test_bad_descriptors_are_rejected(nx, ny, prec, bcx, bcy, ff, code):
 def _fake_handle(nx=64, ny=48, prec=0, bcy=0):
     """A handle over a fake, aligned device address: only host-side calls
     (no HIP work) may be made on it."""
-    d = V.Desc(nx, ny, prec, 0, bcy, 0)
+    d = V.Desc(nx, ny, prec, 0, bcy, 0, 0)
     n = C.c_size_t()
     V.check(V.lib().vanse_workspace_bytes(C.byref(d), C.byref(n)))
     h = C.c_void_p()

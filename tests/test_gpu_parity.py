@@ -271,3 +271,69 @@ def test_full_size_channel_one_step_fp32(oracle):
     _say(f"full-size fp32 one step: max rel err {err:.3e}")
     # FP32 storage of f ~ 0.5 and FP32 arithmetic: a few units of 2^-24
     assert err <= 2e-6
+
+
+# ---- linear drag and the residual observable ---------------------------------------
+
+@pytest.mark.parametrize("bc", ["periodic", "wall"])
+def test_one_step_drag_fp64(oracle, bc):
+    torch = _torch()
+    from paper_2409_02964_amd.vanse import Lattice
+    nx, ny = 77, 41
+    phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 3.0, seed=21) ** 2
+    beta = 1e-3 + 0.2 * W.smoothed_noise(nx, ny, 2.0, seed=22) ** 2
+    us = (1e-3, -4e-4)
+    f0 = W.random_populations(nx, ny, seed=23)
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=(2e-5, 0), bc_y=bc,
+                        drag=(beta, us))
+    ora.set_populations(f0)
+    ora.step(1)
+    lat = Lattice(nx, ny, precision="f64", bc_y=bc, drag=True)
+    lat.set_params(0.5, C1_RATES).set_body_force(2e-5, 0).set_void_fraction(phi)
+    lat.set_drag(beta, us).set_populations(torch.from_numpy(f0)).step(1)
+    fg = lat.read_populations().cpu().numpy()
+    assert np.max(np.abs(fg - ora.f)) <= 1e-14 * np.max(np.abs(ora.f))
+    ref = ora.macroscopic()
+    m = to_np(lat.read_moments())
+    assert rel_l2_u(m, ref) <= 1e-13
+
+
+def test_particle_flow_drag_fp64(oracle):
+    """Eq. (23) flow, 3000 steps, GPU FP64 against the oracle."""
+    _torch()
+    from paper_2409_02964_amd.vanse import Lattice
+    L, a, G = 100, 0.3, 1e-6
+    x = np.arange(L)[None, :] * np.ones((5, 1))
+    phi = 1 + a * (np.sin(2 * np.pi * x / L) - 1)
+    rates = dict(s_c=1.0, s_e=1 / 0.6, s_eps=1.2, s_q=1.4, s_nu=1.25)
+    ora = oracle.Oracle(L, 5, phi, kappa=0.4, rates=rates, g=(G, 0.0),
+                        drag=(phi * (1 - phi), (0.0, 0.0))).init_equilibrium()
+    ora.step(3000)
+    lat = Lattice(L, 5, precision="f64", drag=True)
+    lat.set_params(0.4, rates).set_body_force(G, 0).set_void_fraction(phi)
+    lat.set_drag(phi * (1 - phi)).init_equilibrium().step(3000)
+    m, ref = to_np(lat.read_moments()), ora.macroscopic()
+    # The velocities here are ~5e-6 (u = G/(a phi)), three decades below the
+    # 1e-3 scale at which the FP64 bound of 1e-12 relative is stated; FP64
+    # rounding of O(0.1) populations accumulates to ~sqrt(N) 2^-53 |f| ~ 1e-15
+    # absolute, so the bound is stated as an rms absolute error.
+    rms = math.sqrt(np.mean((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2))
+    _say(f"particle flow t=3000: rms |du| {rms:.3e}, rel-L2 {rel_l2_u(m, ref):.3e}")
+    assert rms <= 1e-15
+
+
+def test_residual_observable_matches_moments():
+    _torch()
+    phi = W.channel_phi(96, 64, seed=5)
+    lat = gpu_lattice(96, 64, phi, "f64", "wall", g=(1e-5, 0)).init_equilibrium()
+    lat.step(10)
+    first = lat.residual()
+    assert first[0] is None
+    m0 = to_np(lat.read_moments())
+    lat.step(1)
+    du2, u2, bad = lat.residual()
+    m1 = to_np(lat.read_moments())
+    ref = np.sum((m1["ux"] - m0["ux"]) ** 2 + (m1["uy"] - m0["uy"]) ** 2)
+    assert bad == 0
+    assert abs(du2 - ref) <= 1e-9 * ref
+    assert abs(u2 - np.sum(m1["ux"] ** 2 + m1["uy"] ** 2)) <= 1e-12 * u2

@@ -392,3 +392,48 @@ def _mms_at(case, n, a, b, us, nu, px, py, t):
     finally:
         WW._mms_coords = orig
     return {k: float(np.asarray(v).ravel()[0]) for k, v in m.items()}
+
+
+# ---- P9: linear drag -----------------------------------------------------------
+
+def _brinkman_error(oracle, H, phi, Da, nu=0.1, G=1e-6):
+    nx = 4
+    k0 = Da * H * H
+    lam = math.sqrt(phi / k0)
+    d = np.arange(H)[:, None] + 0.5
+    exact = G * k0 / (phi * nu) * (1 - np.cosh(lam * (d - H / 2)) / math.cosh(lam * H / 2)) \
+        * np.ones((1, nx))
+    o = oracle.Oracle(nx, H, np.full((H, nx), phi), kappa=min(0.5, phi), rates=rates_for(nu),
+                      g=(G, 0.0), bc_y="wall", drag=(np.full((H, nx), phi * nu / k0), (0, 0)))
+    o.init_fields(np.ones((H, nx)), exact, np.zeros((H, nx)))
+    o.step(20000)
+    u = o.macroscopic()["ux"]
+    return math.sqrt(np.sum((u - exact) ** 2) / np.sum(exact ** 2))
+
+
+@pytest.mark.parametrize("phi,Da", [(0.3, 1e-2), (0.5, 1e-3)])
+def test_brinkman_channel_second_order(oracle, phi, Da):
+    """Porous Poiseuille flow (Eq. 21, Eq. 22 case I) with
+    F^B = phi (G - phi nu u / k0), i.e. drag coefficient beta = phi nu / k0."""
+    e25 = _brinkman_error(oracle, 25, phi, Da)
+    e50 = _brinkman_error(oracle, 50, phi, Da)
+    assert e50 < 3e-3
+    assert 1.7 < math.log(e25 / e50, 2) < 2.3
+
+
+@pytest.mark.parametrize("a", [0.15, 0.3, 0.45])
+def test_particle_flow_eq23(oracle, a):
+    """Steady 1-D flow through phi = 1 + a (sin(2 pi x/L) - 1) with the drag of
+    Eq. (23) (u_s = 0): u = G / (a phi) to leading order (viscous stresses
+    neglected), which exercises F^p of Eq. (13) in a varying void fraction."""
+    L, G = 100, 1e-6
+    x = np.arange(L)[None, :] * np.ones((5, 1))
+    phi = 1 + a * (np.sin(2 * np.pi * x / L) - 1)
+    o = oracle.Oracle(L, 5, phi, kappa=min(0.5, 1 - 2 * a), rates=rates_for(0.1), g=(G, 0.0),
+                      drag=(phi * (1 - phi), (0.0, 0.0)))
+    exact = G / (a * phi)
+    o.init_fields(np.ones_like(phi), exact, np.zeros_like(phi))
+    o.step(40000)
+    m = o.macroscopic()
+    assert math.sqrt(np.sum((m["ux"] - exact) ** 2) / np.sum(exact ** 2)) < 5e-3
+    assert np.max(np.abs(m["uy"])) < 1e-3 * np.max(exact)
