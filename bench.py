@@ -163,6 +163,72 @@ def served_bench(count: int, rate: float, budget_gib: float):
     return out
 
 
+def precision_ladder(n: int, steps: int, out_md: str):
+    """Precision ladder on an n x n channel (the benchmark channel's
+    generator: walls, tanh phi step + noise, seed 2409, G = 1e-7): the FP64
+    oracle against the GPU in FP64, FP32, FP32-shifted and FP16-shifted
+    storage after `steps` steps; writes a short report to `out_md`."""
+    import math
+    import numpy as np
+    import torch
+    from oracle import oracle as O
+    from paper_2409_02964_amd import workloads as W
+    from paper_2409_02964_amd.vanse import Lattice
+
+    def rel(a, b):
+        return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b ** 2)))
+
+    phi = W.channel_phi(n, n, seed=2409)
+    o = O.Oracle(n, n, phi, kappa=KAPPA, rates=RATES, g=(G, 0.0), bc_y="wall").init_equilibrium()
+    t0 = time.perf_counter()
+    chunk = max(1, steps // 20)
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        o.step(k)
+        done += k
+        print(f"oracle {n}x{n}: {done}/{steps} steps, {time.perf_counter() - t0:.0f} s", flush=True)
+    t_oracle = time.perf_counter() - t0
+    ref = o.macroscopic()
+    rows = []
+    for prec in ("f64", "f32", "f32s", "f16s"):
+        lat = Lattice(n, n, precision=prec, bc_y="wall")
+        lat.set_params(KAPPA, RATES).set_body_force(G, 0.0).set_void_fraction(phi)
+        lat.init_equilibrium(1.0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lat.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        m = {k: v.cpu().numpy() for k, v in lat.read_moments().items()}
+        eu = math.sqrt(float(np.sum((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2))
+                       / float(np.sum(ref["ux"] ** 2 + ref["uy"] ** 2)))
+        rows.append((prec, BYTES_PER_NODE[prec], eu, rel(m["p"], ref["p"]),
+                     rel(m["p"] - m["p"].mean(), ref["p"] - ref["p"].mean()),
+                     n * n * steps / dt / 1e6))
+        print(f"{prec}: rel-L2 u {eu:.3e}", flush=True)
+        lat.close()
+    threads = os.environ.get("OMP_NUM_THREADS", str(os.cpu_count()))
+    lines = [f"# Precision ladder: {n}x{n} channel, {steps} steps", "",
+             "Command (from the repository root):", "", "```",
+             f"python bench.py --precision-ladder {n} --ladder-steps {steps}", "```", "",
+             f"Workload: walls in y, G = {G} (F^B = phi G), phi = tanh step 0.4 -> 1.0 + smoothed "
+             f"noise 0.05 (seed 2409), kappa = {KAPPA}, s_nu = 0.8, other rates 1.2, rho0 = 1, "
+             "from rest.  Reference: the FP64 CPU oracle "
+             f"({t_oracle:.0f} s on {threads} OpenMP threads).", "",
+             "| storage | bytes/node | rel-L2(u) | rel-L2(p) | rel-L2(p - <p>) | MLUPS |",
+             "|---|---|---|---|---|---|"]
+    for prec, b, eu, ep, epd, ml in rows:
+        lines.append(f"| {prec} | {b} | {eu:.3e} | {ep:.3e} | {epd:.3e} | {ml:.0f} |")
+    lines += ["", "f64: FP64 arithmetic and storage; f32: FP32 arithmetic and storage of f; "
+              "f32s: FP32 arithmetic, FP32 storage of the deviations from the rest state; "
+              "f16s: FP32 arithmetic, FP16 storage of the deviations scaled by 2^12.  The "
+              "MLUPS column is a single wall-clock run of this size (the populations of "
+              "the smaller formats fit in the 256 MB last-level cache)."]
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    return rows
+
+
 def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
     """Turn rocprofv3 CSV output (a kernel-trace --stats run in prof_dir/trace,
     --pmc FETCH_SIZE in prof_dir/fetch, --pmc WRITE_SIZE in prof_dir/write)
@@ -255,7 +321,15 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="summarize rocprofv3 CSVs in DIR/{trace,fetch,write} into profiles/")
+    ap.add_argument("--precision-ladder", type=int, metavar="N", default=0,
+                    help="run the precision ladder on an N x N channel and write profiles/")
+    ap.add_argument("--ladder-steps", type=int, default=5000)
     args = ap.parse_args()
+    if args.precision_ladder:
+        n = args.precision_ladder
+        precision_ladder(n, args.ladder_steps,
+                         os.path.join(ROOT, "profiles", f"precision_ladder_channel{n}.md"))
+        return
     if args.summarize_profile:
         cmds = open(os.path.join(args.summarize_profile, "commands.txt")).read()
         summarize_profile(args.summarize_profile,

@@ -26,11 +26,12 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc: -O3 without fast-math, no FMA contraction."""
+    """Compile the oracle with gcc: -O3 without fast-math, no FMA contraction,
+    OpenMP over nodes (thread count from OMP_NUM_THREADS)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call([
-            "gcc", "-O3", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+            "gcc", "-O3", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
             "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB

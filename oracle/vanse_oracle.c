@@ -13,7 +13,9 @@
  * paper states the scheme (Sec. 2.3), the 9x9 matrices of Eq. (A1) applied as
  * plain matrix-vector products, push streaming into a fresh array, no fusion,
  * no blocking.  Build with -O3 -ffp-contract=off and without -ffast-math,
- * so there is no FMA contraction and no reassociation.
+ * so there is no FMA contraction and no reassociation.  The per-node loops
+ * may run on several OpenMP threads; no loop reduces across nodes, so the
+ * results do not depend on the thread count.
  *
  * Layout: every field is row-major [ny][nx], index y*nx + x.  Populations
  * are nine such planes, plane i at f + i*nx*ny.  The state held between
@@ -222,6 +224,7 @@ static int nbr_build(const vo_params *P, const unsigned char *mask, vo_nbr *T) {
   T->idx = malloc((size_t)9 * N * sizeof(int));
   T->sgn = malloc((size_t)9 * N);
   if (!T->idx || !T->sgn) return -1;
+#pragma omp parallel for schedule(static)
   for (int y = 0; y < P->ny; ++y)
     for (int x = 0; x < P->nx; ++x)
       for (int i = 0; i < 9; ++i) {
@@ -244,6 +247,7 @@ static void gradient_tab(const vo_params *P, const unsigned char *mask,
                          const vo_nbr *T, const double *psi, int odd,
                          double *gx, double *gy) {
   const int N = P->nx * P->ny;
+#pragma omp parallel for schedule(static)
   for (int c = 0; c < N; ++c) {
     if (is_solid(mask, c)) {
       gx[c] = 0.0;
@@ -269,20 +273,49 @@ void vo_gradient(const vo_params *P, const unsigned char *mask,
   nbr_free(&T);
 }
 
+/* Work arrays of one step, allocated once per run. */
+typedef struct {
+  double *m0, *rho, *ux, *uy, *Fx, *Fy, *rux, *ruy, *mux, *muy, *d, *tmp;
+  double *jx, *jy, *grx, *gry;
+} vo_work;
+
+static void work_free(vo_work *W) {
+  free(W->m0); free(W->rho); free(W->ux); free(W->uy); free(W->Fx); free(W->Fy);
+  free(W->rux); free(W->ruy); free(W->mux); free(W->muy); free(W->d); free(W->tmp);
+  free(W->jx); free(W->jy); free(W->grx); free(W->gry);
+}
+
+static int work_alloc(int N, vo_work *W) {
+  const size_t b = (size_t)N * sizeof(double);
+  W->m0 = malloc(b); W->rho = malloc(b); W->ux = malloc(b); W->uy = malloc(b);
+  W->Fx = malloc(b); W->Fy = malloc(b); W->rux = malloc(b); W->ruy = malloc(b);
+  W->mux = malloc(b); W->muy = malloc(b); W->d = malloc(8 * b); W->tmp = malloc(b);
+  W->jx = malloc(b); W->jy = malloc(b); W->grx = malloc(b); W->gry = malloc(b);
+  if (!W->m0 || !W->rho || !W->ux || !W->uy || !W->Fx || !W->Fy || !W->rux ||
+      !W->ruy || !W->mux || !W->muy || !W->d || !W->tmp || !W->jx || !W->jy ||
+      !W->grx || !W->gry) {
+    work_free(W);
+    return -1;
+  }
+  return 0;
+}
+
 /* ---- macroscopic fields, Eq. (7) with the force of Eq. (13) ---------------
  * rho = sum f / phi; grad rho by Eq. (10); F = (kappa - phi) cs^2 grad rho +
  * F^B; u = (sum e f + F/2) / sum f; p = rho cs^2.  Any output may be NULL. */
-static void macroscopic_tab(const vo_params *P, const vo_nbr *T,
+static void macroscopic_tab(const vo_params *P, const vo_nbr *T, vo_work *W,
                             const double *phi, const unsigned char *mask,
                             const double *fext_x, const double *fext_y,
                             const double *f, double *m0_out, double *rho_out,
                             double *ux_out, double *uy_out, double *Fx_out,
                             double *Fy_out, double *p_out) {
   const int N = P->nx * P->ny;
-  double *m0 = calloc(N, sizeof(double)), *rho = calloc(N, sizeof(double));
-  double *jx = calloc(N, sizeof(double)), *jy = calloc(N, sizeof(double));
-  double *grx = calloc(N, sizeof(double)), *gry = calloc(N, sizeof(double));
+  /* the m0 and rho arrays double as outputs when the caller provides them */
+  double *m0 = m0_out ? m0_out : W->tmp, *rho = rho_out ? rho_out : W->rho;
+  double *jx = W->jx, *jy = W->jy, *grx = W->grx, *gry = W->gry;
+#pragma omp parallel for schedule(static)
   for (int c = 0; c < N; ++c) {
+    m0[c] = rho[c] = jx[c] = jy[c] = 0.0;
     if (is_solid(mask, c)) continue;
     double s = 0.0, sx = 0.0, sy = 0.0;
     for (int i = 0; i < 9; ++i) {
@@ -297,6 +330,7 @@ static void macroscopic_tab(const vo_params *P, const vo_nbr *T,
     rho[c] = s / phi[c];
   }
   gradient_tab(P, mask, T, rho, 0, grx, gry);
+#pragma omp parallel for schedule(static)
   for (int c = 0; c < N; ++c) {
     double ux = 0.0, uy = 0.0, Fx = 0.0, Fy = 0.0;
     if (!is_solid(mask, c)) {
@@ -329,7 +363,6 @@ static void macroscopic_tab(const vo_params *P, const vo_nbr *T,
     if (Fy_out) Fy_out[c] = Fy;
     if (p_out) p_out[c] = rho[c] * CS2;
   }
-  free(m0); free(rho); free(jx); free(jy); free(grx); free(gry);
 }
 
 void vo_macroscopic(const vo_params *P, const double *phi,
@@ -338,31 +371,28 @@ void vo_macroscopic(const vo_params *P, const double *phi,
                     double *rho_out, double *ux_out, double *uy_out,
                     double *Fx_out, double *Fy_out, double *p_out) {
   vo_nbr T;
+  vo_work W;
+  if (work_alloc(P->nx * P->ny, &W) != 0) return;
   if (nbr_build(P, mask, &T) == 0)
-    macroscopic_tab(P, &T, phi, mask, fext_x, fext_y, f, m0_out, rho_out,
+    macroscopic_tab(P, &T, &W, phi, mask, fext_x, fext_y, f, m0_out, rho_out,
                     ux_out, uy_out, Fx_out, Fy_out, p_out);
   nbr_free(&T);
+  work_free(&W);
 }
 
 /* ---- one time step, Eq. (16) followed by streaming ------------------------
  * f: post-stream populations at t; fout receives those at t+1.  phi_next,
  * mask, fext_x, fext_y may be NULL.  Returns 0, or -1 on allocation failure. */
-static int step_tab(const vo_params *P, const vo_nbr *Tp, const double *phi,
-                    const double *phi_next, const unsigned char *mask,
-                    const double *fext_x, const double *fext_y,
-                    const double *f, double *fout) {
+static int step_tab(const vo_params *P, const vo_nbr *Tp, vo_work *W,
+                    const double *phi, const double *phi_next,
+                    const unsigned char *mask, const double *fext_x,
+                    const double *fext_y, const double *f, double *fout) {
   const int nx = P->nx, ny = P->ny, N = nx * ny;
-  double *m0 = malloc(N * sizeof(double)), *rho = malloc(N * sizeof(double));
-  double *ux = malloc(N * sizeof(double)), *uy = malloc(N * sizeof(double));
-  double *Fx = malloc(N * sizeof(double)), *Fy = malloc(N * sizeof(double));
+  double *m0 = W->m0, *rho = W->rho, *ux = W->ux, *uy = W->uy, *Fx = W->Fx,
+         *Fy = W->Fy;
   /* product fields and their eight derivatives (O4-O5) */
-  double *rux = malloc(N * sizeof(double)), *ruy = malloc(N * sizeof(double));
-  double *mux = malloc(N * sizeof(double)), *muy = malloc(N * sizeof(double));
-  double *d = malloc((size_t)8 * N * sizeof(double));
-  double *tmp = malloc(N * sizeof(double));
-  if (!m0 || !rho || !ux || !uy || !Fx || !Fy || !rux || !ruy || !mux ||
-      !muy || !d || !tmp)
-    return -1;
+  double *rux = W->rux, *ruy = W->ruy, *mux = W->mux, *muy = W->muy, *d = W->d,
+         *tmp = W->tmp;
   double *d_rux_x = d, *d_ruy_y = d + N, *d_ux_x = d + 2 * (size_t)N,
          *d_uy_y = d + 3 * (size_t)N, *d_uy_x = d + 4 * (size_t)N,
          *d_ux_y = d + 5 * (size_t)N, *d_mux_x = d + 6 * (size_t)N,
@@ -371,10 +401,11 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, const double *phi,
   const vo_nbr T = *Tp;
 
   /* O1-O3: rho, F = F^p + F^B, u (Eq. 7, Eq. 13) */
-  macroscopic_tab(P, &T, phi, mask, fext_x, fext_y, f, m0, rho, ux, uy, Fx,
+  macroscopic_tab(P, &T, W, phi, mask, fext_x, fext_y, f, m0, rho, ux, uy, Fx,
                   Fy, NULL);
 
   /* O4: node-wise product fields */
+#pragma omp parallel for schedule(static)
   for (int c = 0; c < N; ++c) {
     rux[c] = rho[c] * ux[c];
     ruy[c] = rho[c] * uy[c];
@@ -393,8 +424,11 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, const double *phi,
   const double s[9] = {P->s_c, P->s_e, P->s_eps, P->s_c, P->s_q,
                        P->s_c, P->s_q, P->s_nu, P->s_nu};
 
-  for (size_t k = 0; k < (size_t)9 * N; ++k) fout[k] = 0.0;
+#pragma omp parallel for schedule(static)
+  for (long k = 0; k < 9L * N; ++k) fout[k] = 0.0;
 
+  /* every (target node, direction) of fout is written by exactly one source */
+#pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       const int c = y * nx + x;
@@ -452,8 +486,6 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, const double *phi,
       }
     }
 
-  free(m0); free(rho); free(ux); free(uy); free(Fx); free(Fy);
-  free(rux); free(ruy); free(mux); free(muy); free(d); free(tmp);
   return 0;
 }
 
@@ -461,9 +493,15 @@ int vo_step(const vo_params *P, const double *phi, const double *phi_next,
             const unsigned char *mask, const double *fext_x,
             const double *fext_y, const double *f, double *fout) {
   vo_nbr T;
-  if (nbr_build(P, mask, &T) != 0) return -1;
-  const int rc = step_tab(P, &T, phi, phi_next, mask, fext_x, fext_y, f, fout);
+  vo_work W;
+  if (work_alloc(P->nx * P->ny, &W) != 0) return -1;
+  if (nbr_build(P, mask, &T) != 0) {
+    work_free(&W);
+    return -1;
+  }
+  const int rc = step_tab(P, &T, &W, phi, phi_next, mask, fext_x, fext_y, f, fout);
   nbr_free(&T);
+  work_free(&W);
   return rc;
 }
 
@@ -498,13 +536,25 @@ int vo_run(const vo_params *P, const double *phi, const unsigned char *mask,
   const size_t n9 = (size_t)9 * P->nx * P->ny;
   double *g = malloc(n9 * sizeof(double));
   vo_nbr T;
-  if (!g || nbr_build(P, mask, &T) != 0) return -1;
-  int rc = 0;
-  for (long t = 0; t < nsteps && rc == 0; ++t) {
-    rc = step_tab(P, &T, phi, NULL, mask, fext_x, fext_y, f, g);
-    if (rc == 0) memcpy(f, g, n9 * sizeof(double));
+  vo_work W;
+  if (!g || work_alloc(P->nx * P->ny, &W) != 0) {
+    free(g);
+    return -1;
   }
+  if (nbr_build(P, mask, &T) != 0) {
+    work_free(&W);
+    free(g);
+    return -1;
+  }
+  int rc = 0;
+  double *a = f, *b = g; /* alternate the two arrays; the result ends in f */
+  for (long t = 0; t < nsteps && rc == 0; ++t) {
+    rc = step_tab(P, &T, &W, phi, NULL, mask, fext_x, fext_y, a, b);
+    double *tmp = a; a = b; b = tmp;
+  }
+  if (rc == 0 && a != f) memcpy(f, a, n9 * sizeof(double));
   nbr_free(&T);
+  work_free(&W);
   free(g);
   return rc;
 }

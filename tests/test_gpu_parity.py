@@ -337,3 +337,24 @@ def test_residual_observable_matches_moments():
     assert bad == 0
     assert abs(du2 - ref) <= 1e-9 * ref
     assert abs(u2 - np.sum(m1["ux"] ** 2 + m1["uy"] ** 2)) <= 1e-12 * u2
+
+
+def test_precision_ladder_channel(oracle):
+    """256x256 channel (walls, tanh + noise phi, G = 1e-7 scaled up to 1e-5 so
+    1000 steps carry a clear signal): FP64 meets the FP64 bound, shifted FP32
+    storage beats plain FP32 storage, FP16 shifted storage stays within its
+    11-bit mantissa (rel-L2(u) of a few 1e-3 per 1e3 steps)."""
+    _torch()
+    n, steps = 256, 1000
+    phi = W.channel_phi(n, n, seed=2409)
+    ora = oracle_lattice(oracle, n, n, phi, "wall", g=(1e-5, 0)).init_equilibrium()
+    ora.step(steps)
+    ref = ora.macroscopic()
+    err = {}
+    for prec in ("f64", "f32", "f32s", "f16s"):
+        lat = gpu_lattice(n, n, phi, prec, "wall", g=(1e-5, 0)).init_equilibrium().step(steps)
+        err[prec] = rel_l2_u(to_np(lat.read_moments()), ref)
+    _say("ladder 256^2 x 1000: " + ", ".join(f"{k} {v:.3e}" for k, v in err.items()))
+    assert err["f64"] <= 1e-12
+    assert err["f32s"] <= 2e-4 and err["f32s"] < err["f32"]
+    assert err["f16s"] <= 3e-2
