@@ -73,6 +73,8 @@ def lib():
             L.vo_init_fields.argtypes = [P, _D, _U8, _D, _D, _D, _D]
             L.vo_run.argtypes = [P, _D, _U8, _D, _D, _D, C.c_long]
             L.vo_run.restype = C.c_int
+            L.vo_set_threads.argtypes = [C.c_int]
+            L.vo_threads.restype = C.c_int
             _lib = L
     return _lib
 
@@ -88,6 +90,12 @@ def _f64(a, shape=None):
     if shape is not None:
         a = np.broadcast_to(a, shape).copy() if a.shape != shape else a
     return a
+
+
+def set_threads(n: int) -> int:
+    """Use n OpenMP threads for the per-node loops; returns the count in use."""
+    lib().vo_set_threads(int(n))
+    return lib().vo_threads()
 
 
 def tables():

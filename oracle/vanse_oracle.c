@@ -45,6 +45,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ---- lattice constants, Eq. (5) ------------------------------------------ */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -89,6 +92,23 @@ typedef struct {
   const double *beta;
   double usx, usy;
 } vo_params;
+
+/* ---- threads ------------------------------------------------------------- */
+void vo_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int vo_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ---- small exported helpers (used by the identity tests) ----------------- */
 
