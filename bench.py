@@ -313,7 +313,7 @@ def main():
     ap.add_argument("--rows", type=int, default=TILING[1])
     ap.add_argument("--sol-steps", type=int, default=200,
                     help="launches of the same-pattern copy kernel (0: skip)")
-    ap.add_argument("--cpu-steps", type=int, default=10,
+    ap.add_argument("--cpu-steps", type=int, default=100,
                     help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2000,
                     help="steps of the batched 256-lattice workload (0: skip)")
