@@ -70,6 +70,8 @@ typedef struct {
   int32_t bc_y;            /* VANSE_PERIODIC | VANSE_WALL */
   int32_t has_force_field; /* 1: a per-node force field is added to F^B */
   int32_t has_drag;        /* 1: a per-node linear drag acts (vanse_set_drag) */
+  int32_t has_mask;        /* 1: solid nodes given by vanse_set_mask */
+  int32_t dynamic_phi;     /* 1: phi may change in time (vanse_set_void_fraction_next) */
 } vanse_desc;
 
 /* Diagonal of Gamma in Eq. (16), each in (0, 2):
@@ -82,8 +84,9 @@ typedef struct {
 } vanse_rates;
 
 /* Bytes of device workspace the lattice described by *d needs (256-byte
- * aligned).  Layout: two population buffers, phi, optional force planes, a
- * density scratch plane and reduction space. */
+ * aligned).  Layout: two population buffers, phi, optional phi(t+1),
+ * solid-flag, force and drag planes, a density scratch plane and reduction
+ * space. */
 int vanse_workspace_bytes(const vanse_desc *d, size_t *bytes);
 
 /* Create a lattice whose device state lives in `workspace` (device pointer,
@@ -106,6 +109,25 @@ int vanse_set_body_force(vanse_lattice *h, double gx, double gy,
 /* Void fraction phi: device float64 [ny][nx], each value in (0, 1]
  * (checked; VANSE_ERR_INVALID_ARG otherwise).  Synchronizes the stream. */
 int vanse_set_void_fraction(vanse_lattice *h, const double *phi, void *stream);
+
+/* Time-varying void fraction (Sec. 2.3, Eq. 20): phi(x, t+1) for the next
+ * step, device float64 [ny][nx] in (0, 1] (solid nodes excepted).  The next
+ * vanse_step call must advance exactly one step; it evaluates the d_t phi
+ * term of C_a with the forward difference phi(t+1) - phi(t) and then makes
+ * phi(t+1) the current void fraction.  Without a pending phi(t+1) the void
+ * fraction is held constant.  Needs dynamic_phi; synchronizes the stream. */
+int vanse_set_void_fraction_next(vanse_lattice *h, const double *phi_next,
+                                 void *stream);
+
+/* Solid nodes (Sec. 2.3 and Sec. 3.1: half-way bounce-back on their faces):
+ * device uint8 [ny][nx], nonzero = solid.  A fluid node pulls the opposite
+ * population of its own post-collision state from a solid neighbour's
+ * direction, and the Eq. (10) stencils use the centre node's value for a
+ * solid neighbour (negated for velocity-like fields); solid nodes report
+ * zero moments and populations and are left out of the observables.  Their
+ * phi is not used (any value is accepted there).  Needs has_mask; only
+ * before the populations are set; synchronizes the stream. */
+int vanse_set_mask(vanse_lattice *h, const uint8_t *mask, void *stream);
 
 /* Per-node force added to F^B (e.g. the manufactured-solution forces of
  * Appendix C): device float64 [ny][nx] each.  Needs has_force_field. */
@@ -188,7 +210,9 @@ int vanse_stream_copy(vanse_lattice *h, int64_t n, void *stream);
  * while the batch exists.  The batch keeps a table of the members'
  * parameters and buffer parity in a caller-owned device workspace; it is
  * written again automatically when a member changed or was stepped on its
- * own.  Member handles stay usable (vanse_time, vanse_read_*). */
+ * own.  Member handles stay usable (vanse_time, vanse_read_*).  Lattices with
+ * a mask or a time-varying void fraction are not batched
+ * (VANSE_ERR_UNSUPPORTED). */
 typedef struct vanse_batch vanse_batch;
 
 /* Workspace bytes for a batch of n lattices with the given workgroup width

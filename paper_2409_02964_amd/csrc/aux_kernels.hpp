@@ -61,9 +61,17 @@ __device__ __forceinline__ double decode(S s, T phi, int i, const StepPhys<T>& p
   return double(static_cast<T>(s));
 }
 
+// Solid flags of a node (0 without a mask); bit layout as FEAT_MASK.
+__device__ __forceinline__ unsigned nbr_at(const Geo& G, const uint16_t* __restrict__ nbr, int x,
+                                           int y) {
+  return nbr ? unsigned(nbr[(long long)y * G.pitch + x]) : 0u;
+}
+
 // Receiving node of stored slot (x, y, i): (x + e_i, y + e_i) or, across a
-// wall, (x, y) with direction opp(i).  Returns false for the wall case.
-__device__ __forceinline__ bool receiver(const Geo& G, int x, int y, int i, int* xr, int* yr) {
+// wall or onto a solid node (flag bit i), (x, y) with direction opp(i).
+// Returns false for the bounce-back case.
+__device__ __forceinline__ bool receiver(const Geo& G, int x, int y, int i, unsigned nb, int* xr,
+                                         int* yr) {
   int xn = x + kEX[i];
   int yn = y + kEY[i];
   xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
@@ -72,8 +80,38 @@ __device__ __forceinline__ bool receiver(const Geo& G, int x, int y, int i, int*
   } else {
     yn = yn < 0 ? yn + G.ny : (yn >= G.ny ? yn - G.ny : yn);
   }
+  if (i > 0 && solid_bit(nb, i)) { *xr = x; *yr = y; return false; }
   *xr = xn; *yr = yn;
   return true;
+}
+
+// Solid flags (FEAT_MASK layout) from a dense uint8 mask, nonzero = solid:
+// bit 0 the node, bit i the node standing in for x + e_i, which across a wall
+// is its mirror image in the first or last row.  Counts solid nodes.
+__global__ void build_nbr(Geo G, const uint8_t* __restrict__ mask, uint16_t* __restrict__ nbr,
+                          unsigned long long* __restrict__ nsolid) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  unsigned b = mask[(long long)y * G.nx + x] ? 1u : 0u;
+  for (int i = 1; i < 9; ++i) {
+    int xn = x + kEX[i], yn = y + kEY[i];
+    xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
+    if (G.walls) yn = yn < 0 ? -1 - yn : (yn >= G.ny ? 2 * G.ny - 1 - yn : yn);
+    else yn = yn < 0 ? yn + G.ny : (yn >= G.ny ? yn - G.ny : yn);
+    if (mask[(long long)yn * G.nx + xn]) b |= 1u << i;
+  }
+  nbr[(long long)y * G.pitch + x] = (uint16_t)b;
+  if (b & 1u) atomicAdd(nsolid, 1ull);
+}
+
+// phi = 1 on solid nodes (a finite placeholder; never enters a fluid node).
+template <typename T>
+__global__ void phi_on_solids(Geo G, T* __restrict__ phi, const uint16_t* __restrict__ nbr) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  if (nbr[(long long)y * G.pitch + x] & 1u) phi[(long long)y * G.pitch + x] = T(1);
 }
 
 // Convert a dense float64 field to a pitched plane of T.
@@ -85,13 +123,16 @@ __global__ void convert_field(const double* __restrict__ in, T* __restrict__ out
   if (x < nx && y < ny) out[y * pitch + x] = static_cast<T>(in[y * nx + x]);
 }
 
-// Count entries of a dense field outside (0, 1] (or non-finite).
-__global__ void count_bad_phi(const double* __restrict__ in, long long n,
+// Count entries of a dense field outside (0, 1] (or non-finite), solid
+// nodes (flag bit 0 of nbr, when given) excepted.
+__global__ void count_bad_phi(const double* __restrict__ in, int nx, long long n,
+                              const uint16_t* __restrict__ nbr, int pitch,
                               unsigned long long* __restrict__ bad) {
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const long long stride = (long long)gridDim.x * blockDim.x;
   unsigned long long cnt = 0;
   for (; i < n; i += stride) {
+    if (nbr && (nbr[(i / nx) * pitch + i % nx] & 1u)) continue;
     const double v = in[i];
     if (!(v > 0.0 && v <= 1.0)) ++cnt;
   }
@@ -103,14 +144,22 @@ __global__ void count_bad_phi(const double* __restrict__ in, long long n,
 template <typename S, typename T, bool SHIFT>
 __global__ void fill_state(Geo G, S* __restrict__ buf, const T* __restrict__ phi, StepPhys<T> ph,
                            const double* __restrict__ fin, double rho_init, double ux0, double uy0,
-                           double kappa) {
+                           double kappa, const uint16_t* __restrict__ nbr) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= G.nx || y >= G.ny) return;
   const long long N = (long long)G.nx * G.ny;
+  const unsigned nb = nbr_at(G, nbr, x, y);
+  if (nb & 1u) {  // solid node: the rest state (never pulled by a fluid node)
+    const T ph_x = phi[y * G.pitch + x];
+    for (int i = 0; i < 9; ++i)
+      buf[i * G.plane + (long long)y * G.pitch + x] =
+          encode<S, T, SHIFT>(double(rest_pop(i, ph_x, ph)), ph_x, i, ph);
+    return;
+  }
   for (int i = 0; i < 9; ++i) {
     int xr, yr;
-    const bool through = receiver(G, x, y, i, &xr, &yr);
+    const bool through = receiver(G, x, y, i, nb, &xr, &yr);
     const int j = through ? i : kOPP[i];  // population index at the receiver
     const T phr = phi[yr * G.pitch + xr];
     double f;
@@ -124,15 +173,16 @@ __global__ void fill_state(Geo G, S* __restrict__ buf, const T* __restrict__ phi
 }
 
 // Pull the populations of the current time: f_i(x) = slot_i(x - e_i), or
-// slot_opp(i)(x) when x - e_i is beyond a wall.
+// slot_opp(i)(x) when x - e_i is beyond a wall or solid (flag bit opp(i)).
 template <typename S, typename T, bool SHIFT>
 __device__ __forceinline__ double pull_one(const Geo& G, const S* __restrict__ buf, T phi_x,
-                                           const StepPhys<T>& ph, int x, int y, int i) {
+                                           const StepPhys<T>& ph, int x, int y, int i,
+                                           unsigned nb) {
   int xs = x - kEX[i];
   int ys = y - kEY[i];
   int slot = i;
   xs = xs < 0 ? xs + G.nx : (xs >= G.nx ? xs - G.nx : xs);
-  if (G.walls && (ys < 0 || ys >= G.ny)) {
+  if ((G.walls && (ys < 0 || ys >= G.ny)) || (i > 0 && solid_bit(nb, kOPP[i]))) {
     xs = x; ys = y; slot = kOPP[i];
   } else {
     ys = ys < 0 ? ys + G.ny : (ys >= G.ny ? ys - G.ny : ys);
@@ -141,36 +191,43 @@ __device__ __forceinline__ double pull_one(const Geo& G, const S* __restrict__ b
   return decode<S, T, SHIFT>(s, phi_x, i, ph);  // rest_i depends on phi only for i = 0
 }
 
+// Populations f_i(x, t); zero on solid nodes.
 template <typename S, typename T, bool SHIFT>
 __global__ void read_pops(Geo G, const S* __restrict__ buf, const T* __restrict__ phi,
-                          StepPhys<T> ph, double* __restrict__ out) {
+                          StepPhys<T> ph, double* __restrict__ out,
+                          const uint16_t* __restrict__ nbr) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= G.nx || y >= G.ny) return;
   const long long N = (long long)G.nx * G.ny;
   const T ph_x = phi[y * G.pitch + x];
+  const unsigned nb = nbr_at(G, nbr, x, y);
   for (int i = 0; i < 9; ++i)
-    out[i * N + (long long)y * G.nx + x] = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i);
+    out[i * N + (long long)y * G.nx + x] =
+        (nb & 1u) ? 0.0 : pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i, nb);
 }
 
 // Pass 1 of the macroscopic read-out: delta rho (in T) to a scratch plane.
 template <typename S, typename T, bool SHIFT>
 __global__ void moments_rho(Geo G, const S* __restrict__ buf, const T* __restrict__ phi,
-                            StepPhys<T> ph, T* __restrict__ drho_out) {
+                            StepPhys<T> ph, T* __restrict__ drho_out,
+                            const uint16_t* __restrict__ nbr) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= G.nx || y >= G.ny) return;
   const T ph_x = phi[y * G.pitch + x];
+  const unsigned nb = nbr_at(G, nbr, x, y);
   T dm0 = 0;
   for (int i = 0; i < 9; ++i) {
-    const double f = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i);
+    const double f = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i, nb);
     dm0 += static_cast<T>(f - double(rest_pop(i, ph_x, ph)));
   }
-  drho_out[y * G.pitch + x] = dm0 / ph_x;
+  drho_out[y * G.pitch + x] = (nb & 1u) ? T(0) : dm0 / ph_x;
 }
 
-// Pass 2: grad rho (Eq. 10 with mirror images at walls), F, u, p; optional
-// FP64 block partials of the observables.
+// Pass 2: grad rho (Eq. 10 with mirror images at walls and centre values for
+// solid neighbours), F, u, p; optional FP64 block partials of the
+// observables.  Solid nodes report zeros and are left out of the partials.
 template <typename S, typename T, bool SHIFT, int FEAT>
 __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restrict__ phi,
                             StepPhys<T> ph, const T* __restrict__ drho, const T* __restrict__ fxf,
@@ -178,17 +235,25 @@ __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restric
                             double* __restrict__ rho_o,
                             double* __restrict__ ux_o, double* __restrict__ uy_o,
                             double* __restrict__ p_o, double* __restrict__ partials,
-                            T* __restrict__ uprev, int uprev_valid) {
+                            T* __restrict__ uprev, int uprev_valid,
+                            const uint16_t* __restrict__ nbr) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   double mass = 0.0, u2 = 0.0, umax = 0.0, bad = 0.0, du2 = 0.0;
-  if (x < G.nx && y < G.ny) {
+  const unsigned nb = (x < G.nx && y < G.ny) ? nbr_at(G, nbr, x, y) : 0u;
+  if (x < G.nx && y < G.ny && (nb & 1u)) {
+    const long long o = (long long)y * G.nx + x;
+    if (rho_o) rho_o[o] = 0.0;
+    if (ux_o) ux_o[o] = 0.0;
+    if (uy_o) uy_o[o] = 0.0;
+    if (p_o) p_o[o] = 0.0;
+  } else if (x < G.nx && y < G.ny) {
     const T ph_x = phi[y * G.pitch + x];
     double m0 = 0.0, jx = 0.0, jy = 0.0;
     T dm0 = 0;
     T f[9];
     for (int i = 0; i < 9; ++i) {
-      const double fi = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i);
+      const double fi = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i, nb);
       f[i] = static_cast<T>(fi - double(rest_pop(i, ph_x, ph)));
       m0 += fi;
     }
@@ -196,9 +261,12 @@ __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restric
     T tjx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
     T tjy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
     jx = tjx; jy = tjy;
-    // neighbours of delta-rho; mirror image across walls
-    auto R = [&](int dx, int dy) -> T {
-      int xn = x + dx, yn = y + dy;
+    // neighbours of delta-rho (direction i of Eq. 5); mirror image across
+    // walls, the centre value for a solid neighbour
+    const T rc = drho[y * G.pitch + x];
+    auto R = [&](int i) -> T {
+      if (solid_bit(nb, i)) return rc;
+      int xn = x + kEX[i], yn = y + kEY[i];
       xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
       if (G.walls) {
         yn = yn < 0 ? 0 : (yn >= G.ny ? G.ny - 1 : yn);
@@ -207,19 +275,19 @@ __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restric
       }
       return drho[yn * G.pitch + xn];
     };
-    const T grx = stencil_dx(R(1, 0), R(-1, 0), R(1, 1), R(1, -1), R(-1, 1), R(-1, -1));
-    const T gry = stencil_dy(R(0, 1), R(0, -1), R(1, 1), R(-1, 1), R(1, -1), R(-1, -1));
+    const T grx = stencil_dx(R(1), R(3), R(5), R(8), R(6), R(7));
+    const T gry = stencil_dy(R(2), R(4), R(5), R(6), R(8), R(7));
     const T kp = (ph.kappa - ph_x) * T(1.0 / 3.0);
     const T sg = ph.scale_by_phi ? ph_x : T(1);
     T Fx = kp * grx + sg * ph.gx;
     T Fy = kp * gry + sg * ph.gy;
-    if (FEAT & FEAT_FORCE) {
+    if ((FEAT & FEAT_FORCE) && fxf) {
       Fx += fxf[y * G.pitch + x];
       Fy += fyf[y * G.pitch + x];
     }
     const T tm0 = ph_x * ph.rho0 + dm0;
     T ux, uy;
-    if (FEAT & FEAT_DRAG) {  // u of Eq. (7) with the drag solved in closed form
+    if ((FEAT & FEAT_DRAG) && beta) {  // u of Eq. (7) with the drag solved in closed form
       const T d = ph_x * beta[y * G.pitch + x];
       ux = (tjx + T(0.5) * (Fx + d * ph.usx)) / (tm0 + T(0.5) * d);
       uy = (tjy + T(0.5) * (Fy + d * ph.usy)) / (tm0 + T(0.5) * d);

@@ -10,6 +10,9 @@
 //   m = M f, m+ = m - Gamma (m - m^eq) + (I - Gamma/2)(S + C)
 //                                                        (Eq. 16-19)
 //   f+ = M^-1 m+                                         (Eq. A1)
+// Optional: a per-node force field, a linear drag, a time-varying void
+// fraction (the d_t phi term of Eq. 20) and solid nodes (bounce-back on
+// their faces and the centre-value stand-in of Eq. 10 next to them).
 //
 // Work layout: one workgroup owns a strip of `out_w` columns plus two halo
 // columns on each side (one lane per column) and sweeps a block of rows
@@ -66,6 +69,8 @@ struct StepGeom {
   const void* fxf;
   const void* fyf;
   const void* beta;  // per-node drag coefficient (F^B -= phi beta (u - u_s))
+  const void* phin;  // phi(t+1) (time-varying void fraction; = phi when static)
+  const void* nbr;   // uint16 solid flags per node (see FEAT_MASK), or null
   long long plane;  // elements per population plane (= pitch * ny)
   int nx, ny, pitch;
   int strips, out_w, rows;
@@ -106,6 +111,9 @@ template <>
 __device__ __forceinline__ _Float16 bload<_Float16>(rsrc_t r, unsigned voff, unsigned soff) {
   return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
 }
+__device__ __forceinline__ unsigned bload_u16(rsrc_t r, unsigned voff, unsigned soff) {
+  return unsigned(__builtin_bit_cast(unsigned short, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+}
 __device__ __forceinline__ void bstore(float v, rsrc_t r, unsigned voff, unsigned soff) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
@@ -132,11 +140,31 @@ __device__ __forceinline__ T stencil_dy(T n, T s, T ne, T nw, T se, T sw) {
 // Eq. (17), plus phi and delta-rho of the node.
 template <typename T>
 struct RowState {
-  T dm0, jx, jy, me, mep, mqx, mqy, mpxx, mpxy, phi, drho, beta;
+  T dm0, jx, jy, me, mep, mqx, mqy, mpxx, mpxy, phi, drho, beta, dphi;
+  unsigned nb;
 };
 
-// Optional features of the step (bit mask)
-enum : int { FEAT_FORCE = 1, FEAT_DRAG = 2 };
+// What load_row fetches for one row: the nine pulled populations, phi, and
+// the optional drag coefficient, phi(t+1) and solid flags.
+template <typename S, typename T>
+struct RowIn {
+  S f[9];
+  T phi, beta, phin;
+  unsigned nb;
+};
+
+// Optional features of the step (bit mask).  FEAT_ALL is built with every
+// feature and takes absent inputs as zero (null force, drag and flag planes
+// read as 0 through zero-length buffer descriptors; phin = phi when static).
+enum : int { FEAT_FORCE = 1, FEAT_DRAG = 2, FEAT_DYNPHI = 4, FEAT_MASK = 8, FEAT_ALL = 15 };
+
+// Solid flags of FEAT_MASK, one uint16 per node: bit 0 -- the node itself is
+// solid; bit i (1..8) -- the node standing in for x + e_i (after reflection
+// across a wall) is solid.  A fluid node pulls f_i from its own slot opp(i)
+// when bit opp(i) is set (half-way bounce-back on the solid face), and the
+// Eq. (10) stencils replace a flagged neighbour by the centre value, negated
+// for velocity-like fields.
+__device__ __forceinline__ bool solid_bit(unsigned nb, int i) { return (nb >> i) & 1u; }
 
 // S: storage type of populations (double, float, _Float16)
 // T: arithmetic type (double, float)
@@ -201,8 +229,17 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
   // Issue the ten loads (nine pulled populations and phi) of row yn.  Rows
   // outside a walled domain are clamped to a valid row and never used, so
   // every load is unconditional and in bounds.
-  const rsrc_t betar = make_rsrc(g.beta, (FEAT & FEAT_DRAG) ? unsigned(g.plane) * TB : 0u);
-  auto load_row = [&](int yn, S (&f)[9], T& phi, T& beta) {
+  const rsrc_t betar = make_rsrc(g.beta, ((FEAT & FEAT_DRAG) && g.beta) ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t phinr = make_rsrc(g.phin, (FEAT & FEAT_DYNPHI) ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t nbrr = make_rsrc(g.nbr, ((FEAT & FEAT_MASK) && g.nbr) ? unsigned(g.plane) * 2u : 0u);
+  const rsrc_t fxr = make_rsrc(g.fxf, ((FEAT & FEAT_FORCE) && g.fxf) ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t fyr = make_rsrc(g.fyf, ((FEAT & FEAT_FORCE) && g.fyf) ? unsigned(g.plane) * TB : 0u);
+  auto load_row = [&](int yn, RowIn<S, T>& in) {
+    S (&f)[9] = in.f;
+    T& phi = in.phi;
+    T& beta = in.beta;
+    T& phin = in.phin;
+    unsigned& nb = in.nb;
     int r, rs, rn;
     bool bl = false, bh = false;
     if (WALLS) {
@@ -218,6 +255,26 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
     }
     phi = bload<T>(phir, xcT, unsigned(r) * unsigned(pitch) * TB);
     if (FEAT & FEAT_DRAG) beta = bload<T>(betar, xcT, unsigned(r) * unsigned(pitch) * TB);
+    if (FEAT & FEAT_DYNPHI) phin = bload<T>(phinr, xcT, unsigned(r) * unsigned(pitch) * TB);
+    if constexpr ((FEAT & FEAT_MASK) != 0) {
+      // per-lane choice between the pulled slot and the own node's opposite
+      // slot (solid source): whole byte offsets in the per-lane operand
+      nb = bload_u16(nbrr, unsigned(c) * 2u, unsigned(r) * unsigned(pitch) * 2u);
+      auto pick = [&](unsigned vcol, unsigned soff, int opp) -> S {
+        const unsigned own = poff(opp, r) + xcb;
+        return bload<S>(srcr, solid_bit(nb, opp) ? own : soff + vcol, 0u);
+      };
+      f[0] = bload<S>(srcr, xcb, poff(0, r));
+      f[1] = pick(xmb, poff(1, r), 3);
+      f[3] = pick(xpb, poff(3, r), 1);
+      f[2] = pick(xcb, bl ? poff(4, r) : poff(2, rs), 4);
+      f[5] = pick(bl ? xcb : xmb, bl ? poff(7, r) : poff(5, rs), 7);
+      f[6] = pick(bl ? xcb : xpb, bl ? poff(8, r) : poff(6, rs), 8);
+      f[4] = pick(xcb, bh ? poff(2, r) : poff(4, rn), 2);
+      f[7] = pick(bh ? xcb : xpb, bh ? poff(5, r) : poff(7, rn), 5);
+      f[8] = pick(bh ? xcb : xmb, bh ? poff(6, r) : poff(8, rn), 6);
+      return;
+    }
     f[0] = bload<S>(srcr, xcb, poff(0, r));
     f[1] = bload<S>(srcr, xmb, poff(1, r));
     f[3] = bload<S>(srcr, xpb, poff(3, r));
@@ -233,10 +290,13 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
 
   // One sweep iteration.  A: row yn, B: row yn-1, C: row yn-2.  rA is
   // written, rB/rC are read; bNew is written by B, bOld (row yn-2) read by C.
-  auto body = [&](int k, const S (&f)[9], const T phi_in, const T beta_in, RowState<T>& rA,
+  auto body = [&](int k, const RowIn<S, T>& in, RowState<T>& rA,
                   const RowState<T>& rB, const RowState<T>& rC, T (&bNew)[2],
                   const T (&bOld)[2]) {
     const int yn = y0 - 2 + k;
+    const S (&f)[9] = in.f;
+    const T phi_in = in.phi, beta_in = in.beta, phin_in = in.phin;
+    const unsigned nb_in = in.nb;
 
     // ---------------- stage A: moments of row yn ----------------
     const bool rowA = WALLS ? (yn >= 0 && yn < ny) : true;
@@ -267,6 +327,8 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       rA.mpxy = (q[5] + q[7]) - (q[6] + q[8]);
       rA.phi = phi;
       rA.beta = beta_in;
+      rA.dphi = (FEAT & FEAT_DYNPHI) ? phin_in - phi : T(0);
+      rA.nb = (FEAT & FEAT_MASK) ? nb_in : 0u;
       rA.drho = rA.dm0 * recip(phi);
       s_rho[slot4(yn)][t] = rA.drho;
       if (WALLS && yn == 0) s_rho[slot4(-1)][t] = rA.drho;      // image below
@@ -279,10 +341,22 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
     const bool rowB = (yb >= y0 - 1) && (WALLS ? (yb >= 0 && yb < ny) : true);
     if (rowB && ulane) {
       const int sc = slot4(yb), ss = slot4(yb - 1), sn = slot4(yb + 1);
-      const T rE = s_rho[sc][tr], rW = s_rho[sc][tl];
-      const T rN = s_rho[sn][t], rS = s_rho[ss][t];
-      const T rNE = s_rho[sn][tr], rNW = s_rho[sn][tl];
-      const T rSE = s_rho[ss][tr], rSW = s_rho[ss][tl];
+      T rE = s_rho[sc][tr], rW = s_rho[sc][tl];
+      T rN = s_rho[sn][t], rS = s_rho[ss][t];
+      T rNE = s_rho[sn][tr], rNW = s_rho[sn][tl];
+      T rSE = s_rho[ss][tr], rSW = s_rho[ss][tl];
+      if constexpr ((FEAT & FEAT_MASK) != 0) {  // solid neighbour: centre value
+        const unsigned nb = rB.nb;
+        const T rc = rB.drho;
+        rE = solid_bit(nb, 1) ? rc : rE;
+        rN = solid_bit(nb, 2) ? rc : rN;
+        rW = solid_bit(nb, 3) ? rc : rW;
+        rS = solid_bit(nb, 4) ? rc : rS;
+        rNE = solid_bit(nb, 5) ? rc : rNE;
+        rNW = solid_bit(nb, 6) ? rc : rNW;
+        rSW = solid_bit(nb, 7) ? rc : rSW;
+        rSE = solid_bit(nb, 8) ? rc : rSE;
+      }
       const T grx = stencil_dx(rE, rW, rNE, rSE, rNW, rSW);
       const T gry = stencil_dy(rN, rS, rNE, rNW, rSE, rSW);
       const T phi = rB.phi;
@@ -292,8 +366,8 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       T Fy = kp * gry + sg * ph.gy;
       if (FEAT & FEAT_FORCE) {
         const unsigned ro = unsigned(WALLS ? yb : wrap_index(yb, ny)) * unsigned(pitch) * TB;
-        Fx += bload<T>(make_rsrc(g.fxf, unsigned(g.plane) * TB), xcT, ro);
-        Fy += bload<T>(make_rsrc(g.fyf, unsigned(g.plane) * TB), xcT, ro);
+        Fx += bload<T>(fxr, xcT, ro);
+        Fy += bload<T>(fyr, xcT, ro);
       }
       const T m0 = phi * rho0 + rB.dm0;
       T ux, uy;
@@ -336,13 +410,34 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
     if (yo >= y0 && olane) {
       const int uo = slot4(yo), us = slot4(yo - 1), un = slot4(yo + 1);
       const U4<T> aC = s_u4[uo][t];
-      const U4<T> aE = s_u4[uo][tr], aW = s_u4[uo][tl];
-      const U4<T> aN = s_u4[un][t], aS = s_u4[us][t];
-      const U4<T> aNE = s_u4[un][tr], aNW = s_u4[un][tl];
-      const U4<T> aSE = s_u4[us][tr], aSW = s_u4[us][tl];
-      const U2<T> bN = s_u2[un][t], bS = s_u2[us][t];
-      const U2<T> bNE = s_u2[un][tr], bNW = s_u2[un][tl];
-      const U2<T> bSE = s_u2[us][tr], bSW = s_u2[us][tl];
+      U4<T> aE = s_u4[uo][tr], aW = s_u4[uo][tl];
+      U4<T> aN = s_u4[un][t], aS = s_u4[us][t];
+      U4<T> aNE = s_u4[un][tr], aNW = s_u4[un][tl];
+      U4<T> aSE = s_u4[us][tr], aSW = s_u4[us][tl];
+      U2<T> bN = s_u2[un][t], bS = s_u2[us][t];
+      U2<T> bNE = s_u2[un][tr], bNW = s_u2[un][tl];
+      U2<T> bSE = s_u2[us][tr], bSW = s_u2[us][tl];
+      if constexpr ((FEAT & FEAT_MASK) != 0) {
+        // solid neighbour: the centre's velocity-like fields, negated
+        const unsigned nb = rC.nb;
+        const U2<T> bC = s_u2[uo][t];
+        U4<T> ga;
+        ga.ux = -aC.ux; ga.uy = -aC.uy; ga.mux = -aC.mux; ga.rux = -aC.rux;
+        U2<T> gb;
+        gb.muy = -bC.muy; gb.ruy = -bC.ruy;
+        auto sel4 = [&](U4<T>& v, int i) {
+          const bool s2 = solid_bit(nb, i);
+          v.ux = s2 ? ga.ux : v.ux; v.uy = s2 ? ga.uy : v.uy;
+          v.mux = s2 ? ga.mux : v.mux; v.rux = s2 ? ga.rux : v.rux;
+        };
+        auto sel2 = [&](U2<T>& v, int i) {
+          const bool s2 = solid_bit(nb, i);
+          v.muy = s2 ? gb.muy : v.muy; v.ruy = s2 ? gb.ruy : v.ruy;
+        };
+        sel4(aE, 1); sel4(aN, 2); sel4(aW, 3); sel4(aS, 4);
+        sel4(aNE, 5); sel4(aNW, 6); sel4(aSW, 7); sel4(aSE, 8);
+        sel2(bN, 2); sel2(bS, 4); sel2(bNE, 5); sel2(bNW, 6); sel2(bSW, 7); sel2(bSE, 8);
+      }
 
       // the eight derivatives of Eq. (20), each by Eq. (10)
       const T d_rux_x = stencil_dx(aE.rux, aW.rux, aNE.rux, aSE.rux, aNW.rux, aSW.rux);
@@ -360,9 +455,10 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       const T kmp = kappa - phi;
       const T ux = aC.ux, uy = aC.uy, Fx = bOld[0], Fy = bOld[1];
 
-      // penalty source (Eq. 20); d_t phi = 0 for a static void fraction
-      const T Ca = -kappa * (d_rux_x + d_ruy_y) + T(2) * kmp * rho * (d_ux_x + d_uy_y) +
-                   (T(3) - T(2) * X) * (d_mux_x + d_muy_y);
+      // penalty source (Eq. 20); d_t phi = phi(t+1) - phi(t), zero when static
+      T Ca = -kappa * (d_rux_x + d_ruy_y) + T(2) * kmp * rho * (d_ux_x + d_uy_y) +
+             (T(3) - T(2) * X) * (d_mux_x + d_muy_y);
+      if (FEAT & FEAT_DYNPHI) Ca -= T(2) * X * rho * rC.dphi;
       const T Cb = -kappa * (d_rux_x - d_ruy_y) + T(2.0 / 3.0) * kmp * rho * (d_ux_x - d_uy_y) +
                    (d_mux_x - d_muy_y);
       const T Cc = third * kmp * rho * (d_uy_x + d_ux_y);
@@ -413,6 +509,16 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       o9[6] = b - X2 + Y2 - Qd;
       o9[7] = b - X2 - Y2 + Qd;
       o9[8] = b + X2 - Y2 - Qd;
+      if constexpr ((FEAT & FEAT_MASK) != 0) {  // solid node: keep the rest state
+        if (solid_bit(rC.nb, 0)) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) o9[i] = T(0);
+        }
+      }
+      // Shifted storage holds deviations from the rest state of the void
+      // fraction of the time the next pull runs at: rest_0 changes by
+      // rho0 d_t phi when phi moves.
+      if (SHIFT && (FEAT & FEAT_DYNPHI)) o9[0] -= rho0 * rC.dphi;
 
       if (SHIFT) {
 #pragma unroll
@@ -433,60 +539,59 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
   RowState<T> R0{}, R1{}, R2{};
   T b0[2] = {0, 0}, b1[2] = {0, 0};
   if constexpr (PD == 1) {
-    S fa[9], fb[9];
-    T pa, pb, qa = T(0), qb = T(0);
-    load_row(y0 - 2, fa, pa, qa);
+    RowIn<S, T> ia{}, ib{};
+    load_row(y0 - 2, ia);
     for (int k = 0; k < nit; k += 6) {
-      load_row(y0 - 1 + k, fb, pb, qb);
-      body(k + 0, fa, pa, qa, R0, R2, R1, b0, b1);
+      load_row(y0 - 1 + k, ib);
+      body(k + 0, ia, R0, R2, R1, b0, b1);
       if (k + 1 >= nit) break;
-      load_row(y0 + k, fa, pa, qa);
-      body(k + 1, fb, pb, qb, R1, R0, R2, b1, b0);
+      load_row(y0 + k, ia);
+      body(k + 1, ib, R1, R0, R2, b1, b0);
       if (k + 2 >= nit) break;
-      load_row(y0 + 1 + k, fb, pb, qb);
-      body(k + 2, fa, pa, qa, R2, R1, R0, b0, b1);
+      load_row(y0 + 1 + k, ib);
+      body(k + 2, ia, R2, R1, R0, b0, b1);
       if (k + 3 >= nit) break;
-      load_row(y0 + 2 + k, fa, pa, qa);
-      body(k + 3, fb, pb, qb, R0, R2, R1, b1, b0);
+      load_row(y0 + 2 + k, ia);
+      body(k + 3, ib, R0, R2, R1, b1, b0);
       if (k + 4 >= nit) break;
-      load_row(y0 + 3 + k, fb, pb, qb);
-      body(k + 4, fa, pa, qa, R1, R0, R2, b0, b1);
+      load_row(y0 + 3 + k, ib);
+      body(k + 4, ia, R1, R0, R2, b0, b1);
       if (k + 5 >= nit) break;
-      load_row(y0 + 4 + k, fa, pa, qa);
-      body(k + 5, fb, pb, qb, R2, R1, R0, b1, b0);
+      load_row(y0 + 4 + k, ia);
+      body(k + 5, ib, R2, R1, R0, b1, b0);
     }
   } else {
     static_assert(PD == 2, "prefetch distance 1 or 2");
-    S fa[9], fb[9], fc[9];
-    T pa, pb, pc, qa = T(0), qb = T(0), qc = T(0);
-    load_row(y0 - 2, fa, pa, qa);
-    load_row(y0 - 1, fb, pb, qb);
+    RowIn<S, T> ia{}, ib{}, ic{};
+    load_row(y0 - 2, ia);
+    load_row(y0 - 1, ib);
     for (int k = 0; k < nit; k += 6) {
-      load_row(y0 + k, fc, pc, qc);
-      body(k + 0, fa, pa, qa, R0, R2, R1, b0, b1);
+      load_row(y0 + k, ic);
+      body(k + 0, ia, R0, R2, R1, b0, b1);
       if (k + 1 >= nit) break;
-      load_row(y0 + 1 + k, fa, pa, qa);
-      body(k + 1, fb, pb, qb, R1, R0, R2, b1, b0);
+      load_row(y0 + 1 + k, ia);
+      body(k + 1, ib, R1, R0, R2, b1, b0);
       if (k + 2 >= nit) break;
-      load_row(y0 + 2 + k, fb, pb, qb);
-      body(k + 2, fc, pc, qc, R2, R1, R0, b0, b1);
+      load_row(y0 + 2 + k, ib);
+      body(k + 2, ic, R2, R1, R0, b0, b1);
       if (k + 3 >= nit) break;
-      load_row(y0 + 3 + k, fc, pc, qc);
-      body(k + 3, fa, pa, qa, R0, R2, R1, b1, b0);
+      load_row(y0 + 3 + k, ic);
+      body(k + 3, ia, R0, R2, R1, b1, b0);
       if (k + 4 >= nit) break;
-      load_row(y0 + 4 + k, fa, pa, qa);
-      body(k + 4, fb, pb, qb, R1, R0, R2, b0, b1);
+      load_row(y0 + 4 + k, ia);
+      body(k + 4, ib, R1, R0, R2, b0, b1);
       if (k + 5 >= nit) break;
-      load_row(y0 + 5 + k, fb, pb, qb);
-      body(k + 5, fc, pc, qc, R2, R1, R0, b1, b0);
+      load_row(y0 + 5 + k, ib);
+      body(k + 5, ic, R2, R1, R0, b1, b0);
     }
   }
 }
 
 // One lattice per launch: workgroup b takes strip b % strips, row block
-// b / strips.  WPE: minimum waves per SIMD the register allocation allows.
+// b / strips.  WPE: minimum waves per SIMD the register allocation allows
+// (three for the FP32 FEAT_ALL kernel, whose extra state would spill at four).
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT, int PD = 1,
-          int WPE = (sizeof(T) == 4 ? 4 : 2)>
+          int WPE = (sizeof(T) == 4 ? (FEAT == FEAT_ALL ? 3 : 4) : 2)>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(WPE)))
 vanse_step_kernel(StepGeom g, StepPhys<T> ph) {

@@ -57,7 +57,7 @@ int compute_bytes(int precision) { return precision == VANSE_F64 ? 8 : 4; }
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
 struct Layout {
-  size_t pop[2], phi, fx, fy, beta, drho, uprev, partials, partials2, result, badcount, total;
+  size_t pop[2], phi, phin, nbr, fx, fy, beta, drho, uprev, partials, partials2, result, badcount, total;
   long long plane;
   int pitch;
   long long max_partials;
@@ -74,6 +74,8 @@ int make_layout(const vanse_desc* d, Layout* L) {
   if (d->bc_y != VANSE_PERIODIC && d->bc_y != VANSE_WALL) return fail(VANSE_ERR_INVALID_ARG, "unknown bc_y %d", d->bc_y);
   if (d->has_force_field != 0 && d->has_force_field != 1) return fail(VANSE_ERR_INVALID_ARG, "has_force_field must be 0 or 1");
   if (d->has_drag != 0 && d->has_drag != 1) return fail(VANSE_ERR_INVALID_ARG, "has_drag must be 0 or 1");
+  if (d->has_mask != 0 && d->has_mask != 1) return fail(VANSE_ERR_INVALID_ARG, "has_mask must be 0 or 1");
+  if (d->dynamic_phi != 0 && d->dynamic_phi != 1) return fail(VANSE_ERR_INVALID_ARG, "dynamic_phi must be 0 or 1");
   const long long pitch = pitch_of(d->nx);
   const long long plane = pitch * d->ny;
   if (plane * 9 > (1LL << 31) - 1) return fail(VANSE_ERR_INVALID_ARG, "lattice too large (%d x %d)", d->nx, d->ny);
@@ -87,6 +89,10 @@ int make_layout(const vanse_desc* d, Layout* L) {
   L->plane = plane;
   for (int b = 0; b < 2; ++b) { L->pop[b] = off; off = align256(off + 9 * plane * sb); }
   L->phi = off; off = align256(off + plane * cb);
+  L->phin = 0;
+  if (d->dynamic_phi) { L->phin = off; off = align256(off + plane * cb); }
+  L->nbr = 0;
+  if (d->has_mask) { L->nbr = off; off = align256(off + plane * sizeof(uint16_t)); }
   if (d->has_force_field) {
     L->fx = off; off = align256(off + plane * cb);
     L->fy = off; off = align256(off + plane * cb);
@@ -114,7 +120,7 @@ struct vanse_lattice {
   char* ws;
   int cur;  // buffer holding the current state
   int64_t t;
-  bool phi_set, params_set, state_set, ff_set, drag_set, uprev_valid;
+  bool phi_set, params_set, state_set, ff_set, drag_set, uprev_valid, mask_set, phin_set;
   double usx, usy;  // solid velocity of the linear drag
   double kappa, rho0, gx, gy;
   int scale_by_phi;
@@ -212,13 +218,19 @@ int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& 
   return VANSE_OK;
 }
 
-int feat_of(const vanse_desc& d) { return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0); }
+// Specialised step variants for the force field and the drag; masks and a
+// time-varying void fraction (and any combination with them) use FEAT_ALL.
+int feat_of(const vanse_desc& d) {
+  if (d.has_mask || d.dynamic_phi) return FEAT_ALL;
+  return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0);
+}
 
 // Call fn(std::integral_constant<bool, WALLS>, std::integral_constant<int, FEAT>).
 template <typename Fn>
 int by_variant(const vanse_desc& d, Fn&& fn) {
   const bool walls = d.bc_y == VANSE_WALL;
   switch (feat_of(d)) {
+    case FEAT_ALL: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_ALL>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_ALL>{});
     case 0: return walls ? fn(std::true_type{}, std::integral_constant<int, 0>{}) : fn(std::false_type{}, std::integral_constant<int, 0>{});
     case 1: return walls ? fn(std::true_type{}, std::integral_constant<int, 1>{}) : fn(std::false_type{}, std::integral_constant<int, 1>{});
     case 2: return walls ? fn(std::true_type{}, std::integral_constant<int, 2>{}) : fn(std::false_type{}, std::integral_constant<int, 2>{});
@@ -229,8 +241,12 @@ int by_variant(const vanse_desc& d, Fn&& fn) {
 template <typename S, typename T, bool SHIFT>
 int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
   const StepPhys<T> ph = make_phys<T>(h);
+  if (h->phin_set && n > 1)
+    return fail(VANSE_ERR_INVALID_ARG, "with phi(t+1) set, a call advances one step (asked for %lld)", (long long)n);
   StepGeom g;
   g.phi = h->ws + h->L.phi;
+  g.phin = h->phin_set ? h->ws + h->L.phin : g.phi;
+  g.nbr = h->d.has_mask ? h->ws + h->L.nbr : nullptr;
   g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
   g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
   g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
@@ -252,6 +268,11 @@ int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
     if (rc != VANSE_OK) return rc;
     h->cur ^= 1;
     h->t += 1;
+    if (h->phin_set) {  // phi(t+1) becomes the current void fraction
+      std::swap(h->L.phi, h->L.phin);
+      h->phin_set = false;
+      h->version += 1;
+    }
     if (s == 0) HIP_TRY(hipGetLastError());
   }
   HIP_TRY(hipGetLastError());
@@ -281,6 +302,7 @@ int check_ready(const vanse_lattice* h) {
   if (!h->params_set) return fail(VANSE_ERR_STATE, "kappa and rates not set");
   if (h->d.has_force_field && !h->ff_set) return fail(VANSE_ERR_STATE, "force field not set");
   if (h->d.has_drag && !h->drag_set) return fail(VANSE_ERR_STATE, "drag field not set");
+  if (h->d.has_mask && !h->mask_set) return fail(VANSE_ERR_STATE, "mask not set");
   return VANSE_OK;
 }
 
@@ -314,6 +336,7 @@ int vanse_create(const vanse_desc* d, void* workspace, size_t bytes, vanse_latti
   h->cur = 0;
   h->t = 0;
   h->phi_set = h->params_set = h->state_set = h->ff_set = h->drag_set = h->uprev_valid = false;
+  h->mask_set = h->phin_set = false;
   h->usx = h->usy = 0.0;
   h->kappa = 0.5;
   h->rho0 = 1.0;
@@ -358,26 +381,78 @@ int vanse_set_body_force(vanse_lattice* h, double gx, double gy, int scale_by_ph
   return VANSE_OK;
 }
 
-int vanse_set_void_fraction(vanse_lattice* h, const double* phi, void* stream) {
-  if (int rc = check_handle(h)) return rc;
-  if (!phi) return fail(VANSE_ERR_INVALID_ARG, "phi is NULL");
-  hipStream_t st = static_cast<hipStream_t>(stream);
+// Check a dense phi field (solid nodes excepted) and convert it into the
+// plane at workspace offset `off`; solid nodes get the placeholder phi = 1.
+static int upload_phi(vanse_lattice* h, const double* phi, size_t off, hipStream_t st) {
   unsigned long long* bad = reinterpret_cast<unsigned long long*>(h->ws + h->L.badcount);
   HIP_TRY(hipMemsetAsync(bad, 0, sizeof(*bad), st));
   const long long n = (long long)h->d.nx * h->d.ny;
-  hipLaunchKernelGGL(count_bad_phi, dim3(256), dim3(256), 0, st, phi, n, bad);
+  const uint16_t* nbr = h->mask_set ? (const uint16_t*)(h->ws + h->L.nbr) : nullptr;
+  hipLaunchKernelGGL(count_bad_phi, dim3(256), dim3(256), 0, st, phi, h->d.nx, n, nbr, h->L.pitch, bad);
   HIP_TRY(hipGetLastError());
   unsigned long long nbad = 0;
   HIP_TRY(hipMemcpyAsync(&nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (nbad) return fail(VANSE_ERR_INVALID_ARG, "%llu void-fraction values outside (0, 1]", nbad);
-  void* dst = h->ws + h->L.phi;
-  if (h->d.precision == VANSE_F64)
+  void* dst = h->ws + off;
+  const Geo G = make_geo(h);
+  if (h->d.precision == VANSE_F64) {
     hipLaunchKernelGGL(convert_field<double>, field_grid(h), dim3(256), 0, st, phi, (double*)dst, h->d.nx, h->d.ny, h->L.pitch);
-  else
+    if (nbr) hipLaunchKernelGGL(phi_on_solids<double>, field_grid(h), dim3(256), 0, st, G, (double*)dst, nbr);
+  } else {
     hipLaunchKernelGGL(convert_field<float>, field_grid(h), dim3(256), 0, st, phi, (float*)dst, h->d.nx, h->d.ny, h->L.pitch);
+    if (nbr) hipLaunchKernelGGL(phi_on_solids<float>, field_grid(h), dim3(256), 0, st, G, (float*)dst, nbr);
+  }
   HIP_TRY(hipGetLastError());
+  return VANSE_OK;
+}
+
+int vanse_set_void_fraction(vanse_lattice* h, const double* phi, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!phi) return fail(VANSE_ERR_INVALID_ARG, "phi is NULL");
+  if (h->phin_set) return fail(VANSE_ERR_STATE, "phi(t+1) is pending; step first");
+  if (int rc = upload_phi(h, phi, h->L.phi, static_cast<hipStream_t>(stream))) return rc;
   h->phi_set = true;
+  h->version += 1;
+  return VANSE_OK;
+}
+
+int vanse_set_void_fraction_next(vanse_lattice* h, const double* phi_next, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->d.dynamic_phi) return fail(VANSE_ERR_STATE, "lattice was created without dynamic_phi");
+  if (!phi_next) return fail(VANSE_ERR_INVALID_ARG, "phi_next is NULL");
+  if (!h->phi_set) return fail(VANSE_ERR_STATE, "void fraction not set");
+  if (int rc = upload_phi(h, phi_next, h->L.phin, static_cast<hipStream_t>(stream))) return rc;
+  h->phin_set = true;
+  h->version += 1;
+  return VANSE_OK;
+}
+
+int vanse_set_mask(vanse_lattice* h, const uint8_t* mask, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->d.has_mask) return fail(VANSE_ERR_STATE, "lattice was created without a mask");
+  if (!mask) return fail(VANSE_ERR_INVALID_ARG, "mask is NULL");
+  if (h->state_set) return fail(VANSE_ERR_STATE, "the mask must be set before the populations");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(h->ws + h->L.badcount);
+  HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(*cnt), st));
+  const Geo G = make_geo(h);
+  uint16_t* nbr = (uint16_t*)(h->ws + h->L.nbr);
+  hipLaunchKernelGGL(build_nbr, field_grid(h), dim3(256), 0, st, G, mask, nbr, cnt);
+  HIP_TRY(hipGetLastError());
+  unsigned long long nsolid = 0;
+  HIP_TRY(hipMemcpyAsync(&nsolid, cnt, sizeof(nsolid), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (nsolid == (unsigned long long)h->d.nx * h->d.ny) return fail(VANSE_ERR_INVALID_ARG, "every node is solid");
+  if (h->phi_set) {  // placeholder phi on the solid nodes
+    if (h->d.precision == VANSE_F64)
+      hipLaunchKernelGGL(phi_on_solids<double>, field_grid(h), dim3(256), 0, st, G, (double*)(h->ws + h->L.phi), (const uint16_t*)nbr);
+    else
+      hipLaunchKernelGGL(phi_on_solids<float>, field_grid(h), dim3(256), 0, st, G, (float*)(h->ws + h->L.phi), (const uint16_t*)nbr);
+    HIP_TRY(hipGetLastError());
+  }
+  h->mask_set = true;
+  h->version += 1;
   return VANSE_OK;
 }
 
@@ -430,9 +505,10 @@ static int fill(vanse_lattice* h, const double* fin, double rho0, double ux0, do
     using T = std::remove_pointer_t<decltype(t_tag)>;
     constexpr bool SH = decltype(shift)::value;
     const StepPhys<T> ph = make_phys<T>(h);
+    const uint16_t* nbr = h->d.has_mask ? (const uint16_t*)(h->ws + h->L.nbr) : nullptr;
     hipLaunchKernelGGL((fill_state<S, T, SH>), field_grid(h), dim3(256), 0, st, G,
                        (S*)(h->ws + h->L.pop[0]), (const T*)(h->ws + h->L.phi), ph, fin, rho0, ux0,
-                       uy0, h->kappa);
+                       uy0, h->kappa, nbr);
     return VANSE_OK;
   });
   if (rc) return rc;
@@ -481,7 +557,8 @@ static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double
     const S* buf = (const S*)(h->ws + h->L.pop[h->cur]);
     const T* phi = (const T*)(h->ws + h->L.phi);
     T* drho = (T*)(h->ws + h->L.drho);
-    hipLaunchKernelGGL((moments_rho<S, T, SH>), field_grid(h), dim3(256), 0, st, G, buf, phi, ph, drho);
+    const uint16_t* nbr = h->d.has_mask ? (const uint16_t*)(h->ws + h->L.nbr) : nullptr;
+    hipLaunchKernelGGL((moments_rho<S, T, SH>), field_grid(h), dim3(256), 0, st, G, buf, phi, ph, drho, nbr);
     double* part = partials ? (double*)(h->ws + h->L.partials) : nullptr;
     const T* fx = h->d.has_force_field ? (const T*)(h->ws + h->L.fx) : nullptr;
     const T* fy = h->d.has_force_field ? (const T*)(h->ws + h->L.fy) : nullptr;
@@ -491,7 +568,7 @@ static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double
       T* up = keep_u ? (T*)(h->ws + h->L.uprev) : nullptr;
       hipLaunchKernelGGL((moments_out<S, T, SH, decltype(feat)::value>), field_grid(h), dim3(256), 0, st, G,
                          buf, phi, ph, drho, fx, fy, beta, rho, ux, uy, p, part, up,
-                         (int)(keep_u && h->uprev_valid));
+                         (int)(keep_u && h->uprev_valid), nbr);
       return VANSE_OK;
     });
   });
@@ -516,8 +593,9 @@ int vanse_read_populations(vanse_lattice* h, double* f, void* stream) {
     using T = std::remove_pointer_t<decltype(t_tag)>;
     constexpr bool SH = decltype(shift)::value;
     const StepPhys<T> ph = make_phys<T>(h);
+    const uint16_t* nbr = h->d.has_mask ? (const uint16_t*)(h->ws + h->L.nbr) : nullptr;
     hipLaunchKernelGGL((read_pops<S, T, SH>), field_grid(h), dim3(256), 0, st, G,
-                       (const S*)(h->ws + h->L.pop[h->cur]), (const T*)(h->ws + h->L.phi), ph, f);
+                       (const S*)(h->ws + h->L.pop[h->cur]), (const T*)(h->ws + h->L.phi), ph, f, nbr);
     return VANSE_OK;
   });
   if (rc) return rc;
@@ -668,6 +746,8 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, std::
   for (int k = 0; k < n; ++k) {
     if (!lats[k]) return fail(VANSE_ERR_INVALID_ARG, "lattice %d is NULL", k);
     const vanse_desc& d = lats[k]->d;
+    if (d.has_mask || d.dynamic_phi)
+      return fail(VANSE_ERR_UNSUPPORTED, "lattice %d: batches take lattices without mask or time-varying phi", k);
     if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field ||
         d.has_drag != d0.has_drag)
       return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary, force field or drag", k);
@@ -708,6 +788,8 @@ void fill_entries(vanse_batch* b, std::vector<char>* blob) {
     g.src = h->ws + h->L.pop[0];
     g.dst = h->ws + h->L.pop[1];
     g.phi = h->ws + h->L.phi;
+    g.phin = g.phi;
+    g.nbr = nullptr;
     g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
     g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
     g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
@@ -772,8 +854,12 @@ int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
     using T = std::remove_pointer_t<decltype(t_tag)>;
     constexpr bool SH = decltype(shift)::value;
     return by_variant(b->lats[0]->d, [&](auto walls, auto feat) -> int {
-      batch_launch_t<S, T, SH, decltype(walls)::value, decltype(feat)::value>(b, launch, st);
-      return VANSE_OK;
+      if constexpr (decltype(feat)::value == FEAT_ALL) {
+        return fail(VANSE_ERR_UNSUPPORTED, "batches take lattices without mask or time-varying phi");
+      } else {
+        batch_launch_t<S, T, SH, decltype(walls)::value, decltype(feat)::value>(b, launch, st);
+        return VANSE_OK;
+      }
     });
   });
 }

@@ -29,7 +29,8 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4:
 
 EXPORTS = [
     "vanse_workspace_bytes", "vanse_create", "vanse_destroy", "vanse_set_params",
-    "vanse_set_body_force", "vanse_set_void_fraction", "vanse_set_force_field", "vanse_set_drag",
+    "vanse_set_body_force", "vanse_set_void_fraction", "vanse_set_void_fraction_next",
+    "vanse_set_mask", "vanse_set_force_field", "vanse_set_drag",
     "vanse_init_equilibrium", "vanse_set_populations", "vanse_step", "vanse_read_moments",
     "vanse_read_populations", "vanse_observe", "vanse_residual", "vanse_set_tiling",
     "vanse_get_tiling",
@@ -52,7 +53,7 @@ class Diverged(VanseError):
 class Desc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("precision", C.c_int32),
                 ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("has_force_field", C.c_int32),
-                ("has_drag", C.c_int32)]
+                ("has_drag", C.c_int32), ("has_mask", C.c_int32), ("dynamic_phi", C.c_int32)]
 
 
 class Rates(C.Structure):
@@ -81,6 +82,8 @@ def lib():
                 "vanse_set_params": [vp, d, C.POINTER(Rates)],
                 "vanse_set_body_force": [vp, d, d, i32],
                 "vanse_set_void_fraction": [vp, vp, vp],
+                "vanse_set_void_fraction_next": [vp, vp, vp],
+                "vanse_set_mask": [vp, vp, vp],
                 "vanse_set_force_field": [vp, vp, vp, vp],
                 "vanse_set_drag": [vp, vp, d, d, vp],
                 "vanse_init_equilibrium": [vp, d, d, d, vp],
@@ -125,9 +128,9 @@ def check(rc):
 
 
 def workspace_bytes(nx, ny, precision="f64", bc_y="periodic", force_field=False,
-                    drag=False) -> int:
+                    drag=False, mask=False, dynamic_phi=False) -> int:
     desc = Desc(int(nx), int(ny), PRECISION[precision], 0, BC[bc_y], int(bool(force_field)),
-                int(bool(drag)))
+                int(bool(drag)), int(bool(mask)), int(bool(dynamic_phi)))
     n = C.c_size_t()
     check(lib().vanse_workspace_bytes(C.byref(desc), C.byref(n)))
     return n.value
@@ -144,13 +147,14 @@ class Lattice:
     """One lattice whose device state lives in a torch-allocated workspace."""
 
     def __init__(self, nx, ny, precision="f64", bc_y="periodic", force_field=False,
-                 device=None, workspace=None, drag=False):
+                 device=None, workspace=None, drag=False, mask=False, dynamic_phi=False):
         import torch
         self.nx, self.ny = int(nx), int(ny)
         self.precision = precision
         self.device = torch.device(device or "cuda")
         self.desc = Desc(self.nx, self.ny, PRECISION[precision], 0, BC[bc_y],
-                         int(bool(force_field)), int(bool(drag)))
+                         int(bool(force_field)), int(bool(drag)), int(bool(mask)),
+                         int(bool(dynamic_phi)))
         nbytes = C.c_size_t()
         check(lib().vanse_workspace_bytes(C.byref(self.desc), C.byref(nbytes)))
         if workspace is None:
@@ -195,6 +199,22 @@ class Lattice:
         t = self._field(phi, (self.ny, self.nx))
         check(lib().vanse_set_void_fraction(self.handle, C.c_void_p(t.data_ptr()),
                                             _stream(stream)))
+        return self
+
+    def set_void_fraction_next(self, phi_next, stream=None):
+        """phi(t+1) for the next (single) step; see vanse_set_void_fraction_next."""
+        t = self._field(phi_next, (self.ny, self.nx))
+        check(lib().vanse_set_void_fraction_next(self.handle, C.c_void_p(t.data_ptr()),
+                                                 _stream(stream)))
+        return self
+
+    def set_mask(self, mask, stream=None):
+        """Solid nodes: (ny, nx) array, nonzero = solid (before the populations)."""
+        import torch
+        t = torch.as_tensor(mask).to(self.device).ne(0).to(torch.uint8).contiguous()
+        if tuple(t.shape) != (self.ny, self.nx):
+            raise ValueError(f"expected shape {(self.ny, self.nx)}, got {tuple(t.shape)}")
+        check(lib().vanse_set_mask(self.handle, C.c_void_p(t.data_ptr()), _stream(stream)))
         return self
 
     def set_force_field(self, fx, fy, stream=None):

@@ -15,6 +15,7 @@ Workloads (sizes, fields and forcing as used by the tests and the benchmark):
                            cells, plus seeded periodic-Gaussian-smoothed noise
                            of amplitude 0.05 (sigma = 8 cells), clipped to 1.
   * ``batch_lattices``  -- many periodic lattices with log-uniform sides.
+  * ``solid_mask``, ``cylinder_channel`` -- solid nodes (uint8 masks).
   * ``mms_case``        -- manufactured void fraction, velocity and body force
                            of the paper's convergence tests (Sec. 3.4, Eq. 27-30
                            and Appendix C).
@@ -198,3 +199,38 @@ def served_requests(count: int = 40, rate: float = 4.0, seed: int = 5, lmin: int
         phi = inclusion_phi(L, rng)
         out.append(dict(rid=k, L=L, arrival=t, phi=phi, beta=beta0 + beta1 * (1.0 - phi), g=g))
     return out
+
+
+def solid_mask(nx: int, ny: int, seed: int, discs: int = 3, rmin: float = 1.5,
+               rmax: float = None, singles: int = None):
+    """Solid nodes (uint8, 1 = solid): `discs` periodic discs of radius
+    U[rmin, rmax] (rmax default min(nx, ny)/6) at uniform centres, plus
+    `singles` isolated solid nodes (default nx*ny/200, at least 2) and one
+    solid node on each edge row and column (next to walls and to the
+    periodic seams).  A mask that leaves no fluid node is never returned."""
+    rng = np.random.default_rng(seed)
+    rmax = max(rmin, min(nx, ny) / 6.0) if rmax is None else rmax
+    singles = max(2, nx * ny // 200) if singles is None else singles
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    m = np.zeros((ny, nx), np.uint8)
+    for _ in range(discs):
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        r = rng.uniform(rmin, rmax)
+        dx = xx - cx
+        dy = yy - cy
+        dx = dx - nx * np.round(dx / nx)
+        dy = dy - ny * np.round(dy / ny)
+        m[dx * dx + dy * dy < r * r] = 1
+    for _ in range(singles):
+        m[rng.integers(ny), rng.integers(nx)] = 1
+    m[0, nx // 3] = m[ny - 1, nx // 2] = m[ny // 2, 0] = m[ny // 2, nx - 1] = 1
+    if m.all():
+        m[ny // 2, nx // 2] = 0
+    return m
+
+
+def cylinder_channel(nx: int, ny: int, radius: float):
+    """A channel with walls in y and one solid disc (uint8 mask) centred at
+    (nx/4, ny/2) -- flow past a cylinder between plates."""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    return (((xx + 0.5 - nx / 4) ** 2 + (yy + 0.5 - ny / 2) ** 2) < radius ** 2).astype(np.uint8)

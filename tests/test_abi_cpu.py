@@ -55,10 +55,10 @@ def test_bad_descriptors_are_rejected(nx, ny, prec, bcx, bcy, ff, code):
     assert V.lib().vanse_last_error()
 
 
-def _fake_handle(nx=64, ny=48, prec=0, bcy=0):
+def _fake_handle(nx=64, ny=48, prec=0, bcy=0, mask=0, dynamic=0):
     """A handle over a fake, aligned device address: only host-side calls
     (no HIP work) may be made on it."""
-    d = V.Desc(nx, ny, prec, 0, bcy, 0, 0)
+    d = V.Desc(nx, ny, prec, 0, bcy, 0, 0, mask, dynamic)
     n = C.c_size_t()
     V.check(V.lib().vanse_workspace_bytes(C.byref(d), C.byref(n)))
     h = C.c_void_p()
@@ -116,3 +116,42 @@ def test_error_strings():
     L = V.lib()
     for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.vanse_error_string(code)
+
+
+@pytest.mark.parametrize("mask,dynamic", [(2, 0), (0, 3), (-1, 0)])
+def test_bad_feature_flags_are_rejected(mask, dynamic):
+    d = V.Desc(64, 64, 0, 0, 0, 0, 0, mask, dynamic)
+    n = C.c_size_t()
+    assert V.lib().vanse_workspace_bytes(C.byref(d), C.byref(n)) == -1
+
+
+def test_optional_planes_enlarge_the_workspace():
+    base = V.workspace_bytes(100, 80, "f32")
+    plane = 128 * 80
+    assert V.workspace_bytes(100, 80, "f32", mask=True) >= base + 2 * plane
+    assert V.workspace_bytes(100, 80, "f32", dynamic_phi=True) >= base + 4 * plane
+    assert V.workspace_bytes(100, 80, "f64", dynamic_phi=True) >= V.workspace_bytes(100, 80, "f64") + 8 * plane
+
+
+def test_feature_state_checks_on_the_host():
+    L = V.lib()
+    h = _fake_handle(mask=1, dynamic=1)
+    # phi(t+1) needs phi first; stepping needs the mask; both without GPU work
+    assert L.vanse_set_void_fraction_next(h, C.c_void_p(1 << 40), None) == -4
+    assert L.vanse_set_mask(h, None, None) == -1
+    assert L.vanse_step(h, 1, None) == -4
+    plain = _fake_handle()
+    assert L.vanse_set_mask(plain, C.c_void_p(1 << 40), None) == -4
+    assert L.vanse_set_void_fraction_next(plain, C.c_void_p(1 << 40), None) == -4
+    assert L.vanse_destroy(h) == 0 and L.vanse_destroy(plain) == 0
+
+
+@pytest.mark.parametrize("mask,dynamic", [(1, 0), (0, 1)])
+def test_batches_reject_masks_and_moving_phi(mask, dynamic):
+    L = V.lib()
+    hs = [_fake_handle(), _fake_handle(mask=mask, dynamic=dynamic)]
+    arr = (C.c_void_p * 2)(hs[0].value, hs[1].value)
+    n = C.c_size_t()
+    assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == -6
+    for h in hs:
+        assert L.vanse_destroy(h) == 0

@@ -1,0 +1,302 @@
+"""GPU parity of the optional inputs: solid nodes (a mask) and a
+time-varying void fraction (the d_t phi term of Eq. 20), through the C ABI,
+against the FP64 oracle on the same seeded inputs.
+
+Tolerances as in test_gpu_parity: FP64 one step max|df| <= 1e-14 max|f| on
+fluid nodes; FP64 many steps rel-L2(u) <= 1e-12; reduced precision bounded
+by its storage rounding.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_2409_02964_amd import workloads as W  # noqa: E402
+
+C1_RATES = dict(s_c=1.2, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=0.8)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def lattice(nx, ny, phi, precision="f64", bc_y="periodic", mask=None, dynamic=False,
+            force=None, g=(0.0, 0.0), scale_by_phi=True, kappa=0.5, rates=C1_RATES, tiling=None):
+    from paper_2409_02964_amd.vanse import Lattice
+    lat = Lattice(nx, ny, precision=precision, bc_y=bc_y, mask=mask is not None,
+                  dynamic_phi=dynamic, force_field=force is not None)
+    lat.set_params(kappa, rates).set_body_force(g[0], g[1], scale_by_phi)
+    if mask is not None:
+        lat.set_mask(mask)
+    lat.set_void_fraction(phi)
+    if force is not None:
+        lat.set_force_field(force[0], force[1])
+    if tiling:
+        lat.set_tiling(*tiling)
+    return lat
+
+
+def rel_l2_u(m, ref, fluid=None):
+    sel = np.ones_like(ref["ux"], bool) if fluid is None else fluid
+    num = np.sum((m["ux"][sel] - ref["ux"][sel]) ** 2 + (m["uy"][sel] - ref["uy"][sel]) ** 2)
+    den = np.sum(ref["ux"][sel] ** 2 + ref["uy"][sel] ** 2)
+    return math.sqrt(num / den)
+
+
+def to_np(d):
+    return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+# ---- solid nodes ----------------------------------------------------------------
+
+MASK_SHAPES = [
+    (64, 48, "periodic", None),
+    (61, 37, "wall", None),
+    (253, 9, "periodic", (256, 4)),   # solids on both sides of the strip seam
+    (125, 30, "wall", (128, 7)),
+    (60, 5, "wall", (64, 1)),
+]
+
+
+@pytest.mark.parametrize("nx,ny,bc,tiling", MASK_SHAPES)
+def test_one_step_mask_fp64(oracle, nx, ny, bc, tiling):
+    torch = _torch()
+    _say(f"one-step mask fp64 {nx}x{ny} {bc} tiling={tiling}")
+    phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 2.0, seed=nx + 7 * ny) ** 2
+    mask = W.solid_mask(nx, ny, seed=nx * ny)
+    fluid = mask == 0
+    f0 = W.random_populations(nx, ny, seed=3 + nx)
+    g = (2e-5, -1e-5)
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=g, bc_y=bc, mask=mask)
+    ora.set_populations(f0)
+    ora.step(1)
+    lat = lattice(nx, ny, phi, "f64", bc, mask=mask, g=g, tiling=tiling)
+    lat.set_populations(torch.from_numpy(f0))
+    back = lat.read_populations().cpu().numpy()
+    assert np.max(np.abs(back[:, fluid] - f0[:, fluid])) <= 1e-15 * np.max(np.abs(f0))
+    assert np.all(back[:, ~fluid] == 0.0)
+    lat.step(1)
+    fg = lat.read_populations().cpu().numpy()
+    err = np.max(np.abs(fg[:, fluid] - ora.f[:, fluid])) / np.max(np.abs(ora.f))
+    _say(f"   max rel err {err:.3e}  ({int((~fluid).sum())} solid nodes)")
+    assert err <= 1e-14
+    assert np.all(fg[:, ~fluid] == 0.0)
+
+
+def _cylinder(nx=96, ny=40):
+    phi = W.channel_phi(nx, ny, seed=11, lo=0.6)
+    return phi, W.cylinder_channel(nx, ny, radius=6.0)
+
+
+def test_cylinder_channel_many_steps_fp64(oracle):
+    torch = _torch()
+    nx, ny, steps = 96, 40, 800
+    phi, mask = _cylinder(nx, ny)
+    fluid = mask == 0
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=(2e-6, 0), bc_y="wall",
+                        mask=mask).init_equilibrium()
+    ora.step(steps)
+    ref = ora.macroscopic()
+    lat = lattice(nx, ny, phi, "f64", "wall", mask=mask, g=(2e-6, 0))
+    lat.init_equilibrium(1.0)
+    obs0 = lat.observe()
+    lat.step(steps)
+    m = to_np(lat.read_moments())
+    e = rel_l2_u(m, ref, fluid)
+    obs = lat.observe()
+    mass_ref = float(np.sum(ora.f[:, fluid]))
+    _say(f"cylinder fp64: rel-L2(u) {e:.3e}, mass {obs['mass']:.15e} vs {mass_ref:.15e}")
+    assert e <= 1e-12
+    assert abs(obs["mass"] - mass_ref) <= 1e-13 * mass_ref
+    assert abs(obs["mass"] - obs0["mass"]) <= 1e-13 * obs0["mass"]
+    assert np.all(m["ux"][~fluid] == 0.0) and np.all(m["rho"][~fluid] == 0.0)
+    assert np.max(np.abs(m["rho"][fluid] - ref["rho"][fluid])) <= 1e-14
+
+
+def test_solid_rows_reproduce_walls_gpu():
+    """A periodic lattice with solid first and last rows carries the walled
+    channel on its fluid rows (x-uniform flow; the oracle pin of the same)."""
+    _torch()
+    nx, H = 70, 14
+    y = np.arange(H)[:, None] + 0.5
+    phi_w = (0.6 + 0.3 * np.sin(np.pi * y / H) ** 2) * np.ones((1, nx))
+    walled = lattice(nx, H, phi_w, "f64", "wall", g=(1e-5, 0))
+    phi_m = np.ones((H + 2, nx))
+    phi_m[1:H + 1] = phi_w
+    mask = np.zeros((H + 2, nx), np.uint8)
+    mask[0] = mask[H + 1] = 1
+    masked = lattice(nx, H + 2, phi_m, "f64", "periodic", mask=mask, g=(1e-5, 0))
+    walled.init_equilibrium(1.0)
+    masked.init_equilibrium(1.0)
+    walled.step(1500)
+    masked.step(1500)
+    a, b = to_np(walled.read_moments()), to_np(masked.read_moments())
+    assert np.max(np.abs(a["ux"])) > 1e-4
+    assert np.max(np.abs(a["ux"] - b["ux"][1:H + 1])) <= 1e-13 * np.max(np.abs(a["ux"]))
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 5e-2), ("f32s", 1e-4), ("f16s", 5e-2)])
+def test_cylinder_reduced_precision(oracle, prec, bound):
+    _torch()
+    nx, ny, steps = 96, 40, 400
+    phi, mask = _cylinder(nx, ny)
+    fluid = mask == 0
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=(2e-6, 0), bc_y="wall",
+                        mask=mask).init_equilibrium()
+    ora.step(steps)
+    ref = ora.macroscopic()
+    lat = lattice(nx, ny, phi, prec, "wall", mask=mask, g=(2e-6, 0))
+    lat.init_equilibrium(1.0)
+    lat.step(steps)
+    e = rel_l2_u(to_np(lat.read_moments()), ref, fluid)
+    _say(f"cylinder {prec}: rel-L2(u) {e:.3e}")
+    assert e <= bound
+
+
+def test_mask_errors():
+    torch = _torch()
+    from paper_2409_02964_amd.vanse import Lattice, VanseError
+    phi = np.full((16, 16), 0.8)
+    lat = Lattice(16, 16, "f64", mask=True)
+    lat.set_params(0.5, C1_RATES).set_void_fraction(phi)
+    with pytest.raises(VanseError):  # mask not set yet
+        lat.init_equilibrium(1.0)
+    with pytest.raises(VanseError):  # all solid
+        lat.set_mask(np.ones((16, 16), np.uint8))
+    phi0 = phi.copy()
+    phi0[3, 4] = 0.0   # accepted on a solid node ...
+    m = np.zeros((16, 16), np.uint8)
+    m[3, 4] = 1
+    lat.set_mask(m).set_void_fraction(phi0).init_equilibrium(1.0)
+    with pytest.raises(VanseError):  # ... but the mask is fixed once populations exist
+        lat.set_mask(m)
+    phi0[5, 5] = 0.0   # and rejected on a fluid node
+    with pytest.raises(VanseError):
+        lat.set_void_fraction(phi0)
+    plain = Lattice(16, 16, "f64")
+    with pytest.raises(VanseError):
+        plain.set_mask(torch.zeros(16, 16, dtype=torch.uint8))
+
+
+# ---- time-varying void fraction ----------------------------------------------------
+
+@pytest.mark.parametrize("nx,ny,bc,with_mask", [(48, 40, "periodic", False),
+                                                (61, 37, "wall", False),
+                                                (64, 32, "wall", True)])
+def test_one_step_dynamic_phi_fp64(oracle, nx, ny, bc, with_mask):
+    torch = _torch()
+    _say(f"one-step dynamic phi fp64 {nx}x{ny} {bc} mask={with_mask}")
+    phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 3.0, seed=21) ** 2
+    phin = np.clip(phi + 0.02 * W.smoothed_noise(nx, ny, 3.0, seed=22), 0.3, 1.0)
+    mask = W.solid_mask(nx, ny, seed=5) if with_mask else None
+    fluid = np.ones((ny, nx), bool) if mask is None else mask == 0
+    f0 = W.random_populations(nx, ny, seed=9)
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=(1e-5, 0), bc_y=bc, mask=mask)
+    ora.set_populations(f0)
+    ora.step(1, phi_next=phin)
+    lat = lattice(nx, ny, phi, "f64", bc, mask=mask, dynamic=True, g=(1e-5, 0))
+    lat.set_populations(torch.from_numpy(f0))
+    lat.set_void_fraction_next(phin)
+    lat.step(1)
+    fg = lat.read_populations().cpu().numpy()
+    err = np.max(np.abs(fg[:, fluid] - ora.f[:, fluid])) / np.max(np.abs(ora.f))
+    _say(f"   max rel err {err:.3e}")
+    assert err <= 1e-14
+    # phi(t+1) is now the current void fraction: the moments agree too
+    mg, mo = to_np(lat.read_moments()), ora.macroscopic()
+    assert np.max(np.abs(mg["rho"][fluid] - mo["rho"][fluid])) <= 1e-14
+
+
+def _mms3_pair(oracle, n, precision, steps, a=0.5, b=0.25, nu=0.1, kappa=0.3, us=0.08):
+    torch = _torch()
+    s_nu = 1.0 / (3 * nu + 0.5)
+    rates = dict(s_c=1.0, s_e=1.0 / (nu + 0.5), s_eps=1.2, s_q=1.2, s_nu=s_nu)
+    m0 = W.mms_case("III", n, a, b, us, nu, 0)
+    ora = oracle.Oracle(n, n, m0["phi"], kappa=kappa, rates=rates, scale_by_phi=False,
+                        force=(m0["fx"], m0["fy"]))
+    ora.init_fields(np.ones((n, n)), m0["ux"], m0["uy"])
+    lat = lattice(n, n, m0["phi"], precision, dynamic=True, force=(m0["fx"], m0["fy"]),
+                  scale_by_phi=False, kappa=kappa, rates=rates)
+    lat.set_populations(torch.from_numpy(ora.f.copy()))
+    for t in range(steps):
+        mt = W.mms_case("III", n, a, b, us, nu, t)
+        mn = W.mms_case("III", n, a, b, us, nu, t + 1)
+        ora.fx[...] = mt["fx"]
+        ora.fy[...] = mt["fy"]
+        ora.step(1, phi_next=mn["phi"])
+        lat.set_force_field(mt["fx"], mt["fy"])
+        lat.set_void_fraction_next(mn["phi"])
+        lat.step(1)
+    return to_np(lat.read_moments()), ora.macroscopic()
+
+
+def test_mms_case_III_fp64(oracle):
+    """Eq. (29), moving void fraction and velocity (Appendix C force): the
+    GPU follows the oracle step by step."""
+    m, ref = _mms3_pair(oracle, 32, "f64", 200)
+    e = rel_l2_u(m, ref)
+    _say(f"MMS III fp64 200 steps: rel-L2(u) {e:.3e}")
+    assert e <= 1e-12
+
+
+@pytest.mark.parametrize("prec,bound", [("f32s", 1e-4), ("f16s", 2e-2)])
+def test_mms_case_III_shifted_storage(oracle, prec, bound):
+    """Shifted storage keeps deviations from the rest state of the void
+    fraction the next pull runs at; with a moving phi that reference moves
+    by rho0 d_t phi per step."""
+    m, ref = _mms3_pair(oracle, 32, prec, 200)
+    e = rel_l2_u(m, ref)
+    _say(f"MMS III {prec} 200 steps: rel-L2(u) {e:.3e}")
+    assert e <= bound
+
+
+def test_dynamic_phi_held_constant_without_next():
+    """A dynamic-phi lattice with no phi(t+1) pending steps a static phi:
+    it matches the plain lattice (a different kernel variant) to rounding."""
+    _torch()
+    n = 48
+    phi = W.periodic_wave(n, n)
+    a = lattice(n, n, phi, "f64", dynamic=True, g=(1e-5, 0))
+    b = lattice(n, n, phi, "f64", g=(1e-5, 0))
+    a.init_equilibrium(1.0)
+    b.init_equilibrium(1.0)
+    a.step(300)
+    b.step(300)
+    ma, mb = to_np(a.read_moments()), to_np(b.read_moments())
+    assert rel_l2_u(ma, mb) <= 1e-13
+
+
+def test_dynamic_phi_errors():
+    _torch()
+    from paper_2409_02964_amd.vanse import Lattice, VanseError
+    n = 16
+    phi = np.full((n, n), 0.7)
+    lat = lattice(n, n, phi, "f64", dynamic=True)
+    lat.init_equilibrium(1.0)
+    lat.set_void_fraction_next(phi * 0.99)
+    with pytest.raises(VanseError):  # one step per pending phi(t+1)
+        lat.step(2)
+    with pytest.raises(VanseError):  # phi(t) cannot be replaced while phi(t+1) is pending
+        lat.set_void_fraction(phi)
+    lat.step(1)
+    assert lat.t == 1
+    lat.step(3)  # held constant again
+    bad = phi.copy()
+    bad[2, 2] = 1.5
+    with pytest.raises(VanseError):
+        lat.set_void_fraction_next(bad)
+    plain = Lattice(n, n, "f64")
+    plain.set_params(0.5, C1_RATES).set_void_fraction(phi)
+    with pytest.raises(VanseError):
+        plain.set_void_fraction_next(phi)

@@ -437,3 +437,68 @@ def test_particle_flow_eq23(oracle, a):
     m = o.macroscopic()
     assert math.sqrt(np.sum((m["ux"] - exact) ** 2) / np.sum(exact ** 2)) < 5e-3
     assert np.max(np.abs(m["uy"])) < 1e-3 * np.max(exact)
+
+
+# ---- solid nodes: a channel bounded by solid rows is the walled channel ------
+
+def test_solid_rows_reproduce_walls(oracle):
+    """Half-way bounce-back on the faces of solid nodes (Sec. 3.1) and the
+    centre-value stand-in of Eq. (10) next to them: for a flow that is uniform
+    in x, a periodic lattice whose first and last rows are solid gives the
+    same fluid rows as a channel with walls (whose Eq. 10 stand-ins are mirror
+    images, here equal to the centre values)."""
+    nx, H = 6, 14
+    y = np.arange(H)[:, None] + 0.5
+    phi_w = (0.6 + 0.3 * np.sin(np.pi * y / H) ** 2) * np.ones((1, nx))
+    walled = oracle.Oracle(nx, H, phi_w, kappa=0.5, rates=C1_RATES, g=(1e-5, 0), bc_y="wall")
+    walled.init_equilibrium()
+    phi_m = np.ones((H + 2, nx))
+    phi_m[1:H + 1] = phi_w
+    mask = np.zeros((H + 2, nx), np.uint8)
+    mask[0] = mask[H + 1] = 1
+    masked = oracle.Oracle(nx, H + 2, phi_m, kappa=0.5, rates=C1_RATES, g=(1e-5, 0), mask=mask)
+    masked.init_equilibrium()
+    walled.step(1500)
+    masked.step(1500)
+    a, b = walled.macroscopic(), masked.macroscopic()
+    assert np.max(np.abs(a["ux"])) > 1e-4
+    for k in ("ux", "uy", "rho"):
+        assert np.max(np.abs(a[k] - b[k][1:H + 1])) <= 1e-14 * max(1.0, np.max(np.abs(a[k])))
+    assert np.all(b["ux"][[0, H + 1]] == 0.0)  # solid rows report zeros
+
+
+# ---- manufactured case III: time-varying void fraction ------------------------
+
+def _mms3_error(oracle, n, a, b, nu, kappa, us=0.08, periods=0.5, dt_phi=True):
+    m = W.mms_case("III", n, a, b, us, nu, 0)
+    o = oracle.Oracle(n, n, m["phi"], kappa=kappa, rates=rates_for(nu, s_q=1.2),
+                      scale_by_phi=False, force=(m["fx"], m["fy"]))
+    o.init_fields(np.ones((n, n)), m["ux"], m["uy"])
+    T = int(round(periods * n * n / (4 * us)))
+    for t in range(T):
+        mt = W.mms_case("III", n, a, b, us, nu, t)
+        mn = W.mms_case("III", n, a, b, us, nu, t + 1)
+        o.fx[...] = mt["fx"]
+        o.fy[...] = mt["fy"]
+        if dt_phi:
+            o.step(1, phi_next=mn["phi"])
+        else:  # the plausible mistake: phi moves but d_t phi is left out of C_a
+            o.step(1, phi_next=mt["phi"])
+            o.phi[...] = mn["phi"]
+    mT = W.mms_case("III", n, a, b, us, nu, T)
+    u = o.macroscopic()
+    num = np.sum((u["ux"] - mT["ux"]) ** 2 + (u["uy"] - mT["uy"]) ** 2)
+    return math.sqrt(num / np.sum(mT["ux"] ** 2 + mT["uy"] ** 2))
+
+
+def test_mms_case_III_second_order(oracle):
+    """Sec. 3.4, Eq. (29) with the force of Eq. (C3): the void fraction and the
+    velocity move with speed 4 u_s / n^2 (per step, in both directions), and
+    the scheme converges at second order (half a period of travel).  Without
+    the d_t phi term of Eq. (20) the error stays at tens of percent."""
+    errs = [_mms3_error(oracle, n, 0.5, 0.25, 0.1, 0.3) for n in (16, 32)]
+    slope = math.log(errs[0] / errs[1]) / math.log(2.0)
+    assert 1.7 < slope < 2.3, (errs, slope)
+    assert errs[1] < 0.03
+    wrong = _mms3_error(oracle, 32, 0.5, 0.25, 0.1, 0.3, dt_phi=False)
+    assert wrong > 5 * errs[1]
