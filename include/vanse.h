@@ -100,6 +100,18 @@ int vanse_destroy(vanse_lattice *h);
  * best close to the minimum of phi) and the relaxation rates. */
 int vanse_set_params(vanse_lattice *h, double kappa, const vanse_rates *r);
 
+/* ---- scheme variants (Sec. 2.3 below Eq. 20, Appendix B) ----------------- */
+#define VANSE_MODEL_A 0 /* the consistent VANSE of Eq. (1): -phi grad p, div(phi tau) */
+#define VANSE_MODEL_B 1 /* model B (set I): -grad p, div(tau) */
+
+/* Choose the scheme: model VANSE_MODEL_A (default) or VANSE_MODEL_B --
+ * F^p = (kappa - 1) cs^2 grad rho in place of Eq. (13) and "kappa - phi"
+ * replaced by "kappa - 1" in the source term -- and the equilibrium order:
+ * 3 (default; Eq. 14, moments Eq. 18, penalty Eq. 20) or 2 (the truncated
+ * equilibrium of Appendix B, Eq. B1, moments B2, penalty B3 with twelve
+ * derivatives).  Only before the populations are set. */
+int vanse_set_scheme(vanse_lattice *h, int model, int equilibrium_order);
+
 /* Uniform external acceleration G: F^B = phi*G (scale_by_phi = 1, the form
  * F^B = phi(G - ...) of Sec. 3.1 and Eq. 23) or F^B = G (scale_by_phi = 0).
  * Defaults: G = 0, scale_by_phi = 1. */
@@ -212,7 +224,7 @@ int vanse_stream_copy(vanse_lattice *h, int64_t n, void *stream);
  * written again automatically when a member changed or was stepped on its
  * own.  Member handles stay usable (vanse_time, vanse_read_*).  Lattices with
  * a mask or a time-varying void fraction are not batched
- * (VANSE_ERR_UNSUPPORTED). */
+ * (VANSE_ERR_UNSUPPORTED), and so are lattices with a scheme variant. */
 typedef struct vanse_batch vanse_batch;
 
 /* Workspace bytes for a batch of n lattices with the given workgroup width

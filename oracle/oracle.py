@@ -43,7 +43,8 @@ class _Params(C.Structure):
                 ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double),
                 ("s_nu", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
                 ("scale_by_phi", C.c_int), ("use_penalty", C.c_int),
-                ("beta", C.POINTER(C.c_double)), ("usx", C.c_double), ("usy", C.c_double)]
+                ("beta", C.POINTER(C.c_double)), ("usx", C.c_double), ("usy", C.c_double),
+                ("model_b", C.c_int), ("eq2", C.c_int)]
 
 
 _D = C.POINTER(C.c_double)
@@ -62,6 +63,9 @@ def lib():
                                     C.POINTER(C.c_int)]
             L.vo_feq.argtypes = [C.c_double] * 5 + [_D]
             L.vo_meq.argtypes = [C.c_double] * 5 + [_D]
+            L.vo_feq2.argtypes = [C.c_double] * 5 + [_D]
+            L.vo_meq2.argtypes = [C.c_double] * 5 + [_D]
+            L.vo_penalty_b3.argtypes = [C.c_double] * 5 + [_D, _D]
             L.vo_force_moments.argtypes = [C.c_double] * 4 + [_D]
             L.vo_penalty.argtypes = [C.c_double] * 4 + [_D, _D]
             L.vo_gradient.argtypes = [P, _U8, _D, C.c_int, _D, _D]
@@ -123,6 +127,18 @@ def meq(phi, rho, ux, uy, kappa):
     return out
 
 
+def feq2(phi, rho, ux, uy, kappa):
+    out = np.zeros(9)
+    lib().vo_feq2(phi, rho, ux, uy, kappa, _dp(out))
+    return out
+
+
+def meq2(phi, rho, ux, uy, kappa):
+    out = np.zeros(9)
+    lib().vo_meq2(phi, rho, ux, uy, kappa, _dp(out))
+    return out
+
+
 def force_moments(ux, uy, Fx, Fy):
     out = np.zeros(9)
     lib().vo_force_moments(ux, uy, Fx, Fy, _dp(out))
@@ -133,6 +149,13 @@ def penalty(phi, rho, kappa, dt_phi, d8):
     d8 = _f64(d8)
     out = np.zeros(3)
     lib().vo_penalty(phi, rho, kappa, dt_phi, _dp(d8), _dp(out))
+    return out
+
+
+def penalty_b3(phi, rho, kappa, kmp, dt_phi, d12):
+    d12 = _f64(d12)
+    out = np.zeros(3)
+    lib().vo_penalty_b3(phi, rho, kappa, kmp, dt_phi, _dp(d12), _dp(out))
     return out
 
 
@@ -148,7 +171,7 @@ class Oracle:
 
     def __init__(self, nx, ny, phi, kappa=0.5, rates=None, g=(0.0, 0.0),
                  scale_by_phi=True, bc_x="periodic", bc_y="periodic", mask=None,
-                 force=None, penalty=True, drag=None):
+                 force=None, penalty=True, drag=None, model_b=False, eq2=False):
         r = dict(s_c=1.0, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=1.2)
         if rates:
             r.update(rates)
@@ -156,6 +179,8 @@ class Oracle:
         self.p = _Params(self.nx, self.ny, BC[bc_x], BC[bc_y], float(kappa), r["s_c"],
                          r["s_e"], r["s_eps"], r["s_q"], r["s_nu"], float(g[0]),
                          float(g[1]), 1 if scale_by_phi else 0, 1 if penalty else 0)
+        self.p.model_b = 1 if model_b else 0
+        self.p.eq2 = 1 if eq2 else 0
         shp = (self.ny, self.nx)
         self.phi = _f64(phi, shp)
         if drag is not None:  # (beta field, (usx, usy)): F^B -= phi beta (u - u_s)

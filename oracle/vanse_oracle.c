@@ -91,6 +91,12 @@ typedef struct {
    * Eq. (23), beta = phi*(1 - phi)).  NULL: no drag. */
   const double *beta;
   double usx, usy;
+  /* Model B (set I), Sec. 2.3 below Eq. (20): F^p = (kappa - 1) cs^2 grad rho
+   * and "kappa - phi" -> "kappa - 1" in the source term. */
+  int model_b;
+  /* 1: the second-order equilibrium of Appendix B (B1, moments B2) with the
+   * source term B3 in place of Eq. (14)/(18)/(20). */
+  int eq2;
 } vo_params;
 
 /* ---- threads ------------------------------------------------------------- */
@@ -164,6 +170,24 @@ void vo_meq(double phi, double rho, double ux, double uy, double kappa,
   meq[8] = pr * (ux * uy);
 }
 
+/* Equilibrium moments of the second-order equilibrium, Eq. (B2): those of
+ * Eq. (18) except the energy-flux rows, which are -phi rho u. */
+void vo_meq2(double phi, double rho, double ux, double uy, double kappa,
+             double *meq) {
+  const double X = kappa / phi;
+  const double pr = phi * rho;
+  const double uu = ux * ux + uy * uy;
+  meq[0] = pr;
+  meq[1] = pr * (-4.0 + 3.0 * uu + 2.0 * X);
+  meq[2] = pr * (4.0 - 3.0 * uu - 3.0 * X);
+  meq[3] = pr * ux;
+  meq[4] = -pr * ux;
+  meq[5] = pr * uy;
+  meq[6] = -pr * uy;
+  meq[7] = pr * (ux * ux - uy * uy);
+  meq[8] = pr * (ux * uy);
+}
+
 /* Force moments S = M F of Guo's forcing, Eq. (19). */
 void vo_force_moments(double ux, double uy, double Fx, double Fy, double *S) {
   const double uF = ux * Fx + uy * Fy;
@@ -181,18 +205,43 @@ void vo_force_moments(double ux, double uy, double Fx, double Fy, double *S) {
 /* Penalty source components (C_a, C_b, C_c) of Eq. (20). d[] holds
  * d_x(rho u_x), d_y(rho u_y), d_x u_x, d_y u_y, d_x u_y, d_y u_x,
  * d_x(phi rho u_x), d_y(phi rho u_y) at the node. */
-void vo_penalty(double phi, double rho, double kappa, double dt_phi,
-                const double *d, double *Cabc) {
+/* kmp stands for the factor "kappa - phi" of Eq. (20): kappa - phi for the
+ * consistent VANSE, kappa - 1 for model B. */
+static void penalty20(double phi, double rho, double kappa, double kmp,
+                      double dt_phi, const double *d, double *Cabc) {
   const double X = kappa / phi;
   const double drux_x = d[0], druy_y = d[1], dux_x = d[2], duy_y = d[3];
   const double duy_x = d[4], dux_y = d[5], dmux_x = d[6], dmuy_y = d[7];
   Cabc[0] = -kappa * (drux_x + druy_y) +
-            2.0 * (kappa - phi) * rho * (dux_x + duy_y) +
+            2.0 * kmp * rho * (dux_x + duy_y) +
             (3.0 - 2.0 * X) * (dmux_x + dmuy_y) - 2.0 * X * rho * dt_phi;
   Cabc[1] = -kappa * (drux_x - druy_y) +
-            2.0 / 3.0 * (kappa - phi) * rho * (dux_x - duy_y) +
+            2.0 / 3.0 * kmp * rho * (dux_x - duy_y) +
             (dmux_x - dmuy_y);
-  Cabc[2] = 1.0 / 3.0 * (kappa - phi) * rho * (duy_x + dux_y);
+  Cabc[2] = 1.0 / 3.0 * kmp * rho * (duy_x + dux_y);
+}
+
+void vo_penalty(double phi, double rho, double kappa, double dt_phi,
+                const double *d, double *Cabc) {
+  penalty20(phi, rho, kappa, kappa - phi, dt_phi, d, Cabc);
+}
+
+/* Penalty source of Eq. (B3) for the second-order equilibrium.  d[] holds
+ * the eight derivatives of Eq. (20) followed by d_x(rho u_y), d_y(rho u_x),
+ * d_x(phi rho u_y), d_y(phi rho u_x). */
+void vo_penalty_b3(double phi, double rho, double kappa, double kmp,
+                   double dt_phi, const double *d, double *Cabc) {
+  const double X = kappa / phi;
+  const double drux_x = d[0], druy_y = d[1], dux_x = d[2], duy_y = d[3];
+  const double duy_x = d[4], dux_y = d[5], dmux_x = d[6], dmuy_y = d[7];
+  const double druy_x = d[8], drux_y = d[9], dmuy_x = d[10], dmux_y = d[11];
+  Cabc[0] = -2.0 * kappa * (drux_x + druy_y) + 2.0 * kmp * rho * (dux_x + duy_y) +
+            (4.0 - 2.0 * X) * (dmux_x + dmuy_y) - 2.0 * X * rho * dt_phi;
+  Cabc[1] = -2.0 / 3.0 * kappa * (drux_x - druy_y) +
+            2.0 / 3.0 * kmp * rho * (dux_x - duy_y) +
+            2.0 / 3.0 * (dmux_x - dmuy_y);
+  Cabc[2] = -kappa / 3.0 * (druy_x + drux_y) + 1.0 / 3.0 * kmp * rho * (duy_x + dux_y) +
+            1.0 / 3.0 * (dmuy_x + dmux_y);
 }
 
 /* ---- neighbour lookup with the boundary/ghost rules ------------------------
@@ -309,7 +358,7 @@ static int work_alloc(int N, vo_work *W) {
   const size_t b = (size_t)N * sizeof(double);
   W->m0 = malloc(b); W->rho = malloc(b); W->ux = malloc(b); W->uy = malloc(b);
   W->Fx = malloc(b); W->Fy = malloc(b); W->rux = malloc(b); W->ruy = malloc(b);
-  W->mux = malloc(b); W->muy = malloc(b); W->d = malloc(8 * b); W->tmp = malloc(b);
+  W->mux = malloc(b); W->muy = malloc(b); W->d = malloc(12 * b); W->tmp = malloc(b);
   W->jx = malloc(b); W->jy = malloc(b); W->grx = malloc(b); W->gry = malloc(b);
   if (!W->m0 || !W->rho || !W->ux || !W->uy || !W->Fx || !W->Fy || !W->rux ||
       !W->ruy || !W->mux || !W->muy || !W->d || !W->tmp || !W->jx || !W->jy ||
@@ -354,8 +403,10 @@ static void macroscopic_tab(const vo_params *P, const vo_nbr *T, vo_work *W,
   for (int c = 0; c < N; ++c) {
     double ux = 0.0, uy = 0.0, Fx = 0.0, Fy = 0.0;
     if (!is_solid(mask, c)) {
-      const double Fpx = (P->kappa - phi[c]) * CS2 * grx[c];
-      const double Fpy = (P->kappa - phi[c]) * CS2 * gry[c];
+      /* Eq. (13); model B: F^p = (kappa - 1) cs^2 grad rho */
+      const double kf = P->model_b ? 1.0 : phi[c];
+      const double Fpx = (P->kappa - kf) * CS2 * grx[c];
+      const double Fpy = (P->kappa - kf) * CS2 * gry[c];
       const double sc = P->scale_by_phi ? phi[c] : 1.0;
       double FBx = sc * P->gx, FBy = sc * P->gy;
       if (fext_x) FBx += fext_x[c];
@@ -416,7 +467,9 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, vo_work *W,
   double *d_rux_x = d, *d_ruy_y = d + N, *d_ux_x = d + 2 * (size_t)N,
          *d_uy_y = d + 3 * (size_t)N, *d_uy_x = d + 4 * (size_t)N,
          *d_ux_y = d + 5 * (size_t)N, *d_mux_x = d + 6 * (size_t)N,
-         *d_muy_y = d + 7 * (size_t)N;
+         *d_muy_y = d + 7 * (size_t)N, *d_ruy_x = d + 8 * (size_t)N,
+         *d_rux_y = d + 9 * (size_t)N, *d_muy_x = d + 10 * (size_t)N,
+         *d_mux_y = d + 11 * (size_t)N;
 
   const vo_nbr T = *Tp;
 
@@ -434,12 +487,13 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, vo_work *W,
   }
 
   /* O5: the eight derivatives of Eq. (20), each by Eq. (10) */
-  gradient_tab(P, mask, &T, rux, 1, d_rux_x, tmp);
-  gradient_tab(P, mask, &T, ruy, 1, tmp, d_ruy_y);
+  gradient_tab(P, mask, &T, rux, 1, d_rux_x, d_rux_y);
+  gradient_tab(P, mask, &T, ruy, 1, d_ruy_x, d_ruy_y);
   gradient_tab(P, mask, &T, ux, 1, d_ux_x, d_ux_y);
   gradient_tab(P, mask, &T, uy, 1, d_uy_x, d_uy_y);
-  gradient_tab(P, mask, &T, mux, 1, d_mux_x, tmp);
-  gradient_tab(P, mask, &T, muy, 1, tmp, d_muy_y);
+  gradient_tab(P, mask, &T, mux, 1, d_mux_x, d_mux_y);
+  gradient_tab(P, mask, &T, muy, 1, d_muy_x, d_muy_y);
+  (void)tmp;
 
   const double s[9] = {P->s_c, P->s_e, P->s_eps, P->s_c, P->s_q,
                        P->s_c, P->s_q, P->s_nu, P->s_nu};
@@ -456,10 +510,15 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, vo_work *W,
 
       /* O6: penalty source C = (0, C_a, 0, 0, 0, 0, 0, C_b, C_c), Eq. (20) */
       const double dt_phi = phi_next ? (phi_next[c] - phi[c]) : 0.0;
-      const double dd[8] = {d_rux_x[c], d_ruy_y[c], d_ux_x[c], d_uy_y[c],
-                            d_uy_x[c],  d_ux_y[c],  d_mux_x[c], d_muy_y[c]};
+      const double dd[12] = {d_rux_x[c], d_ruy_y[c], d_ux_x[c], d_uy_y[c],
+                             d_uy_x[c],  d_ux_y[c],  d_mux_x[c], d_muy_y[c],
+                             d_ruy_x[c], d_rux_y[c], d_muy_x[c], d_mux_y[c]};
+      const double kmp = P->kappa - (P->model_b ? 1.0 : phi[c]);
       double Cabc[3];
-      vo_penalty(phi[c], rho[c], P->kappa, dt_phi, dd, Cabc);
+      if (P->eq2)
+        vo_penalty_b3(phi[c], rho[c], P->kappa, kmp, dt_phi, dd, Cabc);
+      else
+        penalty20(phi[c], rho[c], P->kappa, kmp, dt_phi, dd, Cabc);
       double C[9] = {0, Cabc[0], 0, 0, 0, 0, 0, Cabc[1], Cabc[2]};
       if (!P->use_penalty)
         for (int k = 0; k < 9; ++k) C[k] = 0.0;
@@ -472,7 +531,10 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, vo_work *W,
         for (int i = 0; i < 9; ++i) acc += MM[k][i] * fl[i];
         m[k] = acc;
       }
-      vo_meq(phi[c], rho[c], ux[c], uy[c], P->kappa, meq);
+      if (P->eq2)
+        vo_meq2(phi[c], rho[c], ux[c], uy[c], P->kappa, meq);
+      else
+        vo_meq(phi[c], rho[c], ux[c], uy[c], P->kappa, meq);
       vo_force_moments(ux[c], uy[c], Fx[c], Fy[c], S);
 
       /* O8: m+ = m - Gamma (m - m^eq) + (I - Gamma/2)(S + C), Eq. (16) */
@@ -525,14 +587,39 @@ int vo_step(const vo_params *P, const double *phi, const double *phi_next,
   return rc;
 }
 
-/* Initial populations f(0) = f^eq(rho0, u0) of Eq. (14) at every fluid node. */
+/* Second-order truncated equilibrium of Appendix B, Eq. (B1). */
+void vo_feq2(double phi, double rho, double ux, double uy, double kappa,
+             double *feq) {
+  const double uu = ux * ux + uy * uy;
+  double sum_w_nonzero = 0.0;
+  for (int i = 1; i < 9; ++i) sum_w_nonzero += WT[i];
+  feq[0] = phi * rho - sum_w_nonzero * kappa * rho -
+           WT[0] * phi * rho * uu / (2.0 * CS2);
+  for (int i = 1; i < 9; ++i) {
+    const double eu = EX[i] * ux + EY[i] * uy;
+    feq[i] = WT[i] * (kappa * rho + phi * rho * (eu / CS2 + eu * eu / (2.0 * CS2 * CS2) -
+                                                 uu / (2.0 * CS2)));
+  }
+}
+
+/* The equilibrium the scheme relaxes to: Eq. (14), or (B1) with eq2. */
+static void feq_of(const vo_params *P, double phi, double rho, double ux,
+                   double uy, double *feq) {
+  if (P->eq2)
+    vo_feq2(phi, rho, ux, uy, P->kappa, feq);
+  else
+    vo_feq(phi, rho, ux, uy, P->kappa, feq);
+}
+
+/* Initial populations f(0) = f^eq(rho0, u0) of Eq. (14) (or B1) at every
+ * fluid node. */
 void vo_init_equilibrium(const vo_params *P, const double *phi,
                          const unsigned char *mask, double rho0, double ux0,
                          double uy0, double *f) {
   const int N = P->nx * P->ny;
   for (int c = 0; c < N; ++c) {
     double feq[9] = {0};
-    if (!is_solid(mask, c)) vo_feq(phi[c], rho0, ux0, uy0, P->kappa, feq);
+    if (!is_solid(mask, c)) feq_of(P, phi[c], rho0, ux0, uy0, feq);
     for (int i = 0; i < 9; ++i) f[(size_t)i * N + c] = feq[i];
   }
 }
@@ -545,7 +632,7 @@ void vo_init_fields(const vo_params *P, const double *phi,
   const int N = P->nx * P->ny;
   for (int c = 0; c < N; ++c) {
     double feq[9] = {0};
-    if (!is_solid(mask, c)) vo_feq(phi[c], rho[c], ux[c], uy[c], P->kappa, feq);
+    if (!is_solid(mask, c)) feq_of(P, phi[c], rho[c], ux[c], uy[c], feq);
     for (int i = 0; i < 9; ++i) f[(size_t)i * N + c] = feq[i];
   }
 }

@@ -36,16 +36,17 @@ __device__ __forceinline__ T rest_pop(int i, T phi, const StepPhys<T>& ph) {
 }
 
 // Adjusted equilibrium of Eq. (14), written with cs^2 = 1/3 and X = kappa/phi:
-// the third-order factor is (3 - X)/2 on the axes and X on the diagonals.
+// the third-order factor is (3 - X)/2 on the axes and X on the diagonals; 1
+// for the second-order equilibrium of Eq. (B1) (eq2).
 __device__ inline double feq_pop(int i, double phi, double rho, double ux, double uy,
-                                 double kappa) {
+                                 double kappa, int eq2) {
   const double uu = ux * ux + uy * uy;
   if (i == 0) return phi * rho - 5.0 / 9.0 * kappa * rho - 2.0 / 3.0 * phi * rho * uu;
   const double X = kappa / phi;
   const double eu = kEX[i] * ux + kEY[i] * uy;
   const bool axis = i < 5;
   const double w = axis ? 1.0 / 9.0 : 1.0 / 36.0;
-  const double h3 = axis ? 0.5 * (3.0 - X) : X;
+  const double h3 = eq2 ? 1.0 : (axis ? 0.5 * (3.0 - X) : X);
   return w * (kappa * rho + phi * rho * (3.0 * eu * h3 + 4.5 * eu * eu - 1.5 * uu));
 }
 
@@ -166,7 +167,7 @@ __global__ void fill_state(Geo G, S* __restrict__ buf, const T* __restrict__ phi
     if (fin) {
       f = fin[j * N + (long long)yr * G.nx + xr];
     } else {
-      f = feq_pop(j, double(phr), rho_init, ux0, uy0, kappa);
+      f = feq_pop(j, double(phr), rho_init, ux0, uy0, kappa, ph.eq2);
     }
     buf[i * G.plane + (long long)y * G.pitch + x] = encode<S, T, SHIFT>(f, phr, j, ph);
   }
@@ -277,7 +278,7 @@ __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restric
     };
     const T grx = stencil_dx(R(1), R(3), R(5), R(8), R(6), R(7));
     const T gry = stencil_dy(R(2), R(4), R(5), R(6), R(8), R(7));
-    const T kp = (ph.kappa - ph_x) * T(1.0 / 3.0);
+    const T kp = (ph.kappa - (ph.model_b ? T(1) : ph_x)) * T(1.0 / 3.0);  // Eq. (13) / model B
     const T sg = ph.scale_by_phi ? ph_x : T(1);
     T Fx = kp * grx + sg * ph.gx;
     T Fy = kp * gry + sg * ph.gy;

@@ -60,6 +60,8 @@ struct StepPhys {
   T scale, inv_scale;       // storage scale of shifted half storage
   T usx, usy;               // solid velocity of the linear drag
   int scale_by_phi;
+  int model_b;  // model B (set I): kappa - 1 in place of kappa - phi in F^p and C
+  int eq2;      // second-order equilibrium (B1-B2) with the penalty of Eq. (B3)
 };
 
 struct StepGeom {
@@ -153,10 +155,14 @@ struct RowIn {
   unsigned nb;
 };
 
-// Optional features of the step (bit mask).  FEAT_ALL is built with every
-// feature and takes absent inputs as zero (null force, drag and flag planes
-// read as 0 through zero-length buffer descriptors; phin = phi when static).
-enum : int { FEAT_FORCE = 1, FEAT_DRAG = 2, FEAT_DYNPHI = 4, FEAT_MASK = 8, FEAT_ALL = 15 };
+// Optional features of the step (bit mask).  FEAT_SCHEME honours the
+// run-time scheme flags of StepPhys (model B, second-order equilibrium).
+// FEAT_ALL is built with every feature and takes absent inputs as zero (null
+// force, drag and flag planes read as 0 through zero-length buffer
+// descriptors; phin = phi when static).
+enum : int {
+  FEAT_FORCE = 1, FEAT_DRAG = 2, FEAT_DYNPHI = 4, FEAT_MASK = 8, FEAT_SCHEME = 16, FEAT_ALL = 31
+};
 
 // Solid flags of FEAT_MASK, one uint16 per node: bit 0 -- the node itself is
 // solid; bit i (1..8) -- the node standing in for x + e_i (after reflection
@@ -360,7 +366,8 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       const T grx = stencil_dx(rE, rW, rNE, rSE, rNW, rSW);
       const T gry = stencil_dy(rN, rS, rNE, rNW, rSE, rSW);
       const T phi = rB.phi;
-      const T kp = (kappa - phi) * third;
+      const T kf = ((FEAT & FEAT_SCHEME) && ph.model_b) ? T(1) : phi;
+      const T kp = (kappa - kf) * third;  // Eq. (13); kappa - 1 for model B
       const T sg = ph.scale_by_phi ? phi : T(1);
       T Fx = kp * grx + sg * ph.gx;
       T Fy = kp * gry + sg * ph.gy;
@@ -452,16 +459,39 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       const T phi = rC.phi;
       const T rho = rho0 + rC.drho;
       const T X = kappa * recip(phi);
-      const T kmp = kappa - phi;
+      const bool eq2 = (FEAT & FEAT_SCHEME) && ph.eq2;
+      const T kmp = kappa - (((FEAT & FEAT_SCHEME) && ph.model_b) ? T(1) : phi);
       const T ux = aC.ux, uy = aC.uy, Fx = bOld[0], Fy = bOld[1];
 
-      // penalty source (Eq. 20); d_t phi = phi(t+1) - phi(t), zero when static
-      T Ca = -kappa * (d_rux_x + d_ruy_y) + T(2) * kmp * rho * (d_ux_x + d_uy_y) +
+      // penalty source (Eq. 20, or B3 for the second-order equilibrium);
+      // d_t phi = phi(t+1) - phi(t), zero when static
+      T Ca, Cb, Cc;
+      if (eq2) {
+        U2<T> bE = s_u2[uo][tr], bW = s_u2[uo][tl];
+        if constexpr ((FEAT & FEAT_MASK) != 0) {
+          const U2<T> bC = s_u2[uo][t];
+          const bool sE = solid_bit(rC.nb, 1), sW = solid_bit(rC.nb, 3);
+          bE.muy = sE ? -bC.muy : bE.muy; bE.ruy = sE ? -bC.ruy : bE.ruy;
+          bW.muy = sW ? -bC.muy : bW.muy; bW.ruy = sW ? -bC.ruy : bW.ruy;
+        }
+        const T d_ruy_x = stencil_dx(bE.ruy, bW.ruy, bNE.ruy, bSE.ruy, bNW.ruy, bSW.ruy);
+        const T d_muy_x = stencil_dx(bE.muy, bW.muy, bNE.muy, bSE.muy, bNW.muy, bSW.muy);
+        const T d_rux_y = stencil_dy(aN.rux, aS.rux, aNE.rux, aNW.rux, aSE.rux, aSW.rux);
+        const T d_mux_y = stencil_dy(aN.mux, aS.mux, aNE.mux, aNW.mux, aSE.mux, aSW.mux);
+        Ca = T(-2) * kappa * (d_rux_x + d_ruy_y) + T(2) * kmp * rho * (d_ux_x + d_uy_y) +
+             (T(4) - T(2) * X) * (d_mux_x + d_muy_y);
+        Cb = T(-2.0 / 3.0) * kappa * (d_rux_x - d_ruy_y) +
+             T(2.0 / 3.0) * kmp * rho * (d_ux_x - d_uy_y) + T(2.0 / 3.0) * (d_mux_x - d_muy_y);
+        Cc = -third * kappa * (d_ruy_x + d_rux_y) + third * kmp * rho * (d_uy_x + d_ux_y) +
+             third * (d_muy_x + d_mux_y);
+      } else {
+        Ca = -kappa * (d_rux_x + d_ruy_y) + T(2) * kmp * rho * (d_ux_x + d_uy_y) +
              (T(3) - T(2) * X) * (d_mux_x + d_muy_y);
+        Cb = -kappa * (d_rux_x - d_ruy_y) + T(2.0 / 3.0) * kmp * rho * (d_ux_x - d_uy_y) +
+             (d_mux_x - d_muy_y);
+        Cc = third * kmp * rho * (d_uy_x + d_ux_y);
+      }
       if (FEAT & FEAT_DYNPHI) Ca -= T(2) * X * rho * rC.dphi;
-      const T Cb = -kappa * (d_rux_x - d_ruy_y) + T(2.0 / 3.0) * kmp * rho * (d_ux_x - d_uy_y) +
-                   (d_mux_x - d_muy_y);
-      const T Cc = third * kmp * rho * (d_uy_x + d_ux_y);
 
       // equilibria (Eq. 18) minus those of the rest state
       const T m0 = phi * rho0 + rC.dm0;  // phi rho
@@ -469,7 +499,7 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       const T uu = ux * ux + uy * uy;
       const T eq_e = (T(2) * kappa - T(4) * phi) * drho + T(3) * m0 * uu;
       const T eq_ep = (T(4) * phi - T(3) * kappa) * drho - T(3) * m0 * uu;
-      const T qfac = (kappa - T(2) * phi) * rho;  // phi rho (X - 2)
+      const T qfac = eq2 ? -m0 : (kappa - T(2) * phi) * rho;  // phi rho (X - 2), or -phi rho (B2)
       const T eq_qx = qfac * ux, eq_qy = qfac * uy;
       const T eq_pxx = m0 * (ux * ux - uy * uy);
       const T eq_pxy = m0 * (ux * uy);

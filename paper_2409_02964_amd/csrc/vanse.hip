@@ -124,6 +124,7 @@ struct vanse_lattice {
   double usx, usy;  // solid velocity of the linear drag
   double kappa, rho0, gx, gy;
   int scale_by_phi;
+  int model_b, eq2;  // scheme variants (vanse_set_scheme)
   vanse_rates rates;
   int threads, rows;  // launch shape of the step kernel
   bool tiling_default;
@@ -182,6 +183,8 @@ StepPhys<T> make_phys(const vanse_lattice* h) {
   p.usx = T(h->usx);
   p.usy = T(h->usy);
   p.scale_by_phi = h->scale_by_phi;
+  p.model_b = h->model_b;
+  p.eq2 = h->eq2;
   return p;
 }
 
@@ -218,18 +221,20 @@ int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& 
   return VANSE_OK;
 }
 
-// Specialised step variants for the force field and the drag; masks and a
-// time-varying void fraction (and any combination with them) use FEAT_ALL.
-int feat_of(const vanse_desc& d) {
-  if (d.has_mask || d.dynamic_phi) return FEAT_ALL;
+// Specialised step variants for the force field and the drag; masks, a
+// time-varying void fraction and the scheme variants (and any combination
+// with them) use FEAT_ALL.
+int feat_of(const vanse_lattice* h) {
+  const vanse_desc& d = h->d;
+  if (d.has_mask || d.dynamic_phi || h->model_b || h->eq2) return FEAT_ALL;
   return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0);
 }
 
 // Call fn(std::integral_constant<bool, WALLS>, std::integral_constant<int, FEAT>).
 template <typename Fn>
-int by_variant(const vanse_desc& d, Fn&& fn) {
-  const bool walls = d.bc_y == VANSE_WALL;
-  switch (feat_of(d)) {
+int by_variant(const vanse_lattice* h, Fn&& fn) {
+  const bool walls = h->d.bc_y == VANSE_WALL;
+  switch (feat_of(h)) {
     case FEAT_ALL: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_ALL>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_ALL>{});
     case 0: return walls ? fn(std::true_type{}, std::integral_constant<int, 0>{}) : fn(std::false_type{}, std::integral_constant<int, 0>{});
     case 1: return walls ? fn(std::true_type{}, std::integral_constant<int, 1>{}) : fn(std::false_type{}, std::integral_constant<int, 1>{});
@@ -262,7 +267,7 @@ int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
   for (int64_t s = 0; s < n; ++s) {
     g.src = h->ws + h->L.pop[h->cur];
     g.dst = h->ws + h->L.pop[h->cur ^ 1];
-    const int rc = by_variant(h->d, [&](auto walls, auto feat) -> int {
+    const int rc = by_variant(h, [&](auto walls, auto feat) -> int {
       return launch_step_w<S, T, SHIFT, decltype(walls)::value, decltype(feat)::value>(h, g, ph, blocks, st);
     });
     if (rc != VANSE_OK) return rc;
@@ -342,6 +347,7 @@ int vanse_create(const vanse_desc* d, void* workspace, size_t bytes, vanse_latti
   h->rho0 = 1.0;
   h->gx = h->gy = 0.0;
   h->scale_by_phi = 1;
+  h->model_b = h->eq2 = 0;
   h->rates = vanse_rates{1.0, 1.2, 1.2, 1.2, 1.2};
   h->storage_exp = 12;
   h->version = 0;
@@ -366,6 +372,18 @@ int vanse_set_params(vanse_lattice* h, double kappa, const vanse_rates* r) {
   h->kappa = kappa;
   h->rates = *r;
   h->params_set = true;
+  h->version += 1;
+  return VANSE_OK;
+}
+
+int vanse_set_scheme(vanse_lattice* h, int model, int equilibrium_order) {
+  if (int rc = check_handle(h)) return rc;
+  if (model != VANSE_MODEL_A && model != VANSE_MODEL_B) return fail(VANSE_ERR_INVALID_ARG, "unknown model %d", model);
+  if (equilibrium_order != 2 && equilibrium_order != 3)
+    return fail(VANSE_ERR_INVALID_ARG, "equilibrium order must be 2 or 3 (got %d)", equilibrium_order);
+  if (h->state_set) return fail(VANSE_ERR_STATE, "the scheme must be chosen before the populations");
+  h->model_b = model == VANSE_MODEL_B;
+  h->eq2 = equilibrium_order == 2;
   h->version += 1;
   return VANSE_OK;
 }
@@ -563,7 +581,7 @@ static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double
     const T* fx = h->d.has_force_field ? (const T*)(h->ws + h->L.fx) : nullptr;
     const T* fy = h->d.has_force_field ? (const T*)(h->ws + h->L.fy) : nullptr;
     const T* beta = h->d.has_drag ? (const T*)(h->ws + h->L.beta) : nullptr;
-    return by_variant(h->d, [&](auto walls, auto feat) -> int {
+    return by_variant(h, [&](auto walls, auto feat) -> int {
       (void)walls;
       T* up = keep_u ? (T*)(h->ws + h->L.uprev) : nullptr;
       hipLaunchKernelGGL((moments_out<S, T, SH, decltype(feat)::value>), field_grid(h), dim3(256), 0, st, G,
@@ -746,8 +764,9 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, std::
   for (int k = 0; k < n; ++k) {
     if (!lats[k]) return fail(VANSE_ERR_INVALID_ARG, "lattice %d is NULL", k);
     const vanse_desc& d = lats[k]->d;
-    if (d.has_mask || d.dynamic_phi)
-      return fail(VANSE_ERR_UNSUPPORTED, "lattice %d: batches take lattices without mask or time-varying phi", k);
+    if (feat_of(lats[k]) == FEAT_ALL)
+      return fail(VANSE_ERR_UNSUPPORTED,
+                  "lattice %d: batches take lattices without mask, time-varying phi or scheme variant", k);
     if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field ||
         d.has_drag != d0.has_drag)
       return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary, force field or drag", k);
@@ -853,9 +872,9 @@ int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
     using S = std::remove_pointer_t<decltype(s_tag)>;
     using T = std::remove_pointer_t<decltype(t_tag)>;
     constexpr bool SH = decltype(shift)::value;
-    return by_variant(b->lats[0]->d, [&](auto walls, auto feat) -> int {
+    return by_variant(b->lats[0], [&](auto walls, auto feat) -> int {
       if constexpr (decltype(feat)::value == FEAT_ALL) {
-        return fail(VANSE_ERR_UNSUPPORTED, "batches take lattices without mask or time-varying phi");
+        return fail(VANSE_ERR_UNSUPPORTED, "batches take lattices without mask, time-varying phi or scheme variant");
       } else {
         batch_launch_t<S, T, SH, decltype(walls)::value, decltype(feat)::value>(b, launch, st);
         return VANSE_OK;
@@ -935,6 +954,7 @@ int vanse_batch_step(vanse_batch* b, int64_t nsteps, void* stream) {
   for (vanse_lattice* h : b->lats) {
     if (int rc = check_ready(h)) return rc;
     if (!h->state_set) return fail(VANSE_ERR_STATE, "a lattice of the batch has no populations");
+    if (feat_of(h) == FEAT_ALL) return fail(VANSE_ERR_UNSUPPORTED, "a lattice of the batch uses a variant batches do not take");
   }
   if (nsteps == 0) return VANSE_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);

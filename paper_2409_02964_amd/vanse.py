@@ -29,7 +29,8 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4:
 
 EXPORTS = [
     "vanse_workspace_bytes", "vanse_create", "vanse_destroy", "vanse_set_params",
-    "vanse_set_body_force", "vanse_set_void_fraction", "vanse_set_void_fraction_next",
+    "vanse_set_scheme", "vanse_set_body_force", "vanse_set_void_fraction",
+    "vanse_set_void_fraction_next",
     "vanse_set_mask", "vanse_set_force_field", "vanse_set_drag",
     "vanse_init_equilibrium", "vanse_set_populations", "vanse_step", "vanse_read_moments",
     "vanse_read_populations", "vanse_observe", "vanse_residual", "vanse_set_tiling",
@@ -81,6 +82,7 @@ def lib():
                 "vanse_destroy": [vp],
                 "vanse_set_params": [vp, d, C.POINTER(Rates)],
                 "vanse_set_body_force": [vp, d, d, i32],
+                "vanse_set_scheme": [vp, i32, i32],
                 "vanse_set_void_fraction": [vp, vp, vp],
                 "vanse_set_void_fraction_next": [vp, vp, vp],
                 "vanse_set_mask": [vp, vp, vp],
@@ -188,6 +190,12 @@ class Lattice:
         r.update(rates or {})
         rr = Rates(r["s_c"], r["s_e"], r["s_eps"], r["s_q"], r["s_nu"])
         check(lib().vanse_set_params(self.handle, float(kappa), C.byref(rr)))
+        return self
+
+    def set_scheme(self, model="A", equilibrium_order=3):
+        """Model "A" (the consistent VANSE) or "B" (set I), and the
+        equilibrium order 3 (Eq. 14) or 2 (Appendix B); before the populations."""
+        check(lib().vanse_set_scheme(self.handle, {"A": 0, "B": 1}[model], int(equilibrium_order)))
         return self
 
     def set_body_force(self, gx, gy=0.0, scale_by_phi=True):

@@ -155,3 +155,18 @@ def test_batches_reject_masks_and_moving_phi(mask, dynamic):
     assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == -6
     for h in hs:
         assert L.vanse_destroy(h) == 0
+
+
+def test_scheme_validation_on_the_host():
+    L = V.lib()
+    h = _fake_handle()
+    assert L.vanse_set_scheme(h, 2, 3) == -1
+    assert L.vanse_set_scheme(h, 0, 1) == -1
+    assert L.vanse_set_scheme(h, 1, 2) == 0
+    other = _fake_handle()
+    arr = (C.c_void_p * 2)(other.value, h.value)
+    n = C.c_size_t()
+    assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == -6  # variants are not batched
+    assert L.vanse_set_scheme(h, 0, 3) == 0
+    assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == 0
+    assert L.vanse_destroy(h) == 0 and L.vanse_destroy(other) == 0

@@ -1,5 +1,6 @@
-"""GPU parity of the optional inputs: solid nodes (a mask) and a
-time-varying void fraction (the d_t phi term of Eq. 20), through the C ABI,
+"""GPU parity of the optional inputs and scheme variants: solid nodes (a mask), a
+time-varying void fraction (the d_t phi term of Eq. 20), model B and the
+second-order equilibrium of Appendix B, through the C ABI,
 against the FP64 oracle on the same seeded inputs.
 
 Tolerances as in test_gpu_parity: FP64 one step max|df| <= 1e-14 max|f| on
@@ -300,3 +301,83 @@ def test_dynamic_phi_errors():
     plain.set_params(0.5, C1_RATES).set_void_fraction(phi)
     with pytest.raises(VanseError):
         plain.set_void_fraction_next(phi)
+
+
+# ---- scheme variants: model B and the second-order equilibrium ------------------
+
+SCHEMES = [("B", 3), ("A", 2), ("B", 2)]
+
+
+@pytest.mark.parametrize("model,order", SCHEMES)
+@pytest.mark.parametrize("bc,with_mask", [("periodic", False), ("wall", True)])
+def test_one_step_scheme_variants_fp64(oracle, model, order, bc, with_mask):
+    torch = _torch()
+    nx, ny = 57, 34
+    _say(f"one-step scheme {model}/{order} fp64 {bc} mask={with_mask}")
+    phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 2.5, seed=31) ** 2
+    mask = W.solid_mask(nx, ny, seed=8) if with_mask else None
+    fluid = np.ones((ny, nx), bool) if mask is None else mask == 0
+    f0 = W.random_populations(nx, ny, seed=17)
+    g = (1e-5, 2e-6)
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=g, bc_y=bc, mask=mask,
+                        model_b=model == "B", eq2=order == 2)
+    ora.set_populations(f0)
+    ora.step(1)
+    lat = lattice(nx, ny, phi, "f64", bc, mask=mask, g=g)
+    lat.set_scheme(model, order)
+    lat.set_populations(torch.from_numpy(f0)).step(1)
+    fg = lat.read_populations().cpu().numpy()
+    err = np.max(np.abs(fg[:, fluid] - ora.f[:, fluid])) / np.max(np.abs(ora.f))
+    _say(f"   max rel err {err:.3e}")
+    assert err <= 1e-14
+    mg, mo = to_np(lat.read_moments()), ora.macroscopic()
+    assert rel_l2_u(mg, mo, fluid) <= 1e-13  # F^p of model B in the read-out too
+
+
+def test_appendix_b_equilibrium_init_and_mms(oracle):
+    """Eq. (B1) initial state, then manufactured case I with the B scheme:
+    the GPU follows the oracle over 400 steps."""
+    _torch()
+    n, nu = 32, 0.1
+    m = W.mms_case("I", n, 0.5, 0.4, 0.8, nu)
+    rates = dict(s_c=1.0, s_e=1.0 / (nu + 0.5), s_eps=1.2, s_q=1.4, s_nu=1.0 / (3 * nu + 0.5))
+    ora = oracle.Oracle(n, n, m["phi"], kappa=0.1, rates=rates, scale_by_phi=False,
+                        force=(m["fx"], m["fy"]), eq2=True).init_equilibrium(1.0, 0.01, -0.02)
+    lat = lattice(n, n, m["phi"], "f64", force=(m["fx"], m["fy"]), scale_by_phi=False,
+                  kappa=0.1, rates=rates)
+    lat.set_scheme("A", 2).init_equilibrium(1.0, 0.01, -0.02)
+    f_init = lat.read_populations().cpu().numpy()
+    assert np.max(np.abs(f_init - ora.f)) <= 1e-15
+    ora.step(400)
+    lat.step(400)
+    e = rel_l2_u(to_np(lat.read_moments()), ora.macroscopic())
+    _say(f"appendix-B MMS I 400 steps: rel-L2(u) {e:.3e}")
+    assert e <= 1e-12
+
+
+@pytest.mark.parametrize("prec,bound", [("f32s", 1e-4), ("f16s", 5e-2)])
+def test_model_b_reduced_precision(oracle, prec, bound):
+    _torch()
+    nx, ny, steps = 64, 48, 400
+    phi = W.channel_phi(nx, ny, seed=3, lo=0.5)
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=(2e-6, 0), bc_y="wall",
+                        model_b=True).init_equilibrium()
+    ora.step(steps)
+    lat = lattice(nx, ny, phi, prec, "wall", g=(2e-6, 0))
+    lat.set_scheme("B", 3).init_equilibrium(1.0)
+    lat.step(steps)
+    e = rel_l2_u(to_np(lat.read_moments()), ora.macroscopic())
+    _say(f"model B {prec}: rel-L2(u) {e:.3e}")
+    assert e <= bound
+
+
+def test_scheme_errors():
+    _torch()
+    from paper_2409_02964_amd.vanse import VanseError
+    phi = np.full((16, 16), 0.8)
+    lat = lattice(16, 16, phi, "f64")
+    with pytest.raises(VanseError):
+        lat.set_scheme("A", 4)
+    lat.set_scheme("B", 2).init_equilibrium(1.0)
+    with pytest.raises(VanseError):  # fixed once populations exist
+        lat.set_scheme("A", 3)

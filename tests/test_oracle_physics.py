@@ -134,8 +134,11 @@ def textbook_mrt(f, rates, Fx, Fy, steps):
     return f
 
 
+@pytest.mark.parametrize("eq2", [False, True])
 @pytest.mark.parametrize("level", [1.0, 0.6])
-def test_uniform_phi_equal_kappa_is_textbook_mrt(oracle, level):
+def test_uniform_phi_equal_kappa_is_textbook_mrt(oracle, level, eq2):
+    """phi == kappa: F^p = 0, C = 0 and the equilibrium (Eq. 14 with X = 1,
+    or B1) is the standard one -- for both equilibria of the paper."""
     nx, ny = 24, 20
     phi = np.full((ny, nx), level)
     x = np.arange(nx)[None, :]
@@ -145,7 +148,7 @@ def test_uniform_phi_equal_kappa_is_textbook_mrt(oracle, level):
     rho = 1 + 0.01 * np.sin(2 * np.pi * (x / nx + y / ny))
     r = rates_for(0.1, s_c=1.1)
     g = (3e-5, -1e-5)
-    o = oracle.Oracle(nx, ny, phi, kappa=level, rates=r, g=g)
+    o = oracle.Oracle(nx, ny, phi, kappa=level, rates=r, g=g, eq2=eq2)
     o.init_fields(rho, ux, uy)
     f0 = o.f.copy()
     o.step(100)
@@ -208,7 +211,7 @@ def test_equal_rates_without_penalty_is_bgk(oracle):
 
 # ---- P7: shear-wave decay (exercises C_c and C_b) -----------------------------
 
-def _decay_rate(oracle, L, direction, penalty, phi=0.75, kappa=0.5, nu=0.1):
+def _decay_rate(oracle, L, direction, penalty, phi=0.75, kappa=0.5, nu=0.1, **scheme):
     x = np.arange(L)[None, :] * np.ones((L, 1))
     y = np.arange(L)[:, None] * np.ones((1, L))
     A = 1e-4
@@ -223,7 +226,7 @@ def _decay_rate(oracle, L, direction, penalty, phi=0.75, kappa=0.5, nu=0.1):
         ux, uy = A * shape, -A * shape
         proj = lambda m: np.sum((m["ux"] - m["uy"]) * shape)
     o = oracle.Oracle(L, L, np.full((L, L), phi), kappa=kappa, rates=rates_for(nu),
-                      penalty=penalty)
+                      penalty=penalty, **scheme)
     o.init_fields(np.ones((L, L)), ux, uy)
     T = int(round(0.5 / (nu * k2)))
     o.step(T)
@@ -289,10 +292,10 @@ def test_poiseuille_exact_with_tuned_rates_when_phi_equals_kappa(oracle):
 
 # ---- P10: manufactured solutions, second-order convergence ---------------------
 
-def _mms_error(oracle, case, n, a, b, nu, kappa, s_eps, s_q, us=0.8):
+def _mms_error(oracle, case, n, a, b, nu, kappa, s_eps, s_q, us=0.8, **scheme):
     m = W.mms_case(case, n, a, b, us, nu)
     o = oracle.Oracle(n, n, m["phi"], kappa=kappa, rates=rates_for(nu, s_eps=s_eps, s_q=s_q),
-                      scale_by_phi=False, force=(m["fx"], m["fy"]))
+                      scale_by_phi=False, force=(m["fx"], m["fy"]), **scheme)
     o.init_fields(np.ones((n, n)), m["ux"], m["uy"])
     den = np.sum(m["ux"] ** 2 + m["uy"] ** 2)
     chunk = max(10, int(0.5 / (nu * (2 * np.pi / n) ** 2)))
@@ -502,3 +505,84 @@ def test_mms_case_III_second_order(oracle):
     assert errs[1] < 0.03
     wrong = _mms3_error(oracle, 32, 0.5, 0.25, 0.1, 0.3, dt_phi=False)
     assert wrong > 5 * errs[1]
+
+
+
+# ---- Appendix B: the second-order equilibrium and its penalty term -----------
+
+def test_appendix_b_equilibrium_moments(oracle):
+    """M f^eq(B1) = m^eq(B2), and B1 carries mass phi rho, momentum phi rho u
+    and the second moment kappa rho cs^2 I + phi rho u u."""
+    M, _, ex, ey, _, _ = oracle.tables()
+    for phi, rho, ux, uy, kappa in [(0.7, 1.02, 0.03, -0.02, 0.5), (0.35, 0.97, -0.01, 0.04, 0.3)]:
+        f = oracle.feq2(phi, rho, ux, uy, kappa)
+        assert np.allclose(M @ f, oracle.meq2(phi, rho, ux, uy, kappa), rtol=0, atol=1e-15)
+        assert abs(f.sum() - phi * rho) < 1e-15
+        assert abs(ex @ f - phi * rho * ux) < 1e-16 and abs(ey @ f - phi * rho * uy) < 1e-16
+        assert abs((ex * ex) @ f - (kappa * rho * CS2 + phi * rho * ux * ux)) < 1e-15
+        assert abs((ex * ey) @ f - phi * rho * ux * uy) < 1e-16
+        # only the energy-flux rows differ from Eq. (18): -phi rho u against phi rho (X - 2) u
+        d = oracle.meq(phi, rho, ux, uy, kappa) - oracle.meq2(phi, rho, ux, uy, kappa)
+        X = kappa / phi
+        assert np.allclose(d, [0, 0, 0, 0, phi * rho * (X - 1) * ux, 0, phi * rho * (X - 1) * uy, 0, 0],
+                           rtol=0, atol=1e-16)
+
+
+APPB_RUNS = [
+    pytest.param("I", 0.5, 0.4, 0.1, 0.1, 1.2, 1.4, id="I-nu0.1"),
+    pytest.param("II", 0.5, 0.3, 1.0, 0.5, 1.2, 1.4, id="II-nu1.0"),
+]
+
+
+@pytest.mark.parametrize("case,a,b,nu,kappa,s_eps,s_q", APPB_RUNS)
+def test_appendix_b_scheme_second_order(oracle, case, a, b, nu, kappa, s_eps, s_q):
+    """The second-order equilibrium (B1-B2) with the penalty of Eq. (B3)
+    recovers the VANSE as well: manufactured cases I and II converge at
+    second order (slope over n = 32, 64), and without B3 they do not."""
+    errs = [_mms_error(oracle, case, n, a, b, nu, kappa, s_eps, s_q, eq2=True) for n in (16, 32, 64)]
+    slope = math.log(errs[1] / errs[2]) / math.log(2.0)
+    assert 1.7 <= slope <= 2.3, (errs, slope)
+    assert errs[-1] < 0.02
+    wrong = _mms_error(oracle, case, 64, a, b, nu, kappa, s_eps, s_q, eq2=True, penalty=False)
+    assert wrong > 10 * errs[-1]
+
+
+# ---- model B (set I): F^p and the source term with kappa - 1 -------------------
+
+@pytest.mark.parametrize("eq2", [False, True])
+def test_model_b_shear_wave_decays_at_nu_over_phi(oracle, eq2):
+    """Model B (set I) has the viscous term div(tau) without the phi factor:
+    in uniform phi a shear wave obeys phi d_t u = nu lap u, i.e. decays at
+    nu k^2 / phi (second-order convergence), where the consistent VANSE
+    (Eq. 1) gives nu k^2."""
+    phi = 0.75
+    errs = []
+    for L in (16, 32, 64):
+        lam, exact = _decay_rate(oracle, L, "axis", penalty=True, phi=phi, model_b=True, eq2=eq2)
+        errs.append(abs(lam / (exact / phi) - 1))
+    assert errs[-1] < 2e-3 and errs[0] / errs[-1] > 8, errs
+
+
+def _hydrostatic_gradient(oracle, model_b, H=32, G=1e-6):
+    y = np.arange(H)[:, None] + 0.5
+    phi = (0.5 + 0.4 * np.sin(np.pi * y / H) ** 2) * np.ones((1, 4))
+    o = oracle.Oracle(4, H, phi, kappa=0.5, rates=rates_for(0.1), g=(0.0, -G), bc_y="wall",
+                      model_b=model_b).init_equilibrium()
+    o.step(40000)
+    m = o.macroscopic()
+    grad = np.diff(m["rho"][:, 0]) / (-G / CS2)  # (d rho / dy) / (G / cs^2)
+    phim = 0.5 * (phi[1:, 0] + phi[:-1, 0])
+    return grad, phim, np.max(np.abs(m["uy"]))
+
+
+def test_model_a_and_b_hydrostatics(oracle):
+    """A closed column at rest under F^B = phi G with phi(y): the consistent
+    VANSE balances phi grad p = phi G (grad p = G), model B balances
+    grad p = phi G.  Checked away from the two wall-adjacent rows, where the
+    Eq. (10) stand-ins act."""
+    grad, phim, umax = _hydrostatic_gradient(oracle, model_b=False)
+    assert umax < 1e-6
+    assert np.max(np.abs(grad[2:-2] - 1.0)) < 5e-3
+    grad, phim, umax = _hydrostatic_gradient(oracle, model_b=True)
+    assert umax < 1e-6
+    assert np.max(np.abs(grad[2:-2] / phim[2:-2] - 1.0)) < 5e-3
