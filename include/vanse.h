@@ -112,6 +112,15 @@ int vanse_set_params(vanse_lattice *h, double kappa, const vanse_rates *r);
  * derivatives).  Only before the populations are set. */
 int vanse_set_scheme(vanse_lattice *h, int model, int equilibrium_order);
 
+/* Tangential (x) velocities of the walls on the faces y = -1/2 (u_lo) and
+ * y = ny - 1/2 (u_hi); default 0.  A population crossing a moving wall
+ * returns less the odd part of the equilibrium (Eq. 14, or B1) at
+ * (phi(x), rho0, u_w) -- the moving-wall form of half-way bounce-back used for
+ * Couette flow (Sec. 3.1, Eq. 22 II) -- and the Eq. (10) stand-ins across
+ * the wall carry 2 u_w - u.  Needs bc_y = VANSE_WALL; only before the
+ * populations are set. */
+int vanse_set_wall_velocity(vanse_lattice *h, double u_lo, double u_hi);
+
 /* Uniform external acceleration G: F^B = phi*G (scale_by_phi = 1, the form
  * F^B = phi(G - ...) of Sec. 3.1 and Eq. 23) or F^B = G (scale_by_phi = 0).
  * Defaults: G = 0, scale_by_phi = 1. */
@@ -224,7 +233,8 @@ int vanse_stream_copy(vanse_lattice *h, int64_t n, void *stream);
  * written again automatically when a member changed or was stepped on its
  * own.  Member handles stay usable (vanse_time, vanse_read_*).  Lattices with
  * a mask or a time-varying void fraction are not batched
- * (VANSE_ERR_UNSUPPORTED), and so are lattices with a scheme variant. */
+ * (VANSE_ERR_UNSUPPORTED), and so are lattices with a scheme variant or
+ * moving walls. */
 typedef struct vanse_batch vanse_batch;
 
 /* Workspace bytes for a batch of n lattices with the given workgroup width

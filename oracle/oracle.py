@@ -44,7 +44,8 @@ class _Params(C.Structure):
                 ("s_nu", C.c_double), ("gx", C.c_double), ("gy", C.c_double),
                 ("scale_by_phi", C.c_int), ("use_penalty", C.c_int),
                 ("beta", C.POINTER(C.c_double)), ("usx", C.c_double), ("usy", C.c_double),
-                ("model_b", C.c_int), ("eq2", C.c_int)]
+                ("model_b", C.c_int), ("eq2", C.c_int), ("uw_lo", C.c_double),
+                ("uw_hi", C.c_double), ("rho_w", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -171,7 +172,8 @@ class Oracle:
 
     def __init__(self, nx, ny, phi, kappa=0.5, rates=None, g=(0.0, 0.0),
                  scale_by_phi=True, bc_x="periodic", bc_y="periodic", mask=None,
-                 force=None, penalty=True, drag=None, model_b=False, eq2=False):
+                 force=None, penalty=True, drag=None, model_b=False, eq2=False,
+                 wall_velocity=(0.0, 0.0), rho_w=1.0):
         r = dict(s_c=1.0, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=1.2)
         if rates:
             r.update(rates)
@@ -181,6 +183,9 @@ class Oracle:
                          float(g[1]), 1 if scale_by_phi else 0, 1 if penalty else 0)
         self.p.model_b = 1 if model_b else 0
         self.p.eq2 = 1 if eq2 else 0
+        # x velocities of the walls at y = -1/2 and y = ny - 1/2 (bc_y = "wall")
+        self.p.uw_lo, self.p.uw_hi = float(wall_velocity[0]), float(wall_velocity[1])
+        self.p.rho_w = float(rho_w)
         shp = (self.ny, self.nx)
         self.phi = _f64(phi, shp)
         if drag is not None:  # (beta field, (usx, usy)): F^B -= phi beta (u - u_s)

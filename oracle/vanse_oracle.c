@@ -97,6 +97,12 @@ typedef struct {
   /* 1: the second-order equilibrium of Appendix B (B1, moments B2) with the
    * source term B3 in place of Eq. (14)/(18)/(20). */
   int eq2;
+  /* Tangential (x) velocities of the walls on the faces y = -1/2 (lo) and
+   * y = ny - 1/2 (hi), and the density rho_w of the moving-wall bounce-back:
+   * a population f+_i crossing a wall returns as f_opp(i) = f+_i - (f^eq_i -
+   * f^eq_opp(i)) at (phi(x), rho_w, u_w), and the Eq. (10) stand-in across the
+   * wall carries 2 u_w - u (Sec. 3.1, Couette flow of Eq. 22). */
+  double uw_lo, uw_hi, rho_w;
 } vo_params;
 
 /* ---- threads ------------------------------------------------------------- */
@@ -253,9 +259,10 @@ static int is_solid(const unsigned char *mask, int idx) {
 }
 
 static int neighbour(const vo_params *P, const unsigned char *mask, int x,
-                     int y, int dx, int dy, int *sign) {
+                     int y, int dx, int dy, int *sign, int *wall) {
   int xn = x + dx, yn = y + dy;
   int reflected = 0;
+  *wall = 0;
   if (xn < 0 || xn >= P->nx) {
     if (P->bc_x == 0) {
       xn = (xn + P->nx) % P->nx;
@@ -268,14 +275,16 @@ static int neighbour(const vo_params *P, const unsigned char *mask, int x,
     if (P->bc_y == 0) {
       yn = (yn + P->ny) % P->ny;
     } else {
+      *wall = (yn < 0) ? 1 : 2;
       yn = (yn < 0) ? -1 - yn : 2 * P->ny - 1 - yn;
       reflected = 1;
     }
   }
   int idx = yn * P->nx + xn;
-  if (is_solid(mask, idx)) { /* solid neighbour: centre value */
+  if (is_solid(mask, idx)) { /* solid neighbour (at rest): centre value */
     idx = y * P->nx + x;
     reflected = 1;
+    *wall = 0;
   }
   *sign = reflected ? -1 : 1;
   return idx;
@@ -286,21 +295,24 @@ static int neighbour(const vo_params *P, const unsigned char *mask, int x,
 typedef struct {
   int *idx;         /* [9][N] */
   signed char *sgn; /* [9][N] */
+  signed char *wl;  /* [9][N]: 1 / 2 when the stand-in is across the lo / hi y-wall */
 } vo_nbr;
 
 static int nbr_build(const vo_params *P, const unsigned char *mask, vo_nbr *T) {
   const int N = P->nx * P->ny;
   T->idx = malloc((size_t)9 * N * sizeof(int));
   T->sgn = malloc((size_t)9 * N);
-  if (!T->idx || !T->sgn) return -1;
+  T->wl = malloc((size_t)9 * N);
+  if (!T->idx || !T->sgn || !T->wl) return -1;
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < P->ny; ++y)
     for (int x = 0; x < P->nx; ++x)
       for (int i = 0; i < 9; ++i) {
-        int sign;
+        int sign, wall;
         const int c = y * P->nx + x;
-        T->idx[(size_t)i * N + c] = neighbour(P, mask, x, y, EX[i], EY[i], &sign);
+        T->idx[(size_t)i * N + c] = neighbour(P, mask, x, y, EX[i], EY[i], &sign, &wall);
         T->sgn[(size_t)i * N + c] = (signed char)sign;
+        T->wl[(size_t)i * N + c] = (signed char)wall;
       }
   return 0;
 }
@@ -308,13 +320,17 @@ static int nbr_build(const vo_params *P, const unsigned char *mask, vo_nbr *T) {
 static void nbr_free(vo_nbr *T) {
   free(T->idx);
   free(T->sgn);
+  free(T->wl);
 }
 
 /* Isotropic gradient, Eq. (10): d_a psi = 1/(cs^2 dt) sum_i w_i psi(x+e_i) e_ia.
- * odd = 1 for velocity-like fields (negated at reflected stand-ins). */
-static void gradient_tab(const vo_params *P, const unsigned char *mask,
-                         const vo_nbr *T, const double *psi, int odd,
-                         double *gx, double *gy) {
+ * odd = 1 for velocity-like fields (negated at reflected stand-ins).  xcomp
+ * = 1 for the x component of a velocity-like field s u: across a moving wall
+ * its stand-in is s (2 u_w - u), i.e. gains 2 u_w s, with s = 1 (scal NULL)
+ * or scal at the image node. */
+static void gradient_wall(const vo_params *P, const unsigned char *mask,
+                          const vo_nbr *T, const double *psi, int odd, int xcomp,
+                          const double *scal, double *gx, double *gy) {
   const int N = P->nx * P->ny;
 #pragma omp parallel for schedule(static)
   for (int c = 0; c < N; ++c) {
@@ -326,13 +342,24 @@ static void gradient_tab(const vo_params *P, const unsigned char *mask,
     double sx = 0.0, sy = 0.0;
     for (int i = 0; i < 9; ++i) {
       const int n = T->idx[(size_t)i * N + c];
-      const double v = (odd && T->sgn[(size_t)i * N + c] < 0) ? -psi[n] : psi[n];
+      double v = (odd && T->sgn[(size_t)i * N + c] < 0) ? -psi[n] : psi[n];
+      const int wl = T->wl[(size_t)i * N + c];
+      if (odd && xcomp && wl) {
+        const double uw = (wl == 1) ? P->uw_lo : P->uw_hi;
+        v += 2.0 * uw * (scal ? scal[n] : 1.0);
+      }
       sx += WT[i] * v * EX[i];
       sy += WT[i] * v * EY[i];
     }
     gx[c] = sx / CS2;
     gy[c] = sy / CS2;
   }
+}
+
+static void gradient_tab(const vo_params *P, const unsigned char *mask,
+                         const vo_nbr *T, const double *psi, int odd,
+                         double *gx, double *gy) {
+  gradient_wall(P, mask, T, psi, odd, 0, NULL, gx, gy);
 }
 
 void vo_gradient(const vo_params *P, const unsigned char *mask,
@@ -451,6 +478,9 @@ void vo_macroscopic(const vo_params *P, const double *phi,
   work_free(&W);
 }
 
+static void feq_of(const vo_params *P, double phi, double rho, double ux,
+                   double uy, double *feq);
+
 /* ---- one time step, Eq. (16) followed by streaming ------------------------
  * f: post-stream populations at t; fout receives those at t+1.  phi_next,
  * mask, fext_x, fext_y may be NULL.  Returns 0, or -1 on allocation failure. */
@@ -487,12 +517,12 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, vo_work *W,
   }
 
   /* O5: the eight derivatives of Eq. (20), each by Eq. (10) */
-  gradient_tab(P, mask, &T, rux, 1, d_rux_x, d_rux_y);
-  gradient_tab(P, mask, &T, ruy, 1, d_ruy_x, d_ruy_y);
-  gradient_tab(P, mask, &T, ux, 1, d_ux_x, d_ux_y);
-  gradient_tab(P, mask, &T, uy, 1, d_uy_x, d_uy_y);
-  gradient_tab(P, mask, &T, mux, 1, d_mux_x, d_mux_y);
-  gradient_tab(P, mask, &T, muy, 1, d_muy_x, d_muy_y);
+  gradient_wall(P, mask, &T, rux, 1, 1, rho, d_rux_x, d_rux_y);
+  gradient_wall(P, mask, &T, ruy, 1, 0, NULL, d_ruy_x, d_ruy_y);
+  gradient_wall(P, mask, &T, ux, 1, 1, NULL, d_ux_x, d_ux_y);
+  gradient_wall(P, mask, &T, uy, 1, 0, NULL, d_uy_x, d_uy_y);
+  gradient_wall(P, mask, &T, mux, 1, 1, m0, d_mux_x, d_mux_y);
+  gradient_wall(P, mask, &T, muy, 1, 0, NULL, d_muy_x, d_muy_y);
   (void)tmp;
 
   const double s[9] = {P->s_c, P->s_e, P->s_eps, P->s_c, P->s_q,
@@ -554,14 +584,25 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, vo_work *W,
       for (int i = 0; i < 9; ++i) {
         int xn = x + EX[i], yn = y + EY[i];
         int blocked = 0;
+        double uw = 0.0; /* tangential velocity of the wall crossed */
         if (xn < 0 || xn >= nx) {
           if (P->bc_x == 0) xn = (xn + nx) % nx; else blocked = 1;
         }
         if (yn < 0 || yn >= ny) {
-          if (P->bc_y == 0) yn = (yn + ny) % ny; else blocked = 1;
+          if (P->bc_y == 0) {
+            yn = (yn + ny) % ny;
+          } else {
+            blocked = 1;
+            uw = (yn < 0) ? P->uw_lo : P->uw_hi;
+          }
         }
         if (!blocked && is_solid(mask, yn * nx + xn)) blocked = 1;
-        if (blocked)
+        if (blocked && uw != 0.0) {
+          /* moving wall: subtract the odd part of the equilibrium at u_w */
+          double fw[9];
+          feq_of(P, phi[c], P->rho_w, uw, 0.0, fw);
+          fout[(size_t)OPP[i] * N + c] = fp[i] - (fw[i] - fw[OPP[i]]);
+        } else if (blocked)
           fout[(size_t)OPP[i] * N + c] = fp[i];
         else
           fout[(size_t)i * N + (yn * nx + xn)] = fp[i];

@@ -50,6 +50,17 @@ __device__ inline double feq_pop(int i, double phi, double rho, double ux, doubl
   return w * (kappa * rho + phi * rho * (3.0 * eu * h3 + 4.5 * eu * eu - 1.5 * uu));
 }
 
+// Moving-wall correction of a population f+_i that crossed the wall at
+// y = -1/2 (lo) or y = ny - 1/2 (hi): it returns as f_opp(i) = f+_i - delta,
+// delta = f^eq_i - f^eq_opp(i) at (phi, rho0, u_w).
+template <typename T>
+__device__ inline double wall_delta(int i, T phi, bool lo, const StepPhys<T>& ph) {
+  const double uw = double(lo ? ph.uw_lo : ph.uw_hi);
+  if (uw == 0.0) return 0.0;
+  return feq_pop(i, double(phi), double(ph.rho0), uw, 0.0, double(ph.kappa), ph.eq2) -
+         feq_pop(kOPP[i], double(phi), double(ph.rho0), uw, 0.0, double(ph.kappa), ph.eq2);
+}
+
 template <typename S, typename T, bool SHIFT>
 __device__ __forceinline__ S encode(double f, T phi, int i, const StepPhys<T>& ph) {
   if (SHIFT) return static_cast<S>((static_cast<T>(f - double(rest_pop(i, phi, ph)))) * ph.scale);
@@ -169,6 +180,9 @@ __global__ void fill_state(Geo G, S* __restrict__ buf, const T* __restrict__ phi
     } else {
       f = feq_pop(j, double(phr), rho_init, ux0, uy0, kappa, ph.eq2);
     }
+    const int yn = y + kEY[i];
+    if (!through && G.walls && (yn < 0 || yn >= G.ny))  // the pull subtracts it again
+      f += wall_delta(i, phr, yn < 0, ph);
     buf[i * G.plane + (long long)y * G.pitch + x] = encode<S, T, SHIFT>(f, phr, j, ph);
   }
 }
@@ -183,13 +197,18 @@ __device__ __forceinline__ double pull_one(const Geo& G, const S* __restrict__ b
   int ys = y - kEY[i];
   int slot = i;
   xs = xs < 0 ? xs + G.nx : (xs >= G.nx ? xs - G.nx : xs);
-  if ((G.walls && (ys < 0 || ys >= G.ny)) || (i > 0 && solid_bit(nb, kOPP[i]))) {
+  double corr = 0.0;
+  if (G.walls && (ys < 0 || ys >= G.ny)) {
+    corr = wall_delta(kOPP[i], phi_x, ys < 0, ph);
+    xs = x; ys = y; slot = kOPP[i];
+  } else if (i > 0 && solid_bit(nb, kOPP[i])) {
     xs = x; ys = y; slot = kOPP[i];
   } else {
     ys = ys < 0 ? ys + G.ny : (ys >= G.ny ? ys - G.ny : ys);
   }
   const S s = buf[slot * G.plane + (long long)ys * G.pitch + xs];
-  return decode<S, T, SHIFT>(s, phi_x, i, ph);  // rest_i depends on phi only for i = 0
+  // rest_i depends on phi only for i = 0
+  return decode<S, T, SHIFT>(s, phi_x, i, ph) - corr;
 }
 
 // Populations f_i(x, t); zero on solid nodes.

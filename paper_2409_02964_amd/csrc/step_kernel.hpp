@@ -62,6 +62,7 @@ struct StepPhys {
   int scale_by_phi;
   int model_b;  // model B (set I): kappa - 1 in place of kappa - phi in F^p and C
   int eq2;      // second-order equilibrium (B1-B2) with the penalty of Eq. (B3)
+  T uw_lo, uw_hi;  // x velocities of the walls at y = -1/2 and y = ny - 1/2
 };
 
 struct StepGeom {
@@ -156,7 +157,8 @@ struct RowIn {
 };
 
 // Optional features of the step (bit mask).  FEAT_SCHEME honours the
-// run-time scheme flags of StepPhys (model B, second-order equilibrium).
+// run-time scheme flags of StepPhys (model B, second-order equilibrium,
+// moving walls).
 // FEAT_ALL is built with every feature and takes absent inputs as zero (null
 // force, drag and flag planes read as 0 through zero-length buffer
 // descriptors; phin = phi when static).
@@ -319,6 +321,23 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
 #pragma unroll
         for (int i = 5; i < 9; ++i) q[i] = static_cast<T>(f[i]) - ph.rest_diag;
       }
+      if constexpr (WALLS && (FEAT & FEAT_SCHEME) != 0) {
+        // moving walls: a population that crossed the wall returns less the
+        // odd part of the equilibrium at the wall velocity, which for the
+        // diagonals is (e_i . u_w) rho0 phi h3 / 6 with phi h3 = kappa (Eq. 14)
+        // or phi (B1); the axis populations carry no tangential momentum
+        const T kw = (ph.eq2 ? phi : kappa) * rho0 * T(1.0 / 6.0);
+        if (yn == 0) {
+          const T c0 = kw * ph.uw_lo;
+          q[5] += c0;
+          q[6] -= c0;
+        }
+        if (yn == ny - 1) {
+          const T c1 = kw * ph.uw_hi;
+          q[7] -= c1;
+          q[8] += c1;
+        }
+      }
       // rows of M (Eq. A1) applied to the deviations
       const T sa = (q[1] + q[2]) + (q[3] + q[4]);
       const T sd = (q[5] + q[6]) + (q[7] + q[8]);
@@ -403,6 +422,10 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
         U4<T> am;
         U2<T> bm;
         am.ux = -a.ux; am.uy = -a.uy; am.mux = -a.mux; am.rux = -a.rux;
+        if constexpr ((FEAT & FEAT_SCHEME) != 0) {  // moving wall: u -> 2 u_w - u
+          const T uw2 = T(2) * (yb == 0 ? ph.uw_lo : ph.uw_hi);
+          am.ux += uw2; am.mux += uw2 * m0; am.rux += uw2 * rho;
+        }
         bm.muy = -b.muy; bm.ruy = -b.ruy;
         s_u4[sg2][t] = am;
         s_u2[sg2][t] = bm;

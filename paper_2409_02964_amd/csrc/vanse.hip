@@ -125,6 +125,7 @@ struct vanse_lattice {
   double kappa, rho0, gx, gy;
   int scale_by_phi;
   int model_b, eq2;  // scheme variants (vanse_set_scheme)
+  double uw_lo, uw_hi;  // wall velocities (vanse_set_wall_velocity)
   vanse_rates rates;
   int threads, rows;  // launch shape of the step kernel
   bool tiling_default;
@@ -185,6 +186,8 @@ StepPhys<T> make_phys(const vanse_lattice* h) {
   p.scale_by_phi = h->scale_by_phi;
   p.model_b = h->model_b;
   p.eq2 = h->eq2;
+  p.uw_lo = T(h->uw_lo);
+  p.uw_hi = T(h->uw_hi);
   return p;
 }
 
@@ -226,7 +229,8 @@ int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& 
 // with them) use FEAT_ALL.
 int feat_of(const vanse_lattice* h) {
   const vanse_desc& d = h->d;
-  if (d.has_mask || d.dynamic_phi || h->model_b || h->eq2) return FEAT_ALL;
+  if (d.has_mask || d.dynamic_phi || h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0)
+    return FEAT_ALL;
   return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0);
 }
 
@@ -348,6 +352,7 @@ int vanse_create(const vanse_desc* d, void* workspace, size_t bytes, vanse_latti
   h->gx = h->gy = 0.0;
   h->scale_by_phi = 1;
   h->model_b = h->eq2 = 0;
+  h->uw_lo = h->uw_hi = 0.0;
   h->rates = vanse_rates{1.0, 1.2, 1.2, 1.2, 1.2};
   h->storage_exp = 12;
   h->version = 0;
@@ -384,6 +389,17 @@ int vanse_set_scheme(vanse_lattice* h, int model, int equilibrium_order) {
   if (h->state_set) return fail(VANSE_ERR_STATE, "the scheme must be chosen before the populations");
   h->model_b = model == VANSE_MODEL_B;
   h->eq2 = equilibrium_order == 2;
+  h->version += 1;
+  return VANSE_OK;
+}
+
+int vanse_set_wall_velocity(vanse_lattice* h, double u_lo, double u_hi) {
+  if (int rc = check_handle(h)) return rc;
+  if (h->d.bc_y != VANSE_WALL) return fail(VANSE_ERR_STATE, "the lattice has no walls");
+  if (!std::isfinite(u_lo) || !std::isfinite(u_hi)) return fail(VANSE_ERR_INVALID_ARG, "wall velocities must be finite");
+  if (h->state_set) return fail(VANSE_ERR_STATE, "wall velocities must be set before the populations");
+  h->uw_lo = u_lo;
+  h->uw_hi = u_hi;
   h->version += 1;
   return VANSE_OK;
 }

@@ -29,7 +29,8 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4:
 
 EXPORTS = [
     "vanse_workspace_bytes", "vanse_create", "vanse_destroy", "vanse_set_params",
-    "vanse_set_scheme", "vanse_set_body_force", "vanse_set_void_fraction",
+    "vanse_set_scheme", "vanse_set_wall_velocity", "vanse_set_body_force",
+    "vanse_set_void_fraction",
     "vanse_set_void_fraction_next",
     "vanse_set_mask", "vanse_set_force_field", "vanse_set_drag",
     "vanse_init_equilibrium", "vanse_set_populations", "vanse_step", "vanse_read_moments",
@@ -83,6 +84,7 @@ def lib():
                 "vanse_set_params": [vp, d, C.POINTER(Rates)],
                 "vanse_set_body_force": [vp, d, d, i32],
                 "vanse_set_scheme": [vp, i32, i32],
+                "vanse_set_wall_velocity": [vp, d, d],
                 "vanse_set_void_fraction": [vp, vp, vp],
                 "vanse_set_void_fraction_next": [vp, vp, vp],
                 "vanse_set_mask": [vp, vp, vp],
@@ -196,6 +198,11 @@ class Lattice:
         """Model "A" (the consistent VANSE) or "B" (set I), and the
         equilibrium order 3 (Eq. 14) or 2 (Appendix B); before the populations."""
         check(lib().vanse_set_scheme(self.handle, {"A": 0, "B": 1}[model], int(equilibrium_order)))
+        return self
+
+    def set_wall_velocity(self, u_lo=0.0, u_hi=0.0):
+        """x velocities of the walls at y = -1/2 and y = ny - 1/2 (before the populations)."""
+        check(lib().vanse_set_wall_velocity(self.handle, float(u_lo), float(u_hi)))
         return self
 
     def set_body_force(self, gx, gy=0.0, scale_by_phi=True):

@@ -381,3 +381,78 @@ def test_scheme_errors():
     lat.set_scheme("B", 2).init_equilibrium(1.0)
     with pytest.raises(VanseError):  # fixed once populations exist
         lat.set_scheme("A", 3)
+
+
+# ---- moving walls (Couette flow) ---------------------------------------------------
+
+@pytest.mark.parametrize("order,with_mask", [(3, False), (2, False), (3, True)])
+def test_one_step_moving_walls_fp64(oracle, order, with_mask):
+    torch = _torch()
+    nx, ny = 45, 23
+    phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 2.5, seed=41) ** 2
+    mask = W.solid_mask(nx, ny, seed=12) if with_mask else None
+    fluid = np.ones((ny, nx), bool) if mask is None else mask == 0
+    f0 = W.random_populations(nx, ny, seed=23)
+    uw = (3e-3, -2e-3)
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=(1e-5, 0), bc_y="wall",
+                        mask=mask, eq2=order == 2, wall_velocity=uw, rho_w=1.0)
+    ora.set_populations(f0)
+    ora.step(1)
+    lat = lattice(nx, ny, phi, "f64", "wall", mask=mask, g=(1e-5, 0))
+    lat.set_scheme("A", order).set_wall_velocity(*uw)
+    lat.set_populations(torch.from_numpy(f0), rho0=1.0)
+    back = lat.read_populations().cpu().numpy()
+    assert np.max(np.abs(back[:, fluid] - f0[:, fluid])) <= 1e-15 * np.max(np.abs(f0))
+    lat.step(1)
+    fg = lat.read_populations().cpu().numpy()
+    err = np.max(np.abs(fg[:, fluid] - ora.f[:, fluid])) / np.max(np.abs(ora.f))
+    _say(f"moving walls order {order} mask={with_mask}: max rel err {err:.3e}")
+    assert err <= 1e-14
+
+
+@pytest.mark.parametrize("prec,bound", [("f64", 1e-12), ("f32s", 1e-4)])
+def test_porous_couette(oracle, prec, bound):
+    """Eq. (22) II on the GPU: Brinkman drag, lower wall at rest, upper wall
+    at U; against the oracle and, coarsely, the closed form.  The run is six
+    viscous times (61440 steps): the FP64 bound, 1e-12 at 1000 steps, grows
+    with the random walk of the rounding differences (FMA contraction and
+    summation order), as sqrt(steps / 1000)."""
+    _torch()
+    H, nx, nu, phi0, U = 32, 8, 0.1, 0.5, 1e-3
+    k0 = 0.01 * H * H
+    beta = np.full((H, nx), phi0 * nu / k0)
+    rates = dict(s_c=1.0, s_e=1.0 / (nu + 0.5), s_eps=1.2, s_q=1.4, s_nu=1.0 / (3 * nu + 0.5))
+    phi = np.full((H, nx), phi0)
+    ora = oracle.Oracle(nx, H, phi, kappa=0.5, rates=rates, bc_y="wall", drag=(beta, (0, 0)),
+                        wall_velocity=(0.0, U)).init_equilibrium()
+    from paper_2409_02964_amd.vanse import Lattice
+    lat = Lattice(nx, H, precision=prec, bc_y="wall", drag=True)
+    lat.set_params(0.5, rates).set_void_fraction(phi).set_drag(beta)
+    lat.set_wall_velocity(0.0, U).init_equilibrium(1.0)
+    steps = int(6 * H * H / nu)  # several viscous times: the steady profile
+    ora.step(steps)
+    lat.step(steps)
+    m, ref = to_np(lat.read_moments()), ora.macroscopic()
+    e = rel_l2_u(m, ref)
+    y = np.arange(H) + 0.5
+    a = np.sqrt(phi0 / k0)
+    exact = U * np.sinh(a * y) / np.sinh(a * H)
+    e_exact = np.max(np.abs(m["ux"][:, 0] - exact)) / U
+    _say(f"porous Couette {prec}: rel-L2(u) vs oracle {e:.3e}, vs Eq. 22 {e_exact:.3e}")
+    if prec == "f64":
+        bound *= np.sqrt(steps / 1000.0)
+    assert e <= bound
+    assert e_exact < 1e-2
+
+
+def test_wall_velocity_errors():
+    _torch()
+    from paper_2409_02964_amd.vanse import VanseError
+    phi = np.full((16, 16), 0.8)
+    per = lattice(16, 16, phi, "f64", "periodic")
+    with pytest.raises(VanseError):
+        per.set_wall_velocity(0.0, 1e-3)
+    wal = lattice(16, 16, phi, "f64", "wall")
+    wal.set_wall_velocity(0.0, 1e-3).init_equilibrium(1.0)
+    with pytest.raises(VanseError):
+        wal.set_wall_velocity(0.0, 2e-3)

@@ -586,3 +586,38 @@ def test_model_a_and_b_hydrostatics(oracle):
     grad, phim, umax = _hydrostatic_gradient(oracle, model_b=True)
     assert umax < 1e-6
     assert np.max(np.abs(grad[2:-2] / phim[2:-2] - 1.0)) < 5e-3
+
+
+# ---- moving walls: Couette flow (Sec. 3.1, Eq. 22 II) -------------------------
+
+def _couette(oracle, H, phi0, U=1e-3, nu=0.1, k0=None, eq2=False, kappa=0.5):
+    nx = 4
+    yy = np.arange(H) + 0.5  # distance of node centres from the lower wall
+    drag = None if k0 is None else (np.full((H, nx), phi0 * nu / k0), (0.0, 0.0))
+    o = oracle.Oracle(nx, H, np.full((H, nx), phi0), kappa=kappa, rates=rates_for(nu),
+                      bc_y="wall", drag=drag, wall_velocity=(0.0, U), eq2=eq2).init_equilibrium()
+    o.step(int(8 * H * H / nu))
+    u = o.macroscopic()["ux"][:, 0]
+    if k0 is None:
+        exact = U * yy / H
+    else:
+        a = math.sqrt(phi0 / k0)
+        exact = U * np.sinh(a * yy) / math.sinh(a * H)
+    return np.max(np.abs(u - exact)) / U
+
+
+@pytest.mark.parametrize("phi0,eq2", [(0.5, False), (0.8, False), (0.8, True)])
+def test_couette_flow_is_linear(oracle, phi0, eq2):
+    """A wall moving at U returns each crossing population less the odd part
+    of the equilibrium at U (the factors of Eq. 14 included), and the Eq. (10)
+    stand-in across it carries 2U - u: plain Couette flow is then the exact
+    linear profile, for phi != kappa and for either equilibrium."""
+    assert _couette(oracle, 12, phi0, eq2=eq2) < 1e-7
+
+
+def test_porous_couette_second_order(oracle):
+    """Eq. (22) II: Brinkman drag phi nu / k0 (Da = k0/H^2 = 0.01), lower wall
+    at rest, upper wall at U: u = U sinh(sqrt(phi/k0) y) / sinh(sqrt(phi/k0) H)."""
+    errs = [_couette(oracle, H, 0.5, k0=0.01 * H * H) for H in (16, 32, 64)]
+    slope = math.log(errs[0] / errs[2]) / math.log(4.0)
+    assert 1.7 < slope < 2.3 and errs[-1] < 2e-3, errs
