@@ -1,0 +1,51 @@
+// step_inst.hpp -- definitions and explicit instances of the step-kernel
+// launchers for one storage precision, chosen by the including file through
+// VANSE_S (storage type), VANSE_T (arithmetic type) and VANSE_SHIFT.
+//
+// Instances: workgroup widths 64, 128 and 256 for every feature variant the
+// host selects (plain, force field, drag, both, FEAT_ALL), 512 for the plain
+// step; the batched kernel for the first four.
+#include "step_launch.hpp"
+
+namespace vanse_dev {
+
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
+void launch_step_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((vanse_step_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(blocks), dim3(NT), 0, st, g, ph);
+}
+
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
+void launch_batch_nt(const BatchEntry<T>* entries, const int* tile_lattice, int launch, int tiles,
+                     hipStream_t st) {
+  hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(tiles), dim3(NT), 0,
+                     st, entries, tile_lattice, launch);
+}
+
+#define VANSE_STEP_ONE(W, F, NT) \
+  template void launch_step_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, NT>( \
+      const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
+#define VANSE_BATCH_ONE(W, F, NT) \
+  template void launch_batch_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, NT>( \
+      const BatchEntry<VANSE_T>*, const int*, int, int, hipStream_t);
+#define VANSE_WIDTHS(M, W, F) M(W, F, 64) M(W, F, 128) M(W, F, 256)
+#define VANSE_WALLS(M, F) VANSE_WIDTHS(M, false, F) VANSE_WIDTHS(M, true, F)
+
+VANSE_WALLS(VANSE_STEP_ONE, 0)
+VANSE_WALLS(VANSE_STEP_ONE, FEAT_FORCE)
+VANSE_WALLS(VANSE_STEP_ONE, FEAT_DRAG)
+VANSE_WALLS(VANSE_STEP_ONE, FEAT_FORCE | FEAT_DRAG)
+VANSE_WALLS(VANSE_STEP_ONE, FEAT_ALL)
+VANSE_STEP_ONE(false, 0, 512)
+VANSE_STEP_ONE(true, 0, 512)
+
+VANSE_WALLS(VANSE_BATCH_ONE, 0)
+VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE)
+VANSE_WALLS(VANSE_BATCH_ONE, FEAT_DRAG)
+VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE | FEAT_DRAG)
+
+#undef VANSE_STEP_ONE
+#undef VANSE_BATCH_ONE
+#undef VANSE_WIDTHS
+#undef VANSE_WALLS
+
+}  // namespace vanse_dev

@@ -1,0 +1,24 @@
+// step_launch.hpp -- launchers of the step kernels.
+//
+// The kernel instances of each storage precision are compiled in a
+// translation unit of their own (step_f64.hip, step_f32.hip, step_f32s.hip,
+// step_f16s.hip, all built from step_inst.hpp) so that the library compiles
+// in parallel; the host code only declares the launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "step_kernel.hpp"
+
+namespace vanse_dev {
+
+// One lattice: `blocks` workgroups of NT lanes over the tiles of g.
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
+void launch_step_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st);
+
+// Many lattices: one workgroup per tile of the batch table.
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
+void launch_batch_nt(const BatchEntry<T>* entries, const int* tile_lattice, int launch, int tiles,
+                     hipStream_t st);
+
+}  // namespace vanse_dev

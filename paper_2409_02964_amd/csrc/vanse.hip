@@ -17,6 +17,7 @@
 
 #include "aux_kernels.hpp"
 #include "step_kernel.hpp"
+#include "step_launch.hpp"
 #include "vanse.h"
 
 using namespace vanse_dev;
@@ -199,11 +200,6 @@ Geo make_geo(const vanse_lattice* h) {
   G.walls = h->d.bc_y == VANSE_WALL;
   G.plane = h->L.plane;
   return G;
-}
-
-template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-void launch_step_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((vanse_step_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(blocks), dim3(NT), 0, st, g, ph);
 }
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
@@ -872,14 +868,9 @@ void batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
   const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
   const int* TL = reinterpret_cast<const int*>(b->ws + b->tiles_off);
   switch (b->threads) {
-    case 64:
-      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FEAT, 64>), dim3(b->total_tiles), dim3(64), 0, st, E, TL, launch);
-      break;
-    case 128:
-      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FEAT, 128>), dim3(b->total_tiles), dim3(128), 0, st, E, TL, launch);
-      break;
-    default:
-      hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FEAT, 256>), dim3(b->total_tiles), dim3(256), 0, st, E, TL, launch);
+    case 64: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st); break;
+    case 128: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st); break;
+    default: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 256>(E, TL, launch, b->total_tiles, st);
   }
 }
 
