@@ -61,23 +61,68 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(steps: int):
-    """The FP64 oracle on the same channel: `steps` full-lattice steps."""
+def cpu_baseline(steps: int, single_steps: int = 3):
+    """The FP64 oracle on the same channel: `steps` full-lattice steps on up
+    to 16 OpenMP threads (the reported value), and `single_steps` on one."""
     import numpy as np
     from oracle import oracle as O
     from paper_2409_02964_amd import workloads as W
     avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    cores = O.set_threads(max(1, min(16, avail)))
     phi = W.channel_phi(NX, NY, seed=2409)
-    o = O.Oracle(NX, NY, phi, kappa=KAPPA, rates=RATES, g=(G, 0.0), bc_y="wall")
-    o.init_equilibrium()
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    assert np.isfinite(o.f[:, ::512, ::512]).all()
+
+    def run(threads, n):
+        used = O.set_threads(threads)
+        o = O.Oracle(NX, NY, phi, kappa=KAPPA, rates=RATES, g=(G, 0.0), bc_y="wall")
+        o.init_equilibrium()
+        t0 = time.perf_counter()
+        o.step(n)
+        dt = time.perf_counter() - t0
+        assert np.isfinite(o.f[:, ::512, ::512]).all()
+        return used, dt
+
+    out = {}
+    if single_steps > 0:
+        _, dt1 = run(1, single_steps)
+        out["single_thread"] = dict(value=round(NX * NY * single_steps / dt1 / 1e6, 2),
+                                    sample=f"{single_steps} full steps, 1 thread ({dt1:.1f} s)")
+    cores, dt = run(max(1, min(16, avail)), steps)
     return dict(value=NX * NY * steps / dt / 1e6, unit="MLUPS", cores=cores, kind="oracle",
                 sample=f"{steps} full steps of the {NX}x{NY} channel, FP64, {cores} OpenMP "
-                       f"threads ({dt:.1f} s)")
+                       f"threads ({dt:.1f} s)", host_cpus=os.cpu_count(), affinity=avail, **out)
+
+
+def small_bench(steps: int = 1000, graph_steps: int = 100):
+    """The 64 x 64 periodic-wave workload (phi = 0.75 + 0.2 sin cos, G = 1e-6,
+    FP64, the parity case): launch-bound, so timed with one launch per step
+    and with the step loop captured in hipGraphs (a one-lattice batch)."""
+    import torch
+    from paper_2409_02964_amd import workloads as W
+    from paper_2409_02964_amd.vanse import Batch, Lattice
+
+    n = 64
+    lat = Lattice(n, n, precision="f64")
+    lat.set_params(KAPPA, RATES).set_body_force(1e-6, 0.0).set_void_fraction(W.periodic_wave(n, n))
+    lat.init_equilibrium(1.0)
+    lat.step(50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    tl = lat.tiling()  # the single-lattice launch shape, so only the launch path differs
+    b = Batch([lat], threads=tl["threads"], rows=tl["rows"], graph_steps=graph_steps)
+    b.step(graph_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t_graph = time.perf_counter() - t0
+    b.close()
+    return {"workload": f"periodic wave {n}x{n}, FP64, {steps} steps",
+            "plain_us_per_step": round(t_plain / steps * 1e6, 2),
+            "plain_mlups": round(n * n * steps / t_plain / 1e6, 1),
+            "graph_us_per_step": round(t_graph / steps * 1e6, 2),
+            "graph_mlups": round(n * n * steps / t_graph / 1e6, 1), "graph_steps": graph_steps}
 
 
 def batched_bench(steps: int, baseline_steps: int, graph_steps: int = 100):
@@ -320,6 +365,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the served workload (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=4.0)
+    ap.add_argument("--serve-sweep", default="",
+                    help="further arrival rates (comma list) of the served workload")
+    ap.add_argument("--small-steps", type=int, default=1000,
+                    help="steps of the 64x64 FP64 workload, plain and graph-captured (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="summarize rocprofv3 CSVs in DIR/{trace,fetch,write} into profiles/")
@@ -419,10 +468,16 @@ def main():
         "final_umax": obs["umax"],
         "nonfinite": obs["nonfinite"],
     }
+    if args.small_steps > 0:
+        line["small"] = small_bench(args.small_steps)
     if args.batch_steps > 0:
         line["batched"] = batched_bench(args.batch_steps, max(1, args.batch_steps // 10))
     if args.serve_requests > 0:
         line["served"] = served_bench(args.serve_requests, args.serve_rate, args.serve_budget_gib)
+        extra = [float(r) for r in args.serve_sweep.split(",") if r.strip()] if args.serve_sweep else []
+        if extra:
+            line["served_sweep"] = {str(r): served_bench(args.serve_requests, r, args.serve_budget_gib)
+                                    for r in extra}
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(line), flush=True)

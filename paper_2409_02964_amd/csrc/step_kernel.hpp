@@ -176,7 +176,7 @@ __device__ __forceinline__ bool solid_bit(unsigned nb, int i) { return (nb >> i)
 
 // S: storage type of populations (double, float, _Float16)
 // T: arithmetic type (double, float)
-// SHIFT: memory holds deviations g (scaled by ph.scale) instead of f
+// SHIFT: memory holds deviations g (scaled by ph.scale in half storage) instead of f
 // WALLS: half-way bounce-back walls at y = -1/2 and y = ny - 1/2
 // FEAT: FEAT_FORCE adds the per-node force planes to F^B; FEAT_DRAG adds
 //       the linear drag -phi beta (u - u_s) with u solved in closed form
@@ -311,9 +311,10 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
     if (rowA && live) {
       const T phi = phi_in;
       T q[9];
-      if (SHIFT) {
+      if (SHIFT) {  // only half storage carries a scale (2^-e)
 #pragma unroll
-        for (int i = 0; i < 9; ++i) q[i] = static_cast<T>(f[i]) * ph.inv_scale;
+        for (int i = 0; i < 9; ++i)
+          q[i] = sizeof(S) == 2 ? static_cast<T>(f[i]) * ph.inv_scale : static_cast<T>(f[i]);
       } else {
         q[0] = static_cast<T>(f[0]) - (phi * rho0 - ph.rest0_k);
 #pragma unroll
@@ -575,7 +576,8 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
 
       if (SHIFT) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) bstore(static_cast<S>(o9[i] * ph.scale), dstr, xcb, poff(i, yo));
+        for (int i = 0; i < 9; ++i)
+          bstore(static_cast<S>(sizeof(S) == 2 ? o9[i] * ph.scale : o9[i]), dstr, xcb, poff(i, yo));
       } else {
         bstore(static_cast<S>(o9[0] + (phi * rho0 - ph.rest0_k)), dstr, xcb, poff(0, yo));
 #pragma unroll
