@@ -5,15 +5,19 @@ a single 4096 x 4096 D2Q9 channel, half-way bounce-back walls at y = 0 and
 y = H, periodic in x, body force G = 1e-7 along x (F^B = phi G), phi a tanh
 step from 0.4 to 1.0 (width 2 cells) at mid-channel plus seeded smoothed
 noise of amplitude 0.05 (sigma = 8 cells), kappa = 0.5, s_nu = 0.8 and the
-other rates 1.2, FP32 arithmetic and storage.  A "step" is one launch of the
-fused kernel over the whole lattice.
+other rates 1.2, FP32 arithmetic and FP32 storage (of the deviations from the
+rest state).  A "step" is one time step of the whole lattice; the plain step
+runs two time steps per launch of its two-step kernel (the populations cross
+HBM once per two steps).
 
 Prints ONE JSON line (rank 0).  `value` is MLUPS (million lattice-node
 updates per second) over the timed steps, inputs resident in HBM.  The
 `roofline` object prices the step kernel against the 8 TB/s HBM peak with
-the algorithmic bytes per node update (9 population reads + 9 writes + phi);
+the algorithmic bytes per node update (9 population reads + 9 writes + phi)
+times the node updates per launch (two per node for the two-step kernel);
 its duration comes from HIP events recorded on the stream the kernel is
-launched on.  `cpu_baseline` times the FP64 CPU oracle on a bounded sample
+launched on.  `traffic` is the HBM bytes one launch actually moves
+(rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated on the copy kernel).  `cpu_baseline` times the FP64 CPU oracle on a bounded sample
 of the same workload.
 """
 from __future__ import annotations
@@ -32,14 +36,17 @@ NX = NY = 4096
 G = 1e-7
 KAPPA = 0.5
 RATES = dict(s_c=1.2, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=0.8)
-PRECISION = "f32"
-TILING = (256, 69)  # threads per workgroup, rows swept per workgroup (one full round)
+PRECISION = "f32s"  # FP32 arithmetic, FP32 storage of the deviations (76 B per node update)
+TILING = (256, 69)  # single-step launches: threads per workgroup, rows per workgroup
+STEPS_PER_PASS = 2  # time steps per launch of the plain step
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + %HBM peak (D2Q9 MRT-VANSE); batched solves/s + p99 latency"
 BYTES_PER_NODE = {"f64": 9 * 8 * 2 + 8, "f32": 9 * 4 * 2 + 4, "f32s": 9 * 4 * 2 + 4,
                   "f16s": 9 * 2 * 2 + 4}
-KERNEL_SOURCES = ["paper_2409_02964_amd/csrc/step_kernel.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_f32_channel4096_traffic.json")
+KERNEL_SOURCES = ["paper_2409_02964_amd/csrc/step_kernel.hpp",
+                  "paper_2409_02964_amd/csrc/step2_kernel.hpp"]
+PROFILE_PREFIX = os.path.join(ROOT, "profiles", "step2_f32s_channel4096")
+TRAFFIC_FILE = PROFILE_PREFIX + "_traffic.json"
 
 
 def kernel_hash() -> str:
@@ -313,17 +320,20 @@ def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
     f_copy = pick(counters["FETCH_SIZE"], "stream_copy") * 1024
     w_copy = pick(counters["WRITE_SIZE"], "stream_copy") * 1024
     f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
-    f_step = pick(counters["FETCH_SIZE"], "vanse_step_kernel") * 1024 * f_scale
-    w_step = pick(counters["WRITE_SIZE"], "vanse_step_kernel") * 1024 * w_scale
-    alg = BYTES_PER_NODE[PRECISION] * nodes
-    step_ns = float(pick({r["Name"]: r["AverageNs"] for r in stats}, "vanse_step_kernel"))
+    kname = "vanse_step2_kernel" if STEPS_PER_PASS == 2 else "vanse_step_kernel"
+    f_step = pick(counters["FETCH_SIZE"], kname) * 1024 * f_scale
+    w_step = pick(counters["WRITE_SIZE"], kname) * 1024 * w_scale
+    alg = BYTES_PER_NODE[PRECISION] * nodes * STEPS_PER_PASS
+    step_ns = float(pick({r["Name"]: r["AverageNs"] for r in stats}, kname))
     copy_ns = float(pick({r["Name"]: r["AverageNs"] for r in stats}, "stream_copy"))
     rec = {"kernel_hash": kernel_hash(), "bytes_per_launch": int(f_step + w_step),
            "fetch_bytes": int(f_step), "write_bytes": int(w_step),
            "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
-           "algorithmic_bytes": alg, "step_avg_ns": step_ns, "copy_avg_ns": copy_ns}
+           "algorithmic_bytes": alg, "steps_per_launch": STEPS_PER_PASS, "kernel": kname,
+           "step_avg_ns": step_ns, "copy_avg_ns": copy_ns}
     json.dump(rec, open(prefix + "_traffic.json", "w"), indent=1)
-    lines = [f"# rocprofv3: fused step, {NX}x{NY} FP32 channel (walls), tiling {TILING}", "",
+    lines = [f"# rocprofv3: {kname} ({STEPS_PER_PASS} time steps per launch), {NX}x{NY} "
+             f"{PRECISION} channel (walls)", "",
              "Commands (from the repository root; outputs under gpurun_out/prof):", "",
              "```", commands.strip(), "```", "",
              "## Kernel statistics (--kernel-trace --stats)", "",
@@ -334,12 +344,13 @@ def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
     lines += ["", "## HBM traffic per dispatch (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", "",
               "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|"]
     for k in sorted(counters["FETCH_SIZE"]):
-        if "step_kernel" in k or "stream_copy" in k:
+        if "step_kernel" in k or "step2_kernel" in k or "stream_copy" in k:
             lines.append(f"| {k[:90]} | {counters['FETCH_SIZE'][k]:.0f} | "
                          f"{counters['WRITE_SIZE'].get(k, float('nan')):.0f} |")
     lines += ["", f"Calibration with the same-pattern copy ({copy_bytes} B read and written per "
               f"dispatch): FETCH x {f_scale:.4f}, WRITE x {w_scale:.4f}.", "",
-              f"Step kernel: {f_step / 1e6:.1f} MB read + {w_step / 1e6:.1f} MB written = "
+              f"Step kernel ({STEPS_PER_PASS} node updates per node per launch): "
+              f"{f_step / 1e6:.1f} MB read + {w_step / 1e6:.1f} MB written = "
               f"{(f_step + w_step) / 1e6:.1f} MB per launch; algorithmic {alg / 1e6:.1f} MB "
               f"({(f_step + w_step) / alg:.3f}x).  Average duration {step_ns / 1e3:.1f} us -> "
               f"{alg / step_ns:.0f} GB/s algorithmic, {(f_step + w_step) / step_ns:.0f} GB/s "
@@ -356,6 +367,10 @@ def main():
     ap.add_argument("--precision", default=PRECISION, choices=sorted(BYTES_PER_NODE))
     ap.add_argument("--threads", type=int, default=TILING[0])
     ap.add_argument("--rows", type=int, default=TILING[1])
+    ap.add_argument("--steps-per-pass", type=int, default=STEPS_PER_PASS, choices=(1, 2),
+                    help="time steps per launch of the plain step (2: the two-step kernel)")
+    ap.add_argument("--fused-rows", type=int, default=0,
+                    help="rows per workgroup of the two-step kernel (0: one full round)")
     ap.add_argument("--sol-steps", type=int, default=200,
                     help="launches of the same-pattern copy kernel (0: skip)")
     ap.add_argument("--cpu-steps", type=int, default=100,
@@ -383,8 +398,7 @@ def main():
         return
     if args.summarize_profile:
         cmds = open(os.path.join(args.summarize_profile, "commands.txt")).read()
-        summarize_profile(args.summarize_profile,
-                          os.path.join(ROOT, "profiles", "step_f32_channel4096"), cmds)
+        summarize_profile(args.summarize_profile, PROFILE_PREFIX, cmds)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); this build has no "
@@ -402,6 +416,8 @@ def main():
     lat.set_params(KAPPA, RATES).set_body_force(G, 0.0, True)
     lat.set_void_fraction(phi)
     lat.set_tiling(args.threads, args.rows)
+    spp = args.steps_per_pass if args.precision != "f64" else 1
+    lat.set_steps_per_pass(spp, args.fused_rows)
     lat.init_equilibrium(1.0)
     stream = torch.cuda.current_stream(dev)
 
@@ -434,10 +450,14 @@ def main():
     nodes = NX * NY
     sec = gpu_ms / 1e3
     mlups = nodes * args.steps / sec / 1e6
-    per_launch_ms = gpu_ms / max(args.steps, 1)
+    per_step_ms = gpu_ms / max(args.steps, 1)
     bpn = BYTES_PER_NODE[args.precision]
-    achieved = bpn * nodes / (per_launch_ms / 1e3) / 1e9
-    traffic = measured_traffic() if args.precision == PRECISION else None
+    ft = lat.fused_tiling()
+    per_launch = 2 if ft["active"] else 1
+    # algorithmic bytes of one launch over its duration (= per step over per step)
+    achieved = bpn * nodes * per_launch / (per_step_ms * per_launch / 1e3) / 1e9
+    traffic = (measured_traffic()
+               if args.precision == PRECISION and per_launch == STEPS_PER_PASS else None)
     tl = lat.tiling()
 
     line = {
@@ -447,22 +467,25 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(per_launch_ms, 4),
+        "ms_per_step": round(per_step_ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": "f64" if args.precision == "f64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"D2Q9 MRT-VANSE channel {NX}x{NY}, walls in y, G=1e-7, "
                                "phi tanh 0.4->1.0 + smoothed noise 0.05 (seed 2409), kappa=0.5, "
                                "s_nu=0.8, other rates 1.2",
-                   "nx": NX, "ny": NY, "precision": args.precision,
-                   "threads": tl["threads"], "rows": tl["rows"],
-                   "workgroups": tl["workgroups"]},
+                   "nx": NX, "ny": NY, "storage": args.precision, "steps_per_launch": per_launch,
+                   "threads": 512 if per_launch == 2 else tl["threads"],
+                   "rows": ft["rows"] if per_launch == 2 else tl["rows"],
+                   "workgroups": ft["workgroups"] if per_launch == 2 else tl["workgroups"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "algorithmic_bytes_per_launch": bpn * nodes,
+                     "kernel": "vanse_step2_kernel" if per_launch == 2 else "vanse_step_kernel",
+                     "node_updates_per_launch": per_launch * nodes,
+                     "algorithmic_bytes_per_launch": bpn * nodes * per_launch,
                      "same_pattern_copy_gbs": sol},
         "wall_s": round(wall, 3),
         "final_umax": obs["umax"],

@@ -209,6 +209,24 @@ int vanse_set_tiling(vanse_lattice *h, int threads, int rows);
 int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
                      int *workgroups);
 
+/* Time steps per launch of the plain step (FP32 arithmetic, no force
+ * field, drag, mask, moving phi, scheme variant or wall velocity): 1 (the
+ * default) or 2.  With 2, vanse_step advances pairs of steps with one
+ * launch each: a workgroup's first half runs step t -> t+1 into an LDS ring
+ * and its second half step t+1 -> t+2 from it, so the populations cross HBM
+ * once per two steps; an odd step count ends with one single step.  Each
+ * half's arithmetic is the single step's; the intermediate state stays in
+ * FP32 deviations, so FP32-shifted storage gives bitwise the single-step
+ * results and the other storage formats skip one storage rounding.  Other
+ * lattices keep one step per launch.  rows: rows per workgroup of the
+ * two-step kernel (0: one full round of resident workgroups).
+ * VANSE_ERR_UNSUPPORTED for FP64. */
+int vanse_set_steps_per_pass(vanse_lattice *h, int steps, int rows);
+/* Whether the two-step launch is in use (*active), and its rows per
+ * workgroup and workgroups per launch. */
+int vanse_get_fused_tiling(const vanse_lattice *h, int *active, int *rows,
+                           int *workgroups);
+
 /* Exponent e of the storage scale 2^e of VANSE_F16_SHIFTED (default 12):
  * memory holds g * 2^e in FP16.  Only before init. */
 int vanse_set_storage_exponent(vanse_lattice *h, int e);

@@ -2,4 +2,5 @@
 #define VANSE_S _Float16
 #define VANSE_T float
 #define VANSE_SHIFT true
+#define VANSE_FUSED2 1
 #include "step_inst.hpp"

@@ -2,4 +2,5 @@
 #define VANSE_S float
 #define VANSE_T float
 #define VANSE_SHIFT false
+#define VANSE_FUSED2 1
 #include "step_inst.hpp"

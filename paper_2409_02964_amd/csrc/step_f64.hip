@@ -2,4 +2,5 @@
 #define VANSE_S double
 #define VANSE_T double
 #define VANSE_SHIFT false
+#define VANSE_FUSED2 0
 #include "step_inst.hpp"

@@ -4,7 +4,8 @@
 //
 // Instances: workgroup widths 64, 128 and 256 for every feature variant the
 // host selects (plain, force field, drag, both, FEAT_ALL), 512 for the plain
-// step; the batched kernel for the first four.
+// step; the batched kernel for the first four; the two-step kernel of the
+// plain step (256-lane halves) where VANSE_FUSED2 is set.
 #include "step_launch.hpp"
 
 namespace vanse_dev {
@@ -12,6 +13,11 @@ namespace vanse_dev {
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 void launch_step_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st) {
   hipLaunchKernelGGL((vanse_step_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(blocks), dim3(NT), 0, st, g, ph);
+}
+
+template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
+void launch_step2_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((vanse_step2_kernel<S, T, SHIFT, WALLS, NT>), dim3(blocks), dim3(2 * NT), 0, st, g, ph);
 }
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
@@ -42,6 +48,15 @@ VANSE_WALLS(VANSE_BATCH_ONE, 0)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_DRAG)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE | FEAT_DRAG)
+
+// two steps per pass: FP32 arithmetic only (the FP64 rings would not fit
+// two workgroups in a CU's LDS)
+#if VANSE_FUSED2
+template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, false, 256>(
+    const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
+template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, true, 256>(
+    const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
+#endif
 
 #undef VANSE_STEP_ONE
 #undef VANSE_BATCH_ONE

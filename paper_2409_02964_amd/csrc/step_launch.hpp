@@ -8,6 +8,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "step2_kernel.hpp"
 #include "step_kernel.hpp"
 
 namespace vanse_dev {
@@ -15,6 +16,10 @@ namespace vanse_dev {
 // One lattice: `blocks` workgroups of NT lanes over the tiles of g.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 void launch_step_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st);
+
+// One lattice, two time steps per launch: `blocks` workgroups of 2 NT lanes.
+template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
+void launch_step2_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st);
 
 // Many lattices: one workgroup per tile of the batch table.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>

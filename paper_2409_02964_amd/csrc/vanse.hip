@@ -129,6 +129,8 @@ struct vanse_lattice {
   double uw_lo, uw_hi;  // wall velocities (vanse_set_wall_velocity)
   vanse_rates rates;
   int threads, rows;  // launch shape of the step kernel
+  int fuse;           // time steps per launch of the plain step (1 or 2)
+  int rows2;          // rows per workgroup of the two-step kernel (0: default)
   bool tiling_default;
   int storage_exp;
   long long version;  // bumped by every call that changes what the step reads
@@ -243,8 +245,64 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
   }
 }
 
+// Two-step launches of the plain step: FP32 arithmetic, no optional inputs or
+// scheme variants.  Rows per workgroup default to one full round of resident
+// workgroups (two 512-lane workgroups per CU).
+constexpr int kFusedNT = 256;
+constexpr int kFusedOutW = kFusedNT - 10;
+
+bool fused_ok(const vanse_lattice* h) {
+  return h->fuse == 2 && h->d.precision != VANSE_F64 && feat_of(h) == 0;
+}
+
+int fused_rows(const vanse_lattice* h) {
+  if (h->rows2 > 0) return h->rows2;
+  const int strips = (h->d.nx + kFusedOutW - 1) / kFusedOutW;
+  long long nby = (long long)device_cus() * 2 / strips;
+  if (nby < 1) nby = 1;
+  long long r = (h->d.ny + nby - 1) / nby;
+  if (r < 4) r = 4;
+  return (int)r;
+}
+
+template <typename S, typename T, bool SHIFT>
+int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
+  if constexpr (sizeof(T) == 8) {
+    return fail(VANSE_ERR_UNSUPPORTED, "two steps per launch are built for FP32 arithmetic");
+  } else {
+    const StepPhys<T> ph = make_phys<T>(h);
+    StepGeom g{};
+    g.phi = h->ws + h->L.phi;
+    g.phin = g.phi;
+    g.plane = h->L.plane;
+    g.nx = h->d.nx;
+    g.ny = h->d.ny;
+    g.pitch = h->L.pitch;
+    g.out_w = kFusedOutW;
+    g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
+    g.rows = fused_rows(h);
+    const int blocks = g.strips * ((h->d.ny + g.rows - 1) / g.rows);
+    const bool walls = h->d.bc_y == VANSE_WALL;
+    for (int64_t s = 0; s < pairs; ++s) {
+      g.src = h->ws + h->L.pop[h->cur];
+      g.dst = h->ws + h->L.pop[h->cur ^ 1];
+      if (walls) launch_step2_nt<S, T, SHIFT, true, kFusedNT>(g, ph, blocks, st);
+      else launch_step2_nt<S, T, SHIFT, false, kFusedNT>(g, ph, blocks, st);
+      h->cur ^= 1;
+      h->t += 2;
+      if (s == 0) HIP_TRY(hipGetLastError());
+    }
+    return VANSE_OK;
+  }
+}
+
 template <typename S, typename T, bool SHIFT>
 int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
+  if (fused_ok(h) && n >= 2) {
+    if (int rc = run_fused_pairs<S, T, SHIFT>(h, n / 2, st)) return rc;
+    n &= 1;
+    if (n == 0) return VANSE_OK;
+  }
   const StepPhys<T> ph = make_phys<T>(h);
   if (h->phin_set && n > 1)
     return fail(VANSE_ERR_INVALID_ARG, "with phi(t+1) set, a call advances one step (asked for %lld)", (long long)n);
@@ -354,6 +412,8 @@ int vanse_create(const vanse_desc* d, void* workspace, size_t bytes, vanse_latti
   h->version = 0;
   h->tiling_default = true;
   default_tiling(h);
+  h->fuse = 1;
+  h->rows2 = 0;
   *out = h;
   return VANSE_OK;
 }
@@ -690,6 +750,27 @@ int vanse_set_tiling(vanse_lattice* h, int threads, int rows) {
   h->threads = threads;
   h->rows = rows;
   h->tiling_default = false;
+  return VANSE_OK;
+}
+
+int vanse_set_steps_per_pass(vanse_lattice* h, int steps, int rows) {
+  if (int rc = check_handle(h)) return rc;
+  if (steps != 1 && steps != 2) return fail(VANSE_ERR_INVALID_ARG, "steps per pass must be 1 or 2 (got %d)", steps);
+  if (rows < 0) return fail(VANSE_ERR_INVALID_ARG, "rows must be >= 0 (got %d)", rows);
+  if (steps == 2 && h->d.precision == VANSE_F64)
+    return fail(VANSE_ERR_UNSUPPORTED, "two steps per launch are built for FP32 arithmetic");
+  h->fuse = steps;
+  h->rows2 = rows;
+  return VANSE_OK;
+}
+
+int vanse_get_fused_tiling(const vanse_lattice* h, int* active, int* rows, int* workgroups) {
+  if (int rc = check_handle(h)) return rc;
+  const int r = fused_rows(h);
+  const int strips = (h->d.nx + kFusedOutW - 1) / kFusedOutW;
+  if (active) *active = fused_ok(h) ? 1 : 0;
+  if (rows) *rows = r;
+  if (workgroups) *workgroups = strips * ((h->d.ny + r - 1) / r);
   return VANSE_OK;
 }
 

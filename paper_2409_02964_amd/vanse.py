@@ -35,7 +35,7 @@ EXPORTS = [
     "vanse_set_mask", "vanse_set_force_field", "vanse_set_drag",
     "vanse_init_equilibrium", "vanse_set_populations", "vanse_step", "vanse_read_moments",
     "vanse_read_populations", "vanse_observe", "vanse_residual", "vanse_set_tiling",
-    "vanse_get_tiling",
+    "vanse_get_tiling", "vanse_set_steps_per_pass", "vanse_get_fused_tiling",
     "vanse_set_storage_exponent", "vanse_stream_copy", "vanse_time", "vanse_error_string",
     "vanse_last_error", "vanse_batch_workspace_bytes", "vanse_batch_create", "vanse_batch_destroy",
     "vanse_batch_set_graph", "vanse_batch_step", "vanse_batch_tiles",
@@ -99,6 +99,8 @@ def lib():
                 "vanse_residual": [vp, pd, vp],
                 "vanse_set_tiling": [vp, i32, i32],
                 "vanse_get_tiling": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+                "vanse_set_steps_per_pass": [vp, i32, i32],
+                "vanse_get_fused_tiling": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
                 "vanse_set_storage_exponent": [vp, i32],
                 "vanse_stream_copy": [vp, i64, vp],
                 "vanse_time": [vp],
@@ -268,6 +270,16 @@ class Lattice:
         a, b, c = C.c_int(), C.c_int(), C.c_int()
         check(lib().vanse_get_tiling(self.handle, C.byref(a), C.byref(b), C.byref(c)))
         return dict(threads=a.value, rows=b.value, workgroups=c.value)
+
+    def set_steps_per_pass(self, steps=2, rows=0):
+        """Time steps per launch of the plain FP32 step (1 or 2); see vanse.h."""
+        check(lib().vanse_set_steps_per_pass(self.handle, int(steps), int(rows)))
+        return self
+
+    def fused_tiling(self):
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        check(lib().vanse_get_fused_tiling(self.handle, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(active=bool(a.value), rows=b.value, workgroups=c.value)
 
     def set_storage_exponent(self, e):
         check(lib().vanse_set_storage_exponent(self.handle, int(e)))

@@ -1,0 +1,139 @@
+"""Two time steps per launch (vanse_set_steps_per_pass(2)).
+
+The two-step kernel runs the single step's arithmetic twice with the
+intermediate populations kept as FP32 deviations in LDS.  With FP32-shifted
+storage that is exactly what one step per launch stores and loads, so the
+results must agree bitwise; plain FP32 and FP16-shifted storage skip one
+storage rounding per pair and are checked against the FP64 oracle.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_2409_02964_amd import workloads as W  # noqa: E402
+
+RATES = dict(s_c=1.2, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=0.8)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def lattice(nx, ny, phi, precision, bc, fused, rows=0, g=(2e-5, -1e-5), drag=None):
+    from paper_2409_02964_amd.vanse import Lattice
+    lat = Lattice(nx, ny, precision=precision, bc_y=bc, drag=drag is not None)
+    lat.set_params(0.5, RATES).set_body_force(*g).set_void_fraction(phi)
+    if drag is not None:
+        lat.set_drag(drag)
+    if fused:
+        lat.set_steps_per_pass(2, rows)
+    return lat
+
+
+def rel_l2_u(m, ref):
+    num = np.sum((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2)
+    return math.sqrt(num / np.sum(ref["ux"] ** 2 + ref["uy"] ** 2))
+
+
+SHAPES = [
+    (300, 70, "periodic", 0),
+    (253, 130, "wall", 0),
+    (64, 64, "periodic", 0),
+    (97, 2, "wall", 0),      # both walls on every row
+    (1000, 37, "wall", 5),   # many strips and row blocks, ragged tails
+    (247, 33, "periodic", 4),
+    (246, 20, "wall", 3),    # exactly one strip
+    (3, 5, "periodic", 0),   # everything wraps
+]
+
+
+@pytest.mark.parametrize("nx,ny,bc,rows", SHAPES)
+def test_fused_equals_single_steps_f32s(nx, ny, bc, rows):
+    torch = _torch()
+    _say(f"fused vs single f32s {nx}x{ny} {bc} rows={rows}")
+    phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 2.0, seed=nx + ny) ** 2
+    f0 = torch.from_numpy(W.random_populations(nx, ny, seed=7 + nx))
+    a = lattice(nx, ny, phi, "f32s", bc, fused=False)
+    b = lattice(nx, ny, phi, "f32s", bc, fused=True, rows=rows)
+    assert b.fused_tiling()["active"] and not a.fused_tiling()["active"]
+    a.set_populations(f0)
+    b.set_populations(f0)
+    for n in (2, 5, 1, 4):  # pairs, a pair plus a single step, ...
+        a.step(n)
+        b.step(n)
+        fa = a.read_populations().cpu().numpy()
+        fb = b.read_populations().cpu().numpy()
+        assert a.t == b.t
+        assert np.array_equal(fa, fb), (n, float(np.max(np.abs(fa - fb))))
+
+
+@pytest.mark.parametrize("prec,bound", [("f32", 5e-2), ("f16s", 5e-2)])
+def test_fused_periodic_wave_vs_oracle(oracle, prec, bound):
+    _torch()
+    n, steps = 64, 1000
+    phi = W.periodic_wave(n, n)
+    ora = oracle.Oracle(n, n, phi, kappa=0.5, rates=RATES, g=(1e-6, 0)).init_equilibrium()
+    ora.step(steps)
+    ref = ora.macroscopic()
+    single = lattice(n, n, phi, prec, "periodic", fused=False, g=(1e-6, 0))
+    fused = lattice(n, n, phi, prec, "periodic", fused=True, g=(1e-6, 0))
+    out = {}
+    for name, lat in (("single", single), ("fused", fused)):
+        lat.init_equilibrium(1.0)
+        lat.step(steps)
+        out[name] = {k: v.cpu().numpy() for k, v in lat.read_moments().items()}
+    e_s, e_f = rel_l2_u(out["single"], ref), rel_l2_u(out["fused"], ref)
+    _say(f"periodic wave {prec}: rel-L2(u) single {e_s:.3e}, fused {e_f:.3e}")
+    assert e_f <= bound
+    assert e_f <= 1.5 * e_s + 1e-6  # one storage rounding fewer per pair: not worse
+
+
+def test_fused_full_size_channel_bitwise():
+    """The 4096 x 4096 channel (walls, the benchmark field) in FP32-shifted
+    storage: one two-step launch and two single steps agree bitwise."""
+    torch = _torch()
+    n = 4096
+    phi = W.channel_phi(n, n, seed=2409)
+    a = lattice(n, n, phi, "f32s", "wall", fused=False, g=(1e-7, 0))
+    b = lattice(n, n, phi, "f32s", "wall", fused=True, g=(1e-7, 0))
+    for lat in (a, b):
+        lat.init_equilibrium(1.0)
+        lat.step(6)
+    fa, fb = a.read_populations(), b.read_populations()
+    same = bool(torch.equal(fa, fb))
+    _say(f"full-size fused vs single: bitwise {same}; fused tiling {b.fused_tiling()}")
+    assert same
+    a.close()
+    b.close()
+
+
+def test_fused_falls_back_for_variants_and_refuses_fp64():
+    torch = _torch()
+    from paper_2409_02964_amd.vanse import Lattice, VanseError
+    n = 48
+    phi = W.periodic_wave(n, n)
+    beta = np.full((n, n), 1e-3)
+    a = lattice(n, n, phi, "f32", "periodic", fused=False, drag=beta)
+    b = lattice(n, n, phi, "f32", "periodic", fused=True, drag=beta)
+    assert not b.fused_tiling()["active"]  # drag: one step per launch
+    for lat in (a, b):
+        lat.init_equilibrium(1.0)
+        lat.step(7)
+    assert torch.equal(a.read_populations(), b.read_populations())
+    f64 = Lattice(n, n, "f64")
+    with pytest.raises(VanseError):
+        f64.set_steps_per_pass(2)
+    with pytest.raises(VanseError):
+        a.set_steps_per_pass(3)

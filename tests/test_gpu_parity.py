@@ -273,6 +273,32 @@ def test_full_size_channel_one_step_fp32(oracle):
     assert err <= 2e-6
 
 
+def test_full_size_channel_benchmark_launch(oracle):
+    """The benchmark's exact configuration -- 4096 x 4096 channel, its
+    storage precision and two steps per launch with the default two-step
+    tiling -- over two steps from a random state, against two FP64 oracle
+    steps on every population."""
+    torch = _torch()
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    n = bench.NX
+    phi = W.channel_phi(n, n, seed=2409)
+    f0 = W.random_populations(n, n, seed=78)
+    _say("full-size benchmark launch: oracle steps ...")
+    ora = oracle_lattice(oracle, n, n, phi, "wall", g=(bench.G, 0))
+    ora.set_populations(f0)
+    ora.step(2)
+    _say("full-size benchmark launch: gpu ...")
+    lat = gpu_lattice(n, n, phi, bench.PRECISION, "wall", g=(bench.G, 0), tiling=bench.TILING)
+    lat.set_steps_per_pass(bench.STEPS_PER_PASS)
+    assert lat.fused_tiling()["active"] == (bench.STEPS_PER_PASS == 2)
+    lat.set_populations(torch.from_numpy(f0)).step(2)
+    fg = lat.read_populations().cpu().numpy()
+    err = np.max(np.abs(fg - ora.f)) / np.max(np.abs(ora.f))
+    _say(f"full-size {bench.PRECISION}, {bench.STEPS_PER_PASS} steps per launch: max rel err {err:.3e}")
+    assert err <= 2e-6
+
+
 # ---- linear drag and the residual observable ---------------------------------------
 
 @pytest.mark.parametrize("bc", ["periodic", "wall"])
