@@ -53,7 +53,10 @@ __device__ __forceinline__ int pop_slot(int i, int j) {
 template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
 __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int strip,
                                            int by, Step2Lds<T, NT>& L) {
-  const int half = int(threadIdx.x) / NT;  // uniform per wave
+  // uniform per wave (NT is a multiple of the wave size); read from the first
+  // lane so that the compiler keeps everything derived from it -- rows, ring
+  // slots, branches -- in scalar registers
+  const int half = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / NT);
   const int t = int(threadIdx.x) - half * NT;
   const int nx = g.nx, ny = g.ny, pitch = g.pitch;
   const int x0 = strip * g.out_w;
