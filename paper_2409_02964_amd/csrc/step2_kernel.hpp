@@ -20,8 +20,22 @@
 // + k (A: moments), yA - 1 (B: velocity), yA - 2 (C: collision), with three
 // workgroup barriers.  Half 0's collision row P feeds half 1's pull of row
 // P - 1 one iteration later, and rows P - 2 and P - 3 two and three
-// iterations later; the ring keeps three rows of each plane (four for the
-// planes 2, 5, 6 pulled from below).
+// iterations later; the ring keeps four rows of each plane.  Half-way
+// bounce-back at a wall enters half 1's pull through image rows of the ring
+// (row -1 of planes 2, 5, 6 and row ny of planes 4, 7, 8), which half 0
+// fills from the wall row once per sweep, so the pull itself never tests
+// for walls.
+//
+// The Eq. (10) derivatives use the stencil's separable form.  With
+//   D(y) = g(x+1, y) - g(x-1, y),   S(y) = g(x+1, y) + g(x-1, y) + 4 g(x, y)
+// for a field g on row y, the stencil is
+//   12 d_x g(y) = 4 D(y) + D(y-1) + D(y+1),   12 d_y g(y) = S(y+1) - S(y-1).
+// A lane sweeps one column, so each row's D and S are formed once, from the
+// row's own values and its two neighbours in LDS, and the two rows below stay
+// in registers.  The LDS rings of delta-rho and of the velocity data then
+// hold a single row, and the rows beyond a wall (the centre-value image of
+// delta-rho, the negated image of the velocity fields) are formed in
+// registers from the D and S of the wall row.
 //
 // Columns: lane t of either half is column x0 - 5 + t.  Half 0 forms moments
 // on lanes [0, w+10), velocities on [1, w+9), collisions on [2, w+8); half 1
@@ -36,19 +50,39 @@ namespace vanse_dev {
 
 template <typename T, int NT>
 struct Step2Lds {
-  T rho[2][3][NT];      // per half: delta-rho of the last three rows
-  U4<T> u4[2][3][NT];   // per half: velocity data of the last three rows
-  U2<T> u2[2][3][NT];
-  T pop[30][NT];        // half 0's post-collision deviations (see pop_slot)
+  T rho[2][NT];      // per half: delta-rho of the row of stage A (read by B)
+  U4<T> u4[2][NT];   // per half: velocity data of the row of stage B (read by C)
+  U2<T> u2[2][NT];
+  T pop[36][NT];     // half 0's post-collision deviations (see pop_slot)
 };
 
-// Ring row of population plane i for the sweep-relative row index j >= 0:
-// planes 0, 1, 3, 4, 7, 8 keep three rows, planes 2, 5, 6 four.
-__device__ __forceinline__ int pop_slot(int i, int j) {
-  constexpr int base[9] = {0, 3, 18, 6, 9, 22, 26, 12, 15};
-  const bool deep = (i == 2 || i == 5 || i == 6);
-  return base[i] + (deep ? (j & 3) : int(unsigned(j) % 3u));
+// D and S (see above) of delta-rho on one row
+template <typename T>
+struct RhoDS {
+  T d, s;
+};
+
+// D of the fields differentiated in x and S of those differentiated in y by
+// the penalty of Eq. (20) on one row, and the node's velocity
+template <typename T>
+struct VelDS {
+  T d_rux, d_ux, d_uy, d_mux;
+  T s_ruy, s_uy, s_ux, s_muy;
+  T ux, uy;
+};
+
+// the image row beyond a wall: velocity-like fields negated
+template <typename T>
+__device__ __forceinline__ VelDS<T> mirrored(const VelDS<T>& v) {
+  VelDS<T> r;
+  r.d_rux = -v.d_rux; r.d_ux = -v.d_ux; r.d_uy = -v.d_uy; r.d_mux = -v.d_mux;
+  r.s_ruy = -v.s_ruy; r.s_uy = -v.s_uy; r.s_ux = -v.s_ux; r.s_muy = -v.s_muy;
+  r.ux = -v.ux; r.uy = -v.uy;
+  return r;
 }
+
+// Ring row of population plane i for the sweep-relative row index j >= 0
+__device__ __forceinline__ int pop_slot(int i, int j) { return 4 * i + (j & 3); }
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
 __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int strip,
@@ -62,8 +96,12 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
   const int x0 = strip * g.out_w;
   const int w = min(g.out_w, nx - x0);
   const int h = 3 * half;
-  const bool live = t >= h && t < w + 10 - h;
-  const bool ulane = t >= h + 1 && t < w + 9 - h;
+  // Lanes whose moments, velocities and collisions are valid: [h, w+10-h),
+  // [h+1, w+9-h) and [h+2, w+8-h).  Only the collision's stores are masked;
+  // moments, velocities, D and S are formed on every lane (all loads stay in
+  // bounds), so the state carried from row to row is never written under a
+  // lane mask, which would cost a copy of each carried value per row.
+  // Values of the other lanes are never used.
   const bool olane = t >= h + 2 && t < w + 8 - h;
   const int c = wrap_index(x0 - 5 + t, nx);
   const int cm = (c == 0) ? nx - 1 : c - 1;
@@ -72,9 +110,9 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
   constexpr unsigned SB = sizeof(S);
   constexpr unsigned TB = sizeof(T);
 
-  T (*s_rho)[NT] = L.rho[half];
-  U4<T> (*s_u4)[NT] = L.u4[half];
-  U2<T> (*s_u2)[NT] = L.u2[half];
+  T* s_rho = L.rho[half];
+  U4<T>* s_u4 = L.u4[half];
+  U2<T>* s_u2 = L.u2[half];
 
   const unsigned plane_bytes = unsigned(g.plane) * SB;
   const unsigned row_bytes = unsigned(pitch) * SB;
@@ -87,13 +125,11 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
   const int y1 = min(y0 + g.rows, ny);
   const int nit = (y1 - y0) + 11;
   const int yoff = 5 + 4 * half;
-  // sweep-relative row index (>= 0 for every row a ring holds) and the
-  // three-row ring slot of the stage rings
+  // sweep-relative row index of the population ring (>= 0 for every row it
+  // holds)
   auto jr = [&](int y) { return y - y0 + 12; };
-  auto s3 = [&](int y) { return int(unsigned(jr(y)) % 3u); };
 
   const T kappa = ph.kappa, rho0 = ph.rho0;
-  const T third = T(1.0 / 3.0);
   const unsigned xcb = unsigned(c) * SB, xmb = unsigned(cm) * SB, xpb = unsigned(cp) * SB;
   const unsigned xcT = unsigned(c) * TB;
 
@@ -119,51 +155,51 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
       f[0] = bload<S>(srcr, xcb, poff(0, r));
       f[1] = bload<S>(srcr, xmb, poff(1, r));
       f[3] = bload<S>(srcr, xpb, poff(3, r));
-      f[2] = bload<S>(srcr, xcb, bl ? poff(4, r) : poff(2, rs));
-      f[5] = bload<S>(srcr, bl ? xcb : xmb, bl ? poff(7, r) : poff(5, rs));
-      f[6] = bload<S>(srcr, bl ? xcb : xpb, bl ? poff(8, r) : poff(6, rs));
-      f[4] = bload<S>(srcr, xcb, bh ? poff(2, r) : poff(4, rn));
-      f[7] = bload<S>(srcr, bh ? xcb : xpb, bh ? poff(5, r) : poff(7, rn));
-      f[8] = bload<S>(srcr, bh ? xcb : xmb, bh ? poff(6, r) : poff(8, rn));
+      if (WALLS && (bl || bh)) {
+        // a wall row (taken on two rows per sweep, so the others need no
+        // per-lane selects of their column offsets)
+        f[2] = bload<S>(srcr, xcb, bl ? poff(4, r) : poff(2, rs));
+        f[5] = bload<S>(srcr, bl ? xcb : xmb, bl ? poff(7, r) : poff(5, rs));
+        f[6] = bload<S>(srcr, bl ? xcb : xpb, bl ? poff(8, r) : poff(6, rs));
+        f[4] = bload<S>(srcr, xcb, bh ? poff(2, r) : poff(4, rn));
+        f[7] = bload<S>(srcr, bh ? xcb : xpb, bh ? poff(5, r) : poff(7, rn));
+        f[8] = bload<S>(srcr, bh ? xcb : xmb, bh ? poff(6, r) : poff(8, rn));
+      } else {
+        f[2] = bload<S>(srcr, xcb, poff(2, rs));
+        f[5] = bload<S>(srcr, xmb, poff(5, rs));
+        f[6] = bload<S>(srcr, xpb, poff(6, rs));
+        f[4] = bload<S>(srcr, xcb, poff(4, rn));
+        f[7] = bload<S>(srcr, xpb, poff(7, rn));
+        f[8] = bload<S>(srcr, xmb, poff(8, rn));
+      }
     }
   };
 
+  // D and S of the two rows below the one that stage B (rm, rc) and stage C
+  // (vm, vc) read from LDS
+  RhoDS<T> rm{}, rc{};
+  VelDS<T> vm{}, vc{};
+
+  // One sweep iteration.  Rows beyond a wall: above the upper wall stage A
+  // and stage B write the image of row ny - 1 into the single-row rings;
+  // below the lower wall the image of row 0 replaces the carried D and S of
+  // row -1 before the stage that needs it.
   auto body = [&](int k, const RowIn<S, T>& in, RowState<T>& rA, const RowState<T>& rB,
                   const RowState<T>& rC, T (&bNew)[2], const T (&bOld)[2]) {
     const int yA = y0 - yoff + k;
+    if (WALLS && (yA == 1 || yA == 2)) {
+      // a branch taken once per sweep (the asm statement keeps the compiler
+      // from turning it into selects on every row)
+      __asm__ volatile("" ::: "memory");
+      if (yA == 1) rm = rc;              // delta-rho: centre value
+      else vm = mirrored(vc);            // velocity fields: negated
+    }
 
     // ---------------- stage A: moments of row yA ----------------
     const bool rowA = (WALLS ? (yA >= 0 && yA < ny) : true) && (half == 0 || yA >= y0 - 2);
-    if (rowA && live) {
-      const T phi = in.phi;
-      T q[9];
-      if (half == 0) {
-        if (SHIFT) {
-#pragma unroll
-          for (int i = 0; i < 9; ++i)
-            q[i] = sizeof(S) == 2 ? static_cast<T>(in.f[i]) * ph.inv_scale : static_cast<T>(in.f[i]);
-        } else {
-          q[0] = static_cast<T>(in.f[0]) - (phi * rho0 - ph.rest0_k);
-#pragma unroll
-          for (int i = 1; i < 5; ++i) q[i] = static_cast<T>(in.f[i]) - ph.rest_axis;
-#pragma unroll
-          for (int i = 5; i < 9; ++i) q[i] = static_cast<T>(in.f[i]) - ph.rest_diag;
-        }
-      } else {
-        // pull from half 0's ring: f_i(x) = f+_i(x - e_i), bounce-back at walls
-        const bool bl = WALLS && yA == 0, bh = WALLS && yA == ny - 1;
-        const int j0 = jr(yA), jm = j0 - 1, jp = j0 + 1;
-        q[0] = L.pop[pop_slot(0, j0)][t];
-        q[1] = L.pop[pop_slot(1, j0)][tl];
-        q[3] = L.pop[pop_slot(3, j0)][tr];
-        q[2] = bl ? L.pop[pop_slot(4, j0)][t] : L.pop[pop_slot(2, jm)][t];
-        q[5] = bl ? L.pop[pop_slot(7, j0)][t] : L.pop[pop_slot(5, jm)][tl];
-        q[6] = bl ? L.pop[pop_slot(8, j0)][t] : L.pop[pop_slot(6, jm)][tr];
-        q[4] = bh ? L.pop[pop_slot(2, j0)][t] : L.pop[pop_slot(4, jp)][t];
-        q[7] = bh ? L.pop[pop_slot(5, j0)][t] : L.pop[pop_slot(7, jp)][tr];
-        q[8] = bh ? L.pop[pop_slot(6, j0)][t] : L.pop[pop_slot(8, jp)][tl];
-      }
-      // rows of M (Eq. A1) applied to the deviations
+    // rows of M (Eq. A1) applied to the deviations q; formed in each half's
+    // branch so that the two sources of q need not share registers
+    auto moments = [&](const T (&q)[9], T phi) {
       const T sa = (q[1] + q[2]) + (q[3] + q[4]);
       const T sd = (q[5] + q[6]) + (q[7] + q[8]);
       rA.dm0 = q[0] + (sa + sd);
@@ -177,54 +213,88 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
       rA.mpxy = (q[5] + q[7]) - (q[6] + q[8]);
       rA.phi = phi;
       rA.drho = rA.dm0 * recip(phi);
-      s_rho[s3(yA)][t] = rA.drho;
-      // image below the lower wall; it shares its slot with row 2, written
-      // two iterations later, after every stage that reads the image.  Above
-      // the upper wall the image's slot would be row ny - 3's, still read, so
-      // the stages read row ny - 1 itself there instead.
-      if (WALLS && yA == 0) s_rho[s3(-1)][t] = rA.drho;
+    };
+    if (rowA) {
+      const T phi = in.phi;
+      if (half == 0) {
+        T q[9];
+        if (SHIFT) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i)
+            q[i] = sizeof(S) == 2 ? static_cast<T>(in.f[i]) * ph.inv_scale : static_cast<T>(in.f[i]);
+        } else {
+          q[0] = static_cast<T>(in.f[0]) - (phi * rho0 - ph.rest0_k);
+#pragma unroll
+          for (int i = 1; i < 5; ++i) q[i] = static_cast<T>(in.f[i]) - ph.rest_axis;
+#pragma unroll
+          for (int i = 5; i < 9; ++i) q[i] = static_cast<T>(in.f[i]) - ph.rest_diag;
+        }
+        moments(q, phi);
+      } else {
+        // pull from half 0's ring: f_i(x) = f+_i(x - e_i); at a wall the
+        // image rows hold the bounced-back populations
+        T q[9];
+        const int j0 = jr(yA), jm = j0 - 1, jp = j0 + 1;
+        q[0] = L.pop[pop_slot(0, j0)][t];
+        q[1] = L.pop[pop_slot(1, j0)][tl];
+        q[3] = L.pop[pop_slot(3, j0)][tr];
+        q[2] = L.pop[pop_slot(2, jm)][t];
+        q[5] = L.pop[pop_slot(5, jm)][tl];
+        q[6] = L.pop[pop_slot(6, jm)][tr];
+        q[4] = L.pop[pop_slot(4, jp)][t];
+        q[7] = L.pop[pop_slot(7, jp)][tr];
+        q[8] = L.pop[pop_slot(8, jp)][tl];
+        moments(q, phi);
+      }
+      s_rho[t] = rA.drho;
+    } else if (WALLS && yA == ny) {
+      s_rho[t] = rB.drho;  // above the upper wall: row ny - 1 itself
     }
     __syncthreads();
 
     // ---------------- stage B: velocity of row yA - 1 ----------------
+    // D and S of delta-rho on row yA, then grad rho on row yA - 1.  D and S
+    // of rows that do not exist are never used.
     const int yb = yA - 1;
     const bool rowB = (WALLS ? (yb >= 0 && yb < ny) : true) && (yb >= y0 - 4 + 3 * half);
-    if (rowB && ulane) {
-      const int sc = s3(yb), ss = s3(yb - 1);
-      const int sn = (WALLS && yb == ny - 1) ? sc : s3(yb + 1);  // image above the wall
-      const T rE = s_rho[sc][tr], rW = s_rho[sc][tl];
-      const T rN = s_rho[sn][t], rS = s_rho[ss][t];
-      const T rNE = s_rho[sn][tr], rNW = s_rho[sn][tl];
-      const T rSE = s_rho[ss][tr], rSW = s_rho[ss][tl];
-      const T grx = stencil_dx(rE, rW, rNE, rSE, rNW, rSW);
-      const T gry = stencil_dy(rN, rS, rNE, rNW, rSE, rSW);
-      const T phi = rB.phi;
-      const T kp = (kappa - phi) * third;
-      const T sg = ph.scale_by_phi ? phi : T(1);
-      const T Fx = kp * grx + sg * ph.gx;
-      const T Fy = kp * gry + sg * ph.gy;
-      const T m0 = phi * rho0 + rB.dm0;
-      const T inv_m0 = recip(m0);
-      const T ux = (rB.jx + T(0.5) * Fx) * inv_m0;
-      const T uy = (rB.jy + T(0.5) * Fy) * inv_m0;
-      const T rho = rho0 + rB.drho;
-      U4<T> a;
-      U2<T> b;
-      a.ux = ux; a.uy = uy; a.mux = m0 * ux; a.rux = rho * ux;
-      b.muy = m0 * uy; b.ruy = rho * uy;
-      s_u4[s3(yb)][t] = a;
-      s_u2[s3(yb)][t] = b;
-      if (WALLS && yb == 0) {  // mirror image below the lower wall
-        const int sg2 = s3(-1);
-        U4<T> am;
-        U2<T> bm;
-        am.ux = -a.ux; am.uy = -a.uy; am.mux = -a.mux; am.rux = -a.rux;
-        bm.muy = -b.muy; bm.ruy = -b.ruy;
-        s_u4[sg2][t] = am;
-        s_u2[sg2][t] = bm;
+    {
+      RhoDS<T> rn;
+      {
+        const T r0 = s_rho[t], rE = s_rho[tr], rW = s_rho[tl];
+        rn.d = rE - rW;
+        rn.s = (rE + rW) + T(4) * r0;
       }
-      bNew[0] = Fx;
-      bNew[1] = Fy;
+      if (rowB) {
+        const T grx = T(4) * rc.d + (rm.d + rn.d);  // 12 d_x rho (Eq. 10)
+        const T gry = rn.s - rm.s;                  // 12 d_y rho
+        const T phi = rB.phi;
+        const T kp = (kappa - phi) * T(1.0 / 36.0);     // Eq. (13), with the 1/12
+        const T sg = ph.scale_by_phi ? phi : T(1);
+        const T Fx = kp * grx + sg * ph.gx;
+        const T Fy = kp * gry + sg * ph.gy;
+        const T m0 = phi * rho0 + rB.dm0;
+        const T inv_m0 = recip(m0);
+        const T ux = (rB.jx + T(0.5) * Fx) * inv_m0;
+        const T uy = (rB.jy + T(0.5) * Fy) * inv_m0;
+        const T rho = rho0 + rB.drho;
+        U4<T> a;
+        U2<T> b;
+        a.ux = ux; a.uy = uy; a.mux = m0 * ux; a.rux = rho * ux;
+        b.muy = m0 * uy; b.ruy = rho * uy;
+        s_u4[t] = a;
+        s_u2[t] = b;
+        bNew[0] = Fx;
+        bNew[1] = Fy;
+      } else if (WALLS && yb == ny) {  // above the upper wall: row ny - 1, negated
+        U4<T> a = s_u4[t];
+        U2<T> b = s_u2[t];
+        a.ux = -a.ux; a.uy = -a.uy; a.mux = -a.mux; a.rux = -a.rux;
+        b.muy = -b.muy; b.ruy = -b.ruy;
+        s_u4[t] = a;
+        s_u2[t] = b;
+      }
+      rm = rc;
+      rc = rn;
     }
     __syncthreads();
 
@@ -232,114 +302,141 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
     const int yo = yA - 2;
     const bool rowC = (WALLS ? (yo >= 0 && yo < ny) : true) &&
                       (half == 0 ? (yo >= y0 - 3 && yo <= y1 + 2) : (yo >= y0 && yo < y1));
-    if (rowC && olane) {
-      // above the upper wall the image is row ny - 1 itself, velocities negated
-      const bool top = WALLS && yo == ny - 1;
-      const int uo = s3(yo), us = s3(yo - 1), un = top ? uo : s3(yo + 1);
-      const U4<T> aC = s_u4[uo][t];
-      const U4<T> aE = s_u4[uo][tr], aW = s_u4[uo][tl];
-      U4<T> aN = s_u4[un][t];
-      const U4<T> aS = s_u4[us][t];
-      U4<T> aNE = s_u4[un][tr], aNW = s_u4[un][tl];
-      const U4<T> aSE = s_u4[us][tr], aSW = s_u4[us][tl];
-      U2<T> bN = s_u2[un][t];
-      const U2<T> bS = s_u2[us][t];
-      U2<T> bNE = s_u2[un][tr], bNW = s_u2[un][tl];
-      const U2<T> bSE = s_u2[us][tr], bSW = s_u2[us][tl];
-      if (top) {
-        auto neg4 = [](U4<T>& v) { v.ux = -v.ux; v.uy = -v.uy; v.mux = -v.mux; v.rux = -v.rux; };
-        auto neg2 = [](U2<T>& v) { v.muy = -v.muy; v.ruy = -v.ruy; };
-        neg4(aN); neg4(aNE); neg4(aNW);
-        neg2(bN); neg2(bNE); neg2(bNW);
-      }
-
-      // the eight derivatives of Eq. (20), each by Eq. (10)
-      const T d_rux_x = stencil_dx(aE.rux, aW.rux, aNE.rux, aSE.rux, aNW.rux, aSW.rux);
-      const T d_ruy_y = stencil_dy(bN.ruy, bS.ruy, bNE.ruy, bNW.ruy, bSE.ruy, bSW.ruy);
-      const T d_ux_x = stencil_dx(aE.ux, aW.ux, aNE.ux, aSE.ux, aNW.ux, aSW.ux);
-      const T d_uy_y = stencil_dy(aN.uy, aS.uy, aNE.uy, aNW.uy, aSE.uy, aSW.uy);
-      const T d_uy_x = stencil_dx(aE.uy, aW.uy, aNE.uy, aSE.uy, aNW.uy, aSW.uy);
-      const T d_ux_y = stencil_dy(aN.ux, aS.ux, aNE.ux, aNW.ux, aSE.ux, aSW.ux);
-      const T d_mux_x = stencil_dx(aE.mux, aW.mux, aNE.mux, aSE.mux, aNW.mux, aSW.mux);
-      const T d_muy_y = stencil_dy(bN.muy, bS.muy, bNE.muy, bNW.muy, bSE.muy, bSW.muy);
-
-      const T phi = rC.phi;
-      const T rho = rho0 + rC.drho;
-      const T X = kappa * recip(phi);
-      const T kmp = kappa - phi;
-      const T ux = aC.ux, uy = aC.uy, Fx = bOld[0], Fy = bOld[1];
-
-      // penalty source (Eq. 20), static void fraction
-      const T Ca = -kappa * (d_rux_x + d_ruy_y) + T(2) * kmp * rho * (d_ux_x + d_uy_y) +
-                   (T(3) - T(2) * X) * (d_mux_x + d_muy_y);
-      const T Cb = -kappa * (d_rux_x - d_ruy_y) + T(2.0 / 3.0) * kmp * rho * (d_ux_x - d_uy_y) +
-                   (d_mux_x - d_muy_y);
-      const T Cc = third * kmp * rho * (d_uy_x + d_ux_y);
-
-      // equilibria (Eq. 18) minus those of the rest state
-      const T m0 = phi * rho0 + rC.dm0;
-      const T drho = rC.drho;
-      const T uu = ux * ux + uy * uy;
-      const T eq_e = (T(2) * kappa - T(4) * phi) * drho + T(3) * m0 * uu;
-      const T eq_ep = (T(4) * phi - T(3) * kappa) * drho - T(3) * m0 * uu;
-      const T qfac = (kappa - T(2) * phi) * rho;
-      const T eq_qx = qfac * ux, eq_qy = qfac * uy;
-      const T eq_pxx = m0 * (ux * ux - uy * uy);
-      const T eq_pxy = m0 * (ux * uy);
-
-      // force moments (Eq. 19)
-      const T uF = ux * Fx + uy * Fy;
-      const T S1 = T(6) * uF;
-      const T S7 = T(2) * (ux * Fx - uy * Fy);
-      const T S8 = ux * Fy + uy * Fx;
-
-      // relaxation (Eq. 16); conserved moments: m0+ = m0, j+ = j + F
-      const T he = T(1) - T(0.5) * ph.s_e, hep = T(1) - T(0.5) * ph.s_eps;
-      const T hq = T(1) - T(0.5) * ph.s_q, hn = T(1) - T(0.5) * ph.s_nu;
-      const T pe = rC.me - ph.s_e * (rC.me - eq_e) + he * (S1 + Ca);
-      const T pep = rC.mep - ph.s_eps * (rC.mep - eq_ep) - hep * S1;
-      const T pqx = rC.mqx - ph.s_q * (rC.mqx - eq_qx) - hq * Fx;
-      const T pqy = rC.mqy - ph.s_q * (rC.mqy - eq_qy) - hq * Fy;
-      const T ppxx = rC.mpxx - ph.s_nu * (rC.mpxx - eq_pxx) + hn * (S7 + Cb);
-      const T ppxy = rC.mpxy - ph.s_nu * (rC.mpxy - eq_pxy) + hn * (S8 + Cc);
-      const T pm0 = rC.dm0;
-      const T pjx = rC.jx + Fx;
-      const T pjy = rC.jy + Fy;
-
-      // back-transform f+ = M^-1 m+ (Eq. A1)
-      const T a = (T(4) * pm0 - pe - T(2) * pep) * T(1.0 / 36.0);
-      const T b = (T(4) * pm0 + T(2) * pe + pep) * T(1.0 / 36.0);
-      const T X1 = (pjx - pqx) * T(1.0 / 6.0), Y1 = (pjy - pqy) * T(1.0 / 6.0);
-      const T X2 = (T(2) * pjx + pqx) * T(1.0 / 12.0), Y2 = (T(2) * pjy + pqy) * T(1.0 / 12.0);
-      const T Pd = ppxx * T(0.25), Qd = ppxy * T(0.25);
-      T o9[9];
-      o9[0] = (pm0 - pe + pep) * T(1.0 / 9.0);
-      o9[1] = a + X1 + Pd;
-      o9[2] = a + Y1 - Pd;
-      o9[3] = a - X1 + Pd;
-      o9[4] = a - Y1 - Pd;
-      o9[5] = b + X2 + Y2 + Qd;
-      o9[6] = b - X2 + Y2 - Qd;
-      o9[7] = b - X2 - Y2 + Qd;
-      o9[8] = b + X2 - Y2 - Qd;
-
-      if (half == 0) {  // into the ring for the second step
-        const int jo = jr(yo);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) L.pop[pop_slot(i, jo)][t] = o9[i];
-      } else if (SHIFT) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-          bstore(static_cast<S>(sizeof(S) == 2 ? o9[i] * ph.scale : o9[i]), dstr, xcb, poff(i, yo));
-      } else {
-        bstore(static_cast<S>(o9[0] + (phi * rho0 - ph.rest0_k)), dstr, xcb, poff(0, yo));
-#pragma unroll
-        for (int i = 1; i < 5; ++i) bstore(static_cast<S>(o9[i] + ph.rest_axis), dstr, xcb, poff(i, yo));
-#pragma unroll
-        for (int i = 5; i < 9; ++i) bstore(static_cast<S>(o9[i] + ph.rest_diag), dstr, xcb, poff(i, yo));
+    if (WALLS && half == 0 && (yo == 1 || yo == ny) && olane) {
+      // Image rows of the population ring for half 1's pull next to a wall
+      // (half-way bounce-back: the population leaving x across the wall
+      // returns to x in the opposite direction).  Written one iteration after
+      // the wall row, into ring rows that nothing reads until half 1 pulls
+      // the wall row.  Position t takes the value of the lane that the pull
+      // at t - e_i stands for.
+      const int js = jr(yo - 1);  // the wall row
+      if (yo == 1) {  // row -1 from row 0
+        const int jd = js - 1;
+        const T v2 = L.pop[pop_slot(4, js)][t];
+        const T v5 = L.pop[pop_slot(7, js)][tr];
+        const T v6 = L.pop[pop_slot(8, js)][tl];
+        L.pop[pop_slot(2, jd)][t] = v2;
+        L.pop[pop_slot(5, jd)][t] = v5;
+        L.pop[pop_slot(6, jd)][t] = v6;
+      } else {        // row ny from row ny - 1
+        const int jd = js + 1;
+        const T v4 = L.pop[pop_slot(2, js)][t];
+        const T v7 = L.pop[pop_slot(5, js)][tl];
+        const T v8 = L.pop[pop_slot(6, js)][tr];
+        L.pop[pop_slot(4, jd)][t] = v4;
+        L.pop[pop_slot(7, jd)][t] = v7;
+        L.pop[pop_slot(8, jd)][t] = v8;
       }
     }
-    // the ring rows written here are pulled in the next iteration
+    {
+      // D and S of the velocity fields on row yb
+      VelDS<T> vn;
+      {
+        const U4<T> a0 = s_u4[t], aE = s_u4[tr], aW = s_u4[tl];
+        const U2<T> b0 = s_u2[t], bE = s_u2[tr], bW = s_u2[tl];
+        vn.d_rux = aE.rux - aW.rux;
+        vn.d_ux = aE.ux - aW.ux;
+        vn.d_uy = aE.uy - aW.uy;
+        vn.d_mux = aE.mux - aW.mux;
+        vn.s_ruy = (bE.ruy + bW.ruy) + T(4) * b0.ruy;
+        vn.s_uy = (aE.uy + aW.uy) + T(4) * a0.uy;
+        vn.s_ux = (aE.ux + aW.ux) + T(4) * a0.ux;
+        vn.s_muy = (bE.muy + bW.muy) + T(4) * b0.muy;
+        vn.ux = a0.ux;
+        vn.uy = a0.uy;
+      }
+      if (rowC && olane) {
+        // the eight derivatives of Eq. (20), each 12 times its Eq. (10) value
+        const T dx_rux = T(4) * vc.d_rux + (vm.d_rux + vn.d_rux);
+        const T dx_ux = T(4) * vc.d_ux + (vm.d_ux + vn.d_ux);
+        const T dx_uy = T(4) * vc.d_uy + (vm.d_uy + vn.d_uy);
+        const T dx_mux = T(4) * vc.d_mux + (vm.d_mux + vn.d_mux);
+        const T dy_ruy = vn.s_ruy - vm.s_ruy;
+        const T dy_uy = vn.s_uy - vm.s_uy;
+        const T dy_ux = vn.s_ux - vm.s_ux;
+        const T dy_muy = vn.s_muy - vm.s_muy;
+
+        const T phi = rC.phi;
+        const T rho = rho0 + rC.drho;
+        const T X = kappa * recip(phi);
+        const T kr = (kappa - phi) * rho;
+        const T ux = vc.ux, uy = vc.uy, Fx = bOld[0], Fy = bOld[1];
+
+        // penalty source (Eq. 20), static void fraction; the 1/12 of the
+        // derivatives is folded into the coefficients
+        const T Ca = -ph.k12 * (dx_rux + dy_ruy) + (kr * T(1.0 / 6.0)) * (dx_ux + dy_uy) +
+                     (T(0.25) - X * T(1.0 / 6.0)) * (dx_mux + dy_muy);
+        const T Cb = -ph.k12 * (dx_rux - dy_ruy) + (kr * T(1.0 / 18.0)) * (dx_ux - dy_uy) +
+                     T(1.0 / 12.0) * (dx_mux - dy_muy);
+        const T Cc = (kr * T(1.0 / 36.0)) * (dx_uy + dy_ux);
+
+        // equilibria (Eq. 18) minus those of the rest state
+        const T m0 = phi * rho0 + rC.dm0;
+        const T drho = rC.drho;
+        const T uu = ux * ux + uy * uy;
+        const T eq_e = (ph.k2 - T(4) * phi) * drho + T(3) * m0 * uu;
+        const T eq_ep = (T(4) * phi - ph.k3) * drho - T(3) * m0 * uu;
+        const T qfac = (kappa - T(2) * phi) * rho;
+        const T eq_qx = qfac * ux, eq_qy = qfac * uy;
+        const T eq_pxx = m0 * (ux * ux - uy * uy);
+        const T eq_pxy = m0 * (ux * uy);
+
+        // force moments (Eq. 19)
+        const T uF = ux * Fx + uy * Fy;
+        const T S1 = T(6) * uF;
+        const T S7 = T(2) * (ux * Fx - uy * Fy);
+        const T S8 = ux * Fy + uy * Fx;
+
+        // relaxation (Eq. 16); conserved moments: m0+ = m0, j+ = j + F
+        const T he = ph.he, hep = ph.hep, hq = ph.hq, hn = ph.hn;
+        const T pe = rC.me - ph.s_e * (rC.me - eq_e) + he * (S1 + Ca);
+        const T pep = rC.mep - ph.s_eps * (rC.mep - eq_ep) - hep * S1;
+        const T pqx = rC.mqx - ph.s_q * (rC.mqx - eq_qx) - hq * Fx;
+        const T pqy = rC.mqy - ph.s_q * (rC.mqy - eq_qy) - hq * Fy;
+        const T ppxx = rC.mpxx - ph.s_nu * (rC.mpxx - eq_pxx) + hn * (S7 + Cb);
+        const T ppxy = rC.mpxy - ph.s_nu * (rC.mpxy - eq_pxy) + hn * (S8 + Cc);
+        const T pm0 = rC.dm0;
+        const T pjx = rC.jx + Fx;
+        const T pjy = rC.jy + Fy;
+
+        // back-transform f+ = M^-1 m+ (Eq. A1)
+        const T a = (T(4) * pm0 - pe - T(2) * pep) * T(1.0 / 36.0);
+        const T b = (T(4) * pm0 + T(2) * pe + pep) * T(1.0 / 36.0);
+        const T X1 = (pjx - pqx) * T(1.0 / 6.0), Y1 = (pjy - pqy) * T(1.0 / 6.0);
+        const T X2 = (T(2) * pjx + pqx) * T(1.0 / 12.0), Y2 = (T(2) * pjy + pqy) * T(1.0 / 12.0);
+        const T Pd = ppxx * T(0.25), Qd = ppxy * T(0.25);
+        T o9[9];
+        o9[0] = (pm0 - pe + pep) * T(1.0 / 9.0);
+        o9[1] = a + X1 + Pd;
+        o9[2] = a + Y1 - Pd;
+        o9[3] = a - X1 + Pd;
+        o9[4] = a - Y1 - Pd;
+        o9[5] = b + X2 + Y2 + Qd;
+        o9[6] = b - X2 + Y2 - Qd;
+        o9[7] = b - X2 - Y2 + Qd;
+        o9[8] = b + X2 - Y2 - Qd;
+
+        if (half == 0) {  // into the ring for the second step
+          const int jo = jr(yo);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) L.pop[pop_slot(i, jo)][t] = o9[i];
+        } else if (SHIFT) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i)
+            bstore(static_cast<S>(sizeof(S) == 2 ? o9[i] * ph.scale : o9[i]), dstr, xcb, poff(i, yo));
+        } else {
+          bstore(static_cast<S>(o9[0] + (phi * rho0 - ph.rest0_k)), dstr, xcb, poff(0, yo));
+#pragma unroll
+          for (int i = 1; i < 5; ++i) bstore(static_cast<S>(o9[i] + ph.rest_axis), dstr, xcb, poff(i, yo));
+#pragma unroll
+          for (int i = 5; i < 9; ++i) bstore(static_cast<S>(o9[i] + ph.rest_diag), dstr, xcb, poff(i, yo));
+        }
+      }
+      vm = vc;
+      vc = vn;
+    }
+    // the ring rows written here are pulled in the next iteration, and the
+    // single-row rings are rewritten
     __syncthreads();
   };
 

@@ -63,6 +63,11 @@ struct StepPhys {
   int model_b;  // model B (set I): kappa - 1 in place of kappa - phi in F^p and C
   int eq2;      // second-order equilibrium (B1-B2) with the penalty of Eq. (B3)
   T uw_lo, uw_hi;  // x velocities of the walls at y = -1/2 and y = ny - 1/2
+  // Uniform products of the above, formed on the host in T arithmetic (the
+  // same roundings as forming them in a kernel).  The hardware has no scalar
+  // floating-point ALU, so a kernel would hold them in vector registers.
+  T k2, k3, k12;            // 2 kappa, 3 kappa, kappa / 12
+  T he, hep, hq, hn;        // 1 - s/2 for s_e, s_eps, s_q, s_nu (Eq. 16)
 };
 
 struct StepGeom {

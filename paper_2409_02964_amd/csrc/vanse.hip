@@ -191,6 +191,13 @@ StepPhys<T> make_phys(const vanse_lattice* h) {
   p.eq2 = h->eq2;
   p.uw_lo = T(h->uw_lo);
   p.uw_hi = T(h->uw_hi);
+  p.k2 = T(2) * p.kappa;
+  p.k3 = T(3) * p.kappa;
+  p.k12 = p.kappa * T(1.0 / 12.0);
+  p.he = T(1) - T(0.5) * p.s_e;
+  p.hep = T(1) - T(0.5) * p.s_eps;
+  p.hq = T(1) - T(0.5) * p.s_q;
+  p.hn = T(1) - T(0.5) * p.s_nu;
   return p;
 }
 

@@ -1,9 +1,11 @@
 """Two time steps per launch (vanse_set_steps_per_pass(2)).
 
-The two-step kernel runs the single step's arithmetic twice with the
-intermediate populations kept as FP32 deviations in LDS.  With FP32-shifted
-storage that is exactly what one step per launch stores and loads, so the
-results must agree bitwise; plain FP32 and FP16-shifted storage skip one
+The two-step kernel runs the scheme twice per pass with the intermediate
+populations kept as FP32 deviations in LDS.  With FP32-shifted storage that
+is what one step per launch stores and loads; the two kernels differ only in
+the order of the FP32 sums of the Eq. (10) stencils (the two-step kernel
+uses the stencil's separable form), so they agree to FP32 rounding
+(FUSED_RTOL below).  Plain FP32 and FP16-shifted storage also skip one
 storage rounding per pair and are checked against the FP64 oracle.
 """
 import math
@@ -42,6 +44,21 @@ def lattice(nx, ny, phi, precision, bc, fused, rows=0, g=(2e-5, -1e-5), drag=Non
     return lat
 
 
+# The two kernels round the stencil sums differently: a few FP32 ulps (6e-8
+# relative) of the penalty and force terms per step, which the collision (a
+# contraction, |1 - s| < 1) does not amplify.  Measured against how far the
+# state moved (max |f(t) - f(0)|), the difference after the dozen steps
+# compared here stays below 5e-7; 1e-5 leaves a twentyfold margin, while a
+# wrong ring row, lane or wall image is an error of the size of the change
+# itself.
+FUSED_RTOL = 1e-5
+
+
+def fused_rel_diff(fa, fb, f0):
+    """max |fa - fb| / max |fa - f0| (numpy or torch)"""
+    return float(abs(fa - fb).max() / abs(fa - f0).max())
+
+
 def rel_l2_u(m, ref):
     num = np.sum((m["ux"] - ref["ux"]) ** 2 + (m["uy"] - ref["uy"]) ** 2)
     return math.sqrt(num / np.sum(ref["ux"] ** 2 + ref["uy"] ** 2))
@@ -60,11 +77,12 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("nx,ny,bc,rows", SHAPES)
-def test_fused_equals_single_steps_f32s(nx, ny, bc, rows):
+def test_fused_matches_single_steps_f32s(nx, ny, bc, rows):
     torch = _torch()
     _say(f"fused vs single f32s {nx}x{ny} {bc} rows={rows}")
     phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 2.0, seed=nx + ny) ** 2
-    f0 = torch.from_numpy(W.random_populations(nx, ny, seed=7 + nx))
+    f0n = W.random_populations(nx, ny, seed=7 + nx)
+    f0 = torch.from_numpy(f0n)
     a = lattice(nx, ny, phi, "f32s", bc, fused=False)
     b = lattice(nx, ny, phi, "f32s", bc, fused=True, rows=rows)
     assert b.fused_tiling()["active"] and not a.fused_tiling()["active"]
@@ -76,7 +94,9 @@ def test_fused_equals_single_steps_f32s(nx, ny, bc, rows):
         fa = a.read_populations().cpu().numpy()
         fb = b.read_populations().cpu().numpy()
         assert a.t == b.t
-        assert np.array_equal(fa, fb), (n, float(np.max(np.abs(fa - fb))))
+        rel = fused_rel_diff(fa, fb, f0n)
+        _say(f"  after {a.t} steps: max |f_fused - f_single| / max |f - f0| = {rel:.3e}")
+        assert rel <= FUSED_RTOL, (n, rel)
 
 
 @pytest.mark.parametrize("prec,bound", [("f32", 5e-2), ("f16s", 5e-2)])
@@ -100,9 +120,10 @@ def test_fused_periodic_wave_vs_oracle(oracle, prec, bound):
     assert e_f <= 1.5 * e_s + 1e-6  # one storage rounding fewer per pair: not worse
 
 
-def test_fused_full_size_channel_bitwise():
+def test_fused_full_size_channel():
     """The 4096 x 4096 channel (walls, the benchmark field) in FP32-shifted
-    storage: one two-step launch and two single steps agree bitwise."""
+    storage: three two-step launches and six single steps agree to FP32
+    rounding."""
     torch = _torch()
     n = 4096
     phi = W.channel_phi(n, n, seed=2409)
@@ -110,11 +131,13 @@ def test_fused_full_size_channel_bitwise():
     b = lattice(n, n, phi, "f32s", "wall", fused=True, g=(1e-7, 0))
     for lat in (a, b):
         lat.init_equilibrium(1.0)
+    f0 = a.read_populations()
+    for lat in (a, b):
         lat.step(6)
     fa, fb = a.read_populations(), b.read_populations()
-    same = bool(torch.equal(fa, fb))
-    _say(f"full-size fused vs single: bitwise {same}; fused tiling {b.fused_tiling()}")
-    assert same
+    rel = fused_rel_diff(fa, fb, f0)
+    _say(f"full-size fused vs single: relative diff {rel:.3e}; fused tiling {b.fused_tiling()}")
+    assert rel <= FUSED_RTOL
     a.close()
     b.close()
 
