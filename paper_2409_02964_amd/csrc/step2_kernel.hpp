@@ -26,6 +26,11 @@
 // fills from the wall row once per sweep, so the pull itself never tests
 // for walls.
 //
+// Half 0's pulls from HBM: with 4-byte storage each row is loaded straight
+// into LDS (buffer loads with the LDS destination) two rows ahead, into a
+// two-slot staging area, so the loads in flight hold no registers and have
+// two iterations to land; 2-byte storage loads into registers one row ahead.
+//
 // The Eq. (10) derivatives use the stencil's separable form.  With
 //   D(y) = g(x+1, y) - g(x-1, y),   S(y) = g(x+1, y) + g(x-1, y) + 4 g(x, y)
 // for a field g on row y, the stencil is
@@ -53,8 +58,44 @@ struct Step2Lds {
   T rho[2][NT];      // per half: delta-rho of the row of stage A (read by B)
   U4<T> u4[2][NT];   // per half: velocity data of the row of stage B (read by C)
   U2<T> u2[2][NT];
-  T pop[36][NT];     // half 0's post-collision deviations (see pop_slot)
+  T pop[40][NT];     // half 0's post-collision deviations and phi (see pop_slot)
 };
+
+// Half 0's staging of a pulled row (4-byte storage): the nine populations
+// and phi, each lane's values at its own position.  Two slots, each its own
+// LDS object, passed to the tile as distinct restrict pointers: the
+// compiler then orders a read of one slot after the loads into that slot
+// only, not after the loads of the row ahead in flight into the other.
+template <int NT, bool DMA>
+struct Step2Stage {
+  float v[10][NT];
+};
+template <int NT>
+struct Step2Stage<NT, false> {
+  float v[1][1];
+};
+
+// Wait until at most n vector-memory operations of this wave are
+// outstanding (s_waitcnt with expcnt and lgkmcnt left at their maximum).
+// The compiler does not order LDS reads after loads into LDS by itself, so
+// the asm statement keeps the reads that follow below the wait.
+template <int n>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(n >= 0 && n < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+  __asm__ volatile("" ::: "memory");
+}
+
+// Workgroup barrier for LDS traffic: this wave's LDS reads and writes
+// complete, then s_barrier.  Unlike __syncthreads() it does not wait for the
+// wave's loads into LDS (the staging of rows ahead), which wait_vm orders
+// before their readers.
+__device__ __forceinline__ void lds_barrier() {
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));  // lgkmcnt(0)
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+}
 
 // D and S (see above) of delta-rho on one row
 template <typename T>
@@ -81,12 +122,18 @@ __device__ __forceinline__ VelDS<T> mirrored(const VelDS<T>& v) {
   return r;
 }
 
-// Ring row of population plane i for the sweep-relative row index j >= 0
+// Ring row of population plane i (i = 9: phi of the row, for half 1's
+// moments) for the sweep-relative row index j >= 0
 __device__ __forceinline__ int pop_slot(int i, int j) { return 4 * i + (j & 3); }
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
 __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int strip,
-                                           int by, Step2Lds<T, NT>& L) {
+                                           int by, Step2Lds<T, NT>* __restrict__ Lp,
+                                           Step2Stage<NT, sizeof(S) == 4>* __restrict__ st0,
+                                           Step2Stage<NT, sizeof(S) == 4>* __restrict__ st1) {
+  Step2Lds<T, NT>& L = *Lp;
+  constexpr bool DMA = sizeof(S) == 4;
+  static_assert(!DMA || sizeof(T) == 4, "staged rows hold FP32 phi");
   // uniform per wave (NT is a multiple of the wave size); read from the first
   // lane so that the compiler keeps everything derived from it -- rows, ring
   // slots, branches -- in scalar registers
@@ -133,9 +180,10 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
   const unsigned xcb = unsigned(c) * SB, xmb = unsigned(cm) * SB, xpb = unsigned(cp) * SB;
   const unsigned xcT = unsigned(c) * TB;
 
-  // Loads of row yn: half 0 pulls the nine populations from HBM (rows
-  // clamped inside walls, always in bounds) and phi; half 1 only needs phi.
-  auto load_row = [&](int yn, RowIn<S, T>& in) {
+  // The pull of row yn from HBM: ld(i, buffer, lane offset, row offset) for
+  // the nine populations (i = 0..8) and phi (i = 9).  Rows are clamped
+  // inside walls, so every load is in bounds.
+  auto pull_row = [&](int yn, auto&& ld) {
     int r, rs, rn;
     bool bl = false, bh = false;
     if (WALLS) {
@@ -149,29 +197,59 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
       rs = (r == 0) ? ny - 1 : r - 1;
       rn = (r == ny - 1) ? 0 : r + 1;
     }
-    in.phi = bload<T>(phir, xcT, unsigned(r) * unsigned(pitch) * TB);
-    if (half == 0) {
-      S (&f)[9] = in.f;
-      f[0] = bload<S>(srcr, xcb, poff(0, r));
-      f[1] = bload<S>(srcr, xmb, poff(1, r));
-      f[3] = bload<S>(srcr, xpb, poff(3, r));
-      if (WALLS && (bl || bh)) {
-        // a wall row (taken on two rows per sweep, so the others need no
-        // per-lane selects of their column offsets)
-        f[2] = bload<S>(srcr, xcb, bl ? poff(4, r) : poff(2, rs));
-        f[5] = bload<S>(srcr, bl ? xcb : xmb, bl ? poff(7, r) : poff(5, rs));
-        f[6] = bload<S>(srcr, bl ? xcb : xpb, bl ? poff(8, r) : poff(6, rs));
-        f[4] = bload<S>(srcr, xcb, bh ? poff(2, r) : poff(4, rn));
-        f[7] = bload<S>(srcr, bh ? xcb : xpb, bh ? poff(5, r) : poff(7, rn));
-        f[8] = bload<S>(srcr, bh ? xcb : xmb, bh ? poff(6, r) : poff(8, rn));
+    ld(9, phir, xcT, unsigned(r) * unsigned(pitch) * TB);
+    ld(0, srcr, xcb, poff(0, r));
+    ld(1, srcr, xmb, poff(1, r));
+    ld(3, srcr, xpb, poff(3, r));
+    if (WALLS && (bl || bh)) {
+      // a wall row (taken on two rows per sweep, so the others need no
+      // per-lane selects of their column offsets)
+      ld(2, srcr, xcb, bl ? poff(4, r) : poff(2, rs));
+      ld(5, srcr, bl ? xcb : xmb, bl ? poff(7, r) : poff(5, rs));
+      ld(6, srcr, bl ? xcb : xpb, bl ? poff(8, r) : poff(6, rs));
+      ld(4, srcr, xcb, bh ? poff(2, r) : poff(4, rn));
+      ld(7, srcr, bh ? xcb : xpb, bh ? poff(5, r) : poff(7, rn));
+      ld(8, srcr, bh ? xcb : xmb, bh ? poff(6, r) : poff(8, rn));
+    } else {
+      ld(2, srcr, xcb, poff(2, rs));
+      ld(5, srcr, xmb, poff(5, rs));
+      ld(6, srcr, xpb, poff(6, rs));
+      ld(4, srcr, xcb, poff(4, rn));
+      ld(7, srcr, xpb, poff(7, rn));
+      ld(8, srcr, xmb, poff(8, rn));
+    }
+  };
+  // Workgroup barrier: without staging in flight the ordinary one (its
+  // fence waits for nothing else here)
+  auto barrier = [&]() {
+    if constexpr (DMA) lds_barrier();
+    else __syncthreads();
+  };
+  // Register loads of row yn without staging (2-byte storage): half 0 the
+  // pull, half 1 phi.  (With staging half 1 takes phi from the population
+  // ring, where half 0 leaves it, and issues no loads at all.)
+  auto load_row = [&](int yn, RowIn<S, T>& in) {
+    if constexpr (!DMA) {
+      if (half == 0) {
+        pull_row(yn, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
+          if (i == 9) in.phi = bload<T>(rs, v, so);
+          else in.f[i] = bload<S>(rs, v, so);
+        });
       } else {
-        f[2] = bload<S>(srcr, xcb, poff(2, rs));
-        f[5] = bload<S>(srcr, xmb, poff(5, rs));
-        f[6] = bload<S>(srcr, xpb, poff(6, rs));
-        f[4] = bload<S>(srcr, xcb, poff(4, rn));
-        f[7] = bload<S>(srcr, xpb, poff(7, rn));
-        f[8] = bload<S>(srcr, xmb, poff(8, rn));
+        const int r = WALLS ? min(max(yn, 0), ny - 1) : wrap_index(yn, ny);
+        in.phi = bload<T>(phir, xcT, unsigned(r) * unsigned(pitch) * TB);
       }
+    }
+  };
+  // Half 0's loads of row yn into staging slot sl (4-byte storage); each
+  // wave's 64 lanes fill 64 consecutive positions from the wave's base.
+  const int wb = __builtin_amdgcn_readfirstlane(t & ~63);
+  auto stage_row = [&](int yn, int sl) {
+    if constexpr (DMA) {
+      pull_row(yn, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (__attribute__((address_space(3))) void*)&(sl ? st1 : st0)->v[i][wb], 4, v, so, 0, 0);
+      });
     }
   };
 
@@ -184,7 +262,7 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
   // and stage B write the image of row ny - 1 into the single-row rings;
   // below the lower wall the image of row 0 replaces the carried D and S of
   // row -1 before the stage that needs it.
-  auto body = [&](int k, const RowIn<S, T>& in, RowState<T>& rA, const RowState<T>& rB,
+  auto body = [&](int k, int sl, const RowIn<S, T>& in, RowState<T>& rA, const RowState<T>& rB,
                   const RowState<T>& rC, T (&bNew)[2], const T (&bOld)[2]) {
     const int yA = y0 - yoff + k;
     if (WALLS && (yA == 1 || yA == 2)) {
@@ -214,27 +292,46 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
       rA.phi = phi;
       rA.drho = rA.dm0 * recip(phi);
     };
+    // half 0 (4-byte storage): the staged row yA has landed once at most one
+    // batch (row yA + 1) is still in flight
+    if (DMA && half == 0) wait_vm<10>();
     if (rowA) {
-      const T phi = in.phi;
       if (half == 0) {
+        S f[9];
+        T phi;
+        if constexpr (DMA) {
+          const auto* st = sl ? st1 : st0;
+#pragma unroll
+          for (int i = 0; i < 9; ++i) f[i] = __builtin_bit_cast(S, st->v[i][t]);
+          phi = st->v[9][t];
+          // keeps these reads here, next to the wait that orders them: merged
+          // with half 1's read of phi they would wait for the row ahead too
+          __asm__ volatile("" ::: "memory");
+        } else {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) f[i] = in.f[i];
+          phi = in.phi;
+        }
         T q[9];
         if (SHIFT) {
 #pragma unroll
           for (int i = 0; i < 9; ++i)
-            q[i] = sizeof(S) == 2 ? static_cast<T>(in.f[i]) * ph.inv_scale : static_cast<T>(in.f[i]);
+            q[i] = sizeof(S) == 2 ? static_cast<T>(f[i]) * ph.inv_scale : static_cast<T>(f[i]);
         } else {
-          q[0] = static_cast<T>(in.f[0]) - (phi * rho0 - ph.rest0_k);
+          q[0] = static_cast<T>(f[0]) - (phi * rho0 - ph.rest0_k);
 #pragma unroll
-          for (int i = 1; i < 5; ++i) q[i] = static_cast<T>(in.f[i]) - ph.rest_axis;
+          for (int i = 1; i < 5; ++i) q[i] = static_cast<T>(f[i]) - ph.rest_axis;
 #pragma unroll
-          for (int i = 5; i < 9; ++i) q[i] = static_cast<T>(in.f[i]) - ph.rest_diag;
+          for (int i = 5; i < 9; ++i) q[i] = static_cast<T>(f[i]) - ph.rest_diag;
         }
         moments(q, phi);
       } else {
         // pull from half 0's ring: f_i(x) = f+_i(x - e_i); at a wall the
-        // image rows hold the bounced-back populations
+        // image rows hold the bounced-back populations.  phi of the row came
+        // with it.
         T q[9];
         const int j0 = jr(yA), jm = j0 - 1, jp = j0 + 1;
+        const T phi = DMA ? L.pop[pop_slot(9, j0)][t] : in.phi;
         q[0] = L.pop[pop_slot(0, j0)][t];
         q[1] = L.pop[pop_slot(1, j0)][tl];
         q[3] = L.pop[pop_slot(3, j0)][tr];
@@ -250,7 +347,11 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
     } else if (WALLS && yA == ny) {
       s_rho[t] = rB.drho;  // above the upper wall: row ny - 1 itself
     }
-    __syncthreads();
+    barrier();
+
+    // The staging slot of row yA has been read (the barrier above waited for
+    // this wave's LDS reads): it takes row yA + 2.
+    if (DMA && half == 0) stage_row(yA + 2, sl);
 
     // ---------------- stage B: velocity of row yA - 1 ----------------
     // D and S of delta-rho on row yA, then grad rho on row yA - 1.  D and S
@@ -296,7 +397,7 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
       rm = rc;
       rc = rn;
     }
-    __syncthreads();
+    barrier();
 
     // ---------------- stage C: collide row yA - 2 ----------------
     const int yo = yA - 2;
@@ -420,6 +521,7 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
           const int jo = jr(yo);
 #pragma unroll
           for (int i = 0; i < 9; ++i) L.pop[pop_slot(i, jo)][t] = o9[i];
+          if (DMA) L.pop[pop_slot(9, jo)][t] = phi;
         } else if (SHIFT) {
 #pragma unroll
           for (int i = 0; i < 9; ++i)
@@ -437,35 +539,42 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
     }
     // the ring rows written here are pulled in the next iteration, and the
     // single-row rings are rewritten
-    __syncthreads();
+    barrier();
   };
 
-  // Software pipeline as in the single step: the loads of row yA + 1 are in
-  // flight while row yA is processed; unrolled by six (a multiple of the
-  // three-row period of the states) so nothing is copied.
+  // Software pipeline: register loads of row yA + 1 are in flight while row
+  // yA is processed (staged rows two ahead, see stage_row); unrolled by six
+  // (a multiple of the three-row period of the states and of the two
+  // staging slots) so nothing is copied.
   RowState<T> R0{}, R1{}, R2{};
   T b0[2] = {0, 0}, b1[2] = {0, 0};
   RowIn<S, T> ia{}, ib{};
+  if (DMA && half == 0) {
+    stage_row(y0 - yoff, 0);
+    stage_row(y0 - yoff + 1, 1);
+  }
   load_row(y0 - yoff, ia);
   for (int k = 0; k < nit; k += 6) {
     load_row(y0 - yoff + 1 + k, ib);
-    body(k + 0, ia, R0, R2, R1, b0, b1);
+    body(k + 0, 0, ia, R0, R2, R1, b0, b1);
     if (k + 1 >= nit) break;
     load_row(y0 - yoff + 2 + k, ia);
-    body(k + 1, ib, R1, R0, R2, b1, b0);
+    body(k + 1, 1, ib, R1, R0, R2, b1, b0);
     if (k + 2 >= nit) break;
     load_row(y0 - yoff + 3 + k, ib);
-    body(k + 2, ia, R2, R1, R0, b0, b1);
+    body(k + 2, 0, ia, R2, R1, R0, b0, b1);
     if (k + 3 >= nit) break;
     load_row(y0 - yoff + 4 + k, ia);
-    body(k + 3, ib, R0, R2, R1, b1, b0);
+    body(k + 3, 1, ib, R0, R2, R1, b1, b0);
     if (k + 4 >= nit) break;
     load_row(y0 - yoff + 5 + k, ib);
-    body(k + 4, ia, R1, R0, R2, b0, b1);
+    body(k + 4, 0, ia, R1, R0, R2, b0, b1);
     if (k + 5 >= nit) break;
     load_row(y0 - yoff + 6 + k, ia);
-    body(k + 5, ib, R2, R1, R0, b1, b0);
+    body(k + 5, 1, ib, R2, R1, R0, b1, b0);
   }
+  // no load into LDS may outlive the workgroup
+  if (DMA) wait_vm<0>();
 }
 
 // Two time steps per launch: workgroup b takes strip b % strips, row block
@@ -474,8 +583,9 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
 __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(4)))
 vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
   __shared__ Step2Lds<T, NT> lds;
+  __shared__ Step2Stage<NT, sizeof(S) == 4> stage0, stage1;
   step2_tile<S, T, SHIFT, WALLS, NT>(g, ph, int(blockIdx.x) % g.strips, int(blockIdx.x) / g.strips,
-                                     lds);
+                                     &lds, &stage0, &stage1);
 }
 
 }  // namespace vanse_dev
