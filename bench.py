@@ -16,9 +16,12 @@ updates per second) over the timed steps, inputs resident in HBM.  The
 the algorithmic bytes per node update (9 population reads + 9 writes + phi)
 times the node updates per launch (two per node for the two-step kernel);
 its duration comes from HIP events recorded on the stream the kernel is
-launched on.  `traffic` is the HBM bytes one launch actually moves
-(rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated on the copy kernel).  `cpu_baseline` times the FP64 CPU oracle on a bounded sample
-of the same workload.
+launched on.  With two node updates per launch the intermediate state
+never reaches HBM, so `achieved` (both updates' algorithmic bytes) can
+exceed the single-pass HBM ceiling.  `traffic` is the HBM bytes one launch
+actually moves (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated on the copy
+kernel) and `traffic_gbs` that over the launch duration.  `cpu_baseline`
+times the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -486,6 +489,11 @@ def main():
                      "kernel": "vanse_step2_kernel" if per_launch == 2 else "vanse_step_kernel",
                      "node_updates_per_launch": per_launch * nodes,
                      "algorithmic_bytes_per_launch": bpn * nodes * per_launch,
+                     # what the launch moves over its duration: with two
+                     # updates per launch sharing one pass over HBM this, not
+                     # `achieved`, is the rate the memory system sustains
+                     "traffic_gbs": (round(traffic / (per_step_ms * per_launch / 1e3) / 1e9, 1)
+                                     if traffic else None),
                      "same_pattern_copy_gbs": sol},
         "wall_s": round(wall, 3),
         "final_umax": obs["umax"],
