@@ -215,12 +215,13 @@ int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
  * launch each: a workgroup's first half runs step t -> t+1 into an LDS ring
  * and its second half step t+1 -> t+2 from it, so the populations cross HBM
  * once per two steps; an odd step count ends with one single step.  Each
- * half's arithmetic is the single step's; the intermediate state stays in
- * FP32 deviations, so FP32-shifted storage gives bitwise the single-step
- * results and the other storage formats skip one storage rounding.  Other
- * lattices keep one step per launch.  rows: rows per workgroup of the
- * two-step kernel (0: one full round of resident workgroups).
- * VANSE_ERR_UNSUPPORTED for FP64. */
+ * half computes the same scheme as the single step (its Eq. 10 sums in the
+ * stencil's separable form, so the FP32 roundings differ); the intermediate
+ * state stays in FP32 deviations, so FP32-shifted storage matches the
+ * single-step results to FP32 rounding and the other storage formats skip
+ * one storage rounding.  Other lattices keep one step per launch.  rows:
+ * rows per workgroup of the two-step kernel (0: one full round of resident
+ * workgroups).  VANSE_ERR_UNSUPPORTED for FP64. */
 int vanse_set_steps_per_pass(vanse_lattice *h, int steps, int rows);
 /* Whether the two-step launch is in use (*active), and its rows per
  * workgroup and workgroups per launch. */
