@@ -49,6 +49,8 @@
 // covers y0 - 3 .. y1 + 2.
 #pragma once
 
+#include <stdint.h>
+
 #include "step_kernel.hpp"
 
 namespace vanse_dev {
@@ -97,6 +99,46 @@ __device__ __forceinline__ void lds_barrier() {
   __asm__ volatile("" ::: "memory");
 }
 
+// LDS-qualified object type
+template <typename X>
+using lds_t = __attribute__((address_space(3))) X;
+
+// The address of an LDS object as a value the compiler cannot trace back to
+// the object.  The tile takes its three LDS objects as restrict pointers made
+// this way; inlining then tags every LDS access with the object it belongs
+// to, which lets the compiler order a read of one staging slot after the
+// loads into that slot only (a read it cannot attribute waits for every load
+// into LDS in flight, the row ahead included).
+template <typename X>
+__device__ __forceinline__ lds_t<X>* lds_handle(X* p) {
+  unsigned u = unsigned(uintptr_t((lds_t<X>*)p));
+  __asm__ volatile("" : "+s"(u));
+  return (lds_t<X>*)uintptr_t(u);
+}
+
+// Member-wise copies of the velocity records to and from LDS (the implicit
+// copy operations take generic-address-space objects)
+template <typename T>
+__device__ __forceinline__ U4<T> lds_get(const lds_t<U4<T>>& v) {
+  U4<T> r;
+  r.ux = v.ux; r.uy = v.uy; r.mux = v.mux; r.rux = v.rux;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ U2<T> lds_get(const lds_t<U2<T>>& v) {
+  U2<T> r;
+  r.muy = v.muy; r.ruy = v.ruy;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ void lds_put(lds_t<U4<T>>& d, const U4<T>& v) {
+  d.ux = v.ux; d.uy = v.uy; d.mux = v.mux; d.rux = v.rux;
+}
+template <typename T>
+__device__ __forceinline__ void lds_put(lds_t<U2<T>>& d, const U2<T>& v) {
+  d.muy = v.muy; d.ruy = v.ruy;
+}
+
 // D and S (see above) of delta-rho on one row
 template <typename T>
 struct RhoDS {
@@ -127,11 +169,11 @@ __device__ __forceinline__ VelDS<T> mirrored(const VelDS<T>& v) {
 __device__ __forceinline__ int pop_slot(int i, int j) { return 4 * i + (j & 3); }
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
-__device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int strip,
-                                           int by, Step2Lds<T, NT>* __restrict__ Lp,
-                                           Step2Stage<NT, sizeof(S) == 4>* __restrict__ st0,
-                                           Step2Stage<NT, sizeof(S) == 4>* __restrict__ st1) {
-  Step2Lds<T, NT>& L = *Lp;
+__device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int strip, int by,
+                                  lds_t<Step2Lds<T, NT>>* __restrict__ Lp,
+                                  lds_t<Step2Stage<NT, sizeof(S) == 4>>* __restrict__ st0,
+                                  lds_t<Step2Stage<NT, sizeof(S) == 4>>* __restrict__ st1) {
+  auto& L = *Lp;
   constexpr bool DMA = sizeof(S) == 4;
   static_assert(!DMA || sizeof(T) == 4, "staged rows hold FP32 phi");
   // uniform per wave (NT is a multiple of the wave size); read from the first
@@ -157,9 +199,9 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
   constexpr unsigned SB = sizeof(S);
   constexpr unsigned TB = sizeof(T);
 
-  T* s_rho = L.rho[half];
-  U4<T>* s_u4 = L.u4[half];
-  U2<T>* s_u2 = L.u2[half];
+  auto* s_rho = L.rho[half];
+  auto* s_u4 = L.u4[half];
+  auto* s_u2 = L.u2[half];
 
   const unsigned plane_bytes = unsigned(g.plane) * SB;
   const unsigned row_bytes = unsigned(pitch) * SB;
@@ -248,7 +290,7 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
     if constexpr (DMA) {
       pull_row(yn, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
         __builtin_amdgcn_raw_ptr_buffer_load_lds(
-            rs, (__attribute__((address_space(3))) void*)&(sl ? st1 : st0)->v[i][wb], 4, v, so, 0, 0);
+            rs, (lds_t<void>*)&(sl ? st1 : st0)->v[i][wb], 4, v, so, 0, 0);
       });
     }
   };
@@ -382,17 +424,17 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
         U2<T> b;
         a.ux = ux; a.uy = uy; a.mux = m0 * ux; a.rux = rho * ux;
         b.muy = m0 * uy; b.ruy = rho * uy;
-        s_u4[t] = a;
-        s_u2[t] = b;
+        lds_put(s_u4[t], a);
+        lds_put(s_u2[t], b);
         bNew[0] = Fx;
         bNew[1] = Fy;
       } else if (WALLS && yb == ny) {  // above the upper wall: row ny - 1, negated
-        U4<T> a = s_u4[t];
-        U2<T> b = s_u2[t];
+        U4<T> a = lds_get(s_u4[t]);
+        U2<T> b = lds_get(s_u2[t]);
         a.ux = -a.ux; a.uy = -a.uy; a.mux = -a.mux; a.rux = -a.rux;
         b.muy = -b.muy; b.ruy = -b.ruy;
-        s_u4[t] = a;
-        s_u2[t] = b;
+        lds_put(s_u4[t], a);
+        lds_put(s_u2[t], b);
       }
       rm = rc;
       rc = rn;
@@ -433,8 +475,8 @@ __device__ __forceinline__ void step2_tile(const StepGeom& g, const StepPhys<T>&
       // D and S of the velocity fields on row yb
       VelDS<T> vn;
       {
-        const U4<T> a0 = s_u4[t], aE = s_u4[tr], aW = s_u4[tl];
-        const U2<T> b0 = s_u2[t], bE = s_u2[tr], bW = s_u2[tl];
+        const U4<T> a0 = lds_get(s_u4[t]), aE = lds_get(s_u4[tr]), aW = lds_get(s_u4[tl]);
+        const U2<T> b0 = lds_get(s_u2[t]), bE = lds_get(s_u2[tr]), bW = lds_get(s_u2[tl]);
         vn.d_rux = aE.rux - aW.rux;
         vn.d_ux = aE.ux - aW.ux;
         vn.d_uy = aE.uy - aW.uy;
@@ -585,7 +627,7 @@ vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
   __shared__ Step2Lds<T, NT> lds;
   __shared__ Step2Stage<NT, sizeof(S) == 4> stage0, stage1;
   step2_tile<S, T, SHIFT, WALLS, NT>(g, ph, int(blockIdx.x) % g.strips, int(blockIdx.x) / g.strips,
-                                     &lds, &stage0, &stage1);
+                                     lds_handle(&lds), lds_handle(&stage0), lds_handle(&stage1));
 }
 
 }  // namespace vanse_dev
