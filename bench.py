@@ -53,9 +53,15 @@ TRAFFIC_FILE = PROFILE_PREFIX + "_traffic.json"
 
 
 def kernel_hash() -> str:
+    """Hash of the step kernels' code: the sources with comments and
+    whitespace removed, so that the traffic record follows code changes only."""
+    import re
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, p), "rb").read())
+        src = open(os.path.join(ROOT, p)).read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

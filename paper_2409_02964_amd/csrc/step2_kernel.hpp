@@ -10,11 +10,11 @@
 //   half 1 advances the same columns from t+1 to t+2 four rows behind: it
 //          pulls from the LDS ring (the x and y shifts of streaming become
 //          ring indices), and stores to HBM.
-// The arithmetic of each half is that of the plain single step (Sec. 2.3:
-// Eq. 7, 10, 13, 14-20, A1); only where the intermediate populations live
-// differs, so HBM traffic per time step halves.  The intermediate state is
-// kept as FP32 deviations from the rest state, which for FP32-shifted
-// storage is exactly what the single step stores.
+// Each half computes the plain single step's scheme (Sec. 2.3: Eq. 7, 10,
+// 13, 14-20, A1), with the Eq. (10) sums in the separable form below; the
+// intermediate populations never reach HBM, so HBM traffic per time step
+// halves.  The intermediate state is kept as FP32 deviations from the rest
+// state, the format the single step stores with FP32-shifted storage.
 //
 // Per iteration k each half runs three stages on rows yA = y0 - 5 - 4 half
 // + k (A: moments), yA - 1 (B: velocity), yA - 2 (C: collision), with three
@@ -38,9 +38,10 @@
 // A lane sweeps one column, so each row's D and S are formed once, from the
 // row's own values and its two neighbours in LDS, and the two rows below stay
 // in registers.  The LDS rings of delta-rho and of the velocity data then
-// hold a single row, and the rows beyond a wall (the centre-value image of
-// delta-rho, the negated image of the velocity fields) are formed in
-// registers from the D and S of the wall row.
+// hold a single row.  The rows beyond a wall (the centre-value image of
+// delta-rho, the negated image of the velocity fields) are written into
+// those rings above the upper wall and formed in registers from the D and S
+// of row 0 below the lower wall.
 //
 // Columns: lane t of either half is column x0 - 5 + t.  Half 0 forms moments
 // on lanes [0, w+10), velocities on [1, w+9), collisions on [2, w+8); half 1
