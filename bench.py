@@ -144,9 +144,10 @@ def small_bench(steps: int = 1000, graph_steps: int = 100):
 def batched_bench(steps: int, baseline_steps: int, graph_steps: int = 100):
     """Batched workload: 256 independent periodic lattices, sides log-uniform
     in [32, 512] (seed 4), phi = 0.6 + 0.3 sin(2 pi kx x/L) sin(2 pi ky y/L),
-    |G| ~ U[1e-7, 1e-5] along x, FP32, `steps` steps, one launch per step
-    over all lattices (autotuned tile shape, hipGraph-captured loop).  The
-    comparison is the plain path with one launch per lattice per step."""
+    |G| ~ U[1e-7, 1e-5] along x, FP32, `steps` steps, one launch per step (or
+    per two steps) over all lattices (autotuned launch shape, hipGraph-captured
+    loop).  The comparison is the plain path with one launch per lattice per
+    step."""
     import torch
     from paper_2409_02964_amd import workloads as W
     from paper_2409_02964_amd.vanse import Batch, Lattice, autotune_batch
@@ -164,11 +165,12 @@ def batched_bench(steps: int, baseline_steps: int, graph_steps: int = 100):
 
     nodes = sum(sp["L"] ** 2 for sp in specs)
     lats = build()
-    best, _ = autotune_batch(lats, candidates=[(64, 0), (128, 0), (128, 16), (256, 0), (64, 16)],
+    best, _ = autotune_batch(lats, candidates=[(128, 16), (256, 0), (64, 16), (128, 0, 2),
+                                               (128, 32, 2), (256, 48, 2), (64, 24, 2)],
                              steps=10)
     for lat in lats:
         lat.init_equilibrium(1.0)
-    b = Batch(lats, threads=best[0], rows=best[1], graph_steps=graph_steps)
+    b = Batch(lats, threads=best[0], rows=best[1], graph_steps=graph_steps, steps_per_pass=best[2])
     b.step(graph_steps)
     torch.cuda.synchronize()
     for lat in lats:
@@ -193,7 +195,8 @@ def batched_bench(steps: int, baseline_steps: int, graph_steps: int = 100):
     t_plain = (time.perf_counter() - t0) * steps / baseline_steps
     return {"workload": "256 periodic lattices, L log-uniform 32..512 (seed 4), FP32, "
                         f"{steps} steps", "lattices": len(specs), "nodes": nodes,
-            "steps": steps, "threads": best[0], "rows": b.tiles()["rows"],
+            "steps": steps, "steps_per_launch": best[2], "threads": best[0],
+            "rows": b.tiles()["rows"],
             "tiles": b.tiles()["tiles"], "graph_steps": graph_steps,
             "solves_per_s": round(len(specs) / t_batch, 2),
             "mlups": round(nodes * steps / t_batch / 1e6, 1),

@@ -242,9 +242,9 @@ int vanse_stream_copy(vanse_lattice *h, int64_t n, void *stream);
 
 /* ---- batches -------------------------------------------------------------
  * Many independent lattices advanced together: every call to
- * vanse_batch_step launches ONE kernel per time step whose workgroups cover
- * the tiles of all member lattices (tile = strip of threads-4 columns x
- * `rows` rows of one lattice).  Each member's arithmetic is exactly that of
+ * vanse_batch_step launches ONE kernel per time step (or per two, see
+ * vanse_batch_create_ex) whose workgroups cover the tiles of all member
+ * lattices (tile = strip of threads-4 columns x `rows` rows of one lattice).  Each member's arithmetic is exactly that of
  * vanse_step (results are bitwise identical).  Members must share precision,
  * boundary type and the force-field flag, be fully set up, and stay alive
  * while the batch exists.  The batch keeps a table of the members'
@@ -265,9 +265,25 @@ int vanse_batch_create(vanse_lattice *const *lats, int n, int threads, int rows,
                        void *workspace, size_t bytes, vanse_batch **out);
 int vanse_batch_destroy(vanse_batch *b);
 
-/* Capture the step loop in a hipGraph of this many launches (even, > 0;
- * 0 turns graphs off).  Graph launches run on a stream owned by the batch,
- * ordered after and before the caller's stream with events. */
+/* As the two calls above, with steps_per_pass time steps per launch (1 or
+ * 2).  With 2 every launch applies the two-step kernel of
+ * vanse_set_steps_per_pass to all members (FP32 arithmetic, members without
+ * force field or drag, else VANSE_ERR_UNSUPPORTED): threads is then the
+ * width of each half of a workgroup of 2 x threads lanes, a tile is a strip
+ * of threads-10 columns, and rows = 0 gives about four rounds of resident
+ * workgroups.  Each member's results are bitwise those of stepping it alone
+ * with two steps per launch; an odd step count ends with one step of each
+ * member on its own. */
+int vanse_batch_workspace_bytes_ex(vanse_lattice *const *lats, int n, int threads,
+                                   int rows, int steps_per_pass, size_t *bytes);
+int vanse_batch_create_ex(vanse_lattice *const *lats, int n, int threads, int rows,
+                          int steps_per_pass, void *workspace, size_t bytes,
+                          vanse_batch **out);
+
+/* Capture the step loop in hipGraphs of this many time steps (> 0 and a
+ * multiple of 2 x steps per pass, so that a replay covers an even number of
+ * launches; 0 turns graphs off).  Graph launches run on a stream owned by
+ * the batch, ordered after and before the caller's stream with events. */
 int vanse_batch_set_graph(vanse_batch *b, int steps_per_graph);
 
 /* Advance every member nsteps time steps.  Enqueued on `stream`. */

@@ -631,4 +631,30 @@ vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
                                      lds_handle(&lds), lds_handle(&stage0), lds_handle(&stage1));
 }
 
+// Many lattices, two time steps per launch: workgroup b takes tile b of the
+// batch table (lattice tile_lattice[b], strip and row block as in the
+// one-lattice kernel); each member's two buffers alternate with the launch
+// parity as in the one-step batch.
+template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
+__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(4)))
+vanse_batch_step2_kernel(const BatchEntry<T>* __restrict__ entries,
+                         const int* __restrict__ tile_lattice, int launch) {
+  __shared__ Step2Lds<T, NT> lds;
+  __shared__ Step2Stage<NT, sizeof(S) == 4> stage0, stage1;
+  const int k = tile_lattice[blockIdx.x];
+  const BatchEntry<T>& e = entries[k];
+  StepGeom g = e.g;
+  const int par = (e.cur0 + launch) & 1;
+  void* const b0 = const_cast<void*>(e.g.src);
+  void* const b1 = e.g.dst;
+  g.src = par ? b1 : b0;
+  g.dst = par ? b0 : b1;
+  const int local = int(blockIdx.x) - e.first_tile;
+  // a private copy, as the one-lattice kernel's argument: read through the
+  // table the parameters could alias the stores as far as the compiler knows
+  const StepPhys<T> ph = e.ph;
+  step2_tile<S, T, SHIFT, WALLS, NT>(g, ph, local % g.strips, local / g.strips, lds_handle(&lds),
+                                     lds_handle(&stage0), lds_handle(&stage1));
+}
+
 }  // namespace vanse_dev

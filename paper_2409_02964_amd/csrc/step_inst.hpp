@@ -4,8 +4,9 @@
 //
 // Instances: workgroup widths 64, 128 and 256 for every feature variant the
 // host selects (plain, force field, drag, both, FEAT_ALL), 512 for the plain
-// step; the batched kernel for the first four; the two-step kernel of the
-// plain step (256-lane halves) where VANSE_FUSED2 is set.
+// step; the batched kernel for the first four; where VANSE_FUSED2 is set the
+// two-step kernel of the plain step (256-lane halves) and its batched form
+// (halves of 64, 128 or 256 lanes).
 #include "step_launch.hpp"
 
 namespace vanse_dev {
@@ -24,6 +25,13 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 void launch_batch_nt(const BatchEntry<T>* entries, const int* tile_lattice, int launch, int tiles,
                      hipStream_t st) {
   hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(tiles), dim3(NT), 0,
+                     st, entries, tile_lattice, launch);
+}
+
+template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
+void launch_batch2_nt(const BatchEntry<T>* entries, const int* tile_lattice, int launch, int tiles,
+                      hipStream_t st) {
+  hipLaunchKernelGGL((vanse_batch_step2_kernel<S, T, SHIFT, WALLS, NT>), dim3(tiles), dim3(2 * NT), 0,
                      st, entries, tile_lattice, launch);
 }
 
@@ -56,6 +64,12 @@ template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, false, 256>(
     const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
 template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, true, 256>(
     const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
+#define VANSE_BATCH2_ONE(W, NT) \
+  template void launch_batch2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, NT>( \
+      const BatchEntry<VANSE_T>*, const int*, int, int, hipStream_t);
+VANSE_BATCH2_ONE(false, 64) VANSE_BATCH2_ONE(false, 128) VANSE_BATCH2_ONE(false, 256)
+VANSE_BATCH2_ONE(true, 64) VANSE_BATCH2_ONE(true, 128) VANSE_BATCH2_ONE(true, 256)
+#undef VANSE_BATCH2_ONE
 #endif
 
 #undef VANSE_STEP_ONE

@@ -834,6 +834,7 @@ struct vanse_batch {
   std::vector<int> rows;     // rows per workgroup, per lattice
   std::vector<int> first;    // first tile of each lattice
   int threads = 256;
+  int fuse = 1;              // time steps per launch (2: the two-step kernel)
   int total_tiles = 0;
   char* ws = nullptr;
   size_t entries_off = 0, tiles_off = 0;
@@ -849,17 +850,27 @@ struct vanse_batch {
 
 namespace {
 
-int batch_per_cu(int precision, int threads) { return (precision == VANSE_F64 ? 2 : 4) * (256 / threads); }
+// Resident workgroups per CU: one-step workgroups of `threads` lanes (four
+// waves per SIMD in FP32, two in FP64), two-step workgroups of 2 x threads
+// lanes (16 waves per CU).
+int batch_per_cu(int precision, int threads, int fuse) {
+  if (fuse == 2) return 512 / threads;
+  return (precision == VANSE_F64 ? 2 : 4) * (256 / threads);
+}
 
-int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, std::vector<int>* rows_out,
-                 std::vector<int>* first_out, int* total_tiles, size_t* entries_off, size_t* tiles_off,
-                 size_t* bytes) {
+// Columns a tile outputs: threads - 4 for one step, threads - 10 for two
+int batch_out_w(int threads, int fuse) { return threads - (fuse == 2 ? 10 : 4); }
+
+int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int fuse,
+                 std::vector<int>* rows_out, std::vector<int>* first_out, int* total_tiles,
+                 size_t* entries_off, size_t* tiles_off, size_t* bytes) {
   if (!lats || n < 1) return fail(VANSE_ERR_INVALID_ARG, "a batch needs at least one lattice");
   if (threads != 64 && threads != 128 && threads != 256)
     return fail(VANSE_ERR_INVALID_ARG, "batch threads must be 64, 128 or 256 (got %d)", threads);
   if (rows < 0) return fail(VANSE_ERR_INVALID_ARG, "rows must be >= 0");
+  if (fuse != 1 && fuse != 2) return fail(VANSE_ERR_INVALID_ARG, "steps per pass must be 1 or 2 (got %d)", fuse);
   const vanse_desc& d0 = lats[0] ? lats[0]->d : vanse_desc{};
-  const int out_w = threads - 4;
+  const int out_w = batch_out_w(threads, fuse);
   long long strip_rows = 0;
   for (int k = 0; k < n; ++k) {
     if (!lats[k]) return fail(VANSE_ERR_INVALID_ARG, "lattice %d is NULL", k);
@@ -870,13 +881,21 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, std::
     if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field ||
         d.has_drag != d0.has_drag)
       return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary, force field or drag", k);
+    if (fuse == 2 && (d.precision == VANSE_F64 || feat_of(lats[k]) != 0))
+      return fail(VANSE_ERR_UNSUPPORTED,
+                  "lattice %d: two steps per launch take FP32 arithmetic without force field or drag", k);
     strip_rows += (long long)((d.nx + out_w - 1) / out_w) * d.ny;
   }
   int r = rows;
-  if (r == 0) {  // about two rounds of resident workgroups over the whole batch
-    const long long slots = (long long)device_cus() * batch_per_cu(d0.precision, threads);
-    r = (int)((strip_rows + 2 * slots - 1) / (2 * slots));
-    if (r < 8) r = 8;
+  if (r == 0) {
+    // about two rounds of resident workgroups over the whole batch for one
+    // step per launch, four for two (measured on 256 lattices of side 32 to
+    // 512: shorter tiles balance the uneven lattices better than they lose
+    // to the 11 extra rows each two-step tile sweeps)
+    const int rounds = fuse == 2 ? 4 : 2;
+    const long long slots = (long long)device_cus() * batch_per_cu(d0.precision, threads, fuse);
+    r = (int)((strip_rows + rounds * slots - 1) / (rounds * slots));
+    if (r < (fuse == 2 ? 16 : 8)) r = fuse == 2 ? 16 : 8;
   }
   rows_out->assign(n, r);
   first_out->assign(n, 0);
@@ -916,7 +935,7 @@ void fill_entries(vanse_batch* b, std::vector<char>* blob) {
     g.nx = h->d.nx;
     g.ny = h->d.ny;
     g.pitch = h->L.pitch;
-    g.out_w = b->threads - 4;
+    g.out_w = batch_out_w(b->threads, b->fuse);
     g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
     g.rows = b->rows[k];
     E[k].g = g;
@@ -955,6 +974,16 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
 void batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
   const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
   const int* TL = reinterpret_cast<const int*>(b->ws + b->tiles_off);
+  if constexpr (sizeof(T) == 4 && FEAT == 0) {
+    if (b->fuse == 2) {
+      switch (b->threads) {
+        case 64: launch_batch2_nt<S, T, SHIFT, WALLS, 64>(E, TL, launch, b->total_tiles, st); break;
+        case 128: launch_batch2_nt<S, T, SHIFT, WALLS, 128>(E, TL, launch, b->total_tiles, st); break;
+        default: launch_batch2_nt<S, T, SHIFT, WALLS, 256>(E, TL, launch, b->total_tiles, st);
+      }
+      return;
+    }
+  }
   switch (b->threads) {
     case 64: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st); break;
     case 128: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st); break;
@@ -982,22 +1011,28 @@ int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
 
 extern "C" {
 
-int vanse_batch_workspace_bytes(vanse_lattice* const* lats, int n, int threads, int rows, size_t* bytes) {
+int vanse_batch_workspace_bytes_ex(vanse_lattice* const* lats, int n, int threads, int rows,
+                                   int steps_per_pass, size_t* bytes) {
   if (!bytes) return fail(VANSE_ERR_INVALID_ARG, "bytes is NULL");
   std::vector<int> r, f;
   int tiles;
   size_t eo, to;
-  return batch_layout(lats, n, threads, rows, &r, &f, &tiles, &eo, &to, bytes);
+  return batch_layout(lats, n, threads, rows, steps_per_pass, &r, &f, &tiles, &eo, &to, bytes);
 }
 
-int vanse_batch_create(vanse_lattice* const* lats, int n, int threads, int rows, void* workspace,
-                       size_t bytes, vanse_batch** out) {
+int vanse_batch_workspace_bytes(vanse_lattice* const* lats, int n, int threads, int rows, size_t* bytes) {
+  return vanse_batch_workspace_bytes_ex(lats, n, threads, rows, 1, bytes);
+}
+
+int vanse_batch_create_ex(vanse_lattice* const* lats, int n, int threads, int rows, int steps_per_pass,
+                          void* workspace, size_t bytes, vanse_batch** out) {
   if (!out) return fail(VANSE_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   std::vector<int> r, f;
   int tiles;
   size_t eo, to, need;
-  if (int rc = batch_layout(lats, n, threads, rows, &r, &f, &tiles, &eo, &to, &need)) return rc;
+  if (int rc = batch_layout(lats, n, threads, rows, steps_per_pass, &r, &f, &tiles, &eo, &to, &need))
+    return rc;
   if (!workspace || (((uintptr_t)workspace) & 255)) return fail(VANSE_ERR_WORKSPACE, "batch workspace missing or not 256-byte aligned");
   if (bytes < need) return fail(VANSE_ERR_WORKSPACE, "batch workspace too small: %zu < %zu", bytes, need);
   vanse_batch* b = new (std::nothrow) vanse_batch();
@@ -1006,12 +1041,18 @@ int vanse_batch_create(vanse_lattice* const* lats, int n, int threads, int rows,
   b->rows = r;
   b->first = f;
   b->threads = threads;
+  b->fuse = steps_per_pass;
   b->total_tiles = tiles;
   b->ws = static_cast<char*>(workspace);
   b->entries_off = eo;
   b->tiles_off = to;
   *out = b;
   return VANSE_OK;
+}
+
+int vanse_batch_create(vanse_lattice* const* lats, int n, int threads, int rows, void* workspace,
+                       size_t bytes, vanse_batch** out) {
+  return vanse_batch_create_ex(lats, n, threads, rows, 1, workspace, bytes, out);
 }
 
 int vanse_batch_destroy(vanse_batch* b) {
@@ -1026,8 +1067,12 @@ int vanse_batch_destroy(vanse_batch* b) {
 
 int vanse_batch_set_graph(vanse_batch* b, int steps_per_graph) {
   if (!b) return fail(VANSE_ERR_INVALID_ARG, "batch is NULL");
-  if (steps_per_graph < 0 || (steps_per_graph & 1))
-    return fail(VANSE_ERR_INVALID_ARG, "steps per graph must be 0 or a positive even number (got %d)", steps_per_graph);
+  // a graph replays an even number of launches (each member's buffers end
+  // where they started)
+  const int period = 2 * b->fuse;
+  if (steps_per_graph < 0 || steps_per_graph % period)
+    return fail(VANSE_ERR_INVALID_ARG, "steps per graph must be 0 or a positive multiple of %d (got %d)", period,
+                steps_per_graph);
   if (b->graph) {
     (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
@@ -1062,8 +1107,13 @@ int vanse_batch_step(vanse_batch* b, int64_t nsteps, void* stream) {
   if (stale) {
     if (int rc = batch_upload(b, st)) return rc;
   }
-  int64_t left = nsteps;
-  if (b->graph_steps > 0 && left >= b->graph_steps) {
+  // launches of `fuse` steps each; with two steps per launch an odd count
+  // ends with one step of each member on its own
+  const int64_t launches = nsteps / b->fuse;
+  const int64_t rem = nsteps % b->fuse;
+  const int glaunch = b->graph_steps / b->fuse;  // launches per graph
+  int64_t left = launches;
+  if (glaunch > 0 && left >= glaunch) {
     if (!b->own) {
       HIP_TRY(hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking));
       HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
@@ -1077,19 +1127,19 @@ int vanse_batch_step(vanse_batch* b, int64_t nsteps, void* stream) {
     }
     HIP_TRY(hipEventRecord(b->ev_in, st));
     HIP_TRY(hipStreamWaitEvent(b->own, b->ev_in, 0));
-    if (!b->graph && left >= b->graph_steps) {
+    if (!b->graph && left >= glaunch) {
       hipGraph_t graph;
       HIP_TRY(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
-      for (int s = 0; s < b->graph_steps; ++s) batch_launch(b, s, b->own);
+      for (int s = 0; s < glaunch; ++s) batch_launch(b, s, b->own);
       HIP_TRY(hipStreamEndCapture(b->own, &graph));
       const hipError_t e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return fail(VANSE_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
-    while (left >= b->graph_steps) {
+    while (left >= glaunch) {
       HIP_TRY(hipGraphLaunch(b->graph, b->own));
-      b->launched += b->graph_steps;
-      left -= b->graph_steps;
+      b->launched += glaunch;
+      left -= glaunch;
     }
     HIP_TRY(hipEventRecord(b->ev_out, b->own));
     HIP_TRY(hipStreamWaitEvent(st, b->ev_out, 0));
@@ -1102,9 +1152,11 @@ int vanse_batch_step(vanse_batch* b, int64_t nsteps, void* stream) {
   // keep every member handle consistent with the batch
   for (size_t k = 0; k < b->lats.size(); ++k) {
     vanse_lattice* h = b->lats[k];
-    h->t += nsteps;
-    h->cur = (h->cur + (int)(nsteps & 1)) & 1;
+    h->t += launches * b->fuse;
+    h->cur = (h->cur + (int)(launches & 1)) & 1;
   }
+  for (size_t k = 0; rem && k < b->lats.size(); ++k)
+    if (int rc = vanse_step(b->lats[k], rem, stream)) return rc;
   return VANSE_OK;
 }
 

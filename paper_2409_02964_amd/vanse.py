@@ -38,6 +38,7 @@ EXPORTS = [
     "vanse_get_tiling", "vanse_set_steps_per_pass", "vanse_get_fused_tiling",
     "vanse_set_storage_exponent", "vanse_stream_copy", "vanse_time", "vanse_error_string",
     "vanse_last_error", "vanse_batch_workspace_bytes", "vanse_batch_create", "vanse_batch_destroy",
+    "vanse_batch_workspace_bytes_ex", "vanse_batch_create_ex",
     "vanse_batch_set_graph", "vanse_batch_step", "vanse_batch_tiles",
 ]
 
@@ -108,6 +109,10 @@ def lib():
                                                 C.POINTER(C.c_size_t)],
                 "vanse_batch_create": [C.POINTER(vp), i32, i32, i32, vp, C.c_size_t,
                                        C.POINTER(vp)],
+                "vanse_batch_workspace_bytes_ex": [C.POINTER(vp), i32, i32, i32, i32,
+                                                   C.POINTER(C.c_size_t)],
+                "vanse_batch_create_ex": [C.POINTER(vp), i32, i32, i32, i32, vp, C.c_size_t,
+                                          C.POINTER(vp)],
                 "vanse_batch_destroy": [vp],
                 "vanse_batch_set_graph": [vp, i32],
                 "vanse_batch_step": [vp, i64, vp],
@@ -336,28 +341,32 @@ class Lattice:
 
 
 class Batch:
-    """Independent lattices advanced by one kernel launch per time step.
+    """Independent lattices advanced by one kernel launch per time step (per
+    two with ``steps_per_pass=2``: the two-step kernel on every member).
 
     Members must share precision, boundary type and the force-field flag and
     be fully set up; they stay usable individually (read_moments, t).  With
     ``graph_steps`` > 0 step loops are captured in hipGraphs of that many
-    launches."""
+    time steps."""
 
-    def __init__(self, lattices, threads=128, rows=0, graph_steps=0, device=None):
+    def __init__(self, lattices, threads=128, rows=0, graph_steps=0, device=None,
+                 steps_per_pass=1):
         import torch
         self.lattices = list(lattices)
         n = len(self.lattices)
         self._arr = (C.c_void_p * n)(*[l.handle.value for l in self.lattices])
         nbytes = C.c_size_t()
-        check(lib().vanse_batch_workspace_bytes(self._arr, n, int(threads), int(rows),
-                                                C.byref(nbytes)))
+        check(lib().vanse_batch_workspace_bytes_ex(self._arr, n, int(threads), int(rows),
+                                                   int(steps_per_pass), C.byref(nbytes)))
         dev = device or self.lattices[0].device
         self.workspace = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
         self.handle = C.c_void_p()
-        check(lib().vanse_batch_create(self._arr, n, int(threads), int(rows),
-                                       C.c_void_p(self.workspace.data_ptr()),
-                                       self.workspace.numel(), C.byref(self.handle)))
+        check(lib().vanse_batch_create_ex(self._arr, n, int(threads), int(rows),
+                                          int(steps_per_pass),
+                                          C.c_void_p(self.workspace.data_ptr()),
+                                          self.workspace.numel(), C.byref(self.handle)))
         self.threads = int(threads)
+        self.steps_per_pass = int(steps_per_pass)
         if graph_steps:
             self.set_graph(graph_steps)
 
@@ -387,17 +396,21 @@ class Batch:
 
 
 def autotune_batch(lattices, candidates=None, steps=20, repeats=2):
-    """Pick the (threads, rows) of a batch by timing a few launches of each
+    """Pick the launch shape of a batch by timing a few steps of each
     candidate on the real batch (the members are advanced by the trials).
-    Returns (best, timings) with timings in ms per launch."""
+    Candidates are (threads, rows) or (threads, rows, steps_per_pass).
+    Returns (best, timings): best as (threads, rows, steps_per_pass) with the
+    rows the batch chose, timings in ms per time step."""
     import torch
     if candidates is None:
         candidates = [(t, r) for t in (64, 128, 256) for r in (0, 8, 16, 32, 64)]
     times = {}
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    for th, rows in candidates:
-        b = Batch(lattices, threads=th, rows=rows)
+    for cand in candidates:
+        th, rows = cand[0], cand[1]
+        spp = cand[2] if len(cand) > 2 else 1
+        b = Batch(lattices, threads=th, rows=rows, steps_per_pass=spp)
         b.step(2)
         torch.cuda.synchronize()
         best = float("inf")
@@ -407,7 +420,7 @@ def autotune_batch(lattices, candidates=None, steps=20, repeats=2):
             ev1.record()
             torch.cuda.synchronize()
             best = min(best, ev0.elapsed_time(ev1) / steps)
-        times[(th, b.tiles()["rows"])] = best
+        times[(th, b.tiles()["rows"], spp)] = best
         b.close()
     best = min(times, key=times.get)
     return best, times

@@ -95,3 +95,56 @@ def test_batch_rejects_mixed_members():
     b, _ = make(32, 32, 1, "f64")
     with pytest.raises(VanseError):
         Batch([a, b])
+
+
+# ---- two steps per launch ----------------------------------------------------------
+
+@pytest.mark.parametrize("precision,bc", [("f32s", "periodic"), ("f32", "wall"), ("f16s", "wall")])
+@pytest.mark.parametrize("threads,rows,graph,steps", [
+    (64, 0, 0, 8), (128, 5, 4, 11), (256, 0, 8, 13), (64, 40, 4, 9)])
+def test_two_step_batch_bitwise_equals_two_step_single(precision, bc, threads, rows, graph, steps):
+    """A batch with two steps per launch applies the two-step kernel of the
+    single lattice to every member: results are bitwise those of stepping
+    each member alone with two steps per launch, whatever the tiling (the
+    arithmetic of a node does not depend on its tile), including an odd last
+    step."""
+    _torch()
+    from paper_2409_02964_amd.vanse import Batch
+    ref = [make(nx, ny, k, precision, bc)[0] for k, (nx, ny) in enumerate(SIZES)]
+    for lat in ref:
+        lat.set_steps_per_pass(2)
+        lat.step(steps)
+    mem = [make(nx, ny, k, precision, bc)[0] for k, (nx, ny) in enumerate(SIZES)]
+    b = Batch(mem, threads=threads, rows=rows, graph_steps=graph, steps_per_pass=2)
+    b.step(steps)
+    for a, r in zip(mem, ref):
+        assert a.t == r.t == steps
+        assert np.array_equal(a.read_populations().cpu().numpy(),
+                              r.read_populations().cpu().numpy())
+    b.step(4)  # the table is written again after the members' own last step
+    for r in ref:
+        r.step(4)
+    for a, r in zip(mem, ref):
+        assert np.array_equal(a.read_populations().cpu().numpy(),
+                              r.read_populations().cpu().numpy())
+
+
+def test_two_step_batch_rejects_what_it_does_not_take():
+    _torch()
+    from paper_2409_02964_amd.vanse import Batch, Lattice, VanseError
+    f64 = [make(32, 32, 0, "f64")[0]]
+    with pytest.raises(VanseError):
+        Batch(f64, steps_per_pass=2)
+    n = 24
+    drag = Lattice(n, n, precision="f32", drag=True)
+    drag.set_params(0.5, RATES).set_body_force(1e-6, 0).set_void_fraction(np.full((n, n), 0.8))
+    drag.set_drag(np.full((n, n), 1e-3)).init_equilibrium(1.0)
+    with pytest.raises(VanseError):
+        Batch([drag], steps_per_pass=2)
+    ok = [make(32, 32, 0, "f32")[0]]
+    b = Batch(ok, steps_per_pass=2)
+    with pytest.raises(VanseError):
+        b.set_graph(6)  # a replay must cover an even number of two-step launches
+    b.set_graph(8)
+    with pytest.raises(VanseError):
+        Batch(ok, steps_per_pass=3)
