@@ -210,9 +210,9 @@ def served_bench(count: int, rate: float, budget_gib: float):
     per second, periodic lattices with sides log-uniform in [64, 2048] and
     tanh-edged inclusions (phi in [0.35, 1]), G = 1e-6, drag 2e-3 + 1e-2 (1 -
     phi), FP32 arithmetic with FP16 shifted storage, run to a residual of 1e-8
-    or 20000 steps, admitted by device memory within `budget_gib`.  Compared
-    with the same server restricted to one solve at a time (FIFO, one lattice
-    per launch)."""
+    or 20000 steps, admitted by device memory within `budget_gib`, two time
+    steps per launch.  Compared with the same server restricted to one solve
+    at a time (FIFO, one lattice per launch)."""
     from paper_2409_02964_amd import workloads as W
     from paper_2409_02964_amd.serve import SolveServer, summarize
     reqs = W.served_requests(count, rate, seed=5)
@@ -226,6 +226,7 @@ def served_bench(count: int, rate: float, budget_gib: float):
         done = srv.run(reqs)
         out[name] = summarize(done, time.perf_counter() - t0)
         out[name]["max_active"] = max(a for _, a, _, _ in srv.log)
+        out[name]["steps_per_launch"] = srv.steps_per_pass
     return out
 
 

@@ -56,25 +56,28 @@
 
 namespace vanse_dev {
 
-template <typename T, int NT>
+// NP: planes of the population ring -- the nine populations, phi and, with
+// the linear drag, its coefficient beta
+template <typename T, int NT, int NP>
 struct Step2Lds {
   T rho[2][NT];      // per half: delta-rho of the row of stage A (read by B)
   U4<T> u4[2][NT];   // per half: velocity data of the row of stage B (read by C)
   U2<T> u2[2][NT];
-  T pop[40][NT];     // half 0's post-collision deviations and phi (see pop_slot)
+  T pop[4 * NP][NT];  // half 0's post-collision deviations, phi, beta (see pop_slot)
 };
 
-// Half 0's staging of a pulled row (4-byte storage): the nine populations
-// and phi, each lane's values at its own position.  Two slots, each its own
-// LDS object, passed to the tile as distinct restrict pointers: the
-// compiler then orders a read of one slot after the loads into that slot
-// only, not after the loads of the row ahead in flight into the other.
-template <int NT, bool DMA>
+// Half 0's staging of a pulled row (4-byte storage): the nine populations,
+// phi and (with the drag) beta, each lane's values at its own position.  Two
+// slots, each its own LDS object, passed to the tile as distinct restrict
+// pointers: the compiler then orders a read of one slot after the loads into
+// that slot only, not after the loads of the row ahead in flight into the
+// other.
+template <int NT, bool DMA, int NP>
 struct Step2Stage {
-  float v[10][NT];
+  float v[NP][NT];
 };
-template <int NT>
-struct Step2Stage<NT, false> {
+template <int NT, int NP>
+struct Step2Stage<NT, false, NP> {
   float v[1][1];
 };
 
@@ -165,15 +168,24 @@ __device__ __forceinline__ VelDS<T> mirrored(const VelDS<T>& v) {
   return r;
 }
 
-// Ring row of population plane i (i = 9: phi of the row, for half 1's
-// moments) for the sweep-relative row index j >= 0
+// Ring row of population plane i (i = 9: phi of the row, i = 10: beta, for
+// half 1) for the sweep-relative row index j >= 0
 __device__ __forceinline__ int pop_slot(int i, int j) { return 4 * i + (j & 3); }
 
-template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
-__device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int strip, int by,
-                                  lds_t<Step2Lds<T, NT>>* __restrict__ Lp,
-                                  lds_t<Step2Stage<NT, sizeof(S) == 4>>* __restrict__ st0,
-                                  lds_t<Step2Stage<NT, sizeof(S) == 4>>* __restrict__ st1) {
+// Planes a row carries: nine populations and phi, plus beta with the drag
+template <int FEAT>
+constexpr int step2_planes() { return (FEAT & FEAT_DRAG) ? 11 : 10; }
+
+// FEAT: 0 (the plain step) or FEAT_DRAG (the linear drag, u solved in closed
+// form as in the single step)
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
+__device__ inline void step2_tile(
+    const StepGeom& g, const StepPhys<T>& ph, int strip, int by,
+    lds_t<Step2Lds<T, NT, step2_planes<FEAT>()>>* __restrict__ Lp,
+    lds_t<Step2Stage<NT, sizeof(S) == 4, step2_planes<FEAT>()>>* __restrict__ st0,
+    lds_t<Step2Stage<NT, sizeof(S) == 4, step2_planes<FEAT>()>>* __restrict__ st1) {
+  static_assert(FEAT == 0 || FEAT == FEAT_DRAG, "plain step or linear drag");
+  constexpr bool DRAG = FEAT == FEAT_DRAG;
   auto& L = *Lp;
   constexpr bool DMA = sizeof(S) == 4;
   static_assert(!DMA || sizeof(T) == 4, "staged rows hold FP32 phi");
@@ -209,6 +221,7 @@ __device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int 
   const rsrc_t srcr = make_rsrc(g.src, 9u * plane_bytes);
   const rsrc_t dstr = make_rsrc(g.dst, 9u * plane_bytes);
   const rsrc_t phir = make_rsrc(g.phi, unsigned(g.plane) * TB);
+  const rsrc_t betar = make_rsrc(g.beta, DRAG ? unsigned(g.plane) * TB : 0u);
   auto poff = [&](int i, int r) { return unsigned(i) * plane_bytes + unsigned(r) * row_bytes; };
 
   const int y0 = by * g.rows;
@@ -241,6 +254,7 @@ __device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int 
       rn = (r == ny - 1) ? 0 : r + 1;
     }
     ld(9, phir, xcT, unsigned(r) * unsigned(pitch) * TB);
+    if (DRAG) ld(10, betar, xcT, unsigned(r) * unsigned(pitch) * TB);
     ld(0, srcr, xcb, poff(0, r));
     ld(1, srcr, xmb, poff(1, r));
     ld(3, srcr, xpb, poff(3, r));
@@ -269,18 +283,20 @@ __device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int 
     else __syncthreads();
   };
   // Register loads of row yn without staging (2-byte storage): half 0 the
-  // pull, half 1 phi.  (With staging half 1 takes phi from the population
-  // ring, where half 0 leaves it, and issues no loads at all.)
+  // pull, half 1 phi and beta.  (With staging half 1 takes them from the
+  // population ring, where half 0 leaves them, and issues no loads at all.)
   auto load_row = [&](int yn, RowIn<S, T>& in) {
     if constexpr (!DMA) {
       if (half == 0) {
         pull_row(yn, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
           if (i == 9) in.phi = bload<T>(rs, v, so);
+          else if (i == 10) in.beta = bload<T>(rs, v, so);
           else in.f[i] = bload<S>(rs, v, so);
         });
       } else {
         const int r = WALLS ? min(max(yn, 0), ny - 1) : wrap_index(yn, ny);
         in.phi = bload<T>(phir, xcT, unsigned(r) * unsigned(pitch) * TB);
+        if (DRAG) in.beta = bload<T>(betar, xcT, unsigned(r) * unsigned(pitch) * TB);
       }
     }
   };
@@ -347,6 +363,7 @@ __device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int 
 #pragma unroll
           for (int i = 0; i < 9; ++i) f[i] = __builtin_bit_cast(S, st->v[i][t]);
           phi = st->v[9][t];
+          if (DRAG) rA.beta = st->v[10][t];
           // keeps these reads here, next to the wait that orders them: merged
           // with half 1's read of phi they would wait for the row ahead too
           __asm__ volatile("" ::: "memory");
@@ -354,6 +371,7 @@ __device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int 
 #pragma unroll
           for (int i = 0; i < 9; ++i) f[i] = in.f[i];
           phi = in.phi;
+          if (DRAG) rA.beta = in.beta;
         }
         T q[9];
         if (SHIFT) {
@@ -375,6 +393,7 @@ __device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int 
         T q[9];
         const int j0 = jr(yA), jm = j0 - 1, jp = j0 + 1;
         const T phi = DMA ? L.pop[pop_slot(9, j0)][t] : in.phi;
+        if (DRAG) rA.beta = DMA ? L.pop[pop_slot(10, j0)][t] : in.beta;
         q[0] = L.pop[pop_slot(0, j0)][t];
         q[1] = L.pop[pop_slot(1, j0)][tl];
         q[3] = L.pop[pop_slot(3, j0)][tr];
@@ -414,12 +433,23 @@ __device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int 
         const T phi = rB.phi;
         const T kp = (kappa - phi) * T(1.0 / 36.0);     // Eq. (13), with the 1/12
         const T sg = ph.scale_by_phi ? phi : T(1);
-        const T Fx = kp * grx + sg * ph.gx;
-        const T Fy = kp * gry + sg * ph.gy;
+        T Fx = kp * grx + sg * ph.gx;
+        T Fy = kp * gry + sg * ph.gy;
         const T m0 = phi * rho0 + rB.dm0;
-        const T inv_m0 = recip(m0);
-        const T ux = (rB.jx + T(0.5) * Fx) * inv_m0;
-        const T uy = (rB.jy + T(0.5) * Fy) * inv_m0;
+        T ux, uy;
+        if (DRAG) {
+          // F = F' - phi beta (u - u_s) with u = (j + F/2)/m0: solved for u
+          const T d = phi * rB.beta;
+          const T inv = recip(m0 + T(0.5) * d);
+          ux = (rB.jx + T(0.5) * (Fx + d * ph.usx)) * inv;
+          uy = (rB.jy + T(0.5) * (Fy + d * ph.usy)) * inv;
+          Fx -= d * (ux - ph.usx);
+          Fy -= d * (uy - ph.usy);
+        } else {
+          const T inv_m0 = recip(m0);
+          ux = (rB.jx + T(0.5) * Fx) * inv_m0;
+          uy = (rB.jy + T(0.5) * Fy) * inv_m0;
+        }
         const T rho = rho0 + rB.drho;
         U4<T> a;
         U2<T> b;
@@ -565,6 +595,7 @@ __device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int 
 #pragma unroll
           for (int i = 0; i < 9; ++i) L.pop[pop_slot(i, jo)][t] = o9[i];
           if (DMA) L.pop[pop_slot(9, jo)][t] = phi;
+          if (DMA && DRAG) L.pop[pop_slot(10, jo)][t] = rC.beta;
         } else if (SHIFT) {
 #pragma unroll
           for (int i = 0; i < 9; ++i)
@@ -622,25 +653,26 @@ __device__ inline void step2_tile(const StepGeom& g, const StepPhys<T>& ph, int 
 
 // Two time steps per launch: workgroup b takes strip b % strips, row block
 // b / strips; 2 NT lanes (two halves of NT), four waves per SIMD.
-template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(4)))
 vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
-  __shared__ Step2Lds<T, NT> lds;
-  __shared__ Step2Stage<NT, sizeof(S) == 4> stage0, stage1;
-  step2_tile<S, T, SHIFT, WALLS, NT>(g, ph, int(blockIdx.x) % g.strips, int(blockIdx.x) / g.strips,
-                                     lds_handle(&lds), lds_handle(&stage0), lds_handle(&stage1));
+  __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;
+  __shared__ Step2Stage<NT, sizeof(S) == 4, step2_planes<FEAT>()> stage0, stage1;
+  step2_tile<S, T, SHIFT, WALLS, FEAT, NT>(g, ph, int(blockIdx.x) % g.strips,
+                                           int(blockIdx.x) / g.strips, lds_handle(&lds),
+                                           lds_handle(&stage0), lds_handle(&stage1));
 }
 
 // Many lattices, two time steps per launch: workgroup b takes tile b of the
 // batch table (lattice tile_lattice[b], strip and row block as in the
 // one-lattice kernel); each member's two buffers alternate with the launch
 // parity as in the one-step batch.
-template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(4)))
 vanse_batch_step2_kernel(const BatchEntry<T>* __restrict__ entries,
                          const int* __restrict__ tile_lattice, int launch) {
-  __shared__ Step2Lds<T, NT> lds;
-  __shared__ Step2Stage<NT, sizeof(S) == 4> stage0, stage1;
+  __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;
+  __shared__ Step2Stage<NT, sizeof(S) == 4, step2_planes<FEAT>()> stage0, stage1;
   const int k = tile_lattice[blockIdx.x];
   const BatchEntry<T>& e = entries[k];
   StepGeom g = e.g;
@@ -653,8 +685,9 @@ vanse_batch_step2_kernel(const BatchEntry<T>* __restrict__ entries,
   // a private copy, as the one-lattice kernel's argument: read through the
   // table the parameters could alias the stores as far as the compiler knows
   const StepPhys<T> ph = e.ph;
-  step2_tile<S, T, SHIFT, WALLS, NT>(g, ph, local % g.strips, local / g.strips, lds_handle(&lds),
-                                     lds_handle(&stage0), lds_handle(&stage1));
+  step2_tile<S, T, SHIFT, WALLS, FEAT, NT>(g, ph, local % g.strips, local / g.strips,
+                                           lds_handle(&lds), lds_handle(&stage0),
+                                           lds_handle(&stage1));
 }
 
 }  // namespace vanse_dev

@@ -5,8 +5,8 @@
 // Instances: workgroup widths 64, 128 and 256 for every feature variant the
 // host selects (plain, force field, drag, both, FEAT_ALL), 512 for the plain
 // step; the batched kernel for the first four; where VANSE_FUSED2 is set the
-// two-step kernel of the plain step (256-lane halves) and its batched form
-// (halves of 64, 128 or 256 lanes).
+// two-step kernel of the plain step and of the linear drag (256-lane halves)
+// and its batched form (halves of 64, 128 or 256 lanes).
 #include "step_launch.hpp"
 
 namespace vanse_dev {
@@ -16,9 +16,10 @@ void launch_step_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStr
   hipLaunchKernelGGL((vanse_step_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(blocks), dim3(NT), 0, st, g, ph);
 }
 
-template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 void launch_step2_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st) {
-  hipLaunchKernelGGL((vanse_step2_kernel<S, T, SHIFT, WALLS, NT>), dim3(blocks), dim3(2 * NT), 0, st, g, ph);
+  hipLaunchKernelGGL((vanse_step2_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(blocks), dim3(2 * NT), 0,
+                     st, g, ph);
 }
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
@@ -28,11 +29,11 @@ void launch_batch_nt(const BatchEntry<T>* entries, const int* tile_lattice, int 
                      st, entries, tile_lattice, launch);
 }
 
-template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 void launch_batch2_nt(const BatchEntry<T>* entries, const int* tile_lattice, int launch, int tiles,
                       hipStream_t st) {
-  hipLaunchKernelGGL((vanse_batch_step2_kernel<S, T, SHIFT, WALLS, NT>), dim3(tiles), dim3(2 * NT), 0,
-                     st, entries, tile_lattice, launch);
+  hipLaunchKernelGGL((vanse_batch_step2_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(tiles), dim3(2 * NT),
+                     0, st, entries, tile_lattice, launch);
 }
 
 #define VANSE_STEP_ONE(W, F, NT) \
@@ -60,15 +61,17 @@ VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE | FEAT_DRAG)
 // two steps per pass: FP32 arithmetic only (the FP64 rings would not fit
 // two workgroups in a CU's LDS)
 #if VANSE_FUSED2
-template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, false, 256>(
-    const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
-template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, true, 256>(
-    const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
-#define VANSE_BATCH2_ONE(W, NT) \
-  template void launch_batch2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, NT>( \
+#define VANSE_STEP2_ONE(W, F) \
+  template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, 256>( \
+      const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
+#define VANSE_BATCH2_ONE(W, F, NT) \
+  template void launch_batch2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, NT>( \
       const BatchEntry<VANSE_T>*, const int*, int, int, hipStream_t);
-VANSE_BATCH2_ONE(false, 64) VANSE_BATCH2_ONE(false, 128) VANSE_BATCH2_ONE(false, 256)
-VANSE_BATCH2_ONE(true, 64) VANSE_BATCH2_ONE(true, 128) VANSE_BATCH2_ONE(true, 256)
+VANSE_STEP2_ONE(false, 0) VANSE_STEP2_ONE(true, 0)
+VANSE_STEP2_ONE(false, FEAT_DRAG) VANSE_STEP2_ONE(true, FEAT_DRAG)
+VANSE_WALLS(VANSE_BATCH2_ONE, 0)
+VANSE_WALLS(VANSE_BATCH2_ONE, FEAT_DRAG)
+#undef VANSE_STEP2_ONE
 #undef VANSE_BATCH2_ONE
 #endif
 

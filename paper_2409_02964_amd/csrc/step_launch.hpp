@@ -17,8 +17,9 @@ namespace vanse_dev {
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 void launch_step_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st);
 
-// One lattice, two time steps per launch: `blocks` workgroups of 2 NT lanes.
-template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
+// One lattice, two time steps per launch: `blocks` workgroups of 2 NT lanes
+// (FEAT 0 or FEAT_DRAG).
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 void launch_step2_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st);
 
 // Many lattices: one workgroup per tile of the batch table.
@@ -28,7 +29,7 @@ void launch_batch_nt(const BatchEntry<T>* entries, const int* tile_lattice, int 
 
 // Many lattices, two time steps per launch: one workgroup of 2 NT lanes per
 // tile of the batch table.
-template <typename S, typename T, bool SHIFT, bool WALLS, int NT>
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 void launch_batch2_nt(const BatchEntry<T>* entries, const int* tile_lattice, int launch, int tiles,
                       hipStream_t st);
 

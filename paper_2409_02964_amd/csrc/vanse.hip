@@ -252,14 +252,18 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
   }
 }
 
-// Two-step launches of the plain step: FP32 arithmetic, no optional inputs or
-// scheme variants.  Rows per workgroup default to one full round of resident
+// Two-step launches of the plain step and of the linear drag: FP32
+// arithmetic, no other optional input or scheme variant.  Rows per workgroup default to one full round of resident
 // workgroups (two 512-lane workgroups per CU).
 constexpr int kFusedNT = 256;
 constexpr int kFusedOutW = kFusedNT - 10;
 
+// Variants the two-step kernel is built for: the plain step and the linear
+// drag (no force field, mask, moving phi or scheme variant)
+bool fused_feat(const vanse_lattice* h) { return feat_of(h) == 0 || feat_of(h) == FEAT_DRAG; }
+
 bool fused_ok(const vanse_lattice* h) {
-  return h->fuse == 2 && h->d.precision != VANSE_F64 && feat_of(h) == 0;
+  return h->fuse == 2 && h->d.precision != VANSE_F64 && fused_feat(h);
 }
 
 int fused_rows(const vanse_lattice* h) {
@@ -288,13 +292,20 @@ int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
     g.out_w = kFusedOutW;
     g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
     g.rows = fused_rows(h);
+    const bool drag = feat_of(h) == FEAT_DRAG;
+    g.beta = drag ? h->ws + h->L.beta : nullptr;
     const int blocks = g.strips * ((h->d.ny + g.rows - 1) / g.rows);
     const bool walls = h->d.bc_y == VANSE_WALL;
     for (int64_t s = 0; s < pairs; ++s) {
       g.src = h->ws + h->L.pop[h->cur];
       g.dst = h->ws + h->L.pop[h->cur ^ 1];
-      if (walls) launch_step2_nt<S, T, SHIFT, true, kFusedNT>(g, ph, blocks, st);
-      else launch_step2_nt<S, T, SHIFT, false, kFusedNT>(g, ph, blocks, st);
+      if (drag) {
+        if (walls) launch_step2_nt<S, T, SHIFT, true, FEAT_DRAG, kFusedNT>(g, ph, blocks, st);
+        else launch_step2_nt<S, T, SHIFT, false, FEAT_DRAG, kFusedNT>(g, ph, blocks, st);
+      } else {
+        if (walls) launch_step2_nt<S, T, SHIFT, true, 0, kFusedNT>(g, ph, blocks, st);
+        else launch_step2_nt<S, T, SHIFT, false, 0, kFusedNT>(g, ph, blocks, st);
+      }
       h->cur ^= 1;
       h->t += 2;
       if (s == 0) HIP_TRY(hipGetLastError());
@@ -881,9 +892,9 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
     if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field ||
         d.has_drag != d0.has_drag)
       return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary, force field or drag", k);
-    if (fuse == 2 && (d.precision == VANSE_F64 || feat_of(lats[k]) != 0))
+    if (fuse == 2 && (d.precision == VANSE_F64 || !fused_feat(lats[k])))
       return fail(VANSE_ERR_UNSUPPORTED,
-                  "lattice %d: two steps per launch take FP32 arithmetic without force field or drag", k);
+                  "lattice %d: two steps per launch take FP32 arithmetic without force field", k);
     strip_rows += (long long)((d.nx + out_w - 1) / out_w) * d.ny;
   }
   int r = rows;
@@ -974,12 +985,12 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
 void batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
   const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
   const int* TL = reinterpret_cast<const int*>(b->ws + b->tiles_off);
-  if constexpr (sizeof(T) == 4 && FEAT == 0) {
+  if constexpr (sizeof(T) == 4 && (FEAT == 0 || FEAT == FEAT_DRAG)) {
     if (b->fuse == 2) {
       switch (b->threads) {
-        case 64: launch_batch2_nt<S, T, SHIFT, WALLS, 64>(E, TL, launch, b->total_tiles, st); break;
-        case 128: launch_batch2_nt<S, T, SHIFT, WALLS, 128>(E, TL, launch, b->total_tiles, st); break;
-        default: launch_batch2_nt<S, T, SHIFT, WALLS, 256>(E, TL, launch, b->total_tiles, st);
+        case 64: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st); break;
+        case 128: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st); break;
+        default: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 256>(E, TL, launch, b->total_tiles, st);
       }
       return;
     }

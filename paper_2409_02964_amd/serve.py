@@ -7,15 +7,17 @@ time.  The server:
     finished ones free memory);
   * keeps every admitted request's populations resident on the device;
   * advances all admitted requests together, one batched kernel launch per
-    time step, in chunks of `chunk` steps;
+    `steps_per_pass` time steps (two: the two-step kernel, the default where
+    the storage precision allows it), in chunks of `chunk` steps;
   * ends a request when its steady-state residual
         R = ||u(t) - u(t-1)||_2 / ||u(t)||_2
     (two consecutive steps, checked at the end of each chunk) falls below
     `tol`, or at `max_steps`, and frees its memory for waiting requests.
 
 Every request is checked at its own step counts (multiples of `chunk`), and
-the batched step is bitwise identical to the one-lattice step, so a request's
-result does not depend on which other requests shared the GPU with it.
+the batched step is bitwise identical to the one-lattice step (one or two
+steps per launch), so a request's result does not depend on which other
+requests shared the GPU with it.
 """
 from __future__ import annotations
 
@@ -51,7 +53,7 @@ class Solve:
 class SolveServer:
     def __init__(self, memory_budget, precision="f16s", chunk=500, max_steps=20000, tol=1e-8,
                  kappa=0.5, rates=None, threads=128, rows=0, keep_results=False,
-                 max_active=None):
+                 max_active=None, steps_per_pass=None):
         if max_steps % chunk:
             raise ValueError("max_steps must be a multiple of chunk")
         self.budget = int(memory_budget)
@@ -63,6 +65,9 @@ class SolveServer:
         self.rates = rates or dict(s_c=1.2, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=0.8)
         self.threads = threads
         self.rows = rows
+        # two steps per launch unless FP64 (which the two-step kernel lacks)
+        self.steps_per_pass = (1 if precision == "f64" else 2) if steps_per_pass is None \
+            else int(steps_per_pass)
         self.keep_results = keep_results
         self.max_active = max_active  # None: memory decides; 1: one solve at a time (FIFO)
         self.log = []
@@ -119,7 +124,8 @@ class SolveServer:
             if changed or batch is None:
                 if batch is not None:
                     batch.close()
-                batch = Batch([s.lattice for s in active], threads=self.threads, rows=self.rows)
+                batch = Batch([s.lattice for s in active], threads=self.threads, rows=self.rows,
+                              steps_per_pass=self.steps_per_pass)
             # one chunk: chunk-1 steps, keep u, one step, residual of that step
             batch.step(self.chunk - 1)
             for s in active:

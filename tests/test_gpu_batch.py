@@ -21,13 +21,14 @@ def _torch():
     return torch
 
 
-def make(nx, ny, k, precision="f32", bc_y="periodic"):
+def make(nx, ny, k, precision="f32", bc_y="periodic", drag=False):
     from paper_2409_02964_amd.vanse import Lattice
     phi = 0.6 + 0.3 * np.sin(2 * np.pi * (k % 3 + 1) * np.arange(nx)[None, :] / nx) * \
         np.sin(2 * np.pi * (k % 2 + 1) * np.arange(ny)[:, None] / ny)
-    lat = Lattice(nx, ny, precision=precision, bc_y=bc_y)
+    lat = Lattice(nx, ny, precision=precision, bc_y=bc_y, drag=drag)
     lat.set_params(0.5, RATES).set_body_force(1e-6 * (k + 1), 2e-7 * k).set_void_fraction(phi)
-    lat.init_equilibrium(1.0, 1e-3 * k, 0.0)
+    if not drag:  # a drag lattice is initialised once its drag is set
+        lat.init_equilibrium(1.0, 1e-3 * k, 0.0)
     return lat, phi
 
 
@@ -129,6 +130,31 @@ def test_two_step_batch_bitwise_equals_two_step_single(precision, bc, threads, r
                               r.read_populations().cpu().numpy())
 
 
+@pytest.mark.parametrize("precision,bc,threads", [("f16s", "periodic", 128), ("f32s", "wall", 64)])
+def test_two_step_batch_with_drag(precision, bc, threads):
+    """Members with the linear drag (the served workload's variant): bitwise
+    the results of stepping each alone with two steps per launch."""
+    _torch()
+    from paper_2409_02964_amd.vanse import Batch
+
+    def member(k, nx, ny):
+        lat, phi = make(nx, ny, k, precision, bc, drag=True)
+        lat.set_drag(1e-3 + 2e-2 * (1 - phi), (1e-4 * k, 0.0))
+        lat.init_equilibrium(1.0, 1e-3 * k, 0.0)
+        return lat
+
+    ref = [member(k, nx, ny) for k, (nx, ny) in enumerate(SIZES)]
+    for lat in ref:
+        lat.set_steps_per_pass(2)
+        lat.step(10)
+    mem = [member(k, nx, ny) for k, (nx, ny) in enumerate(SIZES)]
+    Batch(mem, threads=threads, graph_steps=4, steps_per_pass=2).step(10)
+    for a, r in zip(mem, ref):
+        assert r.fused_tiling()["active"]
+        assert np.array_equal(a.read_populations().cpu().numpy(),
+                              r.read_populations().cpu().numpy())
+
+
 def test_two_step_batch_rejects_what_it_does_not_take():
     _torch()
     from paper_2409_02964_amd.vanse import Batch, Lattice, VanseError
@@ -136,11 +162,11 @@ def test_two_step_batch_rejects_what_it_does_not_take():
     with pytest.raises(VanseError):
         Batch(f64, steps_per_pass=2)
     n = 24
-    drag = Lattice(n, n, precision="f32", drag=True)
-    drag.set_params(0.5, RATES).set_body_force(1e-6, 0).set_void_fraction(np.full((n, n), 0.8))
-    drag.set_drag(np.full((n, n), 1e-3)).init_equilibrium(1.0)
+    ff = Lattice(n, n, precision="f32", force_field=True)
+    ff.set_params(0.5, RATES).set_body_force(1e-6, 0).set_void_fraction(np.full((n, n), 0.8))
+    ff.set_force_field(np.full((n, n), 1e-7), np.zeros((n, n))).init_equilibrium(1.0)
     with pytest.raises(VanseError):
-        Batch([drag], steps_per_pass=2)
+        Batch([ff], steps_per_pass=2)
     ok = [make(32, 32, 0, "f32")[0]]
     b = Batch(ok, steps_per_pass=2)
     with pytest.raises(VanseError):

@@ -25,15 +25,16 @@ def small_requests():
     return out
 
 
-@pytest.mark.parametrize("precision", ["f16s", "f32"])
-def test_served_results_equal_solo_runs(precision):
+@pytest.mark.parametrize("precision,steps_per_pass", [("f16s", None), ("f32", None), ("f16s", 1)])
+def test_served_results_equal_solo_runs(precision, steps_per_pass):
     _torch()
     from paper_2409_02964_amd.serve import SolveServer
     from paper_2409_02964_amd.vanse import workspace_bytes
     reqs = small_requests()
     need = sorted(workspace_bytes(r["L"], r["L"], precision, drag=True) for r in reqs)
     budget = need[-1] + need[-2] + need[0]  # about three requests at a time
-    kw = dict(precision=precision, chunk=40, max_steps=400, tol=1e-7, keep_results=True)
+    kw = dict(precision=precision, chunk=40, max_steps=400, tol=1e-7, keep_results=True,
+              steps_per_pass=steps_per_pass)
     mix = SolveServer(budget, **kw)
     done = {s.rid: s for s in mix.run(reqs)}
     assert sorted(done) == list(range(len(reqs)))
