@@ -210,8 +210,8 @@ def served_bench(count: int, rate: float, budget_gib: float):
     per second, periodic lattices with sides log-uniform in [64, 2048] and
     tanh-edged inclusions (phi in [0.35, 1]), G = 1e-6, drag 2e-3 + 1e-2 (1 -
     phi), FP32 arithmetic with FP16 shifted storage, run to a residual of 1e-8
-    or 20000 steps, admitted by device memory within `budget_gib`, two time
-    steps per launch.  Compared with the same server restricted to one solve
+    or 20000 steps, admitted by device memory within `budget_gib`, one time
+    step per launch.  Compared with the same server restricted to one solve
     at a time (FIFO, one lattice per launch)."""
     from paper_2409_02964_amd import workloads as W
     from paper_2409_02964_amd.serve import SolveServer, summarize

@@ -901,12 +901,13 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
   if (r == 0) {
     // about two rounds of resident workgroups over the whole batch for one
     // step per launch, four for two (measured on 256 lattices of side 32 to
-    // 512: shorter tiles balance the uneven lattices better than they lose
-    // to the 11 extra rows each two-step tile sweeps)
+    // 512: shorter tiles balance the uneven lattices better), but at least
+    // 32 rows for two (each two-step tile sweeps 11 rows beyond its own)
     const int rounds = fuse == 2 ? 4 : 2;
     const long long slots = (long long)device_cus() * batch_per_cu(d0.precision, threads, fuse);
     r = (int)((strip_rows + rounds * slots - 1) / (rounds * slots));
-    if (r < (fuse == 2 ? 16 : 8)) r = fuse == 2 ? 16 : 8;
+    const int rmin = fuse == 2 ? 32 : 8;
+    if (r < rmin) r = rmin;
   }
   rows_out->assign(n, r);
   first_out->assign(n, 0);

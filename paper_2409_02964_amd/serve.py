@@ -7,8 +7,8 @@ time.  The server:
     finished ones free memory);
   * keeps every admitted request's populations resident on the device;
   * advances all admitted requests together, one batched kernel launch per
-    `steps_per_pass` time steps (two: the two-step kernel, the default where
-    the storage precision allows it), in chunks of `chunk` steps;
+    time step (or per two with steps_per_pass=2), in chunks of `chunk`
+    steps;
   * ends a request when its steady-state residual
         R = ||u(t) - u(t-1)||_2 / ||u(t)||_2
     (two consecutive steps, checked at the end of each chunk) falls below
@@ -53,7 +53,7 @@ class Solve:
 class SolveServer:
     def __init__(self, memory_budget, precision="f16s", chunk=500, max_steps=20000, tol=1e-8,
                  kappa=0.5, rates=None, threads=128, rows=0, keep_results=False,
-                 max_active=None, steps_per_pass=None):
+                 max_active=None, steps_per_pass=1):
         if max_steps % chunk:
             raise ValueError("max_steps must be a multiple of chunk")
         self.budget = int(memory_budget)
@@ -65,9 +65,11 @@ class SolveServer:
         self.rates = rates or dict(s_c=1.2, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=0.8)
         self.threads = threads
         self.rows = rows
-        # two steps per launch unless FP64 (which the two-step kernel lacks)
-        self.steps_per_pass = (1 if precision == "f64" else 2) if steps_per_pass is None \
-            else int(steps_per_pass)
+        # One step per launch by default: a few resident requests do not fill
+        # the GPU, and a two-step tile then waits on its own memory latency at
+        # every row (measured: 2048^2 and smaller FP16 lattices with drag are
+        # slower with two steps per launch in a batch of one).
+        self.steps_per_pass = int(steps_per_pass)
         self.keep_results = keep_results
         self.max_active = max_active  # None: memory decides; 1: one solve at a time (FIFO)
         self.log = []

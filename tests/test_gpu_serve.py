@@ -25,7 +25,7 @@ def small_requests():
     return out
 
 
-@pytest.mark.parametrize("precision,steps_per_pass", [("f16s", None), ("f32", None), ("f16s", 1)])
+@pytest.mark.parametrize("precision,steps_per_pass", [("f16s", 1), ("f32", 1), ("f16s", 2)])
 def test_served_results_equal_solo_runs(precision, steps_per_pass):
     _torch()
     from paper_2409_02964_amd.serve import SolveServer
