@@ -352,8 +352,8 @@ __device__ inline void step2_tile(
       rA.drho = rA.dm0 * recip(phi);
     };
     // half 0 (4-byte storage): the staged row yA has landed once at most one
-    // batch (row yA + 1) is still in flight
-    if (DMA && half == 0) wait_vm<10>();
+    // batch (row yA + 1: one load per plane) is still in flight
+    if (DMA && half == 0) wait_vm<step2_planes<FEAT>()>();
     if (rowA) {
       if (half == 0) {
         S f[9];
