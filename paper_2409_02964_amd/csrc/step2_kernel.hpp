@@ -651,20 +651,22 @@ __device__ inline void step2_tile(
   if (DMA) wait_vm<0>();
 }
 
-// Two time steps per launch: workgroup b takes strip b % strips, row block
-// b / strips; 2 NT lanes (two halves of NT), four waves per SIMD.
+// Two time steps per launch: workgroup b takes tile xcd_tile(b) (strip
+// tile % strips, row block tile / strips); 2 NT lanes (two halves of NT),
+// four waves per SIMD.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(4)))
 vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
   __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;
   __shared__ Step2Stage<NT, sizeof(S) == 4, step2_planes<FEAT>()> stage0, stage1;
-  step2_tile<S, T, SHIFT, WALLS, FEAT, NT>(g, ph, int(blockIdx.x) % g.strips,
-                                           int(blockIdx.x) / g.strips, lds_handle(&lds),
-                                           lds_handle(&stage0), lds_handle(&stage1));
+  const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
+  step2_tile<S, T, SHIFT, WALLS, FEAT, NT>(g, ph, tile % g.strips, tile / g.strips,
+                                           lds_handle(&lds), lds_handle(&stage0),
+                                           lds_handle(&stage1));
 }
 
-// Many lattices, two time steps per launch: workgroup b takes tile b of the
-// batch table (lattice tile_lattice[b], strip and row block as in the
+// Many lattices, two time steps per launch: workgroup b takes tile
+// xcd_tile(b) of the batch table (lattice tile_lattice[b], strip and row block as in the
 // one-lattice kernel); each member's two buffers alternate with the launch
 // parity as in the one-step batch.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
@@ -673,7 +675,8 @@ vanse_batch_step2_kernel(const BatchEntry<T>* __restrict__ entries,
                          const int* __restrict__ tile_lattice, int launch) {
   __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;
   __shared__ Step2Stage<NT, sizeof(S) == 4, step2_planes<FEAT>()> stage0, stage1;
-  const int k = tile_lattice[blockIdx.x];
+  const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
+  const int k = tile_lattice[tile];
   const BatchEntry<T>& e = entries[k];
   StepGeom g = e.g;
   const int par = (e.cur0 + launch) & 1;
@@ -681,7 +684,7 @@ vanse_batch_step2_kernel(const BatchEntry<T>* __restrict__ entries,
   void* const b1 = e.g.dst;
   g.src = par ? b1 : b0;
   g.dst = par ? b0 : b1;
-  const int local = int(blockIdx.x) - e.first_tile;
+  const int local = tile - e.first_tile;
   // a private copy, as the one-lattice kernel's argument: read through the
   // table the parameters could alias the stores as far as the compiler knows
   const StepPhys<T> ph = e.ph;

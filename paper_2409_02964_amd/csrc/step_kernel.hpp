@@ -89,6 +89,15 @@ __device__ __forceinline__ int wrap_index(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Tile of workgroup b of nb.  Workgroups are dealt to the 8 XCDs (each with
+// its own L2) in turn; this order gives each XCD a contiguous run of tiles,
+// so that strips side by side, which read each other's halo columns at the
+// same time, share an L2.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + min(x, r) + i;
+}
+
 // LDS ring slot of a (possibly negative) row index: four rows per ring
 __device__ __forceinline__ int slot4(int y) { return y & 3; }
 
@@ -647,8 +656,8 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
   }
 }
 
-// One lattice per launch: workgroup b takes strip b % strips, row block
-// b / strips.  WPE: minimum waves per SIMD the register allocation allows
+// One lattice per launch: workgroup b takes tile xcd_tile(b) (strip
+// tile % strips, row block tile / strips).  WPE: minimum waves per SIMD the register allocation allows
 // (three for the FP32 FEAT_ALL kernel, whose extra state would spill at four).
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT, int PD = 1,
           int WPE = (sizeof(T) == 4 ? (FEAT == FEAT_ALL ? 3 : 4) : 2)>
@@ -656,13 +665,14 @@ __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(WPE)))
 vanse_step_kernel(StepGeom g, StepPhys<T> ph) {
   __shared__ StepLds<T, NT> lds;
-  step_tile<S, T, SHIFT, WALLS, FEAT, NT, PD>(g, ph, int(blockIdx.x) % g.strips,
-                                                 int(blockIdx.x) / g.strips, lds);
+  const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
+  step_tile<S, T, SHIFT, WALLS, FEAT, NT, PD>(g, ph, tile % g.strips, tile / g.strips, lds);
 }
 
 // Many independent lattices per launch.  Lattice k owns tiles
-// [first_tile_k, first_tile_k + strips_k * row_blocks_k); its two population
-// buffers alternate with parity (cur0_k + launch) & 1.
+// [first_tile_k, first_tile_k + strips_k * row_blocks_k); workgroup b takes
+// tile xcd_tile(b).  The two population buffers of a lattice alternate with
+// parity (cur0_k + launch) & 1.
 template <typename T>
 struct BatchEntry {
   StepGeom g;          // src/dst hold buffer 0 and buffer 1
@@ -678,7 +688,8 @@ __attribute__((amdgpu_waves_per_eu(WPE)))
 vanse_batch_step_kernel(const BatchEntry<T>* __restrict__ entries,
                         const int* __restrict__ tile_lattice, int launch) {
   __shared__ StepLds<T, NT> lds;
-  const int k = tile_lattice[blockIdx.x];
+  const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
+  const int k = tile_lattice[tile];
   const BatchEntry<T>& e = entries[k];
   StepGeom g = e.g;
   const int par = (e.cur0 + launch) & 1;
@@ -686,7 +697,7 @@ vanse_batch_step_kernel(const BatchEntry<T>* __restrict__ entries,
   void* const b1 = e.g.dst;
   g.src = par ? b1 : b0;
   g.dst = par ? b0 : b1;
-  const int local = int(blockIdx.x) - e.first_tile;
+  const int local = tile - e.first_tile;
   step_tile<S, T, SHIFT, WALLS, FEAT, NT, 1>(g, e.ph, local % g.strips, local / g.strips, lds);
 }
 
