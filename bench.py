@@ -109,7 +109,8 @@ def cpu_baseline(steps: int, single_steps: int = 3):
 
 def small_bench(steps: int = 1000, graph_steps: int = 100):
     """The 64 x 64 periodic-wave workload (phi = 0.75 + 0.2 sin cos, G = 1e-6,
-    FP64, the parity case): launch-bound, so timed with one launch per step
+    FP64, the parity case): far too small to fill the GPU, so bound by the
+    latency of a launch and of the row sweep; timed with one launch per step
     and with the step loop captured in hipGraphs (a one-lattice batch)."""
     import torch
     from paper_2409_02964_amd import workloads as W
