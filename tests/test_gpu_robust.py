@@ -1,0 +1,155 @@
+"""Race and coverage checks of the step kernels (GPU).
+
+* Every node written: the buffer a launch writes is filled with NaN first;
+  after the launch no population may be NaN, so no node of the lattice was
+  skipped by the tiling (ragged tails, wall rows, tiny lattices, the second
+  step of a two-step launch, members of a batch).
+* Determinism: the two-step kernel overlaps its LDS staging with compute
+  under hand-placed waits; a missing wait would show as results that differ
+  from run to run, so two runs must agree bitwise.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_2409_02964_amd import workloads as W  # noqa: E402
+
+RATES = dict(s_c=1.2, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=0.8)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def lattice(nx, ny, precision, bc, drag=False, seed=3):
+    from paper_2409_02964_amd.vanse import Lattice
+    phi = W.channel_phi(nx, ny, seed=seed) if ny > 2 else np.full((ny, nx), 0.7)
+    lat = Lattice(nx, ny, precision=precision, bc_y=bc, drag=drag)
+    lat.set_params(0.5, RATES).set_body_force(2e-5, -1e-5).set_void_fraction(phi)
+    if drag:
+        lat.set_drag(1e-3 + 2e-2 * (1 - phi), (1e-4, 0.0))
+    return lat
+
+
+def start_state(lat, seed):
+    """Rest-state weights perturbed by 2% noise, as FP64 populations."""
+    rng = np.random.default_rng(seed)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    return w[:, None, None] * (1.0 + 0.02 * rng.standard_normal((9, lat.ny, lat.nx)))
+
+
+def nan_destination(lat, f0):
+    """Leave NaN in the buffer the next launch writes, then make f0 current.
+
+    A NaN state stepped once by the one-step kernel at its default tiling
+    lands, NaN at every node, in the second buffer (that kernel writes every
+    node: the FP64 one-step parity tests compare every population with the
+    oracle); setting f0 again makes the first buffer current, so the next
+    launch reads f0 and writes over the NaN."""
+    lat.set_populations(np.full((9, lat.ny, lat.nx), np.nan)).step(1)
+    assert np.isnan(lat.read_populations().cpu().numpy()).all()
+    lat.set_populations(f0)
+
+
+SHAPES = [
+    (300, 70, "periodic"),
+    (253, 130, "wall"),
+    (97, 2, "wall"),
+    (1000, 37, "wall"),
+    (247, 33, "periodic"),
+    (246, 20, "wall"),
+    (3, 5, "periodic"),
+    (2, 2, "periodic"),
+]
+
+
+@pytest.mark.parametrize("nx,ny,bc", SHAPES)
+@pytest.mark.parametrize("precision", ["f64", "f32s", "f16s"])
+@pytest.mark.parametrize("tiling", [(64, 3), (256, 1), (512, 64)])
+def test_one_step_writes_every_node(nx, ny, bc, precision, tiling):
+    _torch()
+    lat = lattice(nx, ny, precision, bc)
+    f0 = start_state(lat, nx + ny)
+    nan_destination(lat, f0)
+    lat.set_tiling(*tiling).step(1)
+    f = lat.read_populations().cpu().numpy()
+    _say(f"one step {precision} {nx}x{ny} {bc} tiling {tiling}: {np.isnan(f).sum()} NaN")
+    assert np.isfinite(f).all()
+
+
+@pytest.mark.parametrize("nx,ny,bc", SHAPES)
+@pytest.mark.parametrize("precision", ["f32", "f32s", "f16s"])
+@pytest.mark.parametrize("rows", [0, 3])
+def test_two_step_writes_every_node(nx, ny, bc, precision, rows):
+    _torch()
+    lat = lattice(nx, ny, precision, bc)
+    f0 = start_state(lat, nx + 2 * ny)
+    nan_destination(lat, f0)
+    lat.set_steps_per_pass(2, rows)
+    if not lat.fused_tiling()["active"]:
+        pytest.skip("two-step kernel not taken for this lattice")
+    lat.step(2)
+    f = lat.read_populations().cpu().numpy()
+    _say(f"two steps {precision} {nx}x{ny} {bc} rows {rows}: {np.isnan(f).sum()} NaN")
+    assert np.isfinite(f).all()
+
+
+@pytest.mark.parametrize("spp,precision", [(1, "f64"), (1, "f16s"), (2, "f32s"), (2, "f16s")])
+def test_batch_writes_every_node(spp, precision):
+    _torch()
+    from paper_2409_02964_amd.vanse import Batch
+    sizes = [(64, 64, "wall"), (37, 53, "wall"), (130, 20, "wall"), (17, 5, "wall"), (300, 31, "wall")]
+    lats = []
+    for k, (nx, ny, bc) in enumerate(sizes):
+        lat = lattice(nx, ny, precision, bc, seed=k)
+        nan_destination(lat, start_state(lat, k))
+        lats.append(lat)
+    Batch(lats, threads=128, rows=5, steps_per_pass=spp).step(spp)
+    for lat in lats:
+        f = lat.read_populations().cpu().numpy()
+        assert lat.t == spp
+        assert np.isfinite(f).all(), f"{lat.nx}x{lat.ny}: {np.isnan(f).sum()} NaN"
+
+
+@pytest.mark.parametrize("precision,drag", [("f32s", False), ("f16s", False), ("f32s", True)])
+def test_two_step_determinism(precision, drag):
+    """Two runs of 40 steps on a lattice of many tiles agree bitwise."""
+    _torch()
+    nx, ny = 1500, 700
+    res = []
+    for _ in range(2):
+        lat = lattice(nx, ny, precision, "wall", drag=drag, seed=11)
+        lat.set_steps_per_pass(2).init_equilibrium(1.0)
+        assert lat.fused_tiling()["active"]
+        lat.step(40)
+        res.append(lat.read_populations().cpu().numpy())
+    assert np.array_equal(res[0], res[1])
+
+
+def test_two_step_batch_determinism():
+    _torch()
+    from paper_2409_02964_amd.vanse import Batch, Lattice
+    specs = W.batch_lattices(24, seed=2)
+    res = []
+    for _ in range(2):
+        lats = []
+        for sp in specs:
+            lat = Lattice(sp["L"], sp["L"], precision="f16s", bc_y="wall")
+            lat.set_params(0.5, RATES).set_body_force(sp["g"], 0.0).set_void_fraction(sp["phi"])
+            lat.init_equilibrium(1.0)
+            lats.append(lat)
+        Batch(lats, threads=128, graph_steps=8, steps_per_pass=2).step(16)
+        res.append([l.read_populations().cpu().numpy() for l in lats])
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
