@@ -26,10 +26,11 @@
 // fills from the wall row once per sweep, so the pull itself never tests
 // for walls.
 //
-// Half 0's pulls from HBM: with 4-byte storage each row is loaded straight
-// into LDS (buffer loads with the LDS destination) two rows ahead, into a
-// two-slot staging area, so the loads in flight hold no registers and have
-// two iterations to land; 2-byte storage loads into registers one row ahead.
+// Half 0's pulls from HBM: each row is loaded straight into LDS (buffer
+// loads with the LDS destination) two rows ahead, into a two-slot staging
+// area, so the loads in flight hold no registers and have two iterations to
+// land.  Half 1 issues no loads: phi (and beta) of a row reach it through
+// the population ring with the row.
 //
 // The Eq. (10) derivatives use the stencil's separable form.  With
 //   D(y) = g(x+1, y) - g(x-1, y),   S(y) = g(x+1, y) + g(x-1, y) + 4 g(x, y)
@@ -66,19 +67,16 @@ struct Step2Lds {
   T pop[4 * NP][NT];  // half 0's post-collision deviations, phi, beta (see pop_slot)
 };
 
-// Half 0's staging of a pulled row (4-byte storage): the nine populations,
-// phi and (with the drag) beta, each lane's values at its own position.  Two
-// slots, each its own LDS object, passed to the tile as distinct restrict
-// pointers: the compiler then orders a read of one slot after the loads into
-// that slot only, not after the loads of the row ahead in flight into the
-// other.
-template <int NT, bool DMA, int NP>
+// Half 0's staging of a pulled row: the nine populations, phi and (with the
+// drag) beta, one 4-byte word per lane and plane at the lane's own position
+// (a 2-byte load with LDS destination fills its lane's word, zero-extended).
+// Two slots, each its own LDS object, passed to the tile as distinct
+// restrict pointers: the compiler then orders a read of one slot after the
+// loads into that slot only, not after the loads of the row ahead in flight
+// into the other.
+template <int NT, int NP>
 struct Step2Stage {
   float v[NP][NT];
-};
-template <int NT, int NP>
-struct Step2Stage<NT, false, NP> {
-  float v[1][1];
 };
 
 // Wait until at most n vector-memory operations of this wave are
@@ -182,13 +180,13 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __device__ inline void step2_tile(
     const StepGeom& g, const StepPhys<T>& ph, int strip, int by,
     lds_t<Step2Lds<T, NT, step2_planes<FEAT>()>>* __restrict__ Lp,
-    lds_t<Step2Stage<NT, sizeof(S) == 4, step2_planes<FEAT>()>>* __restrict__ st0,
-    lds_t<Step2Stage<NT, sizeof(S) == 4, step2_planes<FEAT>()>>* __restrict__ st1) {
+    lds_t<Step2Stage<NT, step2_planes<FEAT>()>>* __restrict__ st0,
+    lds_t<Step2Stage<NT, step2_planes<FEAT>()>>* __restrict__ st1) {
   static_assert(FEAT == 0 || FEAT == FEAT_DRAG, "plain step or linear drag");
   constexpr bool DRAG = FEAT == FEAT_DRAG;
   auto& L = *Lp;
-  constexpr bool DMA = sizeof(S) == 4;
-  static_assert(!DMA || sizeof(T) == 4, "staged rows hold FP32 phi");
+  static_assert((sizeof(S) == 4 || sizeof(S) == 2) && sizeof(T) == 4,
+                "4- or 2-byte storage, FP32 arithmetic (staged rows hold FP32 phi)");
   // uniform per wave (NT is a multiple of the wave size); read from the first
   // lane so that the compiler keeps everything derived from it -- rows, ring
   // slots, branches -- in scalar registers
@@ -276,40 +274,15 @@ __device__ inline void step2_tile(
       ld(8, srcr, xmb, poff(8, rn));
     }
   };
-  // Workgroup barrier: without staging in flight the ordinary one (its
-  // fence waits for nothing else here)
-  auto barrier = [&]() {
-    if constexpr (DMA) lds_barrier();
-    else __syncthreads();
-  };
-  // Register loads of row yn without staging (2-byte storage): half 0 the
-  // pull, half 1 phi and beta.  (With staging half 1 takes them from the
-  // population ring, where half 0 leaves them, and issues no loads at all.)
-  auto load_row = [&](int yn, RowIn<S, T>& in) {
-    if constexpr (!DMA) {
-      if (half == 0) {
-        pull_row(yn, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
-          if (i == 9) in.phi = bload<T>(rs, v, so);
-          else if (i == 10) in.beta = bload<T>(rs, v, so);
-          else in.f[i] = bload<S>(rs, v, so);
-        });
-      } else {
-        const int r = WALLS ? min(max(yn, 0), ny - 1) : wrap_index(yn, ny);
-        in.phi = bload<T>(phir, xcT, unsigned(r) * unsigned(pitch) * TB);
-        if (DRAG) in.beta = bload<T>(betar, xcT, unsigned(r) * unsigned(pitch) * TB);
-      }
-    }
-  };
-  // Half 0's loads of row yn into staging slot sl (4-byte storage); each
-  // wave's 64 lanes fill 64 consecutive positions from the wave's base.
+  // Half 0's loads of row yn into staging slot sl; each wave's 64 lanes
+  // fill 64 consecutive words from the wave's base.
   const int wb = __builtin_amdgcn_readfirstlane(t & ~63);
   auto stage_row = [&](int yn, int sl) {
-    if constexpr (DMA) {
-      pull_row(yn, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
-        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-            rs, (lds_t<void>*)&(sl ? st1 : st0)->v[i][wb], 4, v, so, 0, 0);
-      });
-    }
+    pull_row(yn, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
+      auto* d = (lds_t<void>*)&(sl ? st1 : st0)->v[i][wb];
+      if (i >= 9 || sizeof(S) == 4) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 4, v, so, 0, 0);
+      else __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 2, v, so, 0, 0);
+    });
   };
 
   // D and S of the two rows below the one that stage B (rm, rc) and stage C
@@ -321,7 +294,7 @@ __device__ inline void step2_tile(
   // and stage B write the image of row ny - 1 into the single-row rings;
   // below the lower wall the image of row 0 replaces the carried D and S of
   // row -1 before the stage that needs it.
-  auto body = [&](int k, int sl, const RowIn<S, T>& in, RowState<T>& rA, const RowState<T>& rB,
+  auto body = [&](int k, int sl, RowState<T>& rA, const RowState<T>& rB,
                   const RowState<T>& rC, T (&bNew)[2], const T (&bOld)[2]) {
     const int yA = y0 - yoff + k;
     if (WALLS && (yA == 1 || yA == 2)) {
@@ -351,28 +324,23 @@ __device__ inline void step2_tile(
       rA.phi = phi;
       rA.drho = rA.dm0 * recip(phi);
     };
-    // half 0 (4-byte storage): the staged row yA has landed once at most one
-    // batch (row yA + 1: one load per plane) is still in flight
-    if (DMA && half == 0) wait_vm<step2_planes<FEAT>()>();
+    // half 0: the staged row yA has landed once at most one batch (row
+    // yA + 1: one load per plane) is still in flight
+    if (half == 0) wait_vm<step2_planes<FEAT>()>();
     if (rowA) {
       if (half == 0) {
         S f[9];
-        T phi;
-        if constexpr (DMA) {
-          const auto* st = sl ? st1 : st0;
+        const auto* st = sl ? st1 : st0;
 #pragma unroll
-          for (int i = 0; i < 9; ++i) f[i] = __builtin_bit_cast(S, st->v[i][t]);
-          phi = st->v[9][t];
-          if (DRAG) rA.beta = st->v[10][t];
-          // keeps these reads here, next to the wait that orders them: merged
-          // with half 1's read of phi they would wait for the row ahead too
-          __asm__ volatile("" ::: "memory");
-        } else {
-#pragma unroll
-          for (int i = 0; i < 9; ++i) f[i] = in.f[i];
-          phi = in.phi;
-          if (DRAG) rA.beta = in.beta;
+        for (int i = 0; i < 9; ++i) {
+          if constexpr (sizeof(S) == 4) f[i] = __builtin_bit_cast(S, st->v[i][t]);
+          else f[i] = __builtin_bit_cast(S, (unsigned short)__builtin_bit_cast(unsigned, st->v[i][t]));
         }
+        const T phi = st->v[9][t];
+        if (DRAG) rA.beta = st->v[10][t];
+        // keeps these reads here, next to the wait that orders them: merged
+        // with half 1's read of phi they would wait for the row ahead too
+        __asm__ volatile("" ::: "memory");
         T q[9];
         if (SHIFT) {
 #pragma unroll
@@ -392,8 +360,8 @@ __device__ inline void step2_tile(
         // with it.
         T q[9];
         const int j0 = jr(yA), jm = j0 - 1, jp = j0 + 1;
-        const T phi = DMA ? L.pop[pop_slot(9, j0)][t] : in.phi;
-        if (DRAG) rA.beta = DMA ? L.pop[pop_slot(10, j0)][t] : in.beta;
+        const T phi = L.pop[pop_slot(9, j0)][t];
+        if (DRAG) rA.beta = L.pop[pop_slot(10, j0)][t];
         q[0] = L.pop[pop_slot(0, j0)][t];
         q[1] = L.pop[pop_slot(1, j0)][tl];
         q[3] = L.pop[pop_slot(3, j0)][tr];
@@ -409,11 +377,11 @@ __device__ inline void step2_tile(
     } else if (WALLS && yA == ny) {
       s_rho[t] = rB.drho;  // above the upper wall: row ny - 1 itself
     }
-    barrier();
+    lds_barrier();
 
     // The staging slot of row yA has been read (the barrier above waited for
     // this wave's LDS reads): it takes row yA + 2.
-    if (DMA && half == 0) stage_row(yA + 2, sl);
+    if (half == 0) stage_row(yA + 2, sl);
 
     // ---------------- stage B: velocity of row yA - 1 ----------------
     // D and S of delta-rho on row yA, then grad rho on row yA - 1.  D and S
@@ -470,7 +438,7 @@ __device__ inline void step2_tile(
       rm = rc;
       rc = rn;
     }
-    barrier();
+    lds_barrier();
 
     // ---------------- stage C: collide row yA - 2 ----------------
     const int yo = yA - 2;
@@ -594,8 +562,8 @@ __device__ inline void step2_tile(
           const int jo = jr(yo);
 #pragma unroll
           for (int i = 0; i < 9; ++i) L.pop[pop_slot(i, jo)][t] = o9[i];
-          if (DMA) L.pop[pop_slot(9, jo)][t] = phi;
-          if (DMA && DRAG) L.pop[pop_slot(10, jo)][t] = rC.beta;
+          L.pop[pop_slot(9, jo)][t] = phi;
+          if (DRAG) L.pop[pop_slot(10, jo)][t] = rC.beta;
         } else if (SHIFT) {
 #pragma unroll
           for (int i = 0; i < 9; ++i)
@@ -613,42 +581,33 @@ __device__ inline void step2_tile(
     }
     // the ring rows written here are pulled in the next iteration, and the
     // single-row rings are rewritten
-    barrier();
+    lds_barrier();
   };
 
-  // Software pipeline: register loads of row yA + 1 are in flight while row
-  // yA is processed (staged rows two ahead, see stage_row); unrolled by six
-  // (a multiple of the three-row period of the states and of the two
-  // staging slots) so nothing is copied.
+  // Software pipeline: half 0 stages rows two ahead (see stage_row); the
+  // loop is unrolled by six (a multiple of the three-row period of the
+  // states and of the two staging slots) so nothing is copied.
   RowState<T> R0{}, R1{}, R2{};
   T b0[2] = {0, 0}, b1[2] = {0, 0};
-  RowIn<S, T> ia{}, ib{};
-  if (DMA && half == 0) {
+  if (half == 0) {
     stage_row(y0 - yoff, 0);
     stage_row(y0 - yoff + 1, 1);
   }
-  load_row(y0 - yoff, ia);
   for (int k = 0; k < nit; k += 6) {
-    load_row(y0 - yoff + 1 + k, ib);
-    body(k + 0, 0, ia, R0, R2, R1, b0, b1);
+    body(k + 0, 0, R0, R2, R1, b0, b1);
     if (k + 1 >= nit) break;
-    load_row(y0 - yoff + 2 + k, ia);
-    body(k + 1, 1, ib, R1, R0, R2, b1, b0);
+    body(k + 1, 1, R1, R0, R2, b1, b0);
     if (k + 2 >= nit) break;
-    load_row(y0 - yoff + 3 + k, ib);
-    body(k + 2, 0, ia, R2, R1, R0, b0, b1);
+    body(k + 2, 0, R2, R1, R0, b0, b1);
     if (k + 3 >= nit) break;
-    load_row(y0 - yoff + 4 + k, ia);
-    body(k + 3, 1, ib, R0, R2, R1, b1, b0);
+    body(k + 3, 1, R0, R2, R1, b1, b0);
     if (k + 4 >= nit) break;
-    load_row(y0 - yoff + 5 + k, ib);
-    body(k + 4, 0, ia, R1, R0, R2, b0, b1);
+    body(k + 4, 0, R1, R0, R2, b0, b1);
     if (k + 5 >= nit) break;
-    load_row(y0 - yoff + 6 + k, ia);
-    body(k + 5, 1, ib, R2, R1, R0, b1, b0);
+    body(k + 5, 1, R2, R1, R0, b1, b0);
   }
   // no load into LDS may outlive the workgroup
-  if (DMA) wait_vm<0>();
+  wait_vm<0>();
 }
 
 // Two time steps per launch: workgroup b takes tile xcd_tile(b) (strip
@@ -658,7 +617,7 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(4)))
 vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
   __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;
-  __shared__ Step2Stage<NT, sizeof(S) == 4, step2_planes<FEAT>()> stage0, stage1;
+  __shared__ Step2Stage<NT, step2_planes<FEAT>()> stage0, stage1;
   const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
   step2_tile<S, T, SHIFT, WALLS, FEAT, NT>(g, ph, tile % g.strips, tile / g.strips,
                                            lds_handle(&lds), lds_handle(&stage0),
@@ -674,7 +633,7 @@ __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(4))
 vanse_batch_step2_kernel(const BatchEntry<T>* __restrict__ entries,
                          const int* __restrict__ tile_lattice, int launch) {
   __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;
-  __shared__ Step2Stage<NT, sizeof(S) == 4, step2_planes<FEAT>()> stage0, stage1;
+  __shared__ Step2Stage<NT, step2_planes<FEAT>()> stage0, stage1;
   const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
   const int k = tile_lattice[tile];
   const BatchEntry<T>& e = entries[k];
