@@ -64,7 +64,7 @@ extern "C" {
 typedef struct vanse_lattice vanse_lattice;
 
 typedef struct {
-  int32_t nx, ny;          /* nodes; nx >= 2, ny >= 2 */
+  int32_t nx, ny;          /* nodes; nx >= 2, 2 <= ny <= 65535 */
   int32_t precision;       /* VANSE_F64 | VANSE_F32 | ..._SHIFTED */
   int32_t bc_x;            /* VANSE_PERIODIC (walls in x: VANSE_ERR_UNSUPPORTED) */
   int32_t bc_y;            /* VANSE_PERIODIC | VANSE_WALL */
@@ -86,7 +86,10 @@ typedef struct {
 /* Bytes of device workspace the lattice described by *d needs (256-byte
  * aligned).  Layout: two population buffers, phi, optional phi(t+1),
  * solid-flag, force and drag planes, a density scratch plane and reduction
- * space. */
+ * space.  VANSE_ERR_INVALID_ARG for a lattice whose population buffer (nine
+ * planes of the storage type, rows padded to 64 nodes) would reach 4 GiB --
+ * the step kernels address it with 32-bit offsets -- or with more than 65535
+ * rows (set-up and read-out kernels put one row per grid row). */
 int vanse_workspace_bytes(const vanse_desc *d, size_t *bytes);
 
 /* Create a lattice whose device state lives in `workspace` (device pointer,

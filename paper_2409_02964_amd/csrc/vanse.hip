@@ -67,6 +67,8 @@ struct Layout {
 int make_layout(const vanse_desc* d, Layout* L) {
   if (!d) return fail(VANSE_ERR_INVALID_ARG, "desc is NULL");
   if (d->nx < 2 || d->ny < 2) return fail(VANSE_ERR_INVALID_ARG, "nx, ny must be >= 2 (got %d, %d)", d->nx, d->ny);
+  // the set-up and read-out kernels launch one grid row per lattice row
+  if (d->ny > 65535) return fail(VANSE_ERR_INVALID_ARG, "lattice too tall: ny must be <= 65535 (got %d)", d->ny);
   if (storage_bytes(d->precision) == 0) return fail(VANSE_ERR_INVALID_ARG, "unknown precision %d", d->precision);
   if (d->bc_x != VANSE_PERIODIC) {
     if (d->bc_x == VANSE_WALL) return fail(VANSE_ERR_UNSUPPORTED, "walls in x are not built");

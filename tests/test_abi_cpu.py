@@ -47,6 +47,7 @@ def test_workspace_bytes_scales_with_precision():
     (64, 64, 0, 0, 5, 0, -1),
     (64, 64, 0, 0, 0, 2, -1),
     (60000, 60000, 1, 0, 0, 0, -1),
+    (64, 65536, 3, 0, 0, 0, -1),
 ])
 def test_bad_descriptors_are_rejected(nx, ny, prec, bcx, bcy, ff, code):
     d = V.Desc(nx, ny, prec, bcx, bcy, ff, 0)
@@ -170,3 +171,22 @@ def test_scheme_validation_on_the_host():
     assert L.vanse_set_scheme(h, 0, 3) == 0
     assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == 0
     assert L.vanse_destroy(h) == 0 and L.vanse_destroy(other) == 0
+
+
+@pytest.mark.parametrize("prec,sb", [("f64", 8), ("f32", 4), ("f32s", 4), ("f16s", 2)])
+def test_largest_lattice_boundary(prec, sb):
+    """A population buffer (nine planes) must stay below 4 GiB, since the step
+    kernels address it with 32-bit offsets: at 8192 columns the tallest
+    lattice below the limit is accepted and one row more is rejected."""
+    nx = 8192
+    ny = (2 ** 32 - 1) // (9 * sb * nx)
+    assert V.workspace_bytes(nx, ny, prec, "wall") > 2 * 9 * sb * nx * ny
+    with pytest.raises(V.VanseError, match="too large"):
+        V.workspace_bytes(nx, ny + 1, prec, "wall")
+
+
+def test_tallest_lattice():
+    """Rows map to the grid's y dimension of the set-up and read-out kernels."""
+    assert V.workspace_bytes(64, 65535, "f16s", "wall") > 0
+    with pytest.raises(V.VanseError, match="too tall"):
+        V.workspace_bytes(64, 65536, "f16s", "wall")
