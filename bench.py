@@ -20,7 +20,8 @@ launched on.  With two node updates per launch the intermediate state
 never reaches HBM, so `achieved` (both updates' algorithmic bytes) can
 exceed the single-pass HBM ceiling.  `traffic` is the HBM bytes one launch
 actually moves (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated on the copy
-kernel) and `traffic_gbs` that over the launch duration.  `cpu_baseline`
+kernel), `traffic_gbs` that over the launch duration and `traffic_frac`
+the fraction of the HBM peak it is.  `cpu_baseline`
 times the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -509,6 +510,8 @@ def main():
                      # `achieved`, is the rate the memory system sustains
                      "traffic_gbs": (round(traffic / (per_step_ms * per_launch / 1e3) / 1e9, 1)
                                      if traffic else None),
+                     "traffic_frac": (round(traffic / (per_step_ms * per_launch / 1e3) / 1e9
+                                            / HBM_PEAK_GBS, 4) if traffic else None),
                      "same_pattern_copy_gbs": sol},
         "wall_s": round(wall, 3),
         "final_umax": obs["umax"],
