@@ -73,6 +73,8 @@ SHAPES = [
     (247, 33, "periodic", 4),
     (246, 20, "wall", 3),    # exactly one strip
     (3, 5, "periodic", 0),   # everything wraps
+    (253, 130, "wall", 1),   # one row per workgroup: every row a block edge
+    (130, 67, "periodic", 2),
 ]
 
 

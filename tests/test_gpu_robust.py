@@ -90,7 +90,7 @@ def test_one_step_writes_every_node(nx, ny, bc, precision, tiling):
 
 @pytest.mark.parametrize("nx,ny,bc", SHAPES)
 @pytest.mark.parametrize("precision", ["f32", "f32s", "f16s"])
-@pytest.mark.parametrize("rows", [0, 3])
+@pytest.mark.parametrize("rows", [0, 1, 3])
 def test_two_step_writes_every_node(nx, ny, bc, precision, rows):
     _torch()
     lat = lattice(nx, ny, precision, bc)
