@@ -7,6 +7,8 @@
 * Determinism: the two-step kernel overlaps its LDS staging with compute
   under hand-placed waits; a missing wait would show as results that differ
   from run to run, so two runs must agree bitwise.
+* Independence: lattices and batches stepped concurrently on several
+  streams give the results of stepping them one after the other.
 """
 import sys
 
@@ -153,3 +155,38 @@ def test_two_step_batch_determinism():
         res.append([l.read_populations().cpu().numpy() for l in lats])
     for a, b in zip(*res):
         assert np.array_equal(a, b)
+
+
+def test_concurrent_streams_match_sequential():
+    """Lattices and a batch stepped at the same time on three streams share
+    no device state: every result equals stepping them one after the other."""
+    torch = _torch()
+    from paper_2409_02964_amd.vanse import Batch
+
+    def make():
+        a = lattice(300, 120, "f32s", "wall").set_steps_per_pass(2)
+        b = lattice(257, 90, "f16s", "periodic")
+        c = [lattice(n, n, "f32", "wall", seed=n) for n in (40, 96, 130)]
+        for x in [a, b] + c:
+            x.init_equilibrium(1.0)
+        return a, b, c
+
+    a0, b0, c0 = make()
+    bt0 = Batch(c0, threads=128, steps_per_pass=2)
+    for _ in range(10):
+        a0.step(3)
+        b0.step(3)
+        bt0.step(3)
+    torch.cuda.synchronize()
+    a1, b1, c1 = make()
+    bt1 = Batch(c1, threads=128, steps_per_pass=2)
+    torch.cuda.synchronize()
+    s = [torch.cuda.Stream() for _ in range(3)]
+    for _ in range(10):
+        a1.step(3, stream=s[0])
+        b1.step(3, stream=s[1])
+        bt1.step(3, stream=s[2])
+    torch.cuda.synchronize()
+    for x, y in zip([a0, b0] + c0, [a1, b1] + c1):
+        assert x.t == y.t == 30
+        assert torch.equal(x.read_populations(), y.read_populations())
