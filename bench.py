@@ -260,8 +260,8 @@ def precision_ladder(n: int, steps: int, out_md: str):
     t_oracle = time.perf_counter() - t0
     ref = o.macroscopic()
     rows = []
-    for prec, spp in (("f64", 1), ("f32", 1), ("f32s", 1), ("f16s", 1), ("f32", 2), ("f32s", 2),
-                      ("f16s", 2)):
+    for prec, spp in (("f64", 1), ("f32", 1), ("f32s", 1), ("f16s", 1), ("f64", 2), ("f32", 2),
+                      ("f32s", 2), ("f16s", 2)):
         lat = Lattice(n, n, precision=prec, bc_y="wall")
         lat.set_params(KAPPA, RATES).set_body_force(G, 0.0).set_void_fraction(phi)
         if spp == 2:
@@ -295,9 +295,10 @@ def precision_ladder(n: int, steps: int, out_md: str):
     lines += ["", "f64: FP64 arithmetic and storage; f32: FP32 arithmetic and storage of f; "
               "f32s: FP32 arithmetic, FP32 storage of the deviations from the rest state; "
               "f16s: FP32 arithmetic, FP16 storage of the deviations scaled by 2^12.  Two steps "
-              "per launch keep the intermediate state in FP32 in LDS (one storage rounding "
-              "per two steps).  The MLUPS column is a single wall-clock run of this size (the "
-              "populations of the smaller formats fit in the 256 MB last-level cache)."]
+              "per launch keep the intermediate state in LDS in the arithmetic type (one "
+              "storage rounding per two steps).  The MLUPS column is a single wall-clock run "
+              "of this size (the populations of the smaller formats fit in the 256 MB "
+              "last-level cache)."]
     open(out_md, "w").write("\n".join(lines) + "\n")
     return rows
 
@@ -435,7 +436,7 @@ def main():
     lat.set_params(KAPPA, RATES).set_body_force(G, 0.0, True)
     lat.set_void_fraction(phi)
     lat.set_tiling(args.threads, args.rows)
-    spp = args.steps_per_pass if args.precision != "f64" else 1
+    spp = args.steps_per_pass
     lat.set_steps_per_pass(spp, args.fused_rows)
     lat.init_equilibrium(1.0)
     stream = torch.cuda.current_stream(dev)

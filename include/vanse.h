@@ -212,19 +212,20 @@ int vanse_set_tiling(vanse_lattice *h, int threads, int rows);
 int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
                      int *workgroups);
 
-/* Time steps per launch of the plain step or the linear drag (FP32
- * arithmetic, no force field, mask, moving phi, scheme variant or wall
- * velocity): 1 (the default) or 2.  With 2, vanse_step advances pairs of steps with one
+/* Time steps per launch of the plain step or the linear drag (no force
+ * field, mask, moving phi, scheme variant or wall velocity): 1 (the default)
+ * or 2.  With 2, vanse_step advances pairs of steps with one
  * launch each: a workgroup's first half runs step t -> t+1 into an LDS ring
  * and its second half step t+1 -> t+2 from it, so the populations cross HBM
  * once per two steps; an odd step count ends with one single step.  Each
  * half computes the same scheme as the single step (its Eq. 10 sums in the
- * stencil's separable form, so the FP32 roundings differ); the intermediate
- * state stays in FP32 deviations, so FP32-shifted storage matches the
- * single-step results to FP32 rounding and the other storage formats skip
- * one storage rounding.  Other lattices keep one step per launch.  rows:
- * rows per workgroup of the two-step kernel (0: one full round of resident
- * workgroups).  VANSE_ERR_UNSUPPORTED for FP64. */
+ * stencil's separable form, so the roundings differ); the intermediate
+ * state stays in deviations of the arithmetic type (FP32, or FP64 for
+ * VANSE_F64), so FP32-shifted and FP64 storage match the single-step
+ * results to rounding and the other storage formats skip one storage
+ * rounding.  Halves of 256 lanes in FP32 arithmetic and of 128 in FP64.
+ * Other lattices keep one step per launch.  rows: rows per workgroup of the
+ * two-step kernel (0: one full round of resident workgroups). */
 int vanse_set_steps_per_pass(vanse_lattice *h, int steps, int rows);
 /* Whether the two-step launch is in use (*active), and its rows per
  * workgroup and workgroups per launch. */

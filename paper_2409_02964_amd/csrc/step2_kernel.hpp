@@ -68,15 +68,16 @@ struct Step2Lds {
 };
 
 // Half 0's staging of a pulled row: the nine populations, phi and (with the
-// drag) beta, one 4-byte word per lane and plane at the lane's own position
-// (a 2-byte load with LDS destination fills its lane's word, zero-extended).
-// Two slots, each its own LDS object, passed to the tile as distinct
-// restrict pointers: the compiler then orders a read of one slot after the
-// loads into that slot only, not after the loads of the row ahead in flight
-// into the other.
-template <int NT, int NP>
+// drag) beta, as NW rows of 4-byte words, each lane's word at its own
+// position.  A 2-byte load with LDS destination fills its lane's word,
+// zero-extended; an 8-byte value takes two words, its low half in row 2i
+// and its high half in row 2i + 1.  Two slots, each its own LDS object,
+// passed to the tile as distinct restrict pointers: the compiler then orders
+// a read of one slot after the loads into that slot only, not after the
+// loads of the row ahead in flight into the other.
+template <int NT, int NW>
 struct Step2Stage {
-  float v[NP][NT];
+  float v[NW][NT];
 };
 
 // Wait until at most n vector-memory operations of this wave are
@@ -141,6 +142,20 @@ __device__ __forceinline__ void lds_put(lds_t<U2<T>>& d, const U2<T>& v) {
   d.muy = v.muy; d.ruy = v.ruy;
 }
 
+// Value i of a staged row (type X: 8, 4 or 2 bytes) on lane t
+template <typename X, int NT, int NW>
+__device__ __forceinline__ X staged(const lds_t<Step2Stage<NT, NW>>* st, int i, int t) {
+  if constexpr (sizeof(X) == 8) {
+    const unsigned long long lo = __builtin_bit_cast(unsigned, float(st->v[2 * i][t]));
+    const unsigned long long hi = __builtin_bit_cast(unsigned, float(st->v[2 * i + 1][t]));
+    return __builtin_bit_cast(X, lo | (hi << 32));
+  } else if constexpr (sizeof(X) == 4) {
+    return __builtin_bit_cast(X, float(st->v[i][t]));
+  } else {
+    return __builtin_bit_cast(X, (unsigned short)__builtin_bit_cast(unsigned, float(st->v[i][t])));
+  }
+}
+
 // D and S (see above) of delta-rho on one row
 template <typename T>
 struct RhoDS {
@@ -174,19 +189,29 @@ __device__ __forceinline__ int pop_slot(int i, int j) { return 4 * i + (j & 3); 
 template <int FEAT>
 constexpr int step2_planes() { return (FEAT & FEAT_DRAG) ? 11 : 10; }
 
+// 4-byte words of a staged row: one per plane, two for 8-byte values
+template <typename S, int FEAT>
+constexpr int step2_words() { return step2_planes<FEAT>() * (sizeof(S) == 8 ? 2 : 1); }
+
+// Waves per SIMD of the two-step kernels: four in FP32 arithmetic (128
+// registers), two in FP64 (256)
+template <typename T>
+constexpr int step2_waves() { return sizeof(T) == 8 ? 2 : 4; }
+
 // FEAT: 0 (the plain step) or FEAT_DRAG (the linear drag, u solved in closed
 // form as in the single step)
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __device__ inline void step2_tile(
     const StepGeom& g, const StepPhys<T>& ph, int strip, int by,
     lds_t<Step2Lds<T, NT, step2_planes<FEAT>()>>* __restrict__ Lp,
-    lds_t<Step2Stage<NT, step2_planes<FEAT>()>>* __restrict__ st0,
-    lds_t<Step2Stage<NT, step2_planes<FEAT>()>>* __restrict__ st1) {
+    lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st0,
+    lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st1) {
   static_assert(FEAT == 0 || FEAT == FEAT_DRAG, "plain step or linear drag");
   constexpr bool DRAG = FEAT == FEAT_DRAG;
   auto& L = *Lp;
-  static_assert((sizeof(S) == 4 || sizeof(S) == 2) && sizeof(T) == 4,
-                "4- or 2-byte storage, FP32 arithmetic (staged rows hold FP32 phi)");
+  static_assert(((sizeof(S) == 4 || sizeof(S) == 2) && sizeof(T) == 4) ||
+                    (sizeof(S) == 8 && sizeof(T) == 8),
+                "4- or 2-byte storage with FP32 arithmetic, or FP64 throughout");
   // uniform per wave (NT is a multiple of the wave size); read from the first
   // lane so that the compiler keeps everything derived from it -- rows, ring
   // slots, branches -- in scalar registers
@@ -279,9 +304,18 @@ __device__ inline void step2_tile(
   const int wb = __builtin_amdgcn_readfirstlane(t & ~63);
   auto stage_row = [&](int yn, int sl) {
     pull_row(yn, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
-      auto* d = (lds_t<void>*)&(sl ? st1 : st0)->v[i][wb];
-      if (i >= 9 || sizeof(S) == 4) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 4, v, so, 0, 0);
-      else __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 2, v, so, 0, 0);
+      auto* st = sl ? st1 : st0;
+      if constexpr (sizeof(S) == 8) {
+        // low and high words (phi and beta are FP64 too); the high word's 4
+        // bytes go into the uniform offset: an immediate offset would move
+        // the LDS destination as well
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_t<void>*)&st->v[2 * i][wb], 4, v, so, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_t<void>*)&st->v[2 * i + 1][wb], 4, v, so + 4u, 0, 0);
+      } else {
+        auto* d = (lds_t<void>*)&st->v[i][wb];
+        if (i >= 9 || sizeof(S) == 4) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 4, v, so, 0, 0);
+        else __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 2, v, so, 0, 0);
+      }
     });
   };
 
@@ -326,18 +360,15 @@ __device__ inline void step2_tile(
     };
     // half 0: the staged row yA has landed once at most one batch (row
     // yA + 1: one load per plane) is still in flight
-    if (half == 0) wait_vm<step2_planes<FEAT>()>();
+    if (half == 0) wait_vm<step2_words<S, FEAT>()>();
     if (rowA) {
       if (half == 0) {
         S f[9];
         const auto* st = sl ? st1 : st0;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          if constexpr (sizeof(S) == 4) f[i] = __builtin_bit_cast(S, st->v[i][t]);
-          else f[i] = __builtin_bit_cast(S, (unsigned short)__builtin_bit_cast(unsigned, st->v[i][t]));
-        }
-        const T phi = st->v[9][t];
-        if (DRAG) rA.beta = st->v[10][t];
+        for (int i = 0; i < 9; ++i) f[i] = staged<S>(st, i, t);
+        const T phi = staged<T>(st, 9, t);
+        if (DRAG) rA.beta = staged<T>(st, 10, t);
         // keeps these reads here, next to the wait that orders them: merged
         // with half 1's read of phi they would wait for the row ahead too
         __asm__ volatile("" ::: "memory");
@@ -614,10 +645,10 @@ __device__ inline void step2_tile(
 // tile % strips, row block tile / strips); 2 NT lanes (two halves of NT),
 // four waves per SIMD.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(step2_waves<T>())))
 vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
   __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;
-  __shared__ Step2Stage<NT, step2_planes<FEAT>()> stage0, stage1;
+  __shared__ Step2Stage<NT, step2_words<S, FEAT>()> stage0, stage1;
   const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
   step2_tile<S, T, SHIFT, WALLS, FEAT, NT>(g, ph, tile % g.strips, tile / g.strips,
                                            lds_handle(&lds), lds_handle(&stage0),
@@ -629,11 +660,11 @@ vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
 // one-lattice kernel); each member's two buffers alternate with the launch
 // parity as in the one-step batch.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(step2_waves<T>())))
 vanse_batch_step2_kernel(const BatchEntry<T>* __restrict__ entries,
                          const int* __restrict__ tile_lattice, int launch) {
   __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;
-  __shared__ Step2Stage<NT, step2_planes<FEAT>()> stage0, stage1;
+  __shared__ Step2Stage<NT, step2_words<S, FEAT>()> stage0, stage1;
   const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
   const int k = tile_lattice[tile];
   const BatchEntry<T>& e = entries[k];

@@ -2,5 +2,6 @@
 #define VANSE_S float
 #define VANSE_T float
 #define VANSE_SHIFT false
-#define VANSE_FUSED2 1
+#define VANSE_FUSED2_NT 256
+#define VANSE_FUSED2_BATCH 1
 #include "step_inst.hpp"

@@ -2,5 +2,6 @@
 #define VANSE_S double
 #define VANSE_T double
 #define VANSE_SHIFT false
-#define VANSE_FUSED2 0
+#define VANSE_FUSED2_NT 128
+#define VANSE_FUSED2_BATCH 0
 #include "step_inst.hpp"

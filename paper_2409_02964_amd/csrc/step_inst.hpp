@@ -4,9 +4,11 @@
 //
 // Instances: workgroup widths 64, 128 and 256 for every feature variant the
 // host selects (plain, force field, drag, both, FEAT_ALL), 512 for the plain
-// step; the batched kernel for the first four; where VANSE_FUSED2 is set the
-// two-step kernel of the plain step and of the linear drag (256-lane halves)
-// and its batched form (halves of 64, 128 or 256 lanes).
+// step; the batched kernel for the first four; the two-step kernel of the
+// plain step and of the linear drag with halves of VANSE_FUSED2_NT lanes
+// (256 in FP32 arithmetic, 128 in FP64, whose rings take twice the LDS), and
+// where VANSE_FUSED2_BATCH is set its batched form (halves of 64, 128 or 256
+// lanes).
 #include "step_launch.hpp"
 
 namespace vanse_dev {
@@ -58,20 +60,19 @@ VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_DRAG)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE | FEAT_DRAG)
 
-// two steps per pass: FP32 arithmetic only (the FP64 rings would not fit
-// two workgroups in a CU's LDS)
-#if VANSE_FUSED2
+// two steps per pass
 #define VANSE_STEP2_ONE(W, F) \
-  template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, 256>( \
+  template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, VANSE_FUSED2_NT>( \
       const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
+VANSE_STEP2_ONE(false, 0) VANSE_STEP2_ONE(true, 0)
+VANSE_STEP2_ONE(false, FEAT_DRAG) VANSE_STEP2_ONE(true, FEAT_DRAG)
+#undef VANSE_STEP2_ONE
+#if VANSE_FUSED2_BATCH
 #define VANSE_BATCH2_ONE(W, F, NT) \
   template void launch_batch2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, NT>( \
       const BatchEntry<VANSE_T>*, const int*, int, int, hipStream_t);
-VANSE_STEP2_ONE(false, 0) VANSE_STEP2_ONE(true, 0)
-VANSE_STEP2_ONE(false, FEAT_DRAG) VANSE_STEP2_ONE(true, FEAT_DRAG)
 VANSE_WALLS(VANSE_BATCH2_ONE, 0)
 VANSE_WALLS(VANSE_BATCH2_ONE, FEAT_DRAG)
-#undef VANSE_STEP2_ONE
 #undef VANSE_BATCH2_ONE
 #endif
 

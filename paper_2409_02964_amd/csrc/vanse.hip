@@ -257,23 +257,24 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
   }
 }
 
-// Two-step launches of the plain step and of the linear drag: FP32
-// arithmetic, no other optional input or scheme variant.  Rows per workgroup default to one full round of resident
-// workgroups (two 512-lane workgroups per CU).
-constexpr int kFusedNT = 256;
-constexpr int kFusedOutW = kFusedNT - 10;
+// Two-step launches of the plain step and of the linear drag, no other
+// optional input or scheme variant.  Halves of 256 lanes in FP32 arithmetic
+// and of 128 in FP64 (whose LDS rings take twice the bytes per lane); each
+// outputs its half's width less 10 columns.  Rows per workgroup default to
+// one full round of resident workgroups (two per CU in either precision).
+template <typename T>
+constexpr int fused_nt() { return sizeof(T) == 8 ? 128 : 256; }
+int fused_out_w(const vanse_lattice* h) { return (h->d.precision == VANSE_F64 ? 128 : 256) - 10; }
 
 // Variants the two-step kernel is built for: the plain step and the linear
 // drag (no force field, mask, moving phi or scheme variant)
 bool fused_feat(const vanse_lattice* h) { return feat_of(h) == 0 || feat_of(h) == FEAT_DRAG; }
 
-bool fused_ok(const vanse_lattice* h) {
-  return h->fuse == 2 && h->d.precision != VANSE_F64 && fused_feat(h);
-}
+bool fused_ok(const vanse_lattice* h) { return h->fuse == 2 && fused_feat(h); }
 
 int fused_rows(const vanse_lattice* h) {
   if (h->rows2 > 0) return h->rows2;
-  const int strips = (h->d.nx + kFusedOutW - 1) / kFusedOutW;
+  const int strips = (h->d.nx + fused_out_w(h) - 1) / fused_out_w(h);
   long long nby = (long long)device_cus() * 2 / strips;
   if (nby < 1) nby = 1;
   long long r = (h->d.ny + nby - 1) / nby;
@@ -283,9 +284,8 @@ int fused_rows(const vanse_lattice* h) {
 
 template <typename S, typename T, bool SHIFT>
 int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
-  if constexpr (sizeof(T) == 8) {
-    return fail(VANSE_ERR_UNSUPPORTED, "two steps per launch are built for FP32 arithmetic");
-  } else {
+  constexpr int NT = fused_nt<T>();
+  {
     const StepPhys<T> ph = make_phys<T>(h);
     StepGeom g{};
     g.phi = h->ws + h->L.phi;
@@ -294,7 +294,7 @@ int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
     g.nx = h->d.nx;
     g.ny = h->d.ny;
     g.pitch = h->L.pitch;
-    g.out_w = kFusedOutW;
+    g.out_w = NT - 10;
     g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
     g.rows = fused_rows(h);
     const bool drag = feat_of(h) == FEAT_DRAG;
@@ -305,11 +305,11 @@ int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
       g.src = h->ws + h->L.pop[h->cur];
       g.dst = h->ws + h->L.pop[h->cur ^ 1];
       if (drag) {
-        if (walls) launch_step2_nt<S, T, SHIFT, true, FEAT_DRAG, kFusedNT>(g, ph, blocks, st);
-        else launch_step2_nt<S, T, SHIFT, false, FEAT_DRAG, kFusedNT>(g, ph, blocks, st);
+        if (walls) launch_step2_nt<S, T, SHIFT, true, FEAT_DRAG, NT>(g, ph, blocks, st);
+        else launch_step2_nt<S, T, SHIFT, false, FEAT_DRAG, NT>(g, ph, blocks, st);
       } else {
-        if (walls) launch_step2_nt<S, T, SHIFT, true, 0, kFusedNT>(g, ph, blocks, st);
-        else launch_step2_nt<S, T, SHIFT, false, 0, kFusedNT>(g, ph, blocks, st);
+        if (walls) launch_step2_nt<S, T, SHIFT, true, 0, NT>(g, ph, blocks, st);
+        else launch_step2_nt<S, T, SHIFT, false, 0, NT>(g, ph, blocks, st);
       }
       h->cur ^= 1;
       h->t += 2;
@@ -780,8 +780,6 @@ int vanse_set_steps_per_pass(vanse_lattice* h, int steps, int rows) {
   if (int rc = check_handle(h)) return rc;
   if (steps != 1 && steps != 2) return fail(VANSE_ERR_INVALID_ARG, "steps per pass must be 1 or 2 (got %d)", steps);
   if (rows < 0) return fail(VANSE_ERR_INVALID_ARG, "rows must be >= 0 (got %d)", rows);
-  if (steps == 2 && h->d.precision == VANSE_F64)
-    return fail(VANSE_ERR_UNSUPPORTED, "two steps per launch are built for FP32 arithmetic");
   h->fuse = steps;
   h->rows2 = rows;
   return VANSE_OK;
@@ -790,7 +788,7 @@ int vanse_set_steps_per_pass(vanse_lattice* h, int steps, int rows) {
 int vanse_get_fused_tiling(const vanse_lattice* h, int* active, int* rows, int* workgroups) {
   if (int rc = check_handle(h)) return rc;
   const int r = fused_rows(h);
-  const int strips = (h->d.nx + kFusedOutW - 1) / kFusedOutW;
+  const int strips = (h->d.nx + fused_out_w(h) - 1) / fused_out_w(h);
   if (active) *active = fused_ok(h) ? 1 : 0;
   if (rows) *rows = r;
   if (workgroups) *workgroups = strips * ((h->d.ny + r - 1) / r);
@@ -899,7 +897,7 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
       return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary, force field or drag", k);
     if (fuse == 2 && (d.precision == VANSE_F64 || !fused_feat(lats[k])))
       return fail(VANSE_ERR_UNSUPPORTED,
-                  "lattice %d: two steps per launch take FP32 arithmetic without force field", k);
+                  "lattice %d: batched two steps per launch take FP32 arithmetic without force field", k);
     strip_rows += (long long)((d.nx + out_w - 1) / out_w) * d.ny;
   }
   int r = rows;

@@ -68,12 +68,14 @@ def periodic_mismatch(torch, f, fn):
     return worst
 
 
-def test_largest_fp64_lattice_against_oracle(oracle):
+@pytest.mark.parametrize("spp", [1, 2])
+def test_largest_fp64_lattice_against_oracle(oracle, spp):
     torch = _torch()
     ny = max_rows("f64")
     phi = narrow_phi(ny)
-    _say(f"FP64 {NX} x {ny} ({9 * NX * ny * 8 / 2**30:.3f} GiB per buffer), 3 steps")
-    lat = lattice(NX, ny, "f64", np.tile(phi, (1, NX // PERIOD)), 1)
+    _say(f"FP64 {NX} x {ny} ({9 * NX * ny * 8 / 2**30:.3f} GiB per buffer), "
+         f"{spp} step(s) per launch, 3 steps")
+    lat = lattice(NX, ny, "f64", np.tile(phi, (1, NX // PERIOD)), spp)
     lat.step(3)
     f = lat.read_populations()
     lat.close()

@@ -91,7 +91,7 @@ def test_one_step_writes_every_node(nx, ny, bc, precision, tiling):
 
 
 @pytest.mark.parametrize("nx,ny,bc", SHAPES)
-@pytest.mark.parametrize("precision", ["f32", "f32s", "f16s"])
+@pytest.mark.parametrize("precision", ["f64", "f32", "f32s", "f16s"])
 @pytest.mark.parametrize("rows", [0, 1, 3])
 def test_two_step_writes_every_node(nx, ny, bc, precision, rows):
     _torch()
@@ -124,7 +124,8 @@ def test_batch_writes_every_node(spp, precision):
         assert np.isfinite(f).all(), f"{lat.nx}x{lat.ny}: {np.isnan(f).sum()} NaN"
 
 
-@pytest.mark.parametrize("precision,drag", [("f32s", False), ("f16s", False), ("f32s", True)])
+@pytest.mark.parametrize("precision,drag", [("f32s", False), ("f16s", False), ("f32s", True),
+                                            ("f64", False)])
 def test_two_step_determinism(precision, drag):
     """Two runs of 40 steps on a lattice of many tiles agree bitwise."""
     _torch()
