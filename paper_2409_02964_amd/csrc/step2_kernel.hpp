@@ -13,8 +13,10 @@
 // Each half computes the plain single step's scheme (Sec. 2.3: Eq. 7, 10,
 // 13, 14-20, A1), with the Eq. (10) sums in the separable form below; the
 // intermediate populations never reach HBM, so HBM traffic per time step
-// halves.  The intermediate state is kept as FP32 deviations from the rest
-// state, the format the single step stores with FP32-shifted storage.
+// halves.  The intermediate state is kept as deviations from the rest state
+// in the arithmetic type: with FP32 arithmetic the format the single step
+// stores with FP32-shifted storage; FP64 keeps it in FP64 (halves of 128
+// lanes then, as the rings take twice the bytes per lane).
 //
 // Per iteration k each half runs three stages on rows yA = y0 - 5 - 4 half
 // + k (A: moments), yA - 1 (B: velocity), yA - 2 (C: collision), with three
@@ -359,7 +361,7 @@ __device__ inline void step2_tile(
       rA.drho = rA.dm0 * recip(phi);
     };
     // half 0: the staged row yA has landed once at most one batch (row
-    // yA + 1: one load per plane) is still in flight
+    // yA + 1: one load per staged word row) is still in flight
     if (half == 0) wait_vm<step2_words<S, FEAT>()>();
     if (rowA) {
       if (half == 0) {
