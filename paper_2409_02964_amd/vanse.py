@@ -277,7 +277,7 @@ class Lattice:
         return dict(threads=a.value, rows=b.value, workgroups=c.value)
 
     def set_steps_per_pass(self, steps=2, rows=0):
-        """Time steps per launch of the plain FP32 step (1 or 2); see vanse.h."""
+        """Time steps per launch of the plain step or the linear drag (1 or 2); see vanse.h."""
         check(lib().vanse_set_steps_per_pass(self.handle, int(steps), int(rows)))
         return self
 
