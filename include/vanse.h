@@ -271,8 +271,8 @@ int vanse_batch_destroy(vanse_batch *b);
 
 /* As the two calls above, with steps_per_pass time steps per launch (1 or
  * 2).  With 2 every launch applies the two-step kernel of
- * vanse_set_steps_per_pass to all members (FP32 arithmetic, members without
- * force field, else VANSE_ERR_UNSUPPORTED): threads is then the
+ * vanse_set_steps_per_pass to all members (members without force field,
+ * and threads 64 or 128 in FP64; else VANSE_ERR_UNSUPPORTED): threads is then the
  * width of each half of a workgroup of 2 x threads lanes, a tile is a strip
  * of threads-10 columns, and rows = 0 gives about four rounds of resident
  * workgroups.  Each member's results are bitwise those of stepping it alone

@@ -3,5 +3,5 @@
 #define VANSE_T float
 #define VANSE_SHIFT false
 #define VANSE_FUSED2_NT 256
-#define VANSE_FUSED2_BATCH 1
+#define VANSE_FUSED2_BATCH_MAX 256
 #include "step_inst.hpp"

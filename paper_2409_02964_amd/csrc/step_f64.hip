@@ -3,5 +3,5 @@
 #define VANSE_T double
 #define VANSE_SHIFT false
 #define VANSE_FUSED2_NT 128
-#define VANSE_FUSED2_BATCH 0
+#define VANSE_FUSED2_BATCH_MAX 128
 #include "step_inst.hpp"

@@ -7,8 +7,7 @@
 // step; the batched kernel for the first four; the two-step kernel of the
 // plain step and of the linear drag with halves of VANSE_FUSED2_NT lanes
 // (256 in FP32 arithmetic, 128 in FP64, whose rings take twice the LDS), and
-// where VANSE_FUSED2_BATCH is set its batched form (halves of 64, 128 or 256
-// lanes).
+// its batched form with halves of 64 lanes up to VANSE_FUSED2_BATCH_MAX.
 #include "step_launch.hpp"
 
 namespace vanse_dev {
@@ -67,14 +66,19 @@ VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE | FEAT_DRAG)
 VANSE_STEP2_ONE(false, 0) VANSE_STEP2_ONE(true, 0)
 VANSE_STEP2_ONE(false, FEAT_DRAG) VANSE_STEP2_ONE(true, FEAT_DRAG)
 #undef VANSE_STEP2_ONE
-#if VANSE_FUSED2_BATCH
 #define VANSE_BATCH2_ONE(W, F, NT) \
   template void launch_batch2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, NT>( \
       const BatchEntry<VANSE_T>*, const int*, int, int, hipStream_t);
-VANSE_WALLS(VANSE_BATCH2_ONE, 0)
-VANSE_WALLS(VANSE_BATCH2_ONE, FEAT_DRAG)
-#undef VANSE_BATCH2_ONE
+#if VANSE_FUSED2_BATCH_MAX >= 256
+#define VANSE_BATCH2_WIDTHS(W, F) VANSE_BATCH2_ONE(W, F, 64) VANSE_BATCH2_ONE(W, F, 128) \
+  VANSE_BATCH2_ONE(W, F, 256)
+#else
+#define VANSE_BATCH2_WIDTHS(W, F) VANSE_BATCH2_ONE(W, F, 64) VANSE_BATCH2_ONE(W, F, 128)
 #endif
+VANSE_BATCH2_WIDTHS(false, 0) VANSE_BATCH2_WIDTHS(true, 0)
+VANSE_BATCH2_WIDTHS(false, FEAT_DRAG) VANSE_BATCH2_WIDTHS(true, FEAT_DRAG)
+#undef VANSE_BATCH2_WIDTHS
+#undef VANSE_BATCH2_ONE
 
 #undef VANSE_STEP_ONE
 #undef VANSE_BATCH_ONE

@@ -864,12 +864,12 @@ struct vanse_batch {
 
 namespace {
 
-// Resident workgroups per CU: one-step workgroups of `threads` lanes (four
-// waves per SIMD in FP32, two in FP64), two-step workgroups of 2 x threads
-// lanes (16 waves per CU).
+// Resident workgroups per CU: 16 waves per CU in FP32 arithmetic (four per
+// SIMD), 8 in FP64; a one-step workgroup has `threads` lanes, a two-step
+// one 2 x threads.
 int batch_per_cu(int precision, int threads, int fuse) {
-  if (fuse == 2) return 512 / threads;
-  return (precision == VANSE_F64 ? 2 : 4) * (256 / threads);
+  const int waves_per_cu = precision == VANSE_F64 ? 8 : 16;
+  return waves_per_cu * 64 / (fuse * threads);
 }
 
 // Columns a tile outputs: threads - 4 for one step, threads - 10 for two
@@ -884,6 +884,9 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
   if (rows < 0) return fail(VANSE_ERR_INVALID_ARG, "rows must be >= 0");
   if (fuse != 1 && fuse != 2) return fail(VANSE_ERR_INVALID_ARG, "steps per pass must be 1 or 2 (got %d)", fuse);
   const vanse_desc& d0 = lats[0] ? lats[0]->d : vanse_desc{};
+  // FP64 rings take twice the LDS per lane: halves of at most 128 lanes
+  if (fuse == 2 && lats[0] && d0.precision == VANSE_F64 && threads == 256)
+    return fail(VANSE_ERR_UNSUPPORTED, "FP64 batches with two steps per launch take 64 or 128 threads");
   const int out_w = batch_out_w(threads, fuse);
   long long strip_rows = 0;
   for (int k = 0; k < n; ++k) {
@@ -895,9 +898,9 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
     if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field ||
         d.has_drag != d0.has_drag)
       return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary, force field or drag", k);
-    if (fuse == 2 && (d.precision == VANSE_F64 || !fused_feat(lats[k])))
+    if (fuse == 2 && !fused_feat(lats[k]))
       return fail(VANSE_ERR_UNSUPPORTED,
-                  "lattice %d: batched two steps per launch take FP32 arithmetic without force field", k);
+                  "lattice %d: two steps per launch take the plain step or the drag, no force field", k);
     strip_rows += (long long)((d.nx + out_w - 1) / out_w) * d.ny;
   }
   int r = rows;
@@ -989,12 +992,17 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
 void batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
   const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
   const int* TL = reinterpret_cast<const int*>(b->ws + b->tiles_off);
-  if constexpr (sizeof(T) == 4 && (FEAT == 0 || FEAT == FEAT_DRAG)) {
+  if constexpr (FEAT == 0 || FEAT == FEAT_DRAG) {
     if (b->fuse == 2) {
-      switch (b->threads) {
-        case 64: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st); break;
-        case 128: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st); break;
-        default: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 256>(E, TL, launch, b->total_tiles, st);
+      if constexpr (sizeof(T) == 8) {  // halves of 64 or 128 lanes (batch_layout)
+        if (b->threads == 64) launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st);
+        else launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st);
+      } else {
+        switch (b->threads) {
+          case 64: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st); break;
+          case 128: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st); break;
+          default: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 256>(E, TL, launch, b->total_tiles, st);
+        }
       }
       return;
     }

@@ -160,7 +160,7 @@ def test_two_step_batch_rejects_what_it_does_not_take():
     from paper_2409_02964_amd.vanse import Batch, Lattice, VanseError
     f64 = [make(32, 32, 0, "f64")[0]]
     with pytest.raises(VanseError):
-        Batch(f64, steps_per_pass=2)
+        Batch(f64, threads=256, steps_per_pass=2)  # FP64 halves: 64 or 128 lanes
     n = 24
     ff = Lattice(n, n, precision="f32", force_field=True)
     ff.set_params(0.5, RATES).set_body_force(1e-6, 0).set_void_fraction(np.full((n, n), 0.8))
@@ -174,3 +174,32 @@ def test_two_step_batch_rejects_what_it_does_not_take():
     b.set_graph(8)
     with pytest.raises(VanseError):
         Batch(ok, steps_per_pass=3)
+
+
+@pytest.mark.parametrize("bc,drag", [("wall", False), ("periodic", True)])
+@pytest.mark.parametrize("threads,rows,graph,steps", [(64, 0, 0, 9), (128, 5, 4, 10), (128, 0, 0, 7)])
+def test_two_step_batch_fp64(bc, drag, threads, rows, graph, steps):
+    """FP64 batches with two steps per launch (halves of 64 or 128 lanes):
+    bitwise the results of stepping each member alone with two steps per
+    launch."""
+    _torch()
+    from paper_2409_02964_amd.vanse import Batch
+
+    def member(k, nx, ny):
+        lat, phi = make(nx, ny, k, "f64", bc, drag=drag)
+        if drag:
+            lat.set_drag(1e-3 + 2e-2 * (1 - phi), (1e-4 * k, 0.0))
+            lat.init_equilibrium(1.0, 1e-3 * k, 0.0)
+        return lat
+
+    ref = [member(k, nx, ny) for k, (nx, ny) in enumerate(SIZES)]
+    for lat in ref:
+        lat.set_steps_per_pass(2)
+        assert lat.fused_tiling()["active"]
+        lat.step(steps)
+    mem = [member(k, nx, ny) for k, (nx, ny) in enumerate(SIZES)]
+    Batch(mem, threads=threads, rows=rows, graph_steps=graph, steps_per_pass=2).step(steps)
+    for a, r in zip(mem, ref):
+        assert a.t == r.t == steps
+        assert np.array_equal(a.read_populations().cpu().numpy(),
+                              r.read_populations().cpu().numpy())
