@@ -212,9 +212,9 @@ int vanse_set_tiling(vanse_lattice *h, int threads, int rows);
 int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
                      int *workgroups);
 
-/* Time steps per launch of the plain step or the linear drag (no force
- * field, mask, moving phi, scheme variant or wall velocity): 1 (the default)
- * or 2.  With 2, vanse_step advances pairs of steps with one
+/* Time steps per launch of the plain step, with or without the force field
+ * and the linear drag (no mask, moving phi, scheme variant or wall
+ * velocity): 1 (the default) or 2.  With 2, vanse_step advances pairs of steps with one
  * launch each: a workgroup's first half runs step t -> t+1 into an LDS ring
  * and its second half step t+1 -> t+2 from it, so the populations cross HBM
  * once per two steps; an odd step count ends with one single step.  Each
@@ -271,8 +271,8 @@ int vanse_batch_destroy(vanse_batch *b);
 
 /* As the two calls above, with steps_per_pass time steps per launch (1 or
  * 2).  With 2 every launch applies the two-step kernel of
- * vanse_set_steps_per_pass to all members (members without force field,
- * and threads 64 or 128 in FP64; else VANSE_ERR_UNSUPPORTED): threads is then the
+ * vanse_set_steps_per_pass to all members (threads 64 or 128 in FP64,
+ * else VANSE_ERR_UNSUPPORTED): threads is then the
  * width of each half of a workgroup of 2 x threads lanes, a tile is a strip
  * of threads-10 columns, and rows = 0 gives about four rounds of resident
  * workgroups.  Each member's results are bitwise those of stepping it alone

@@ -200,16 +200,18 @@ constexpr int step2_words() { return step2_planes<FEAT>() * (sizeof(S) == 8 ? 2 
 template <typename T>
 constexpr int step2_waves() { return sizeof(T) == 8 ? 2 : 4; }
 
-// FEAT: 0 (the plain step) or FEAT_DRAG (the linear drag, u solved in closed
-// form as in the single step)
+// FEAT: the plain step plus any of FEAT_FORCE (a per-node force field added
+// to F^B) and FEAT_DRAG (the linear drag, u solved in closed form as in the
+// single step)
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __device__ inline void step2_tile(
     const StepGeom& g, const StepPhys<T>& ph, int strip, int by,
     lds_t<Step2Lds<T, NT, step2_planes<FEAT>()>>* __restrict__ Lp,
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st0,
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st1) {
-  static_assert(FEAT == 0 || FEAT == FEAT_DRAG, "plain step or linear drag");
-  constexpr bool DRAG = FEAT == FEAT_DRAG;
+  static_assert((FEAT & ~(FEAT_FORCE | FEAT_DRAG)) == 0, "force field and linear drag only");
+  constexpr bool DRAG = (FEAT & FEAT_DRAG) != 0;
+  constexpr bool FORCE = (FEAT & FEAT_FORCE) != 0;
   auto& L = *Lp;
   static_assert(((sizeof(S) == 4 || sizeof(S) == 2) && sizeof(T) == 4) ||
                     (sizeof(S) == 8 && sizeof(T) == 8),
@@ -247,6 +249,8 @@ __device__ inline void step2_tile(
   const rsrc_t dstr = make_rsrc(g.dst, 9u * plane_bytes);
   const rsrc_t phir = make_rsrc(g.phi, unsigned(g.plane) * TB);
   const rsrc_t betar = make_rsrc(g.beta, DRAG ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t fxr = make_rsrc(g.fxf, FORCE ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t fyr = make_rsrc(g.fyf, FORCE ? unsigned(g.plane) * TB : 0u);
   auto poff = [&](int i, int r) { return unsigned(i) * plane_bytes + unsigned(r) * row_bytes; };
 
   const int y0 = by * g.rows;
@@ -363,6 +367,15 @@ __device__ inline void step2_tile(
     // half 0: the staged row yA has landed once at most one batch (row
     // yA + 1: one load per staged word row) is still in flight
     if (half == 0) wait_vm<step2_words<S, FEAT>()>();
+    // the force field of stage B's row, loaded into registers here so that
+    // the loads land while stage A runs (they take no LDS)
+    T fex = T(0), fey = T(0);
+    if (FORCE) {
+      const int yf = yA - 1;
+      const unsigned ro = unsigned(WALLS ? min(max(yf, 0), ny - 1) : wrap_index(yf, ny)) * unsigned(pitch) * TB;
+      fex = bload<T>(fxr, xcT, ro);
+      fey = bload<T>(fyr, xcT, ro);
+    }
     if (rowA) {
       if (half == 0) {
         S f[9];
@@ -436,6 +449,10 @@ __device__ inline void step2_tile(
         const T sg = ph.scale_by_phi ? phi : T(1);
         T Fx = kp * grx + sg * ph.gx;
         T Fy = kp * gry + sg * ph.gy;
+        if (FORCE) {
+          Fx += fex;
+          Fy += fey;
+        }
         const T m0 = phi * rho0 + rB.dm0;
         T ux, uy;
         if (DRAG) {

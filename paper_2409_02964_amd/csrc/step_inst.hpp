@@ -5,7 +5,7 @@
 // Instances: workgroup widths 64, 128 and 256 for every feature variant the
 // host selects (plain, force field, drag, both, FEAT_ALL), 512 for the plain
 // step; the batched kernel for the first four; the two-step kernel of the
-// plain step and of the linear drag with halves of VANSE_FUSED2_NT lanes
+// first four with halves of VANSE_FUSED2_NT lanes
 // (256 in FP32 arithmetic, 128 in FP64, whose rings take twice the LDS), and
 // its batched form with halves of 64 lanes up to VANSE_FUSED2_BATCH_MAX.
 #include "step_launch.hpp"
@@ -63,8 +63,8 @@ VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE | FEAT_DRAG)
 #define VANSE_STEP2_ONE(W, F) \
   template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, VANSE_FUSED2_NT>( \
       const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
-VANSE_STEP2_ONE(false, 0) VANSE_STEP2_ONE(true, 0)
-VANSE_STEP2_ONE(false, FEAT_DRAG) VANSE_STEP2_ONE(true, FEAT_DRAG)
+#define VANSE_STEP2_FEATS(M, W) M(W, 0) M(W, FEAT_DRAG) M(W, FEAT_FORCE) M(W, FEAT_FORCE | FEAT_DRAG)
+VANSE_STEP2_FEATS(VANSE_STEP2_ONE, false) VANSE_STEP2_FEATS(VANSE_STEP2_ONE, true)
 #undef VANSE_STEP2_ONE
 #define VANSE_BATCH2_ONE(W, F, NT) \
   template void launch_batch2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, NT>( \
@@ -75,8 +75,8 @@ VANSE_STEP2_ONE(false, FEAT_DRAG) VANSE_STEP2_ONE(true, FEAT_DRAG)
 #else
 #define VANSE_BATCH2_WIDTHS(W, F) VANSE_BATCH2_ONE(W, F, 64) VANSE_BATCH2_ONE(W, F, 128)
 #endif
-VANSE_BATCH2_WIDTHS(false, 0) VANSE_BATCH2_WIDTHS(true, 0)
-VANSE_BATCH2_WIDTHS(false, FEAT_DRAG) VANSE_BATCH2_WIDTHS(true, FEAT_DRAG)
+VANSE_STEP2_FEATS(VANSE_BATCH2_WIDTHS, false) VANSE_STEP2_FEATS(VANSE_BATCH2_WIDTHS, true)
+#undef VANSE_STEP2_FEATS
 #undef VANSE_BATCH2_WIDTHS
 #undef VANSE_BATCH2_ONE
 

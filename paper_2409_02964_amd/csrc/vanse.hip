@@ -257,8 +257,8 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
   }
 }
 
-// Two-step launches of the plain step and of the linear drag, no other
-// optional input or scheme variant.  Halves of 256 lanes in FP32 arithmetic
+// Two-step launches of the plain step with the force field and the linear
+// drag or without, no other optional input or scheme variant.  Halves of 256 lanes in FP32 arithmetic
 // and of 128 in FP64 (whose LDS rings take twice the bytes per lane); each
 // outputs its half's width less 10 columns.  Rows per workgroup default to
 // one full round of resident workgroups (two per CU in either precision).
@@ -266,9 +266,9 @@ template <typename T>
 constexpr int fused_nt() { return sizeof(T) == 8 ? 128 : 256; }
 int fused_out_w(const vanse_lattice* h) { return (h->d.precision == VANSE_F64 ? 128 : 256) - 10; }
 
-// Variants the two-step kernel is built for: the plain step and the linear
-// drag (no force field, mask, moving phi or scheme variant)
-bool fused_feat(const vanse_lattice* h) { return feat_of(h) == 0 || feat_of(h) == FEAT_DRAG; }
+// Variants the two-step kernel is built for: the plain step with or without
+// the force field and the linear drag (no mask, moving phi or scheme variant)
+bool fused_feat(const vanse_lattice* h) { return (feat_of(h) & ~(FEAT_FORCE | FEAT_DRAG)) == 0; }
 
 bool fused_ok(const vanse_lattice* h) { return h->fuse == 2 && fused_feat(h); }
 
@@ -297,19 +297,27 @@ int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
     g.out_w = NT - 10;
     g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
     g.rows = fused_rows(h);
-    const bool drag = feat_of(h) == FEAT_DRAG;
-    g.beta = drag ? h->ws + h->L.beta : nullptr;
+    const int feat = feat_of(h);
+    g.beta = (feat & FEAT_DRAG) ? h->ws + h->L.beta : nullptr;
+    g.fxf = (feat & FEAT_FORCE) ? h->ws + h->L.fx : nullptr;
+    g.fyf = (feat & FEAT_FORCE) ? h->ws + h->L.fy : nullptr;
     const int blocks = g.strips * ((h->d.ny + g.rows - 1) / g.rows);
     const bool walls = h->d.bc_y == VANSE_WALL;
     for (int64_t s = 0; s < pairs; ++s) {
       g.src = h->ws + h->L.pop[h->cur];
       g.dst = h->ws + h->L.pop[h->cur ^ 1];
-      if (drag) {
-        if (walls) launch_step2_nt<S, T, SHIFT, true, FEAT_DRAG, NT>(g, ph, blocks, st);
-        else launch_step2_nt<S, T, SHIFT, false, FEAT_DRAG, NT>(g, ph, blocks, st);
-      } else {
-        if (walls) launch_step2_nt<S, T, SHIFT, true, 0, NT>(g, ph, blocks, st);
-        else launch_step2_nt<S, T, SHIFT, false, 0, NT>(g, ph, blocks, st);
+      auto go = [&](auto walls_c, auto feat_c) {
+        launch_step2_nt<S, T, SHIFT, decltype(walls_c)::value, decltype(feat_c)::value, NT>(g, ph, blocks, st);
+      };
+      auto with_walls = [&](auto feat_c) {
+        if (walls) go(std::true_type{}, feat_c);
+        else go(std::false_type{}, feat_c);
+      };
+      switch (feat) {
+        case FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_DRAG>{}); break;
+        case FEAT_FORCE: with_walls(std::integral_constant<int, FEAT_FORCE>{}); break;
+        case FEAT_FORCE | FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_FORCE | FEAT_DRAG>{}); break;
+        default: with_walls(std::integral_constant<int, 0>{});
       }
       h->cur ^= 1;
       h->t += 2;
@@ -900,7 +908,7 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
       return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary, force field or drag", k);
     if (fuse == 2 && !fused_feat(lats[k]))
       return fail(VANSE_ERR_UNSUPPORTED,
-                  "lattice %d: two steps per launch take the plain step or the drag, no force field", k);
+                  "lattice %d: two steps per launch take the force field and the drag only", k);
     strip_rows += (long long)((d.nx + out_w - 1) / out_w) * d.ny;
   }
   int r = rows;
@@ -992,7 +1000,7 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
 void batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
   const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
   const int* TL = reinterpret_cast<const int*>(b->ws + b->tiles_off);
-  if constexpr (FEAT == 0 || FEAT == FEAT_DRAG) {
+  if constexpr ((FEAT & ~(FEAT_FORCE | FEAT_DRAG)) == 0) {
     if (b->fuse == 2) {
       if constexpr (sizeof(T) == 8) {  // halves of 64 or 128 lanes (batch_layout)
         if (b->threads == 64) launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st);

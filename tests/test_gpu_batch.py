@@ -161,12 +161,6 @@ def test_two_step_batch_rejects_what_it_does_not_take():
     f64 = [make(32, 32, 0, "f64")[0]]
     with pytest.raises(VanseError):
         Batch(f64, threads=256, steps_per_pass=2)  # FP64 halves: 64 or 128 lanes
-    n = 24
-    ff = Lattice(n, n, precision="f32", force_field=True)
-    ff.set_params(0.5, RATES).set_body_force(1e-6, 0).set_void_fraction(np.full((n, n), 0.8))
-    ff.set_force_field(np.full((n, n), 1e-7), np.zeros((n, n))).init_equilibrium(1.0)
-    with pytest.raises(VanseError):
-        Batch([ff], steps_per_pass=2)
     ok = [make(32, 32, 0, "f32")[0]]
     b = Batch(ok, steps_per_pass=2)
     with pytest.raises(VanseError):
@@ -201,5 +195,34 @@ def test_two_step_batch_fp64(bc, drag, threads, rows, graph, steps):
     Batch(mem, threads=threads, rows=rows, graph_steps=graph, steps_per_pass=2).step(steps)
     for a, r in zip(mem, ref):
         assert a.t == r.t == steps
+        assert np.array_equal(a.read_populations().cpu().numpy(),
+                              r.read_populations().cpu().numpy())
+
+
+@pytest.mark.parametrize("precision,threads", [("f32s", 128), ("f16s", 64), ("f64", 128)])
+def test_two_step_batch_with_force_field(precision, threads):
+    """Members with a per-node force field and the drag (members share their
+    variant): bitwise the results of stepping each alone with two steps per
+    launch."""
+    _torch()
+    from paper_2409_02964_amd.vanse import Batch, Lattice
+
+    def member(k, nx, ny):
+        lat = Lattice(nx, ny, precision=precision, bc_y="wall", force_field=True, drag=True)
+        phi = 0.6 + 0.3 * np.sin(2 * np.pi * np.arange(nx)[None, :] / nx) * np.cos(2 * np.pi * np.arange(ny)[:, None] / ny)
+        lat.set_params(0.5, RATES).set_body_force(1e-6 * (k + 1), 0.0).set_void_fraction(phi)
+        lat.set_drag(1e-3 + 2e-2 * (1 - phi))
+        lat.set_force_field(1e-6 * np.cos(2 * np.pi * np.arange(ny)[:, None] / ny) * np.ones((ny, nx)),
+                            np.full((ny, nx), -2e-7 * k))
+        return lat.init_equilibrium(1.0)
+
+    ref = [member(k, nx, ny) for k, (nx, ny) in enumerate(SIZES)]
+    for lat in ref:
+        lat.set_steps_per_pass(2)
+        assert lat.fused_tiling()["active"]
+        lat.step(9)
+    mem = [member(k, nx, ny) for k, (nx, ny) in enumerate(SIZES)]
+    Batch(mem, threads=threads, graph_steps=4, steps_per_pass=2).step(9)
+    for a, r in zip(mem, ref):
         assert np.array_equal(a.read_populations().cpu().numpy(),
                               r.read_populations().cpu().numpy())

@@ -33,12 +33,15 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def lattice(nx, ny, phi, precision, bc, fused, rows=0, g=(2e-5, -1e-5), drag=None):
+def lattice(nx, ny, phi, precision, bc, fused, rows=0, g=(2e-5, -1e-5), drag=None, force=None):
     from paper_2409_02964_amd.vanse import Lattice
-    lat = Lattice(nx, ny, precision=precision, bc_y=bc, drag=drag is not None)
+    lat = Lattice(nx, ny, precision=precision, bc_y=bc, drag=drag is not None,
+                  force_field=force is not None)
     lat.set_params(0.5, RATES).set_body_force(*g).set_void_fraction(phi)
     if drag is not None:
         lat.set_drag(drag)
+    if force is not None:
+        lat.set_force_field(*force)
     if fused:
         lat.set_steps_per_pass(2, rows)
     return lat
@@ -181,14 +184,15 @@ def test_fused_falls_back_for_variants():
     from paper_2409_02964_amd.vanse import Lattice, VanseError
     n = 48
     phi = W.periodic_wave(n, n)
-    force = (np.full((n, n), 1e-6), np.zeros((n, n)))
-    a = Lattice(n, n, "f32", force_field=True)
-    b = Lattice(n, n, "f32", force_field=True)
+    mask = np.zeros((n, n), dtype=np.uint8)
+    mask[10:14, 20:26] = 1
+    a = Lattice(n, n, "f32", mask=True)
+    b = Lattice(n, n, "f32", mask=True)
     for lat in (a, b):
         lat.set_params(0.5, RATES).set_body_force(1e-6, 0).set_void_fraction(phi)
-        lat.set_force_field(*force)
+        lat.set_mask(mask)
     b.set_steps_per_pass(2)
-    assert not b.fused_tiling()["active"]  # force field: one step per launch
+    assert not b.fused_tiling()["active"]  # solid nodes: one step per launch
     for lat in (a, b):
         lat.init_equilibrium(1.0)
         lat.step(7)
@@ -255,4 +259,55 @@ def test_fused_fp64_vs_oracle(oracle, bc, drag, steps):
     m = {k: v.cpu().numpy() for k, v in lat.read_moments().items()}
     err = rel_l2_u(m, ref)
     _say(f"f64 two steps per launch, {bc}, drag={drag}: rel-L2(u) vs oracle {err:.3e}")
+    assert err <= 1e-12
+
+
+# ---- the per-node force field (added to F^B in stage B) ----------------------------
+
+@pytest.mark.parametrize("prec,bc,nx,ny,rows,drag", [
+    ("f32s", "wall", 253, 130, 0, False), ("f32s", "periodic", 300, 70, 1, True),
+    ("f16s", "wall", 97, 40, 0, False), ("f64", "wall", 246, 60, 0, True),
+    ("f64", "periodic", 130, 67, 3, False)])
+def test_fused_force_field_matches_single_steps(prec, bc, nx, ny, rows, drag):
+    """A per-node force field with two steps per launch against one step per
+    launch, to rounding (FP32-shifted and FP64; FP16-shifted as for the drag)."""
+    torch = _torch()
+    _say(f"fused force field vs single {prec} {nx}x{ny} {bc} rows={rows} drag={drag}")
+    phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 2.0, seed=nx + ny) ** 2
+    force = (1e-5 * W.smoothed_noise(nx, ny, 3.0, seed=1), -1e-5 * W.smoothed_noise(nx, ny, 3.0, seed=2))
+    beta = (1e-3 + 0.2 * W.smoothed_noise(nx, ny, 2.0, seed=ny) ** 2) if drag else None
+    f0n = W.random_populations(nx, ny, seed=17 + nx)
+    f0 = torch.from_numpy(f0n)
+    a = lattice(nx, ny, phi, prec, bc, fused=False, drag=beta, force=force)
+    b = lattice(nx, ny, phi, prec, bc, fused=True, rows=rows, drag=beta, force=force)
+    assert b.fused_tiling()["active"] and not a.fused_tiling()["active"]
+    a.set_populations(f0)
+    b.set_populations(f0)
+    for n in (2, 5, 4):
+        a.step(n)
+        b.step(n)
+    rel = fused_rel_diff(a.read_populations().cpu().numpy(), b.read_populations().cpu().numpy(), f0n)
+    _say(f"  after {a.t} steps: relative difference {rel:.3e}")
+    bound = {"f32s": FUSED_RTOL, "f16s": 2e-3, "f64": FUSED_RTOL64}[prec]
+    assert rel <= bound
+
+
+def test_fused_force_field_fp64_vs_oracle(oracle):
+    """FP64, two steps per launch, a per-node force field on a walled channel
+    against the FP64 oracle at rel-L2(u) <= 1e-12."""
+    _torch()
+    n, steps = 72, 400
+    phi = W.channel_phi(n, n, seed=6)
+    force = (2e-6 * W.smoothed_noise(n, n, 3.0, seed=3), 1e-6 * W.smoothed_noise(n, n, 3.0, seed=4))
+    g = (1e-6, 0)
+    ora = oracle.Oracle(n, n, phi, kappa=0.5, rates=RATES, g=g, bc_y="wall",
+                        force=force).init_equilibrium()
+    ora.step(steps)
+    ref = ora.macroscopic()
+    lat = lattice(n, n, phi, "f64", "wall", fused=True, g=g, force=force)
+    assert lat.fused_tiling()["active"]
+    lat.init_equilibrium(1.0).step(steps)
+    m = {k: v.cpu().numpy() for k, v in lat.read_moments().items()}
+    err = rel_l2_u(m, ref)
+    _say(f"f64 two steps per launch with a force field: rel-L2(u) vs oracle {err:.3e}")
     assert err <= 1e-12
