@@ -257,11 +257,12 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
   }
 }
 
-// Two-step launches of the plain step with the force field and the linear
-// drag or without, no other optional input or scheme variant.  Halves of 256 lanes in FP32 arithmetic
-// and of 128 in FP64 (whose LDS rings take twice the bytes per lane); each
-// outputs its half's width less 10 columns.  Rows per workgroup default to
-// one full round of resident workgroups (two per CU in either precision).
+// Two-step launches of the plain step with or without the force field and
+// the linear drag (no other optional input or scheme variant).  Halves of
+// 256 lanes in FP32 arithmetic and of 128 in FP64 (whose LDS rings take
+// twice the bytes per lane); each outputs its half's width less 10 columns.
+// Rows per workgroup default to one full round of resident workgroups (two
+// per CU in either precision).
 template <typename T>
 constexpr int fused_nt() { return sizeof(T) == 8 ? 128 : 256; }
 int fused_out_w(const vanse_lattice* h) { return (h->d.precision == VANSE_F64 ? 128 : 256) - 10; }
@@ -285,46 +286,44 @@ int fused_rows(const vanse_lattice* h) {
 template <typename S, typename T, bool SHIFT>
 int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
   constexpr int NT = fused_nt<T>();
-  {
-    const StepPhys<T> ph = make_phys<T>(h);
-    StepGeom g{};
-    g.phi = h->ws + h->L.phi;
-    g.phin = g.phi;
-    g.plane = h->L.plane;
-    g.nx = h->d.nx;
-    g.ny = h->d.ny;
-    g.pitch = h->L.pitch;
-    g.out_w = NT - 10;
-    g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
-    g.rows = fused_rows(h);
-    const int feat = feat_of(h);
-    g.beta = (feat & FEAT_DRAG) ? h->ws + h->L.beta : nullptr;
-    g.fxf = (feat & FEAT_FORCE) ? h->ws + h->L.fx : nullptr;
-    g.fyf = (feat & FEAT_FORCE) ? h->ws + h->L.fy : nullptr;
-    const int blocks = g.strips * ((h->d.ny + g.rows - 1) / g.rows);
-    const bool walls = h->d.bc_y == VANSE_WALL;
-    for (int64_t s = 0; s < pairs; ++s) {
-      g.src = h->ws + h->L.pop[h->cur];
-      g.dst = h->ws + h->L.pop[h->cur ^ 1];
-      auto go = [&](auto walls_c, auto feat_c) {
-        launch_step2_nt<S, T, SHIFT, decltype(walls_c)::value, decltype(feat_c)::value, NT>(g, ph, blocks, st);
-      };
-      auto with_walls = [&](auto feat_c) {
-        if (walls) go(std::true_type{}, feat_c);
-        else go(std::false_type{}, feat_c);
-      };
-      switch (feat) {
-        case FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_DRAG>{}); break;
-        case FEAT_FORCE: with_walls(std::integral_constant<int, FEAT_FORCE>{}); break;
-        case FEAT_FORCE | FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_FORCE | FEAT_DRAG>{}); break;
-        default: with_walls(std::integral_constant<int, 0>{});
-      }
-      h->cur ^= 1;
-      h->t += 2;
-      if (s == 0) HIP_TRY(hipGetLastError());
+  const StepPhys<T> ph = make_phys<T>(h);
+  StepGeom g{};
+  g.phi = h->ws + h->L.phi;
+  g.phin = g.phi;
+  g.plane = h->L.plane;
+  g.nx = h->d.nx;
+  g.ny = h->d.ny;
+  g.pitch = h->L.pitch;
+  g.out_w = NT - 10;
+  g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
+  g.rows = fused_rows(h);
+  const int feat = feat_of(h);
+  g.beta = (feat & FEAT_DRAG) ? h->ws + h->L.beta : nullptr;
+  g.fxf = (feat & FEAT_FORCE) ? h->ws + h->L.fx : nullptr;
+  g.fyf = (feat & FEAT_FORCE) ? h->ws + h->L.fy : nullptr;
+  const int blocks = g.strips * ((h->d.ny + g.rows - 1) / g.rows);
+  const bool walls = h->d.bc_y == VANSE_WALL;
+  for (int64_t s = 0; s < pairs; ++s) {
+    g.src = h->ws + h->L.pop[h->cur];
+    g.dst = h->ws + h->L.pop[h->cur ^ 1];
+    auto go = [&](auto walls_c, auto feat_c) {
+      launch_step2_nt<S, T, SHIFT, decltype(walls_c)::value, decltype(feat_c)::value, NT>(g, ph, blocks, st);
+    };
+    auto with_walls = [&](auto feat_c) {
+      if (walls) go(std::true_type{}, feat_c);
+      else go(std::false_type{}, feat_c);
+    };
+    switch (feat) {
+      case FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_DRAG>{}); break;
+      case FEAT_FORCE: with_walls(std::integral_constant<int, FEAT_FORCE>{}); break;
+      case FEAT_FORCE | FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_FORCE | FEAT_DRAG>{}); break;
+      default: with_walls(std::integral_constant<int, 0>{});
     }
-    return VANSE_OK;
+    h->cur ^= 1;
+    h->t += 2;
+    if (s == 0) HIP_TRY(hipGetLastError());
   }
+  return VANSE_OK;
 }
 
 template <typename S, typename T, bool SHIFT>
