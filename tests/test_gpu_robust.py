@@ -9,6 +9,8 @@
   from run to run, so two runs must agree bitwise.
 * Independence: lattices and batches stepped concurrently on several
   streams give the results of stepping them one after the other.
+* Checkpoint and resume: populations read out and set again continue
+  bitwise; a non-finite node is reported as divergence.
 """
 import sys
 
@@ -191,3 +193,40 @@ def test_concurrent_streams_match_sequential():
     for x, y in zip([a0, b0] + c0, [a1, b1] + c1):
         assert x.t == y.t == 30
         assert torch.equal(x.read_populations(), y.read_populations())
+
+
+@pytest.mark.parametrize("precision,spp", [("f64", 1), ("f64", 2), ("f32", 1), ("f32s", 2),
+                                           ("f16s", 1), ("f16s", 2)])
+def test_checkpoint_resume_is_bitwise(precision, spp):
+    """Populations read out (FP64 f) and set again continue bitwise as if the
+    run had never stopped: the stored format decodes to f and encodes back
+    exactly (FP64 sums of a stored value and the rest state are exact)."""
+    torch = _torch()
+    nx, ny = 300, 70
+    a = lattice(nx, ny, precision, "wall", drag=True)
+    a.set_steps_per_pass(spp).init_equilibrium(1.0, 2e-3, 0.0)
+    a.step(7)
+    ck = a.read_populations().cpu().numpy()
+    a.step(10)
+    b = lattice(nx, ny, precision, "wall", drag=True)
+    b.set_steps_per_pass(spp).set_populations(ck)
+    assert torch.equal(b.read_populations(), torch.from_numpy(ck).to(b.read_populations().device))
+    b.step(10)
+    assert torch.equal(a.read_populations(), b.read_populations())
+
+
+def test_non_finite_state_is_reported():
+    """A non-finite population is counted by the FP64 observables and raised
+    as divergence; it spreads to the node's neighbours with the stream."""
+    _torch()
+    from paper_2409_02964_amd.vanse import Diverged
+    lat = lattice(64, 48, "f32s", "periodic")
+    f = start_state(lat, 5)
+    f[3, 20, 30] = np.inf
+    lat.set_populations(f).step(3)
+    o = lat.observe(raise_on_diverged=False)
+    assert o["nonfinite"] >= 1
+    with pytest.raises(Diverged):
+        lat.observe()
+    with pytest.raises(Diverged):  # the residual reports it too
+        lat.residual()
