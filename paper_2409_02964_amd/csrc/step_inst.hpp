@@ -3,7 +3,8 @@
 // VANSE_S (storage type), VANSE_T (arithmetic type) and VANSE_SHIFT.
 //
 // Instances: workgroup widths 64, 128 and 256 for every feature variant the
-// host selects (plain, force field, drag, both, FEAT_ALL), 512 for the plain
+// host selects (plain, force field, drag, both, a moving phi with both,
+// FEAT_ALL), 512 for the plain
 // step; the batched kernel for the first four; the two-step kernel of the
 // first four with halves of VANSE_FUSED2_NT lanes
 // (256 in FP32 arithmetic, 128 in FP64, whose rings take twice the LDS), and
@@ -50,6 +51,7 @@ VANSE_WALLS(VANSE_STEP_ONE, 0)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_FORCE)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_FORCE | FEAT_DRAG)
+VANSE_WALLS(VANSE_STEP_ONE, FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_ALL)
 VANSE_STEP_ONE(false, 0, 512)
 VANSE_STEP_ONE(true, 0, 512)

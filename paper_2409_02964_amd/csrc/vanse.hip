@@ -234,15 +234,21 @@ int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& 
   return VANSE_OK;
 }
 
-// Specialised step variants for the force field and the drag; masks, a
-// time-varying void fraction and the scheme variants (and any combination
+// Specialised step variants: the force field and the drag; a time-varying
+// void fraction with either or both (one instance, FEAT_MOVING, whose absent
+// planes read as zero); masks and the scheme variants (and any combination
 // with them) use FEAT_ALL.
+constexpr int FEAT_MOVING = FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG;
 int feat_of(const vanse_lattice* h) {
   const vanse_desc& d = h->d;
-  if (d.has_mask || d.dynamic_phi || h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0)
-    return FEAT_ALL;
+  if (d.has_mask || h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0) return FEAT_ALL;
+  if (d.dynamic_phi) return FEAT_MOVING;
   return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0);
 }
+
+// Variants batches take: the force field and the drag (no mask, moving phi or
+// scheme variant)
+bool batch_feat(int feat) { return (feat & ~(FEAT_FORCE | FEAT_DRAG)) == 0; }
 
 // Call fn(std::integral_constant<bool, WALLS>, std::integral_constant<int, FEAT>).
 template <typename Fn>
@@ -250,6 +256,7 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
   const bool walls = h->d.bc_y == VANSE_WALL;
   switch (feat_of(h)) {
     case FEAT_ALL: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_ALL>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_ALL>{});
+    case FEAT_MOVING: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MOVING>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MOVING>{});
     case 0: return walls ? fn(std::true_type{}, std::integral_constant<int, 0>{}) : fn(std::false_type{}, std::integral_constant<int, 0>{});
     case 1: return walls ? fn(std::true_type{}, std::integral_constant<int, 1>{}) : fn(std::false_type{}, std::integral_constant<int, 1>{});
     case 2: return walls ? fn(std::true_type{}, std::integral_constant<int, 2>{}) : fn(std::false_type{}, std::integral_constant<int, 2>{});
@@ -269,7 +276,7 @@ int fused_out_w(const vanse_lattice* h) { return (h->d.precision == VANSE_F64 ? 
 
 // Variants the two-step kernel is built for: the plain step with or without
 // the force field and the linear drag (no mask, moving phi or scheme variant)
-bool fused_feat(const vanse_lattice* h) { return (feat_of(h) & ~(FEAT_FORCE | FEAT_DRAG)) == 0; }
+bool fused_feat(const vanse_lattice* h) { return batch_feat(feat_of(h)); }
 
 bool fused_ok(const vanse_lattice* h) { return h->fuse == 2 && fused_feat(h); }
 
@@ -899,7 +906,7 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
   for (int k = 0; k < n; ++k) {
     if (!lats[k]) return fail(VANSE_ERR_INVALID_ARG, "lattice %d is NULL", k);
     const vanse_desc& d = lats[k]->d;
-    if (feat_of(lats[k]) == FEAT_ALL)
+    if (!batch_feat(feat_of(lats[k])))
       return fail(VANSE_ERR_UNSUPPORTED,
                   "lattice %d: batches take lattices without mask, time-varying phi or scheme variant", k);
     if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field ||
@@ -1027,7 +1034,7 @@ int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
     using T = std::remove_pointer_t<decltype(t_tag)>;
     constexpr bool SH = decltype(shift)::value;
     return by_variant(b->lats[0], [&](auto walls, auto feat) -> int {
-      if constexpr (decltype(feat)::value == FEAT_ALL) {
+      if constexpr (!((decltype(feat)::value & ~(FEAT_FORCE | FEAT_DRAG)) == 0)) {
         return fail(VANSE_ERR_UNSUPPORTED, "batches take lattices without mask, time-varying phi or scheme variant");
       } else {
         batch_launch_t<S, T, SH, decltype(walls)::value, decltype(feat)::value>(b, launch, st);
@@ -1124,7 +1131,7 @@ int vanse_batch_step(vanse_batch* b, int64_t nsteps, void* stream) {
   for (vanse_lattice* h : b->lats) {
     if (int rc = check_ready(h)) return rc;
     if (!h->state_set) return fail(VANSE_ERR_STATE, "a lattice of the batch has no populations");
-    if (feat_of(h) == FEAT_ALL) return fail(VANSE_ERR_UNSUPPORTED, "a lattice of the batch uses a variant batches do not take");
+    if (!batch_feat(feat_of(h))) return fail(VANSE_ERR_UNSUPPORTED, "a lattice of the batch uses a variant batches do not take");
   }
   if (nsteps == 0) return VANSE_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -33,16 +33,19 @@ def _say(msg):
 
 
 def lattice(nx, ny, phi, precision="f64", bc_y="periodic", mask=None, dynamic=False,
-            force=None, g=(0.0, 0.0), scale_by_phi=True, kappa=0.5, rates=C1_RATES, tiling=None):
+            force=None, g=(0.0, 0.0), scale_by_phi=True, kappa=0.5, rates=C1_RATES, tiling=None,
+            drag=None):
     from paper_2409_02964_amd.vanse import Lattice
     lat = Lattice(nx, ny, precision=precision, bc_y=bc_y, mask=mask is not None,
-                  dynamic_phi=dynamic, force_field=force is not None)
+                  dynamic_phi=dynamic, force_field=force is not None, drag=drag is not None)
     lat.set_params(kappa, rates).set_body_force(g[0], g[1], scale_by_phi)
     if mask is not None:
         lat.set_mask(mask)
     lat.set_void_fraction(phi)
     if force is not None:
         lat.set_force_field(force[0], force[1])
+    if drag is not None:
+        lat.set_drag(drag[0], drag[1])
     if tiling:
         lat.set_tiling(*tiling)
     return lat
@@ -192,21 +195,29 @@ def test_mask_errors():
 
 # ---- time-varying void fraction ----------------------------------------------------
 
-@pytest.mark.parametrize("nx,ny,bc,with_mask", [(48, 40, "periodic", False),
-                                                (61, 37, "wall", False),
-                                                (64, 32, "wall", True)])
-def test_one_step_dynamic_phi_fp64(oracle, nx, ny, bc, with_mask):
+@pytest.mark.parametrize("nx,ny,bc,with_mask,coupled", [(48, 40, "periodic", False, False),
+                                                        (61, 37, "wall", False, False),
+                                                        (64, 32, "wall", True, False),
+                                                        (61, 37, "wall", False, True),
+                                                        (50, 44, "periodic", False, True)])
+def test_one_step_dynamic_phi_fp64(oracle, nx, ny, bc, with_mask, coupled):
+    """A moving void fraction (with a force field and a drag when coupled, as
+    for particles: the kernel instance for a moving phi reads absent force
+    and drag planes as zero) against the oracle."""
     torch = _torch()
-    _say(f"one-step dynamic phi fp64 {nx}x{ny} {bc} mask={with_mask}")
+    _say(f"one-step dynamic phi fp64 {nx}x{ny} {bc} mask={with_mask} coupled={coupled}")
     phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 3.0, seed=21) ** 2
     phin = np.clip(phi + 0.02 * W.smoothed_noise(nx, ny, 3.0, seed=22), 0.3, 1.0)
     mask = W.solid_mask(nx, ny, seed=5) if with_mask else None
     fluid = np.ones((ny, nx), bool) if mask is None else mask == 0
     f0 = W.random_populations(nx, ny, seed=9)
-    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=(1e-5, 0), bc_y=bc, mask=mask)
+    force = (2e-6 * W.smoothed_noise(nx, ny, 3.0, seed=23), -1e-6 * W.smoothed_noise(nx, ny, 3.0, seed=24)) if coupled else None
+    drag = (1e-3 + 2e-2 * (1 - phi), (3e-4, -1e-4)) if coupled else None
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=(1e-5, 0), bc_y=bc, mask=mask,
+                        force=force, drag=drag)
     ora.set_populations(f0)
     ora.step(1, phi_next=phin)
-    lat = lattice(nx, ny, phi, "f64", bc, mask=mask, dynamic=True, g=(1e-5, 0))
+    lat = lattice(nx, ny, phi, "f64", bc, mask=mask, dynamic=True, g=(1e-5, 0), force=force, drag=drag)
     lat.set_populations(torch.from_numpy(f0))
     lat.set_void_fraction_next(phin)
     lat.step(1)
