@@ -658,9 +658,10 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
 
 // One lattice per launch: workgroup b takes tile xcd_tile(b) (strip
 // tile % strips, row block tile / strips).  WPE: minimum waves per SIMD the register allocation allows
-// (three for the FP32 FEAT_ALL kernel, whose extra state would spill at four).
+// (three for the FP32 kernels with solid nodes and further inputs, whose
+// extra state would spill at four).
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT, int PD = 1,
-          int WPE = (sizeof(T) == 4 ? (FEAT == FEAT_ALL ? 3 : 4) : 2)>
+          int WPE = (sizeof(T) == 4 ? (((FEAT & FEAT_MASK) && FEAT != FEAT_MASK) ? 3 : 4) : 2)>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(WPE)))
 vanse_step_kernel(StepGeom g, StepPhys<T> ph) {

@@ -236,12 +236,14 @@ int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& 
 
 // Specialised step variants: the force field and the drag; a time-varying
 // void fraction with either or both (one instance, FEAT_MOVING, whose absent
-// planes read as zero); masks and the scheme variants (and any combination
-// with them) use FEAT_ALL.
+// planes read as zero); solid nodes alone (FEAT_MASK); solid nodes with any
+// of those (FEAT_MASK | FEAT_MOVING).  The scheme variants use FEAT_ALL.
 constexpr int FEAT_MOVING = FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG;
 int feat_of(const vanse_lattice* h) {
   const vanse_desc& d = h->d;
-  if (d.has_mask || h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0) return FEAT_ALL;
+  if (h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0) return FEAT_ALL;
+  if (d.has_mask)
+    return (d.dynamic_phi || d.has_force_field || d.has_drag) ? (FEAT_MASK | FEAT_MOVING) : FEAT_MASK;
   if (d.dynamic_phi) return FEAT_MOVING;
   return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0);
 }
@@ -256,6 +258,8 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
   const bool walls = h->d.bc_y == VANSE_WALL;
   switch (feat_of(h)) {
     case FEAT_ALL: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_ALL>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_ALL>{});
+    case FEAT_MASK | FEAT_MOVING: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MASK | FEAT_MOVING>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MASK | FEAT_MOVING>{});
+    case FEAT_MASK: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MASK>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MASK>{});
     case FEAT_MOVING: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MOVING>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MOVING>{});
     case 0: return walls ? fn(std::true_type{}, std::integral_constant<int, 0>{}) : fn(std::false_type{}, std::integral_constant<int, 0>{});
     case 1: return walls ? fn(std::true_type{}, std::integral_constant<int, 1>{}) : fn(std::false_type{}, std::integral_constant<int, 1>{});

@@ -199,7 +199,8 @@ def test_mask_errors():
                                                         (61, 37, "wall", False, False),
                                                         (64, 32, "wall", True, False),
                                                         (61, 37, "wall", False, True),
-                                                        (50, 44, "periodic", False, True)])
+                                                        (50, 44, "periodic", False, True),
+                                                        (64, 32, "wall", True, True)])
 def test_one_step_dynamic_phi_fp64(oracle, nx, ny, bc, with_mask, coupled):
     """A moving void fraction (with a force field and a drag when coupled, as
     for particles: the kernel instance for a moving phi reads absent force
