@@ -4,7 +4,8 @@
 //
 // Instances: workgroup widths 64, 128 and 256 for every feature variant the
 // host selects (plain, force field, drag, both, a moving phi with both,
-// solid nodes alone or with all of those, FEAT_ALL), 512 for the plain
+// solid nodes alone or with all of those, the scheme variants with all of
+// those, FEAT_ALL), 512 for the plain
 // step; the batched kernel for the first four; the two-step kernel of the
 // first four with halves of VANSE_FUSED2_NT lanes
 // (256 in FP32 arithmetic, 128 in FP64, whose rings take twice the LDS), and
@@ -54,6 +55,7 @@ VANSE_WALLS(VANSE_STEP_ONE, FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_MASK)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_MASK | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
+VANSE_WALLS(VANSE_STEP_ONE, FEAT_SCHEME | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_ALL)
 VANSE_STEP_ONE(false, 0, 512)
 VANSE_STEP_ONE(true, 0, 512)

@@ -237,13 +237,18 @@ int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& 
 // Specialised step variants: the force field and the drag; a time-varying
 // void fraction with either or both (one instance, FEAT_MOVING, whose absent
 // planes read as zero); solid nodes alone (FEAT_MASK); solid nodes with any
-// of those (FEAT_MASK | FEAT_MOVING).  The scheme variants use FEAT_ALL.
+// of those (FEAT_MASK | FEAT_MOVING); the scheme variants with any of those
+// (FEAT_SCHEME | FEAT_MOVING).  Scheme variants with solid nodes use
+// FEAT_ALL.
 constexpr int FEAT_MOVING = FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG;
 int feat_of(const vanse_lattice* h) {
   const vanse_desc& d = h->d;
-  if (h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0) return FEAT_ALL;
-  if (d.has_mask)
+  const bool scheme = h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0;
+  if (d.has_mask) {
+    if (scheme) return FEAT_ALL;
     return (d.dynamic_phi || d.has_force_field || d.has_drag) ? (FEAT_MASK | FEAT_MOVING) : FEAT_MASK;
+  }
+  if (scheme) return FEAT_SCHEME | FEAT_MOVING;
   if (d.dynamic_phi) return FEAT_MOVING;
   return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0);
 }
@@ -258,6 +263,7 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
   const bool walls = h->d.bc_y == VANSE_WALL;
   switch (feat_of(h)) {
     case FEAT_ALL: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_ALL>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_ALL>{});
+    case FEAT_SCHEME | FEAT_MOVING: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_SCHEME | FEAT_MOVING>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_SCHEME | FEAT_MOVING>{});
     case FEAT_MASK | FEAT_MOVING: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MASK | FEAT_MOVING>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MASK | FEAT_MOVING>{});
     case FEAT_MASK: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MASK>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MASK>{});
     case FEAT_MOVING: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MOVING>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MOVING>{});
