@@ -6,7 +6,8 @@
 // host selects (plain, force field, drag, both, a moving phi with both,
 // solid nodes alone or with all of those, the scheme variants with all of
 // those, FEAT_ALL), 512 for the plain
-// step; the batched kernel for the first four; the two-step kernel of the
+// step; the batched kernel for all but the last two (a moving phi is not
+// batched); the two-step kernel of the
 // first four with halves of VANSE_FUSED2_NT lanes
 // (256 in FP32 arithmetic, 128 in FP64, whose rings take twice the LDS), and
 // its batched form with halves of 64 lanes up to VANSE_FUSED2_BATCH_MAX.
@@ -64,6 +65,9 @@ VANSE_WALLS(VANSE_BATCH_ONE, 0)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_DRAG)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE | FEAT_DRAG)
+VANSE_WALLS(VANSE_BATCH_ONE, FEAT_MASK)
+VANSE_WALLS(VANSE_BATCH_ONE, FEAT_MASK | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
+VANSE_WALLS(VANSE_BATCH_ONE, FEAT_SCHEME | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
 
 // two steps per pass
 #define VANSE_STEP2_ONE(W, F) \

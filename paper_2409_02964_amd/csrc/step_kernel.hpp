@@ -683,7 +683,7 @@ struct BatchEntry {
 };
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT,
-          int WPE = (sizeof(T) == 4 ? 4 : 2)>
+          int WPE = (sizeof(T) == 4 ? (((FEAT & FEAT_MASK) && FEAT != FEAT_MASK) ? 3 : 4) : 2)>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(WPE)))
 vanse_batch_step_kernel(const BatchEntry<T>* __restrict__ entries,
@@ -699,7 +699,10 @@ vanse_batch_step_kernel(const BatchEntry<T>* __restrict__ entries,
   g.src = par ? b1 : b0;
   g.dst = par ? b0 : b1;
   const int local = tile - e.first_tile;
-  step_tile<S, T, SHIFT, WALLS, FEAT, NT, 1>(g, e.ph, local % g.strips, local / g.strips, lds);
+  // a private copy, as the one-lattice kernel's argument (read through the
+  // table the parameters could alias the stores as far as the compiler knows)
+  const StepPhys<T> ph = e.ph;
+  step_tile<S, T, SHIFT, WALLS, FEAT, NT, 1>(g, ph, local % g.strips, local / g.strips, lds);
 }
 
 }  // namespace vanse_dev

@@ -253,9 +253,12 @@ int feat_of(const vanse_lattice* h) {
   return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0);
 }
 
-// Variants batches take: the force field and the drag (no mask, moving phi or
-// scheme variant)
+// Variants the two-step kernel takes: the force field and the drag
 bool batch_feat(int feat) { return (feat & ~(FEAT_FORCE | FEAT_DRAG)) == 0; }
+
+// Lattices batches take: any variant with an instance of its own (not
+// FEAT_ALL) and no moving phi (its phi(t+1) is given step by step)
+bool batch_ok(const vanse_lattice* h) { return !h->d.dynamic_phi && feat_of(h) != FEAT_ALL; }
 
 // Call fn(std::integral_constant<bool, WALLS>, std::integral_constant<int, FEAT>).
 template <typename Fn>
@@ -916,12 +919,13 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
   for (int k = 0; k < n; ++k) {
     if (!lats[k]) return fail(VANSE_ERR_INVALID_ARG, "lattice %d is NULL", k);
     const vanse_desc& d = lats[k]->d;
-    if (!batch_feat(feat_of(lats[k])))
+    if (!batch_ok(lats[k]))
       return fail(VANSE_ERR_UNSUPPORTED,
-                  "lattice %d: batches take lattices without mask, time-varying phi or scheme variant", k);
+                  "lattice %d: batches take no time-varying phi, nor a scheme variant with solid nodes", k);
     if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field ||
-        d.has_drag != d0.has_drag)
-      return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in precision, boundary, force field or drag", k);
+        d.has_drag != d0.has_drag || feat_of(lats[k]) != feat_of(lats[0]))
+      return fail(VANSE_ERR_INVALID_ARG,
+                  "lattice %d differs in precision, boundary, force field, drag, mask or scheme variant", k);
     if (fuse == 2 && !fused_feat(lats[k]))
       return fail(VANSE_ERR_UNSUPPORTED,
                   "lattice %d: two steps per launch take the force field and the drag only", k);
@@ -969,7 +973,7 @@ void fill_entries(vanse_batch* b, std::vector<char>* blob) {
     g.dst = h->ws + h->L.pop[1];
     g.phi = h->ws + h->L.phi;
     g.phin = g.phi;
-    g.nbr = nullptr;
+    g.nbr = h->d.has_mask ? h->ws + h->L.nbr : nullptr;
     g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
     g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
     g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
@@ -1044,8 +1048,8 @@ int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
     using T = std::remove_pointer_t<decltype(t_tag)>;
     constexpr bool SH = decltype(shift)::value;
     return by_variant(b->lats[0], [&](auto walls, auto feat) -> int {
-      if constexpr (!((decltype(feat)::value & ~(FEAT_FORCE | FEAT_DRAG)) == 0)) {
-        return fail(VANSE_ERR_UNSUPPORTED, "batches take lattices without mask, time-varying phi or scheme variant");
+      if constexpr (decltype(feat)::value == FEAT_ALL || decltype(feat)::value == FEAT_MOVING) {
+        return fail(VANSE_ERR_UNSUPPORTED, "batches take no time-varying phi, nor a scheme variant with solid nodes");
       } else {
         batch_launch_t<S, T, SH, decltype(walls)::value, decltype(feat)::value>(b, launch, st);
         return VANSE_OK;
@@ -1141,7 +1145,7 @@ int vanse_batch_step(vanse_batch* b, int64_t nsteps, void* stream) {
   for (vanse_lattice* h : b->lats) {
     if (int rc = check_ready(h)) return rc;
     if (!h->state_set) return fail(VANSE_ERR_STATE, "a lattice of the batch has no populations");
-    if (!batch_feat(feat_of(h))) return fail(VANSE_ERR_UNSUPPORTED, "a lattice of the batch uses a variant batches do not take");
+    if (!batch_ok(h)) return fail(VANSE_ERR_UNSUPPORTED, "a lattice of the batch uses a variant batches do not take");
   }
   if (nsteps == 0) return VANSE_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);

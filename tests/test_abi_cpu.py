@@ -147,13 +147,17 @@ def test_feature_state_checks_on_the_host():
     assert L.vanse_destroy(h) == 0 and L.vanse_destroy(plain) == 0
 
 
-@pytest.mark.parametrize("mask,dynamic", [(1, 0), (0, 1)])
-def test_batches_reject_masks_and_moving_phi(mask, dynamic):
+@pytest.mark.parametrize("first,second,code", [
+    (dict(), dict(mask=1), -1),               # members differ in their variant
+    (dict(), dict(dynamic=1), -6),            # a moving phi is not batched
+    (dict(dynamic=1), dict(dynamic=1), -6),
+    (dict(mask=1), dict(mask=1), 0)])         # solid nodes are
+def test_batch_variant_rules(first, second, code):
     L = V.lib()
-    hs = [_fake_handle(), _fake_handle(mask=mask, dynamic=dynamic)]
+    hs = [_fake_handle(**first), _fake_handle(**second)]
     arr = (C.c_void_p * 2)(hs[0].value, hs[1].value)
     n = C.c_size_t()
-    assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == -6
+    assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == code
     for h in hs:
         assert L.vanse_destroy(h) == 0
 
@@ -167,8 +171,12 @@ def test_scheme_validation_on_the_host():
     other = _fake_handle()
     arr = (C.c_void_p * 2)(other.value, h.value)
     n = C.c_size_t()
-    assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == -6  # variants are not batched
+    assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == -1  # members differ
+    assert L.vanse_set_scheme(other, 1, 2) == 0
+    assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == 0   # same variant
     assert L.vanse_set_scheme(h, 0, 3) == 0
+    assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == -1
+    assert L.vanse_set_scheme(other, 0, 3) == 0
     assert L.vanse_batch_workspace_bytes(arr, 2, 128, 0, C.byref(n)) == 0
     assert L.vanse_destroy(h) == 0 and L.vanse_destroy(other) == 0
 

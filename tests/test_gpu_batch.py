@@ -226,3 +226,41 @@ def test_two_step_batch_with_force_field(precision, threads):
     for a, r in zip(mem, ref):
         assert np.array_equal(a.read_populations().cpu().numpy(),
                               r.read_populations().cpu().numpy())
+
+
+@pytest.mark.parametrize("variant,precision", [("mask", "f32s"), ("mask", "f64"), ("mask_drag", "f16s"),
+                                               ("model_b", "f32s"), ("moving_walls_drag", "f64")])
+def test_batch_masks_and_scheme_variants(variant, precision):
+    """Members with solid nodes or a scheme variant (model B, moving walls):
+    bitwise the results of stepping each member alone."""
+    _torch()
+    from paper_2409_02964_amd import workloads as W
+    from paper_2409_02964_amd.vanse import Batch, Lattice
+    sizes = [(64, 48), (37, 53), (130, 20), (90, 31)]
+
+    def member(k, nx, ny):
+        mask = variant.startswith("mask")
+        drag = variant.endswith("drag")
+        lat = Lattice(nx, ny, precision=precision, bc_y="wall", mask=mask, drag=drag)
+        phi = 0.6 + 0.3 * np.sin(2 * np.pi * np.arange(nx)[None, :] / nx) * np.cos(2 * np.pi * np.arange(ny)[:, None] / ny)
+        lat.set_params(0.5, RATES).set_body_force(1e-6 * (k + 1), 0.0)
+        if mask:
+            lat.set_mask(W.solid_mask(nx, ny, seed=k))
+        if variant == "model_b":
+            lat.set_scheme("B", 3)
+        if variant.startswith("moving_walls"):
+            lat.set_wall_velocity(-1e-3 * k, 2e-3)
+        lat.set_void_fraction(phi)
+        if drag:
+            lat.set_drag(1e-3 + 2e-2 * (1 - phi))
+        return lat.init_equilibrium(1.0, 1e-3, 0.0)
+
+    ref = [member(k, nx, ny) for k, (nx, ny) in enumerate(sizes)]
+    for lat in ref:
+        lat.step(11)
+    mem = [member(k, nx, ny) for k, (nx, ny) in enumerate(sizes)]
+    Batch(mem, threads=128, rows=7, graph_steps=0).step(11)
+    for a, r in zip(mem, ref):
+        assert a.t == r.t == 11
+        assert np.array_equal(a.read_populations().cpu().numpy(),
+                              r.read_populations().cpu().numpy())
