@@ -380,6 +380,78 @@ def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
     print(json.dumps(rec))
 
 
+# Kernel variants timed by --variants: (name, storage, steps per launch, options)
+VARIANTS = [
+    ("plain", "f32s", 1, {}),
+    ("plain", "f32s", 2, {}),
+    ("plain", "f16s", 1, {}),
+    ("plain", "f16s", 2, {}),
+    ("plain", "f64", 1, {}),
+    ("plain", "f64", 2, {}),
+    ("force field", "f32s", 1, {"force": True}),
+    ("force field", "f32s", 2, {"force": True}),
+    ("drag", "f32s", 2, {"drag": True}),
+    ("moving phi, force field, drag", "f32s", 1, {"dynamic": True, "force": True, "drag": True}),
+    ("solid nodes", "f32s", 1, {"mask": True}),
+    ("solid nodes", "f64", 1, {"mask": True}),
+    ("solid nodes, force field, drag", "f32s", 1, {"mask": True, "force": True, "drag": True}),
+    ("model B", "f32s", 1, {"model_b": True}),
+    ("moving walls, drag", "f32s", 1, {"wall_u": 1e-3, "drag": True}),
+    ("model B, solid nodes", "f32s", 1, {"model_b": True, "mask": True}),
+]
+
+
+def variants_bench(steps: int):
+    """Every kernel variant on the 4096 x 4096 benchmark channel: `steps`
+    steps each (after 4 untimed), timed with HIP events on the launch stream;
+    prints one JSON line per variant and a markdown table."""
+    import numpy as np
+    import torch
+    from paper_2409_02964_amd import workloads as W
+    from paper_2409_02964_amd.vanse import Lattice
+    phi = W.channel_phi(NX, NY, seed=2409)
+    mask = W.solid_mask(NX, NY, seed=5)
+    fx = 1e-7 * W.smoothed_noise(NX, NY, 8.0, seed=1)
+    beta = 1e-3 + 1e-2 * (1 - phi)
+    rows = []
+    for name, prec, spp, o in VARIANTS:
+        lat = Lattice(NX, NY, precision=prec, bc_y="wall", mask=o.get("mask", False),
+                      dynamic_phi=o.get("dynamic", False), force_field=o.get("force", False),
+                      drag=o.get("drag", False))
+        lat.set_params(KAPPA, RATES).set_body_force(G, 0.0, True)
+        if o.get("mask"):
+            lat.set_mask(mask)
+        if o.get("model_b"):
+            lat.set_scheme("B", 3)
+        if o.get("wall_u"):
+            lat.set_wall_velocity(0.0, o["wall_u"])
+        lat.set_void_fraction(phi)
+        if o.get("force"):
+            lat.set_force_field(fx, np.zeros_like(fx))
+        if o.get("drag"):
+            lat.set_drag(beta)
+        lat.set_steps_per_pass(spp).init_equilibrium(1.0)
+        stream = torch.cuda.current_stream()
+        lat.step(4, stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        lat.step(steps, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / steps * 1e3
+        rec = {"variant": name, "storage": prec, "steps_per_launch": spp,
+               "us_per_step": round(us, 1), "glups": round(NX * NY / us / 1e3, 1)}
+        print(json.dumps(rec), flush=True)
+        rows.append(rec)
+        lat.close()
+    print("| variant | storage | steps/launch | µs per step | GLUPS |")
+    print("|---|---|---|---|---|")
+    for r in rows:
+        print(f"| {r['variant']} | {r['storage']} | {r['steps_per_launch']} | {r['us_per_step']} | {r['glups']} |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -411,7 +483,12 @@ def main():
     ap.add_argument("--precision-ladder", type=int, metavar="N", default=0,
                     help="run the precision ladder on an N x N channel and write profiles/")
     ap.add_argument("--ladder-steps", type=int, default=5000)
+    ap.add_argument("--variants", type=int, metavar="STEPS", default=0,
+                    help="time every kernel variant on the benchmark channel (STEPS steps each)")
     args = ap.parse_args()
+    if args.variants:
+        variants_bench(args.variants)
+        return
     if args.precision_ladder:
         n = args.precision_ladder
         precision_ladder(n, args.ladder_steps,
