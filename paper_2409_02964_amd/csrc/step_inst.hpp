@@ -55,6 +55,7 @@ VANSE_WALLS(VANSE_STEP_ONE, FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_MASK)
+VANSE_WALLS(VANSE_STEP_ONE, FEAT_MASK | FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_MASK | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_SCHEME | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_STEP_ONE, FEAT_ALL)
@@ -66,6 +67,7 @@ VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_DRAG)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_MASK)
+VANSE_WALLS(VANSE_BATCH_ONE, FEAT_MASK | FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_MASK | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
 VANSE_WALLS(VANSE_BATCH_ONE, FEAT_SCHEME | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
 

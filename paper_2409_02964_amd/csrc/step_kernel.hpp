@@ -658,10 +658,12 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
 
 // One lattice per launch: workgroup b takes tile xcd_tile(b) (strip
 // tile % strips, row block tile / strips).  WPE: minimum waves per SIMD the register allocation allows
-// (three for the FP32 kernels with solid nodes and further inputs, whose
-// extra state would spill at four).
+// (three for the FP32 kernels with solid nodes and a moving phi or scheme
+// variant, whose extra state would spill heavily at four; with solid nodes
+// alone or with the force field and drag a few registers spill at four,
+// which measures faster than three).
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT, int PD = 1,
-          int WPE = (sizeof(T) == 4 ? (((FEAT & FEAT_MASK) && FEAT != FEAT_MASK) ? 3 : 4) : 2)>
+          int WPE = (sizeof(T) == 4 ? (((FEAT & FEAT_MASK) && (FEAT & (FEAT_DYNPHI | FEAT_SCHEME))) ? 3 : 4) : 2)>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(WPE)))
 vanse_step_kernel(StepGeom g, StepPhys<T> ph) {
@@ -683,7 +685,7 @@ struct BatchEntry {
 };
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT,
-          int WPE = (sizeof(T) == 4 ? (((FEAT & FEAT_MASK) && FEAT != FEAT_MASK) ? 3 : 4) : 2)>
+          int WPE = (sizeof(T) == 4 ? (((FEAT & FEAT_MASK) && (FEAT & (FEAT_DYNPHI | FEAT_SCHEME))) ? 3 : 4) : 2)>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(WPE)))
 vanse_batch_step_kernel(const BatchEntry<T>* __restrict__ entries,

@@ -236,8 +236,9 @@ int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& 
 
 // Specialised step variants: the force field and the drag; a time-varying
 // void fraction with either or both (one instance, FEAT_MOVING, whose absent
-// planes read as zero); solid nodes alone (FEAT_MASK); solid nodes with any
-// of those (FEAT_MASK | FEAT_MOVING); the scheme variants with any of those
+// planes read as zero); solid nodes alone (FEAT_MASK), with the force field
+// or the drag (FEAT_MASK | FEAT_FORCE | FEAT_DRAG) or with a moving phi
+// (FEAT_MASK | FEAT_MOVING); the scheme variants with any of those
 // (FEAT_SCHEME | FEAT_MOVING).  Scheme variants with solid nodes use
 // FEAT_ALL.
 constexpr int FEAT_MOVING = FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG;
@@ -246,7 +247,8 @@ int feat_of(const vanse_lattice* h) {
   const bool scheme = h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0;
   if (d.has_mask) {
     if (scheme) return FEAT_ALL;
-    return (d.dynamic_phi || d.has_force_field || d.has_drag) ? (FEAT_MASK | FEAT_MOVING) : FEAT_MASK;
+    if (d.dynamic_phi) return FEAT_MASK | FEAT_MOVING;
+    return (d.has_force_field || d.has_drag) ? (FEAT_MASK | FEAT_FORCE | FEAT_DRAG) : FEAT_MASK;
   }
   if (scheme) return FEAT_SCHEME | FEAT_MOVING;
   if (d.dynamic_phi) return FEAT_MOVING;
@@ -268,6 +270,7 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
     case FEAT_ALL: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_ALL>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_ALL>{});
     case FEAT_SCHEME | FEAT_MOVING: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_SCHEME | FEAT_MOVING>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_SCHEME | FEAT_MOVING>{});
     case FEAT_MASK | FEAT_MOVING: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MASK | FEAT_MOVING>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MASK | FEAT_MOVING>{});
+    case FEAT_MASK | FEAT_FORCE | FEAT_DRAG: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MASK | FEAT_FORCE | FEAT_DRAG>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MASK | FEAT_FORCE | FEAT_DRAG>{});
     case FEAT_MASK: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MASK>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MASK>{});
     case FEAT_MOVING: return walls ? fn(std::true_type{}, std::integral_constant<int, FEAT_MOVING>{}) : fn(std::false_type{}, std::integral_constant<int, FEAT_MOVING>{});
     case 0: return walls ? fn(std::true_type{}, std::integral_constant<int, 0>{}) : fn(std::false_type{}, std::integral_constant<int, 0>{});

@@ -98,6 +98,33 @@ def test_one_step_mask_fp64(oracle, nx, ny, bc, tiling):
     assert np.all(fg[:, ~fluid] == 0.0)
 
 
+@pytest.mark.parametrize("nx,ny,bc,force,drag", [(61, 37, "wall", True, True), (50, 44, "periodic", True, False),
+                                                  (64, 32, "wall", False, True)])
+def test_one_step_mask_force_drag_fp64(oracle, nx, ny, bc, force, drag):
+    """Solid nodes with a force field and/or drag (their own kernel instance)
+    against the oracle."""
+    torch = _torch()
+    _say(f"one-step mask + force={force} drag={drag} fp64 {nx}x{ny} {bc}")
+    phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 2.0, seed=nx + 3 * ny) ** 2
+    mask = W.solid_mask(nx, ny, seed=nx + ny)
+    fluid = mask == 0
+    f0 = W.random_populations(nx, ny, seed=5 + nx)
+    g = (2e-5, -1e-5)
+    fc = (2e-6 * W.smoothed_noise(nx, ny, 3.0, seed=31), -1e-6 * W.smoothed_noise(nx, ny, 3.0, seed=32)) if force else None
+    dr = (1e-3 + 2e-2 * (1 - phi), (3e-4, -1e-4)) if drag else None
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=g, bc_y=bc, mask=mask, force=fc, drag=dr)
+    ora.set_populations(f0)
+    ora.step(1)
+    lat = lattice(nx, ny, phi, "f64", bc, mask=mask, g=g, force=fc, drag=dr)
+    lat.set_populations(torch.from_numpy(f0))
+    lat.step(1)
+    fg = lat.read_populations().cpu().numpy()
+    err = np.max(np.abs(fg[:, fluid] - ora.f[:, fluid])) / np.max(np.abs(ora.f))
+    _say(f"   max rel err {err:.3e}")
+    assert err <= 1e-14
+    assert np.all(fg[:, ~fluid] == 0.0)
+
+
 def _cylinder(nx=96, ny=40):
     phi = W.channel_phi(nx, ny, seed=11, lo=0.6)
     return phi, W.cylinder_channel(nx, ny, radius=6.0)
