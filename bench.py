@@ -395,6 +395,7 @@ VARIANTS = [
     ("solid nodes", "f32s", 1, {"mask": True}),
     ("solid nodes", "f64", 1, {"mask": True}),
     ("solid nodes, force field, drag", "f32s", 1, {"mask": True, "force": True, "drag": True}),
+    ("solid nodes, moving phi", "f32s", 1, {"mask": True, "dynamic": True}),
     ("model B", "f32s", 1, {"model_b": True}),
     ("moving walls, drag", "f32s", 1, {"wall_u": 1e-3, "drag": True}),
     ("model B, solid nodes", "f32s", 1, {"model_b": True, "mask": True}),
