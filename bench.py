@@ -396,6 +396,7 @@ VARIANTS = [
     ("solid nodes", "f64", 1, {"mask": True}),
     ("solid nodes, force field, drag", "f32s", 1, {"mask": True, "force": True, "drag": True}),
     ("solid nodes, moving phi", "f32s", 1, {"mask": True, "dynamic": True}),
+    ("walls in x (a closed box)", "f32s", 1, {"xwalls": True}),
     ("model B", "f32s", 1, {"model_b": True}),
     ("moving walls, drag", "f32s", 1, {"wall_u": 1e-3, "drag": True}),
     ("model B, solid nodes", "f32s", 1, {"model_b": True, "mask": True}),
@@ -417,6 +418,7 @@ def variants_bench(steps: int):
     rows = []
     for name, prec, spp, o in VARIANTS:
         lat = Lattice(NX, NY, precision=prec, bc_y="wall", mask=o.get("mask", False),
+                      bc_x="wall" if o.get("xwalls") else "periodic",
                       dynamic_phi=o.get("dynamic", False), force_field=o.get("force", False),
                       drag=o.get("drag", False))
         lat.set_params(KAPPA, RATES).set_body_force(G, 0.0, True)

@@ -66,7 +66,8 @@ typedef struct vanse_lattice vanse_lattice;
 typedef struct {
   int32_t nx, ny;          /* nodes; nx >= 2, 2 <= ny <= 65535 */
   int32_t precision;       /* VANSE_F64 | VANSE_F32 | ..._SHIFTED */
-  int32_t bc_x;            /* VANSE_PERIODIC (walls in x: VANSE_ERR_UNSUPPORTED) */
+  int32_t bc_x;            /* VANSE_PERIODIC | VANSE_WALL; walls in x step with the
+                              solid-node kernel, one step per launch */
   int32_t bc_y;            /* VANSE_PERIODIC | VANSE_WALL */
   int32_t has_force_field; /* 1: a per-node force field is added to F^B */
   int32_t has_drag;        /* 1: a per-node linear drag acts (vanse_set_drag) */
@@ -213,8 +214,8 @@ int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
                      int *workgroups);
 
 /* Time steps per launch of the plain step, with or without the force field
- * and the linear drag (no mask, moving phi, scheme variant or wall
- * velocity): 1 (the default) or 2.  With 2, vanse_step advances pairs of steps with one
+ * and the linear drag (no mask, walls in x, moving phi, scheme variant or
+ * wall velocity): 1 (the default) or 2.  With 2, vanse_step advances pairs of steps with one
  * launch each: a workgroup's first half runs step t -> t+1 into an LDS ring
  * and its second half step t+1 -> t+2 from it, so the populations cross HBM
  * once per two steps; an odd step count ends with one single step.  Each

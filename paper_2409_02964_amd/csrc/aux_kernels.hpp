@@ -22,6 +22,7 @@ __constant__ int kOPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 struct Geo {
   int nx, ny, pitch, walls;
+  int xwalls;  // half-way walls at x = -1/2 and x = nx - 1/2 as well
   long long plane;
 };
 
@@ -86,6 +87,7 @@ __device__ __forceinline__ bool receiver(const Geo& G, int x, int y, int i, unsi
                                          int* yr) {
   int xn = x + kEX[i];
   int yn = y + kEY[i];
+  if (G.xwalls && (xn < 0 || xn >= G.nx)) { *xr = x; *yr = y; return false; }
   xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
   if (G.walls) {
     if (yn < 0 || yn >= G.ny) { *xr = x; *yr = y; return false; }
@@ -99,7 +101,8 @@ __device__ __forceinline__ bool receiver(const Geo& G, int x, int y, int i, unsi
 
 // Solid flags (FEAT_MASK layout) from a dense uint8 mask, nonzero = solid:
 // bit 0 the node, bit i the node standing in for x + e_i, which across a wall
-// is its mirror image in the first or last row.  Counts solid nodes.
+// is its mirror image in the first or last row (or column).  Counts solid
+// nodes.
 __global__ void build_nbr(Geo G, const uint8_t* __restrict__ mask, uint16_t* __restrict__ nbr,
                           unsigned long long* __restrict__ nsolid) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -108,7 +111,8 @@ __global__ void build_nbr(Geo G, const uint8_t* __restrict__ mask, uint16_t* __r
   unsigned b = mask[(long long)y * G.nx + x] ? 1u : 0u;
   for (int i = 1; i < 9; ++i) {
     int xn = x + kEX[i], yn = y + kEY[i];
-    xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
+    if (G.xwalls) xn = xn < 0 ? -1 - xn : (xn >= G.nx ? 2 * G.nx - 1 - xn : xn);
+    else xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
     if (G.walls) yn = yn < 0 ? -1 - yn : (yn >= G.ny ? 2 * G.ny - 1 - yn : yn);
     else yn = yn < 0 ? yn + G.ny : (yn >= G.ny ? yn - G.ny : yn);
     if (mask[(long long)yn * G.nx + xn]) b |= 1u << i;
@@ -196,12 +200,13 @@ __device__ __forceinline__ double pull_one(const Geo& G, const S* __restrict__ b
   int xs = x - kEX[i];
   int ys = y - kEY[i];
   int slot = i;
+  const bool xout = xs < 0 || xs >= G.nx;
   xs = xs < 0 ? xs + G.nx : (xs >= G.nx ? xs - G.nx : xs);
   double corr = 0.0;
   if (G.walls && (ys < 0 || ys >= G.ny)) {
     corr = wall_delta(kOPP[i], phi_x, ys < 0, ph);
     xs = x; ys = y; slot = kOPP[i];
-  } else if (i > 0 && solid_bit(nb, kOPP[i])) {
+  } else if (i > 0 && (solid_bit(nb, kOPP[i]) || (G.xwalls && xout))) {
     xs = x; ys = y; slot = kOPP[i];
   } else {
     ys = ys < 0 ? ys + G.ny : (ys >= G.ny ? ys - G.ny : ys);
@@ -287,7 +292,8 @@ __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restric
     auto R = [&](int i) -> T {
       if (solid_bit(nb, i)) return rc;
       int xn = x + kEX[i], yn = y + kEY[i];
-      xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
+      if (G.xwalls) xn = xn < 0 ? 0 : (xn >= G.nx ? G.nx - 1 : xn);
+      else xn = xn < 0 ? xn + G.nx : (xn >= G.nx ? xn - G.nx : xn);
       if (G.walls) {
         yn = yn < 0 ? 0 : (yn >= G.ny ? G.ny - 1 : yn);
       } else {

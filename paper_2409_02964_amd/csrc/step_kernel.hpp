@@ -81,6 +81,7 @@ struct StepGeom {
   const void* nbr;   // uint16 solid flags per node (see FEAT_MASK), or null
   long long plane;  // elements per population plane (= pitch * ny)
   int nx, ny, pitch;
+  int xwalls;       // half-way walls at x = -1/2 and x = nx - 1/2 (FEAT_MASK instances)
   int strips, out_w, rows;
 };
 
@@ -221,10 +222,28 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
   const bool live = t < w + 4;                 // pulls and delta-rho
   const bool ulane = t >= 1 && t < w + 3;      // velocity
   const bool olane = t >= 2 && t < w + 2;      // collision and store
-  const int c = wrap_index(x0 - 2 + t, nx);
-  const int cm = (c == 0) ? nx - 1 : c - 1;
-  const int cp = (c == nx - 1) ? 0 : c + 1;
-  const int tl = max(t - 1, 0), tr = min(t + 1, NT - 1);
+  // Walls in x (solid-node instances only): a halo lane beyond a face
+  // stands for the mirror column c.  It pulls and computes exactly as the
+  // lane of column c (slot tc of this strip), reading its stencils around
+  // tc, and stores the velocity-like results negated.  The face columns pull
+  // across the face from their own opposite slots (flags fb).
+  const int xg = x0 - 2 + t;
+  const bool xw = (FEAT & FEAT_MASK) != 0 && g.xwalls != 0;
+  int c, cm, cp, tc = t;
+  if (xw) {
+    c = min(max(xg < 0 ? -1 - xg : (xg >= nx ? 2 * nx - 1 - xg : xg), 0), nx - 1);
+    cm = max(c - 1, 0);
+    cp = min(c + 1, nx - 1);
+    tc = min(max(t + (c - xg), 0), NT - 1);
+  } else {
+    c = wrap_index(xg, nx);
+    cm = (c == 0) ? nx - 1 : c - 1;
+    cp = (c == nx - 1) ? 0 : c + 1;
+  }
+  // per-lane conditions (kept as lane masks, not registers)
+  const bool xmir = xw && (xg < 0 || xg >= nx);
+  const bool xlo = xw && c == 0, xhi = xw && c == nx - 1;
+  const int tl = max(tc - 1, 0), tr = min(tc + 1, NT - 1);
   constexpr unsigned SB = sizeof(S);
   constexpr unsigned TB = sizeof(T);
 
@@ -282,9 +301,11 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       // per-lane choice between the pulled slot and the own node's opposite
       // slot (solid source): whole byte offsets in the per-lane operand
       nb = bload_u16(nbrr, unsigned(c) * 2u, unsigned(r) * unsigned(pitch) * 2u);
+      const unsigned pnb = nb | (xlo ? (1u << 3) | (1u << 6) | (1u << 7) : 0u) |
+                           (xhi ? (1u << 1) | (1u << 5) | (1u << 8) : 0u);
       auto pick = [&](unsigned vcol, unsigned soff, int opp) -> S {
         const unsigned own = poff(opp, r) + xcb;
-        return bload<S>(srcr, solid_bit(nb, opp) ? own : soff + vcol, 0u);
+        return bload<S>(srcr, solid_bit(pnb, opp) ? own : soff + vcol, 0u);
       };
       f[0] = bload<S>(srcr, xcb, poff(0, r));
       f[1] = pick(xmb, poff(1, r), 3);
@@ -382,7 +403,7 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
     if (rowB && ulane) {
       const int sc = slot4(yb), ss = slot4(yb - 1), sn = slot4(yb + 1);
       T rE = s_rho[sc][tr], rW = s_rho[sc][tl];
-      T rN = s_rho[sn][t], rS = s_rho[ss][t];
+      T rN = s_rho[sn][tc], rS = s_rho[ss][tc];
       T rNE = s_rho[sn][tr], rNW = s_rho[sn][tl];
       T rSE = s_rho[ss][tr], rSW = s_rho[ss][tl];
       if constexpr ((FEAT & FEAT_MASK) != 0) {  // solid neighbour: centre value
@@ -430,8 +451,18 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       U2<T> b;
       a.ux = ux; a.uy = uy; a.mux = m0 * ux; a.rux = rho * ux;
       b.muy = m0 * uy; b.ruy = rho * uy;
-      s_u4[slot4(yb)][t] = a;
-      s_u2[slot4(yb)][t] = b;
+      if constexpr ((FEAT & FEAT_MASK) != 0) {  // mirror lane beyond an x-wall
+        U4<T> ax;
+        U2<T> bx;
+        ax.ux = xmir ? -a.ux : a.ux; ax.uy = xmir ? -a.uy : a.uy;
+        ax.mux = xmir ? -a.mux : a.mux; ax.rux = xmir ? -a.rux : a.rux;
+        bx.muy = xmir ? -b.muy : b.muy; bx.ruy = xmir ? -b.ruy : b.ruy;
+        s_u4[slot4(yb)][t] = ax;
+        s_u2[slot4(yb)][t] = bx;
+      } else {
+        s_u4[slot4(yb)][t] = a;
+        s_u2[slot4(yb)][t] = b;
+      }
       if (WALLS && (yb == 0 || yb == ny - 1)) {  // mirror image beyond the wall
         const int sg2 = slot4(yb == 0 ? -1 : ny);
         U4<T> am;
@@ -454,18 +485,18 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
     const int yo = yn - 2;
     if (yo >= y0 && olane) {
       const int uo = slot4(yo), us = slot4(yo - 1), un = slot4(yo + 1);
-      const U4<T> aC = s_u4[uo][t];
+      const U4<T> aC = s_u4[uo][tc];
       U4<T> aE = s_u4[uo][tr], aW = s_u4[uo][tl];
-      U4<T> aN = s_u4[un][t], aS = s_u4[us][t];
+      U4<T> aN = s_u4[un][tc], aS = s_u4[us][tc];
       U4<T> aNE = s_u4[un][tr], aNW = s_u4[un][tl];
       U4<T> aSE = s_u4[us][tr], aSW = s_u4[us][tl];
-      U2<T> bN = s_u2[un][t], bS = s_u2[us][t];
+      U2<T> bN = s_u2[un][tc], bS = s_u2[us][tc];
       U2<T> bNE = s_u2[un][tr], bNW = s_u2[un][tl];
       U2<T> bSE = s_u2[us][tr], bSW = s_u2[us][tl];
       if constexpr ((FEAT & FEAT_MASK) != 0) {
         // solid neighbour: the centre's velocity-like fields, negated
         const unsigned nb = rC.nb;
-        const U2<T> bC = s_u2[uo][t];
+        const U2<T> bC = s_u2[uo][tc];
         U4<T> ga;
         ga.ux = -aC.ux; ga.uy = -aC.uy; ga.mux = -aC.mux; ga.rux = -aC.rux;
         U2<T> gb;
@@ -507,7 +538,7 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       if (eq2) {
         U2<T> bE = s_u2[uo][tr], bW = s_u2[uo][tl];
         if constexpr ((FEAT & FEAT_MASK) != 0) {
-          const U2<T> bC = s_u2[uo][t];
+          const U2<T> bC = s_u2[uo][tc];
           const bool sE = solid_bit(rC.nb, 1), sW = solid_bit(rC.nb, 3);
           bE.muy = sE ? -bC.muy : bE.muy; bE.ruy = sE ? -bC.ruy : bE.ruy;
           bW.muy = sW ? -bC.muy : bW.muy; bW.ruy = sW ? -bC.ruy : bW.ruy;

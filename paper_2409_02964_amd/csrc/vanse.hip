@@ -70,10 +70,7 @@ int make_layout(const vanse_desc* d, Layout* L) {
   // the set-up and read-out kernels launch one grid row per lattice row
   if (d->ny > 65535) return fail(VANSE_ERR_INVALID_ARG, "lattice too tall: ny must be <= 65535 (got %d)", d->ny);
   if (storage_bytes(d->precision) == 0) return fail(VANSE_ERR_INVALID_ARG, "unknown precision %d", d->precision);
-  if (d->bc_x != VANSE_PERIODIC) {
-    if (d->bc_x == VANSE_WALL) return fail(VANSE_ERR_UNSUPPORTED, "walls in x are not built");
-    return fail(VANSE_ERR_INVALID_ARG, "unknown bc_x %d", d->bc_x);
-  }
+  if (d->bc_x != VANSE_PERIODIC && d->bc_x != VANSE_WALL) return fail(VANSE_ERR_INVALID_ARG, "unknown bc_x %d", d->bc_x);
   if (d->bc_y != VANSE_PERIODIC && d->bc_y != VANSE_WALL) return fail(VANSE_ERR_INVALID_ARG, "unknown bc_y %d", d->bc_y);
   if (d->has_force_field != 0 && d->has_force_field != 1) return fail(VANSE_ERR_INVALID_ARG, "has_force_field must be 0 or 1");
   if (d->has_drag != 0 && d->has_drag != 1) return fail(VANSE_ERR_INVALID_ARG, "has_drag must be 0 or 1");
@@ -212,6 +209,7 @@ Geo make_geo(const vanse_lattice* h) {
   G.ny = h->d.ny;
   G.pitch = h->L.pitch;
   G.walls = h->d.bc_y == VANSE_WALL;
+  G.xwalls = h->d.bc_x == VANSE_WALL;
   G.plane = h->L.plane;
   return G;
 }
@@ -240,12 +238,13 @@ int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& 
 // or the drag (FEAT_MASK | FEAT_FORCE | FEAT_DRAG) or with a moving phi
 // (FEAT_MASK | FEAT_MOVING); the scheme variants with any of those
 // (FEAT_SCHEME | FEAT_MOVING).  Scheme variants with solid nodes use
-// FEAT_ALL.
+// FEAT_ALL.  Walls in x take the solid-node instances, with or without a
+// mask (an absent flag plane reads as zero).
 constexpr int FEAT_MOVING = FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG;
 int feat_of(const vanse_lattice* h) {
   const vanse_desc& d = h->d;
   const bool scheme = h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0;
-  if (d.has_mask) {
+  if (d.has_mask || d.bc_x == VANSE_WALL) {
     if (scheme) return FEAT_ALL;
     if (d.dynamic_phi) return FEAT_MASK | FEAT_MOVING;
     return (d.has_force_field || d.has_drag) ? (FEAT_MASK | FEAT_FORCE | FEAT_DRAG) : FEAT_MASK;
@@ -363,6 +362,7 @@ int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
   g.phi = h->ws + h->L.phi;
   g.phin = h->phin_set ? h->ws + h->L.phin : g.phi;
   g.nbr = h->d.has_mask ? h->ws + h->L.nbr : nullptr;
+  g.xwalls = h->d.bc_x == VANSE_WALL;
   g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
   g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
   g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
@@ -925,7 +925,8 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
     if (!batch_ok(lats[k]))
       return fail(VANSE_ERR_UNSUPPORTED,
                   "lattice %d: batches take no time-varying phi, nor a scheme variant with solid nodes", k);
-    if (d.precision != d0.precision || d.bc_y != d0.bc_y || d.has_force_field != d0.has_force_field ||
+    if (d.precision != d0.precision || d.bc_x != d0.bc_x || d.bc_y != d0.bc_y ||
+        d.has_force_field != d0.has_force_field ||
         d.has_drag != d0.has_drag || feat_of(lats[k]) != feat_of(lats[0]))
       return fail(VANSE_ERR_INVALID_ARG,
                   "lattice %d differs in precision, boundary, force field, drag, mask or scheme variant", k);
@@ -977,6 +978,7 @@ void fill_entries(vanse_batch* b, std::vector<char>* blob) {
     g.phi = h->ws + h->L.phi;
     g.phin = g.phi;
     g.nbr = h->d.has_mask ? h->ws + h->L.nbr : nullptr;
+    g.xwalls = h->d.bc_x == VANSE_WALL;
     g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
     g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
     g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;

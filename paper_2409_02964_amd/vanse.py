@@ -158,12 +158,13 @@ class Lattice:
     """One lattice whose device state lives in a torch-allocated workspace."""
 
     def __init__(self, nx, ny, precision="f64", bc_y="periodic", force_field=False,
-                 device=None, workspace=None, drag=False, mask=False, dynamic_phi=False):
+                 device=None, workspace=None, drag=False, mask=False, dynamic_phi=False,
+                 bc_x="periodic"):
         import torch
         self.nx, self.ny = int(nx), int(ny)
         self.precision = precision
         self.device = torch.device(device or "cuda")
-        self.desc = Desc(self.nx, self.ny, PRECISION[precision], 0, BC[bc_y],
+        self.desc = Desc(self.nx, self.ny, PRECISION[precision], BC[bc_x], BC[bc_y],
                          int(bool(force_field)), int(bool(drag)), int(bool(mask)),
                          int(bool(dynamic_phi)))
         nbytes = C.c_size_t()

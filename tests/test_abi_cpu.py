@@ -43,7 +43,7 @@ def test_workspace_bytes_scales_with_precision():
     (1, 64, 0, 0, 0, 0, -1),
     (64, 1, 0, 0, 0, 0, -1),
     (64, 64, 7, 0, 0, 0, -1),
-    (64, 64, 0, 1, 0, 0, -6),
+    (64, 64, 0, 2, 0, 0, -1),
     (64, 64, 0, 0, 5, 0, -1),
     (64, 64, 0, 0, 0, 2, -1),
     (60000, 60000, 1, 0, 0, 0, -1),
@@ -56,10 +56,10 @@ def test_bad_descriptors_are_rejected(nx, ny, prec, bcx, bcy, ff, code):
     assert V.lib().vanse_last_error()
 
 
-def _fake_handle(nx=64, ny=48, prec=0, bcy=0, mask=0, dynamic=0):
+def _fake_handle(nx=64, ny=48, prec=0, bcy=0, mask=0, dynamic=0, bcx=0):
     """A handle over a fake, aligned device address: only host-side calls
     (no HIP work) may be made on it."""
-    d = V.Desc(nx, ny, prec, 0, bcy, 0, 0, mask, dynamic)
+    d = V.Desc(nx, ny, prec, bcx, bcy, 0, 0, mask, dynamic)
     n = C.c_size_t()
     V.check(V.lib().vanse_workspace_bytes(C.byref(d), C.byref(n)))
     h = C.c_void_p()
@@ -151,7 +151,9 @@ def test_feature_state_checks_on_the_host():
     (dict(), dict(mask=1), -1),               # members differ in their variant
     (dict(), dict(dynamic=1), -6),            # a moving phi is not batched
     (dict(dynamic=1), dict(dynamic=1), -6),
-    (dict(mask=1), dict(mask=1), 0)])         # solid nodes are
+    (dict(mask=1), dict(mask=1), 0),          # solid nodes are
+    (dict(bcx=1), dict(bcx=1, mask=1), 0),    # walls in x, with or without solid nodes
+    (dict(bcx=1), dict(mask=1), -1)])         # the same instance, other x boundaries
 def test_batch_variant_rules(first, second, code):
     L = V.lib()
     hs = [_fake_handle(**first), _fake_handle(**second)]
