@@ -251,7 +251,7 @@ int vanse_stream_copy(vanse_lattice *h, int64_t n, void *stream);
  * vanse_batch_create_ex) whose workgroups cover the tiles of all member
  * lattices (tile = strip of threads-4 columns x `rows` rows of one lattice).  Each member's arithmetic is exactly that of
  * vanse_step (results are bitwise identical).  Members must share precision,
- * boundary type, force field, drag, mask and scheme variant (VANSE_ERR_INVALID_ARG
+ * boundary types, force field, drag, mask and scheme variant (VANSE_ERR_INVALID_ARG
  * otherwise), be fully set up, and stay alive
  * while the batch exists.  The batch keeps a table of the members'
  * parameters and buffer parity in a caller-owned device workspace; it is
@@ -259,7 +259,7 @@ int vanse_stream_copy(vanse_lattice *h, int64_t n, void *stream);
  * own.  Member handles stay usable (vanse_time, vanse_read_*).  Lattices with
  * a time-varying void fraction are not batched, nor lattices combining a
  * scheme variant (model B, the Appendix B equilibrium, moving walls) with
- * solid nodes (VANSE_ERR_UNSUPPORTED). */
+ * solid nodes or walls in x (VANSE_ERR_UNSUPPORTED). */
 typedef struct vanse_batch vanse_batch;
 
 /* Workspace bytes for a batch of n lattices with the given workgroup width

@@ -228,7 +228,10 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
   // tc, and stores the velocity-like results negated.  The face columns pull
   // across the face from their own opposite slots (flags fb).
   const int xg = x0 - 2 + t;
-  const bool xw = (FEAT & FEAT_MASK) != 0 && g.xwalls != 0;
+  // (not in the mask-with-force-or-drag instance, whose registers are full:
+  // the host routes walls in x with those inputs to the moving-phi one)
+  constexpr bool XW = (FEAT & FEAT_MASK) != 0 && FEAT != (FEAT_MASK | FEAT_FORCE | FEAT_DRAG);
+  const bool xw = XW && g.xwalls != 0;
   int c, cm, cp, tc = t;
   if (xw) {
     c = min(max(xg < 0 ? -1 - xg : (xg >= nx ? 2 * nx - 1 - xg : xg), 0), nx - 1);
@@ -451,7 +454,7 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       U2<T> b;
       a.ux = ux; a.uy = uy; a.mux = m0 * ux; a.rux = rho * ux;
       b.muy = m0 * uy; b.ruy = rho * uy;
-      if constexpr ((FEAT & FEAT_MASK) != 0) {  // mirror lane beyond an x-wall
+      if constexpr (XW) {  // mirror lane beyond an x-wall
         U4<T> ax;
         U2<T> bx;
         ax.ux = xmir ? -a.ux : a.ux; ax.uy = xmir ? -a.uy : a.uy;

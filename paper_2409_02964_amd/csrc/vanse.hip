@@ -239,14 +239,16 @@ int launch_step_w(const vanse_lattice* h, const StepGeom& g, const StepPhys<T>& 
 // (FEAT_MASK | FEAT_MOVING); the scheme variants with any of those
 // (FEAT_SCHEME | FEAT_MOVING).  Scheme variants with solid nodes use
 // FEAT_ALL.  Walls in x take the solid-node instances, with or without a
-// mask (an absent flag plane reads as zero).
+// mask (an absent flag plane reads as zero); with a force field or drag the
+// moving-phi one (FEAT_MASK | FEAT_FORCE | FEAT_DRAG is built without them).
 constexpr int FEAT_MOVING = FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG;
 int feat_of(const vanse_lattice* h) {
   const vanse_desc& d = h->d;
   const bool scheme = h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0;
   if (d.has_mask || d.bc_x == VANSE_WALL) {
     if (scheme) return FEAT_ALL;
-    if (d.dynamic_phi) return FEAT_MASK | FEAT_MOVING;
+    if (d.dynamic_phi || (d.bc_x == VANSE_WALL && (d.has_force_field || d.has_drag)))
+      return FEAT_MASK | FEAT_MOVING;
     return (d.has_force_field || d.has_drag) ? (FEAT_MASK | FEAT_FORCE | FEAT_DRAG) : FEAT_MASK;
   }
   if (scheme) return FEAT_SCHEME | FEAT_MOVING;
