@@ -102,6 +102,17 @@ int main(void) {
     bad |= run_case("walls 12x8, model B, App. B, moving walls", P, 1, 1, 1);
   }
   {
+    vo_params P = params(11, 7, 1);
+    P.bc_x = 1;
+    P.uw_hi = 2e-3;
+    bad |= run_case("box 11x7, walls in x, mask, force field, drag, lid", P, 1, 1, 1);
+  }
+  {
+    vo_params P = params(5, 9, 0);
+    P.bc_x = 1;
+    bad |= run_case("walls in x 5x9, periodic in y, mask", P, 1, 0, 0);
+  }
+  {
     vo_params P = params(9, 6, 1);
     P.use_penalty = 0;
     P.scale_by_phi = 0;
