@@ -239,8 +239,8 @@ int vanse_set_storage_exponent(vanse_lattice *h, int e);
 
 /* Measurement helper, not part of the method: n launches of a kernel with
  * the step's exact memory pattern (pull of the nine populations with the
- * same shifts and bounce-back, written back unchanged to the other buffer;
- * 9 reads + 9 writes per node, no arithmetic).  It is the speed-of-light
+ * same shifts and bounce-back at y-walls, written back unchanged to the
+ * other buffer; 9 reads + 9 writes per node, no arithmetic; x always wraps).  It is the speed-of-light
  * reference for the step's HBM traffic and the calibration kernel for
  * memory counters.  It permutes the stored state; t is not advanced. */
 int vanse_stream_copy(vanse_lattice *h, int64_t n, void *stream);
