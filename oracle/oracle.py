@@ -45,7 +45,9 @@ class _Params(C.Structure):
                 ("scale_by_phi", C.c_int), ("use_penalty", C.c_int),
                 ("beta", C.POINTER(C.c_double)), ("usx", C.c_double), ("usy", C.c_double),
                 ("model_b", C.c_int), ("eq2", C.c_int), ("uw_lo", C.c_double),
-                ("uw_hi", C.c_double), ("rho_w", C.c_double)]
+                ("uw_hi", C.c_double), ("rho_w", C.c_double),
+                ("nee_lo", C.c_int), ("nee_hi", C.c_int), ("un_lo", C.c_double),
+                ("un_hi", C.c_double)]
 
 
 _D = C.POINTER(C.c_double)
@@ -173,7 +175,7 @@ class Oracle:
     def __init__(self, nx, ny, phi, kappa=0.5, rates=None, g=(0.0, 0.0),
                  scale_by_phi=True, bc_x="periodic", bc_y="periodic", mask=None,
                  force=None, penalty=True, drag=None, model_b=False, eq2=False,
-                 wall_velocity=(0.0, 0.0), rho_w=1.0):
+                 wall_velocity=(0.0, 0.0), rho_w=1.0, velocity_rows=(None, None)):
         r = dict(s_c=1.0, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=1.2)
         if rates:
             r.update(rates)
@@ -186,6 +188,14 @@ class Oracle:
         # x velocities of the walls at y = -1/2 and y = ny - 1/2 (bc_y = "wall")
         self.p.uw_lo, self.p.uw_hi = float(wall_velocity[0]), float(wall_velocity[1])
         self.p.rho_w = float(rho_w)
+        # velocity boundary rows (non-equilibrium extrapolation, Sec. 3.1):
+        # x velocity of the first / last row, None for an ordinary row
+        lo, hi = velocity_rows
+        if (lo is not None or hi is not None) and bc_y != "wall":
+            raise ValueError("velocity rows need walls in y")
+        self.p.nee_lo, self.p.un_lo = (0, 0.0) if lo is None else (1, float(lo))
+        self.p.nee_hi, self.p.un_hi = (0, 0.0) if hi is None else (1, float(hi))
+        self.velocity_rows = velocity_rows
         shp = (self.ny, self.nx)
         self.phi = _f64(phi, shp)
         if drag is not None:  # (beta field, (usx, usy)): F^B -= phi beta (u - u_s)
@@ -261,10 +271,18 @@ class Oracle:
                           _dp(gx), _dp(gy))
         return gx, gy
 
+    def fluid(self):
+        """Boolean (ny, nx) map of the fluid nodes: not solid and not on a
+        velocity boundary row."""
+        m = np.ones((self.ny, self.nx), bool) if self.mask is None else self.mask == 0
+        m = m.copy()
+        if self.p.nee_lo:
+            m[0] = False
+        if self.p.nee_hi:
+            m[-1] = False
+        return m
+
     def mass(self):
         """Total mass: exactly rounded sum over fluid nodes of sum_i f_i."""
         import math
-        f = self.f
-        if self.mask is not None:
-            f = f[:, self.mask == 0]
-        return math.fsum(f.ravel().tolist())
+        return math.fsum(self.f[:, self.fluid()].ravel().tolist())

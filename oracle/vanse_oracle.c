@@ -103,7 +103,27 @@ typedef struct {
    * f^eq_opp(i)) at (phi(x), rho_w, u_w), and the Eq. (10) stand-in across the
    * wall carries 2 u_w - u (Sec. 3.1, Couette flow of Eq. 22). */
   double uw_lo, uw_hi, rho_w;
+  /* Velocity boundary of Couette flow by non-equilibrium extrapolation
+   * (Sec. 3.1, the paper's ref. [47]): nee_lo / nee_hi make the first / last
+   * row a row of boundary nodes lying on the wall, moving with x velocity
+   * un_lo / un_hi.  Needs bc_y = 1 and at least three rows.  Such a node is
+   * not evolved by the scheme: after every collision its post-collision
+   * populations are the equilibrium at (phi(x_b), rho(x_f), u_w) plus the
+   * post-collision non-equilibrium part of its fluid neighbour x_f across the
+   * row (f+ - f^eq at (phi(x_f), rho(x_f), u(x_f))), with the density
+   * extrapolated as rho(x_b) = rho(x_f).  The Eq. (10) stencils of x_f see
+   * rho(x_b) = rho(x_f) and u(x_b) = u_w there. */
+  int nee_lo, nee_hi;
+  double un_lo, un_hi;
 } vo_params;
+
+/* Boundary-row kind of row y: 1 lower, 2 upper velocity row, 0 otherwise. */
+static int nee_row(const vo_params *P, int y) {
+  if (P->bc_y == 0) return 0;
+  if (P->nee_lo && y == 0) return 1;
+  if (P->nee_hi && y == P->ny - 1) return 2;
+  return 0;
+}
 
 /* ---- threads ------------------------------------------------------------- */
 void vo_set_threads(int n) {
@@ -373,12 +393,13 @@ void vo_gradient(const vo_params *P, const unsigned char *mask,
 typedef struct {
   double *m0, *rho, *ux, *uy, *Fx, *Fy, *rux, *ruy, *mux, *muy, *d, *tmp;
   double *jx, *jy, *grx, *gry;
+  double *fp; /* [9][N] post-collision populations of one step */
 } vo_work;
 
 static void work_free(vo_work *W) {
   free(W->m0); free(W->rho); free(W->ux); free(W->uy); free(W->Fx); free(W->Fy);
   free(W->rux); free(W->ruy); free(W->mux); free(W->muy); free(W->d); free(W->tmp);
-  free(W->jx); free(W->jy); free(W->grx); free(W->gry);
+  free(W->jx); free(W->jy); free(W->grx); free(W->gry); free(W->fp);
 }
 
 static int work_alloc(int N, vo_work *W) {
@@ -387,9 +408,10 @@ static int work_alloc(int N, vo_work *W) {
   W->Fx = malloc(b); W->Fy = malloc(b); W->rux = malloc(b); W->ruy = malloc(b);
   W->mux = malloc(b); W->muy = malloc(b); W->d = malloc(12 * b); W->tmp = malloc(b);
   W->jx = malloc(b); W->jy = malloc(b); W->grx = malloc(b); W->gry = malloc(b);
+  W->fp = malloc(9 * b);
   if (!W->m0 || !W->rho || !W->ux || !W->uy || !W->Fx || !W->Fy || !W->rux ||
       !W->ruy || !W->mux || !W->muy || !W->d || !W->tmp || !W->jx || !W->jy ||
-      !W->grx || !W->gry) {
+      !W->grx || !W->gry || !W->fp) {
     work_free(W);
     return -1;
   }
@@ -425,11 +447,28 @@ static void macroscopic_tab(const vo_params *P, const vo_nbr *T, vo_work *W,
     jy[c] = sy;
     rho[c] = s / phi[c];
   }
+  /* velocity boundary rows: the density of the fluid neighbour across the
+   * row, and phi*rho formed from it */
+  if (P->nee_lo || P->nee_hi) {
+    for (int y = 0; y < P->ny; ++y) {
+      const int kind = nee_row(P, y);
+      if (!kind) continue;
+      const int yf = (kind == 1) ? 1 : P->ny - 2;
+      for (int x = 0; x < P->nx; ++x) {
+        const int c = y * P->nx + x;
+        rho[c] = rho[yf * P->nx + x];
+        m0[c] = phi[c] * rho[c];
+      }
+    }
+  }
   gradient_tab(P, mask, T, rho, 0, grx, gry);
 #pragma omp parallel for schedule(static)
   for (int c = 0; c < N; ++c) {
     double ux = 0.0, uy = 0.0, Fx = 0.0, Fy = 0.0;
-    if (!is_solid(mask, c)) {
+    const int kind = nee_row(P, c / P->nx);
+    if (kind) {
+      ux = (kind == 1) ? P->un_lo : P->un_hi; /* the wall velocity; F unused */
+    } else if (!is_solid(mask, c)) {
       /* Eq. (13); model B: F^p = (kappa - 1) cs^2 grad rho */
       const double kf = P->model_b ? 1.0 : phi[c];
       const double Fpx = (P->kappa - kf) * CS2 * grx[c];
@@ -528,15 +567,14 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, vo_work *W,
   const double s[9] = {P->s_c, P->s_e, P->s_eps, P->s_c, P->s_q,
                        P->s_c, P->s_q, P->s_nu, P->s_nu};
 
-#pragma omp parallel for schedule(static)
-  for (long k = 0; k < 9L * N; ++k) fout[k] = 0.0;
+  double *fpost = W->fp;
 
-  /* every (target node, direction) of fout is written by exactly one source */
+  /* O6-O9 at every fluid node */
 #pragma omp parallel for schedule(static)
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       const int c = y * nx + x;
-      if (is_solid(mask, c)) continue;
+      if (is_solid(mask, c) || nee_row(P, y)) continue;
 
       /* O6: penalty source C = (0, C_a, 0, 0, 0, 0, 0, C_b, C_c), Eq. (20) */
       const double dt_phi = phi_next ? (phi_next[c] - phi[c]) : 0.0;
@@ -572,15 +610,43 @@ static int step_tab(const vo_params *P, const vo_nbr *Tp, vo_work *W,
         mp[k] = m[k] - s[k] * (m[k] - meq[k]) + (1.0 - 0.5 * s[k]) * (S[k] + C[k]);
 
       /* O9: f+ = M^-1 m+ (Eq. A1) */
-      double fp[9];
       for (int i = 0; i < 9; ++i) {
         double acc = 0.0;
         for (int k = 0; k < 9; ++k) acc += MINV36[i][k] * mp[k];
-        fp[i] = acc / 36.0;
+        fpost[(size_t)i * N + c] = acc / 36.0;
       }
+    }
 
-      /* O10: push streaming f_i(x+e_i, t+1) = f+_i(x, t); half-way bounce-back
-       * off walls and solid nodes: f_opp(i)(x, t+1) = f+_i(x, t). */
+  /* Velocity boundary rows (non-equilibrium extrapolation, Sec. 3.1):
+   * f+(x_b) = f^eq(phi(x_b), rho(x_f), u_w) + f+(x_f) - f^eq(phi(x_f), rho(x_f), u(x_f)) */
+  for (int y = 0; y < ny; ++y) {
+    const int kind = nee_row(P, y);
+    if (!kind) continue;
+    const int yf = (kind == 1) ? 1 : ny - 2;
+    const double uw = (kind == 1) ? P->un_lo : P->un_hi;
+    for (int x = 0; x < nx; ++x) {
+      const int c = y * nx + x, cf = yf * nx + x;
+      double eb[9], ef[9];
+      feq_of(P, phi[c], rho[cf], uw, 0.0, eb);
+      feq_of(P, phi[cf], rho[cf], ux[cf], uy[cf], ef);
+      for (int i = 0; i < 9; ++i)
+        fpost[(size_t)i * N + c] = eb[i] + (fpost[(size_t)i * N + cf] - ef[i]);
+    }
+  }
+
+#pragma omp parallel for schedule(static)
+  for (long k = 0; k < 9L * N; ++k) fout[k] = 0.0;
+
+  /* O10: push streaming f_i(x+e_i, t+1) = f+_i(x, t); half-way bounce-back
+   * off walls and solid nodes: f_opp(i)(x, t+1) = f+_i(x, t).  Every (target
+   * node, direction) of fout is written by exactly one source. */
+#pragma omp parallel for schedule(static)
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const int c = y * nx + x;
+      if (is_solid(mask, c)) continue;
+      double fp[9];
+      for (int i = 0; i < 9; ++i) fp[i] = fpost[(size_t)i * N + c];
       for (int i = 0; i < 9; ++i) {
         int xn = x + EX[i], yn = y + EY[i];
         int blocked = 0;

@@ -113,6 +113,20 @@ int main(void) {
     bad |= run_case("walls in x 5x9, periodic in y, mask", P, 1, 0, 0);
   }
   {
+    vo_params P = params(10, 3, 1);
+    P.nee_lo = P.nee_hi = 1;
+    P.un_lo = -1e-3;
+    P.un_hi = 2e-3;
+    bad |= run_case("walls 10x3, velocity rows on both faces, drag", P, 0, 1, 1);
+  }
+  {
+    vo_params P = params(7, 9, 1);
+    P.eq2 = 1;
+    P.nee_hi = 1;
+    P.un_hi = 1e-3;
+    bad |= run_case("walls 7x9, App. B, upper velocity row", P, 0, 0, 0);
+  }
+  {
     vo_params P = params(9, 6, 1);
     P.use_penalty = 0;
     P.scale_by_phi = 0;
