@@ -119,11 +119,38 @@ int vanse_set_scheme(vanse_lattice *h, int model, int equilibrium_order);
 /* Tangential (x) velocities of the walls on the faces y = -1/2 (u_lo) and
  * y = ny - 1/2 (u_hi); default 0.  A population crossing a moving wall
  * returns less the odd part of the equilibrium (Eq. 14, or B1) at
- * (phi(x), rho0, u_w) -- the moving-wall form of half-way bounce-back used for
- * Couette flow (Sec. 3.1, Eq. 22 II) -- and the Eq. (10) stand-ins across
- * the wall carry 2 u_w - u.  Needs bc_y = VANSE_WALL; only before the
- * populations are set. */
+ * (phi(x), rho0, u_w), and the Eq. (10) stand-ins across the wall carry
+ * 2 u_w - u.  This moving form of half-way bounce-back is an alternative to
+ * the paper's own velocity condition for Couette flow (Sec. 3.1 imposes it
+ * by non-equilibrium extrapolation: vanse_set_velocity_rows); it keeps every
+ * row a fluid row and a closed box's lid on the face.  Needs bc_y =
+ * VANSE_WALL; only before the populations are set. */
 int vanse_set_wall_velocity(vanse_lattice *h, double u_lo, double u_hi);
+
+/* Velocity boundary rows: the moving-wall condition of Couette flow in
+ * Sec. 3.1 (Eq. 22 II), imposed by non-equilibrium extrapolation (the
+ * paper's ref. [47]).  `faces` is VANSE_FACE_LO and/or VANSE_FACE_HI: the
+ * first (y = 0) and/or last (y = ny - 1) row becomes a row of boundary nodes
+ * lying on a wall that moves with x velocity u_lo / u_hi.  Such a node is not
+ * evolved by the scheme.  After every collision its post-collision
+ * populations are set from the fluid node x_f next to it across the row:
+ *   f+_i(x_b) = f^eq_i(phi(x_b), rho(x_f), u_w) + f+_i(x_f) - f^eq_i(phi(x_f), rho(x_f), u(x_f))
+ * with f^eq of Eq. (14), or B1 with the Appendix B equilibrium; the density
+ * is extrapolated as rho(x_b) = rho(x_f).  The Eq. (10) stencils of x_f see
+ * rho(x_f) and u_w at x_b.  vanse_read_moments reports rho(x_f), u_w and
+ * rho(x_f)/3 on the row; it is left out of vanse_observe and
+ * vanse_residual (mass is not conserved through it).  The face beyond the
+ * row stays a half-way wall, which no population crossing it reaches a fluid
+ * node through.  With a velocity row on the upper face only, the walls of a
+ * channel are ny - 1/2 apart.  Needs bc_y = VANSE_WALL, ny >= 3, bc_x =
+ * VANSE_PERIODIC and no mask (VANSE_ERR_UNSUPPORTED otherwise), no half-way
+ * wall velocity on the same face; only before the populations are set.
+ * faces = 0 removes the rows.  One step per launch, in the step-kernel
+ * instance that carries every optional input; batches do not take such
+ * lattices (VANSE_ERR_UNSUPPORTED). */
+#define VANSE_FACE_LO 1
+#define VANSE_FACE_HI 2
+int vanse_set_velocity_rows(vanse_lattice *h, int faces, double u_lo, double u_hi);
 
 /* Uniform external acceleration G: F^B = phi*G (scale_by_phi = 1, the form
  * F^B = phi(G - ...) of Sec. 3.1 and Eq. 23) or F^B = G (scale_by_phi = 0).
@@ -178,8 +205,19 @@ int vanse_set_populations(vanse_lattice *h, const double *f, double rho0,
                           void *stream);
 
 /* Advance nsteps >= 0 time steps (collision of Eq. 16, then streaming with
- * bounce-back).  Enqueued only; does not synchronize. */
+ * bounce-back).  Enqueued only; does not synchronize -- unless a check
+ * interval is set (below). */
 int vanse_step(vanse_lattice *h, int64_t nsteps, void *stream);
+
+/* Divergence check inside vanse_step: with k > 0, every time t that is a
+ * multiple of k reached during a vanse_step call is followed by the FP64
+ * observables of vanse_observe (enqueued between the launches; the record
+ * of the last one is what vanse_observe would return at that t), and the
+ * call ends with one synchronizing read: VANSE_ERR_DIVERGED, with the first
+ * such t in vanse_last_error(), when one of them counted a non-finite node.
+ * The steps run to the end of the call either way (t advances by nsteps).
+ * k = 0 (the default) turns the check off.  Batches do not run it. */
+int vanse_set_check_interval(vanse_lattice *h, int64_t k);
 
 /* rho = sum f / phi, u = (sum e f + F/2) / sum f, p = rho/3 (Eq. 7, with
  * F = F^p + F^B of Eq. 13) of the populations at the current t.  Device
@@ -257,9 +295,9 @@ int vanse_stream_copy(vanse_lattice *h, int64_t n, void *stream);
  * parameters and buffer parity in a caller-owned device workspace; it is
  * written again automatically when a member changed or was stepped on its
  * own.  Member handles stay usable (vanse_time, vanse_read_*).  Lattices with
- * a time-varying void fraction are not batched, nor lattices combining a
- * scheme variant (model B, the Appendix B equilibrium, moving walls) with
- * solid nodes or walls in x (VANSE_ERR_UNSUPPORTED). */
+ * a time-varying void fraction or velocity rows are not batched, nor
+ * lattices combining a scheme variant (model B, the Appendix B equilibrium,
+ * moving walls) with solid nodes or walls in x (VANSE_ERR_UNSUPPORTED). */
 typedef struct vanse_batch vanse_batch;
 
 /* Workspace bytes for a batch of n lattices with the given workgroup width

@@ -24,7 +24,17 @@ struct Geo {
   int nx, ny, pitch, walls;
   int xwalls;  // half-way walls at x = -1/2 and x = nx - 1/2 as well
   long long plane;
+  int nee_lo, nee_hi;  // velocity boundary rows (first / last row), see StepPhys
+  double un_lo, un_hi;
 };
+
+// Kind of row y: 1 (2) when it is the lower (upper) velocity boundary row.
+__device__ __forceinline__ int vel_row_kind(const Geo& G, int y) {
+  if (!G.walls) return 0;
+  if (G.nee_lo && y == 0) return 1;
+  if (G.nee_hi && y == G.ny - 1) return 2;
+  return 0;
+}
 
 constexpr int NOBS = 5;  // observables per reduction record
 
@@ -240,11 +250,14 @@ __global__ void moments_rho(Geo G, const S* __restrict__ buf, const T* __restric
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= G.nx || y >= G.ny) return;
-  const T ph_x = phi[y * G.pitch + x];
-  const unsigned nb = nbr_at(G, nbr, x, y);
+  // a velocity row takes the density of the fluid row next to it
+  const int kind = vel_row_kind(G, y);
+  const int ys = kind == 1 ? 1 : (kind == 2 ? G.ny - 2 : y);
+  const T ph_x = phi[ys * G.pitch + x];
+  const unsigned nb = nbr_at(G, nbr, x, ys);
   T dm0 = 0;
   for (int i = 0; i < 9; ++i) {
-    const double f = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i, nb);
+    const double f = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, ys, i, nb);
     dm0 += static_cast<T>(f - double(rest_pop(i, ph_x, ph)));
   }
   drho_out[y * G.pitch + x] = (nb & 1u) ? T(0) : dm0 / ph_x;
@@ -266,12 +279,22 @@ __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restric
   const int y = blockIdx.y;
   double mass = 0.0, u2 = 0.0, umax = 0.0, bad = 0.0, du2 = 0.0;
   const unsigned nb = (x < G.nx && y < G.ny) ? nbr_at(G, nbr, x, y) : 0u;
+  const int vkind = (x < G.nx && y < G.ny) ? vel_row_kind(G, y) : 0;
   if (x < G.nx && y < G.ny && (nb & 1u)) {
     const long long o = (long long)y * G.nx + x;
     if (rho_o) rho_o[o] = 0.0;
     if (ux_o) ux_o[o] = 0.0;
     if (uy_o) uy_o[o] = 0.0;
     if (p_o) p_o[o] = 0.0;
+  } else if (vkind) {
+    // velocity row: the wall velocity and the fluid neighbour's density; not
+    // a fluid node, so left out of the observables
+    const long long o = (long long)y * G.nx + x;
+    const double rho = double(ph.rho0 + drho[y * G.pitch + x]);
+    if (rho_o) rho_o[o] = rho;
+    if (ux_o) ux_o[o] = vkind == 1 ? G.un_lo : G.un_hi;
+    if (uy_o) uy_o[o] = 0.0;
+    if (p_o) p_o[o] = rho / 3.0;
   } else if (x < G.nx && y < G.ny) {
     const T ph_x = phi[y * G.pitch + x];
     double m0 = 0.0, jx = 0.0, jy = 0.0;
@@ -404,6 +427,19 @@ __global__ void reduce_partials(const double* __restrict__ partials, long long n
   }
   if (threadIdx.x == 0)
     for (int q = 0; q < NOBS; ++q) out[(long long)blockIdx.x * NOBS + q] = red[q][0];
+}
+
+// In-step divergence check: reset the flag (first time a non-finite node was
+// seen, -1 for none) ...
+__global__ void set_flag(long long* __restrict__ flag, long long v) {
+  if (threadIdx.x == 0) *flag = v;
+}
+
+// ... and record time t in it when the reduced observables (record field 3,
+// the non-finite count) show a non-finite node and no earlier check did.
+__global__ void note_nonfinite(const double* __restrict__ rec, long long t,
+                               long long* __restrict__ flag) {
+  if (threadIdx.x == 0 && rec[3] > 0.0 && *flag < 0) *flag = t;
 }
 
 // Speed-of-light reference with the step's memory pattern: every node pulls

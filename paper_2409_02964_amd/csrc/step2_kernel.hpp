@@ -674,18 +674,18 @@ vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
                                            lds_handle(&stage1));
 }
 
-// Many lattices, two time steps per launch: workgroup b takes tile
-// xcd_tile(b) of the batch table (lattice tile_lattice[b], strip and row block as in the
-// one-lattice kernel); each member's two buffers alternate with the launch
-// parity as in the one-step batch.
+// Many lattices, two time steps per launch: workgroup b takes the tile that
+// entry xcd_tile(b) of the tile map names (lattice, and strip and row block
+// as in the one-lattice kernel); each member's two buffers alternate with
+// the launch parity as in the one-step batch.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(step2_waves<T>())))
 vanse_batch_step2_kernel(const BatchEntry<T>* __restrict__ entries,
-                         const int* __restrict__ tile_lattice, int launch) {
+                         const int2* __restrict__ tile_map, int launch) {
   __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;
   __shared__ Step2Stage<NT, step2_words<S, FEAT>()> stage0, stage1;
-  const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
-  const int k = tile_lattice[tile];
+  const int2 tm = tile_map[xcd_tile(int(blockIdx.x), int(gridDim.x))];
+  const int k = tm.x;
   const BatchEntry<T>& e = entries[k];
   StepGeom g = e.g;
   const int par = (e.cur0 + launch) & 1;
@@ -693,7 +693,7 @@ vanse_batch_step2_kernel(const BatchEntry<T>* __restrict__ entries,
   void* const b1 = e.g.dst;
   g.src = par ? b1 : b0;
   g.dst = par ? b0 : b1;
-  const int local = tile - e.first_tile;
+  const int local = tm.y;
   // a private copy, as the one-lattice kernel's argument: read through the
   // table the parameters could alias the stores as far as the compiler knows
   const StepPhys<T> ph = e.ph;

@@ -27,17 +27,17 @@ void launch_step2_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipSt
 }
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-void launch_batch_nt(const BatchEntry<T>* entries, const int* tile_lattice, int launch, int tiles,
+void launch_batch_nt(const BatchEntry<T>* entries, const int2* tile_map, int launch, int tiles,
                      hipStream_t st) {
   hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(tiles), dim3(NT), 0,
-                     st, entries, tile_lattice, launch);
+                     st, entries, tile_map, launch);
 }
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-void launch_batch2_nt(const BatchEntry<T>* entries, const int* tile_lattice, int launch, int tiles,
+void launch_batch2_nt(const BatchEntry<T>* entries, const int2* tile_map, int launch, int tiles,
                       hipStream_t st) {
   hipLaunchKernelGGL((vanse_batch_step2_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(tiles), dim3(2 * NT),
-                     0, st, entries, tile_lattice, launch);
+                     0, st, entries, tile_map, launch);
 }
 
 #define VANSE_STEP_ONE(W, F, NT) \
@@ -45,7 +45,7 @@ void launch_batch2_nt(const BatchEntry<T>* entries, const int* tile_lattice, int
       const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
 #define VANSE_BATCH_ONE(W, F, NT) \
   template void launch_batch_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, NT>( \
-      const BatchEntry<VANSE_T>*, const int*, int, int, hipStream_t);
+      const BatchEntry<VANSE_T>*, const int2*, int, int, hipStream_t);
 #define VANSE_WIDTHS(M, W, F) M(W, F, 64) M(W, F, 128) M(W, F, 256)
 #define VANSE_WALLS(M, F) VANSE_WIDTHS(M, false, F) VANSE_WIDTHS(M, true, F)
 
@@ -80,7 +80,7 @@ VANSE_STEP2_FEATS(VANSE_STEP2_ONE, false) VANSE_STEP2_FEATS(VANSE_STEP2_ONE, tru
 #undef VANSE_STEP2_ONE
 #define VANSE_BATCH2_ONE(W, F, NT) \
   template void launch_batch2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, NT>( \
-      const BatchEntry<VANSE_T>*, const int*, int, int, hipStream_t);
+      const BatchEntry<VANSE_T>*, const int2*, int, int, hipStream_t);
 #if VANSE_FUSED2_BATCH_MAX >= 256
 #define VANSE_BATCH2_WIDTHS(W, F) VANSE_BATCH2_ONE(W, F, 64) VANSE_BATCH2_ONE(W, F, 128) \
   VANSE_BATCH2_ONE(W, F, 256)

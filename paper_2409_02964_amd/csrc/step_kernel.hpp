@@ -68,7 +68,33 @@ struct StepPhys {
   // floating-point ALU, so a kernel would hold them in vector registers.
   T k2, k3, k12;            // 2 kappa, 3 kappa, kappa / 12
   T he, hep, hq, hn;        // 1 - s/2 for s_e, s_eps, s_q, s_nu (Eq. 16)
+  // Velocity boundary rows (Sec. 3.1, Couette flow; FEAT_ALL with walls):
+  // the first (nee_lo) or last (nee_hi) row lies on a wall moving with x
+  // velocity un_lo / un_hi and is set by non-equilibrium extrapolation from
+  // the fluid row next to it (see vel_row_eq).
+  int nee_lo, nee_hi;
+  T un_lo, un_hi;
 };
+
+// Equilibrium of Eq. (14) (or B1 with eq2) less the rest state, population
+// I: f^eq_I(phi, rho, u) - f^eq_I(phi, rho0, 0) with drho = rho - rho0.  With
+// X = kappa/phi, phi times the third-order factor is (3 phi - kappa)/2 on
+// the axes and kappa on the diagonals (phi for the second-order form).
+template <int I, typename T>
+__device__ __forceinline__ T eq_dev(T phi, T rho, T drho, T ux, T uy, T kappa, bool eq2) {
+  const T pr = phi * rho;
+  const T uu = ux * ux + uy * uy;
+  if constexpr (I == 0) {
+    return (phi - kappa * T(5.0 / 9.0)) * drho - T(2.0 / 3.0) * pr * uu;
+  } else {
+    constexpr bool axis = I < 5;
+    const T v = I == 1 ? ux : I == 2 ? uy : I == 3 ? -ux : I == 4 ? -uy
+              : I == 5 ? ux + uy : I == 6 ? uy - ux : I == 7 ? -(ux + uy) : ux - uy;
+    const T c3 = eq2 ? phi : (axis ? T(0.5) * (T(3) * phi - kappa) : kappa);
+    const T wi = axis ? T(1.0 / 9.0) : T(1.0 / 36.0);
+    return wi * (kappa * drho + T(3) * rho * c3 * v + T(4.5) * pr * v * v - T(1.5) * pr * uu);
+  }
+}
 
 struct StepGeom {
   const void* src;
@@ -249,6 +275,9 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
   const int tl = max(tc - 1, 0), tr = min(tc + 1, NT - 1);
   constexpr unsigned SB = sizeof(S);
   constexpr unsigned TB = sizeof(T);
+  // velocity boundary rows: built into the instance with every feature only
+  // (elsewhere their code would push the register budget into spills)
+  constexpr bool NEE = WALLS && FEAT == FEAT_ALL;
 
   // one buffer descriptor per array; the plane and the row go into the
   // uniform offset, the column into the per-lane offset (each population
@@ -397,6 +426,11 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       s_rho[slot4(yn)][t] = rA.drho;
       if (WALLS && yn == 0) s_rho[slot4(-1)][t] = rA.drho;      // image below
       if (WALLS && yn == ny - 1) s_rho[slot4(ny)][t] = rA.drho; // image above
+      if constexpr (NEE) {
+        // a velocity row takes the density of the fluid row next to it
+        if (ph.nee_lo && yn == 1) s_rho[slot4(0)][t] = rA.drho;
+        if (ph.nee_hi && yn == ny - 1) s_rho[slot4(yn)][t] = rB.drho;
+      }
     }
     __syncthreads();
 
@@ -454,6 +488,18 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       U2<T> b;
       a.ux = ux; a.uy = uy; a.mux = m0 * ux; a.rux = rho * ux;
       b.muy = m0 * uy; b.ruy = rho * uy;
+      if constexpr (NEE) {
+        // velocity row: the wall velocity, with the density of the fluid row
+        // next to it (row 1 is this iteration's stage-A row, row ny - 2 its
+        // stage-C row)
+        const bool lo = ph.nee_lo && yb == 0, hi = ph.nee_hi && yb == ny - 1;
+        if (lo || hi) {
+          const T rf = rho0 + (lo ? rA.drho : rC.drho);
+          const T uw = lo ? ph.un_lo : ph.un_hi;
+          a.ux = uw; a.uy = T(0); a.mux = phi * rf * uw; a.rux = rf * uw;
+          b.muy = T(0); b.ruy = T(0);
+        }
+      }
       if constexpr (XW) {  // mirror lane beyond an x-wall
         U4<T> ax;
         U2<T> bx;
@@ -617,22 +663,52 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
           for (int i = 0; i < 9; ++i) o9[i] = T(0);
         }
       }
+      // Store deviations o (rest state of void fraction ph_n) on row r.
       // Shifted storage holds deviations from the rest state of the void
       // fraction of the time the next pull runs at: rest_0 changes by
-      // rho0 d_t phi when phi moves.
-      if (SHIFT && (FEAT & FEAT_DYNPHI)) o9[0] -= rho0 * rC.dphi;
+      // rho0 d_t phi when phi moves (dph_n).
+      auto store_row = [&](T (&o)[9], T ph_n, T dph_n, int r) {
+        if (SHIFT && (FEAT & FEAT_DYNPHI)) o[0] -= rho0 * dph_n;
+        if (SHIFT) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i)
+            bstore(static_cast<S>(sizeof(S) == 2 ? o[i] * ph.scale : o[i]), dstr, xcb, poff(i, r));
+        } else {
+          bstore(static_cast<S>(o[0] + (ph_n * rho0 - ph.rest0_k)), dstr, xcb, poff(0, r));
+#pragma unroll
+          for (int i = 1; i < 5; ++i) bstore(static_cast<S>(o[i] + ph.rest_axis), dstr, xcb, poff(i, r));
+#pragma unroll
+          for (int i = 5; i < 9; ++i) bstore(static_cast<S>(o[i] + ph.rest_diag), dstr, xcb, poff(i, r));
+        }
+      };
 
-      if (SHIFT) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-          bstore(static_cast<S>(sizeof(S) == 2 ? o9[i] * ph.scale : o9[i]), dstr, xcb, poff(i, yo));
-      } else {
-        bstore(static_cast<S>(o9[0] + (phi * rho0 - ph.rest0_k)), dstr, xcb, poff(0, yo));
-#pragma unroll
-        for (int i = 1; i < 5; ++i) bstore(static_cast<S>(o9[i] + ph.rest_axis), dstr, xcb, poff(i, yo));
-#pragma unroll
-        for (int i = 5; i < 9; ++i) bstore(static_cast<S>(o9[i] + ph.rest_diag), dstr, xcb, poff(i, yo));
+      if constexpr (NEE) {
+        // Velocity rows (Sec. 3.1: non-equilibrium extrapolation for the
+        // moving wall of Couette flow).  The fluid row next to a velocity row
+        // also sets that row's post-collision state,
+        //   f+(x_b) = f^eq(phi_b, rho_f, u_w) + f+(x_f) - f^eq(phi_f, rho_f, u_f),
+        // here on deviations; the velocity row itself stores nothing.
+        auto vel_row = [&](int rb, T uw) {
+          const unsigned ro = unsigned(rb) * unsigned(pitch) * TB;
+          const T phb = bload<T>(phir, xcT, ro);
+          const T dphb = (FEAT & FEAT_DYNPHI) ? bload<T>(phinr, xcT, ro) - phb : T(0);
+          T ob[9];
+          ob[0] = o9[0] + (eq_dev<0>(phb, rho, drho, uw, T(0), kappa, eq2) - eq_dev<0>(phi, rho, drho, ux, uy, kappa, eq2));
+          ob[1] = o9[1] + (eq_dev<1>(phb, rho, drho, uw, T(0), kappa, eq2) - eq_dev<1>(phi, rho, drho, ux, uy, kappa, eq2));
+          ob[2] = o9[2] + (eq_dev<2>(phb, rho, drho, uw, T(0), kappa, eq2) - eq_dev<2>(phi, rho, drho, ux, uy, kappa, eq2));
+          ob[3] = o9[3] + (eq_dev<3>(phb, rho, drho, uw, T(0), kappa, eq2) - eq_dev<3>(phi, rho, drho, ux, uy, kappa, eq2));
+          ob[4] = o9[4] + (eq_dev<4>(phb, rho, drho, uw, T(0), kappa, eq2) - eq_dev<4>(phi, rho, drho, ux, uy, kappa, eq2));
+          ob[5] = o9[5] + (eq_dev<5>(phb, rho, drho, uw, T(0), kappa, eq2) - eq_dev<5>(phi, rho, drho, ux, uy, kappa, eq2));
+          ob[6] = o9[6] + (eq_dev<6>(phb, rho, drho, uw, T(0), kappa, eq2) - eq_dev<6>(phi, rho, drho, ux, uy, kappa, eq2));
+          ob[7] = o9[7] + (eq_dev<7>(phb, rho, drho, uw, T(0), kappa, eq2) - eq_dev<7>(phi, rho, drho, ux, uy, kappa, eq2));
+          ob[8] = o9[8] + (eq_dev<8>(phb, rho, drho, uw, T(0), kappa, eq2) - eq_dev<8>(phi, rho, drho, ux, uy, kappa, eq2));
+          store_row(ob, phb, dphb, rb);
+        };
+        if (ph.nee_lo && yo == 1) vel_row(0, ph.un_lo);
+        if (ph.nee_hi && yo == ny - 2) vel_row(ny - 1, ph.un_hi);
+        if ((ph.nee_lo && yo == 0) || (ph.nee_hi && yo == ny - 1)) return;
       }
+      store_row(o9, phi, rC.dphi, yo);
     }
   };
 
@@ -706,10 +782,12 @@ vanse_step_kernel(StepGeom g, StepPhys<T> ph) {
   step_tile<S, T, SHIFT, WALLS, FEAT, NT, PD>(g, ph, tile % g.strips, tile / g.strips, lds);
 }
 
-// Many independent lattices per launch.  Lattice k owns tiles
-// [first_tile_k, first_tile_k + strips_k * row_blocks_k); workgroup b takes
-// tile xcd_tile(b).  The two population buffers of a lattice alternate with
-// parity (cur0_k + launch) & 1.
+// Many independent lattices per launch.  Entry xcd_tile(b) of the tile map
+// gives workgroup b its lattice and the tile's index within that lattice
+// (strip local % strips, row block local / strips); the host orders the map
+// so that workgroups, in launch order, take the tiles with the most rows
+// first.  The two population buffers of a lattice alternate with parity
+// (cur0_k + launch) & 1.
 template <typename T>
 struct BatchEntry {
   StepGeom g;          // src/dst hold buffer 0 and buffer 1
@@ -723,10 +801,10 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT,
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(WPE)))
 vanse_batch_step_kernel(const BatchEntry<T>* __restrict__ entries,
-                        const int* __restrict__ tile_lattice, int launch) {
+                        const int2* __restrict__ tile_map, int launch) {
   __shared__ StepLds<T, NT> lds;
-  const int tile = xcd_tile(int(blockIdx.x), int(gridDim.x));
-  const int k = tile_lattice[tile];
+  const int2 tm = tile_map[xcd_tile(int(blockIdx.x), int(gridDim.x))];
+  const int k = tm.x;
   const BatchEntry<T>& e = entries[k];
   StepGeom g = e.g;
   const int par = (e.cur0 + launch) & 1;
@@ -734,7 +812,7 @@ vanse_batch_step_kernel(const BatchEntry<T>* __restrict__ entries,
   void* const b1 = e.g.dst;
   g.src = par ? b1 : b0;
   g.dst = par ? b0 : b1;
-  const int local = tile - e.first_tile;
+  const int local = tm.y;
   // a private copy, as the one-lattice kernel's argument (read through the
   // table the parameters could alias the stores as far as the compiler knows)
   const StepPhys<T> ph = e.ph;

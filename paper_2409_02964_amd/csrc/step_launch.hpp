@@ -24,13 +24,13 @@ void launch_step2_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipSt
 
 // Many lattices: one workgroup per tile of the batch table.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-void launch_batch_nt(const BatchEntry<T>* entries, const int* tile_lattice, int launch, int tiles,
+void launch_batch_nt(const BatchEntry<T>* entries, const int2* tile_map, int launch, int tiles,
                      hipStream_t st);
 
 // Many lattices, two time steps per launch: one workgroup of 2 NT lanes per
 // tile of the batch table.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-void launch_batch2_nt(const BatchEntry<T>* entries, const int* tile_lattice, int launch, int tiles,
+void launch_batch2_nt(const BatchEntry<T>* entries, const int2* tile_map, int launch, int tiles,
                       hipStream_t st);
 
 }  // namespace vanse_dev

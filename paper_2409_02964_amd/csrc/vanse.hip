@@ -6,6 +6,7 @@
 // the caller's stream.  No device memory is allocated here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <type_traits>
@@ -58,7 +59,8 @@ int compute_bytes(int precision) { return precision == VANSE_F64 ? 8 : 4; }
 int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 
 struct Layout {
-  size_t pop[2], phi, phin, nbr, fx, fy, beta, drho, uprev, partials, partials2, result, badcount, total;
+  size_t pop[2], phi, phin, nbr, fx, fy, beta, drho, uprev, partials, partials2, result, badcount,
+      check, total;
   long long plane;
   int pitch;
   long long max_partials;
@@ -108,6 +110,7 @@ int make_layout(const vanse_desc* d, Layout* L) {
   L->partials2 = off; off = align256(off + 1024 * NOBS * sizeof(double));
   L->result = off; off = align256(off + NOBS * sizeof(double));
   L->badcount = off; off = align256(off + sizeof(unsigned long long));
+  L->check = off; off = align256(off + sizeof(long long));
   L->total = off;
   return VANSE_OK;
 }
@@ -126,6 +129,8 @@ struct vanse_lattice {
   int scale_by_phi;
   int model_b, eq2;  // scheme variants (vanse_set_scheme)
   double uw_lo, uw_hi;  // wall velocities (vanse_set_wall_velocity)
+  int nee_lo, nee_hi;   // velocity boundary rows (vanse_set_velocity_rows)
+  double un_lo, un_hi;
   vanse_rates rates;
   int threads, rows;  // launch shape of the step kernel
   int fuse;           // time steps per launch of the plain step (1 or 2)
@@ -133,6 +138,7 @@ struct vanse_lattice {
   bool tiling_default;
   int storage_exp;
   long long version;  // bumped by every call that changes what the step reads
+  int64_t check_every;  // vanse_step runs the observables at multiples of this t (0: never)
 };
 
 namespace {
@@ -200,6 +206,10 @@ StepPhys<T> make_phys(const vanse_lattice* h) {
   p.hep = T(1) - T(0.5) * p.s_eps;
   p.hq = T(1) - T(0.5) * p.s_q;
   p.hn = T(1) - T(0.5) * p.s_nu;
+  p.nee_lo = h->nee_lo;
+  p.nee_hi = h->nee_hi;
+  p.un_lo = T(h->un_lo);
+  p.un_hi = T(h->un_hi);
   return p;
 }
 
@@ -211,6 +221,10 @@ Geo make_geo(const vanse_lattice* h) {
   G.walls = h->d.bc_y == VANSE_WALL;
   G.xwalls = h->d.bc_x == VANSE_WALL;
   G.plane = h->L.plane;
+  G.nee_lo = h->nee_lo;
+  G.nee_hi = h->nee_hi;
+  G.un_lo = h->un_lo;
+  G.un_hi = h->un_hi;
   return G;
 }
 
@@ -245,6 +259,7 @@ constexpr int FEAT_MOVING = FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG;
 int feat_of(const vanse_lattice* h) {
   const vanse_desc& d = h->d;
   const bool scheme = h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0;
+  if (h->nee_lo || h->nee_hi) return FEAT_ALL;  // velocity rows: built there only
   if (d.has_mask || d.bc_x == VANSE_WALL) {
     if (scheme) return FEAT_ALL;
     if (d.dynamic_phi || (d.bc_x == VANSE_WALL && (d.has_force_field || d.has_drag)))
@@ -462,6 +477,8 @@ int vanse_create(const vanse_desc* d, void* workspace, size_t bytes, vanse_latti
   h->scale_by_phi = 1;
   h->model_b = h->eq2 = 0;
   h->uw_lo = h->uw_hi = 0.0;
+  h->nee_lo = h->nee_hi = 0;
+  h->un_lo = h->un_hi = 0.0;
   h->rates = vanse_rates{1.0, 1.2, 1.2, 1.2, 1.2};
   h->storage_exp = 12;
   h->version = 0;
@@ -469,6 +486,7 @@ int vanse_create(const vanse_desc* d, void* workspace, size_t bytes, vanse_latti
   default_tiling(h);
   h->fuse = 1;
   h->rows2 = 0;
+  h->check_every = 0;
   *out = h;
   return VANSE_OK;
 }
@@ -509,8 +527,31 @@ int vanse_set_wall_velocity(vanse_lattice* h, double u_lo, double u_hi) {
   if (h->d.bc_y != VANSE_WALL) return fail(VANSE_ERR_STATE, "the lattice has no walls");
   if (!std::isfinite(u_lo) || !std::isfinite(u_hi)) return fail(VANSE_ERR_INVALID_ARG, "wall velocities must be finite");
   if (h->state_set) return fail(VANSE_ERR_STATE, "wall velocities must be set before the populations");
+  if ((h->nee_lo && u_lo != 0.0) || (h->nee_hi && u_hi != 0.0))
+    return fail(VANSE_ERR_INVALID_ARG, "a face with a velocity row takes no half-way wall velocity");
   h->uw_lo = u_lo;
   h->uw_hi = u_hi;
+  h->version += 1;
+  return VANSE_OK;
+}
+
+int vanse_set_velocity_rows(vanse_lattice* h, int faces, double u_lo, double u_hi) {
+  if (int rc = check_handle(h)) return rc;
+  if (faces < 0 || faces > (VANSE_FACE_LO | VANSE_FACE_HI))
+    return fail(VANSE_ERR_INVALID_ARG, "faces must be a combination of VANSE_FACE_LO and VANSE_FACE_HI");
+  if (h->d.bc_y != VANSE_WALL) return fail(VANSE_ERR_STATE, "the lattice has no walls");
+  if (h->d.bc_x != VANSE_PERIODIC || h->d.has_mask)
+    return fail(VANSE_ERR_UNSUPPORTED, "velocity rows are built for lattices periodic in x without solid nodes");
+  if (h->d.ny < 3) return fail(VANSE_ERR_INVALID_ARG, "velocity rows need ny >= 3 (got %d)", h->d.ny);
+  if (!std::isfinite(u_lo) || !std::isfinite(u_hi)) return fail(VANSE_ERR_INVALID_ARG, "velocities must be finite");
+  if (h->state_set) return fail(VANSE_ERR_STATE, "velocity rows must be set before the populations");
+  const int lo = (faces & VANSE_FACE_LO) ? 1 : 0, hi = (faces & VANSE_FACE_HI) ? 1 : 0;
+  if ((lo && h->uw_lo != 0.0) || (hi && h->uw_hi != 0.0))
+    return fail(VANSE_ERR_INVALID_ARG, "a face with a half-way wall velocity cannot be a velocity row");
+  h->nee_lo = lo;
+  h->nee_hi = hi;
+  h->un_lo = lo ? u_lo : 0.0;
+  h->un_hi = hi ? u_hi : 0.0;
   h->version += 1;
   return VANSE_OK;
 }
@@ -676,20 +717,65 @@ int vanse_set_populations(vanse_lattice* h, const double* f, double rho0, void* 
   return fill(h, f, rho0, 0.0, 0.0, stream);
 }
 
+static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double* p, bool partials,
+                   void* stream, bool keep_u = false);
+static int reduce_on_device(vanse_lattice* h, hipStream_t st);
+
+static int advance(vanse_lattice* h, int64_t n, hipStream_t st) {
+  return by_precision(h, [&](auto* s_tag, auto* t_tag, auto shift) -> int {
+    using S = std::remove_pointer_t<decltype(s_tag)>;
+    using T = std::remove_pointer_t<decltype(t_tag)>;
+    return run_steps<S, T, decltype(shift)::value>(h, n, st);
+  });
+}
+
 int vanse_step(vanse_lattice* h, int64_t nsteps, void* stream) {
   if (int rc = check_ready(h)) return rc;
   if (!h->state_set) return fail(VANSE_ERR_STATE, "populations not initialised");
   if (nsteps < 0) return fail(VANSE_ERR_INVALID_ARG, "nsteps must be >= 0");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  return by_precision(h, [&](auto* s_tag, auto* t_tag, auto shift) -> int {
-    using S = std::remove_pointer_t<decltype(s_tag)>;
-    using T = std::remove_pointer_t<decltype(t_tag)>;
-    return run_steps<S, T, decltype(shift)::value>(h, nsteps, st);
-  });
+  if (h->check_every <= 0) return advance(h, nsteps, st);
+  // Observables at every multiple of check_every: enqueued between the
+  // launches, each one's non-finite count folded into a device flag that
+  // holds the first time it was seen; one synchronizing read at the end.
+  long long* flag = reinterpret_cast<long long*>(h->ws + h->L.check);
+  bool checked = false;
+  while (nsteps > 0) {
+    const int64_t k = h->check_every;
+    const int64_t m = std::min<int64_t>(nsteps, k - h->t % k);
+    if (int rc = advance(h, m, st)) return rc;
+    nsteps -= m;
+    if (h->t % k == 0) {
+      if (!checked) {
+        hipLaunchKernelGGL(set_flag, dim3(1), dim3(64), 0, st, flag, -1LL);
+        checked = true;
+      }
+      if (int rc = moments(h, nullptr, nullptr, nullptr, nullptr, true, stream)) return rc;
+      if (int rc = reduce_on_device(h, st)) return rc;
+      hipLaunchKernelGGL(note_nonfinite, dim3(1), dim3(64), 0, st,
+                         (const double*)(h->ws + h->L.result), (long long)h->t, flag);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  if (!checked) return VANSE_OK;
+  long long tbad = -1;
+  HIP_TRY(hipMemcpyAsync(&tbad, flag, sizeof(tbad), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (tbad >= 0)
+    return fail(VANSE_ERR_DIVERGED, "non-finite values observed at t = %lld (checked every %lld steps)",
+                tbad, (long long)h->check_every);
+  return VANSE_OK;
+}
+
+int vanse_set_check_interval(vanse_lattice* h, int64_t k) {
+  if (int rc = check_handle(h)) return rc;
+  if (k < 0) return fail(VANSE_ERR_INVALID_ARG, "check interval must be >= 0 (got %lld)", (long long)k);
+  h->check_every = k;
+  return VANSE_OK;
 }
 
 static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double* p, bool partials,
-                   void* stream, bool keep_u = false) {
+                   void* stream, bool keep_u) {
   if (int rc = check_ready(h)) return rc;
   if (!h->state_set) return fail(VANSE_ERR_STATE, "populations not initialised");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -724,7 +810,7 @@ static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double
 
 int vanse_read_moments(vanse_lattice* h, double* rho, double* ux, double* uy, double* p, void* stream) {
   if (!rho) return fail(VANSE_ERR_INVALID_ARG, "rho output is NULL");
-  return moments(h, rho, ux, uy, p, false, stream);
+  return moments(h, rho, ux, uy, p, false, stream, false);
 }
 
 int vanse_read_populations(vanse_lattice* h, double* f, void* stream) {
@@ -748,9 +834,9 @@ int vanse_read_populations(vanse_lattice* h, double* f, void* stream) {
   return VANSE_OK;
 }
 
-// Reduce the block partials of the last moments pass to one record and copy
-// it to the host (synchronizes the stream).
-static int reduce_to_host(vanse_lattice* h, double* rec, hipStream_t st) {
+// Reduce the block partials of the last moments pass to one record in the
+// workspace (enqueued only).
+static int reduce_on_device(vanse_lattice* h, hipStream_t st) {
   long long n = (long long)((h->d.nx + 255) / 256) * h->d.ny;
   const double* in = (const double*)(h->ws + h->L.partials);
   double* mid = (double*)(h->ws + h->L.partials2);
@@ -761,6 +847,13 @@ static int reduce_to_host(vanse_lattice* h, double* rec, hipStream_t st) {
   hipLaunchKernelGGL(reduce_partials, dim3((unsigned)nchunks), dim3(256), 0, st, in, n, chunk, mid);
   hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, (const double*)mid, nchunks, nchunks, res);
   HIP_TRY(hipGetLastError());
+  return VANSE_OK;
+}
+
+// The same, copied to the host (synchronizes the stream).
+static int reduce_to_host(vanse_lattice* h, double* rec, hipStream_t st) {
+  if (int rc = reduce_on_device(h, st)) return rc;
+  const double* res = (const double*)(h->ws + h->L.result);
   HIP_TRY(hipMemcpyAsync(rec, res, NOBS * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return VANSE_OK;
@@ -768,7 +861,7 @@ static int reduce_to_host(vanse_lattice* h, double* rec, hipStream_t st) {
 
 int vanse_observe(vanse_lattice* h, double* out, void* stream) {
   if (!out) return fail(VANSE_ERR_INVALID_ARG, "out is NULL");
-  if (int rc = moments(h, nullptr, nullptr, nullptr, nullptr, true, stream)) return rc;
+  if (int rc = moments(h, nullptr, nullptr, nullptr, nullptr, true, stream, false)) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
   double rec[NOBS];
   if (int rc = reduce_to_host(h, rec, st)) return rc;
@@ -926,7 +1019,8 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
     const vanse_desc& d = lats[k]->d;
     if (!batch_ok(lats[k]))
       return fail(VANSE_ERR_UNSUPPORTED,
-                  "lattice %d: batches take no time-varying phi, nor a scheme variant with solid nodes", k);
+                  "lattice %d: batches take no time-varying phi, velocity rows, nor a scheme variant "
+                  "with solid nodes", k);
     if (d.precision != d0.precision || d.bc_x != d0.bc_x || d.bc_y != d0.bc_y ||
         d.has_force_field != d0.has_force_field ||
         d.has_drag != d0.has_drag || feat_of(lats[k]) != feat_of(lats[0]))
@@ -963,7 +1057,7 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
                                                                             : sizeof(BatchEntry<float>);
   *entries_off = 0;
   *tiles_off = align256((size_t)n * esz);
-  *bytes = align256(*tiles_off + (size_t)tiles * sizeof(int));
+  *bytes = align256(*tiles_off + (size_t)tiles * sizeof(int2));
   return VANSE_OK;
 }
 
@@ -998,19 +1092,50 @@ void fill_entries(vanse_batch* b, std::vector<char>* blob) {
   }
 }
 
-// Upload the lattice table and the tile -> lattice map (host pageable copies,
+// Tile map of a batch: for every tile position, the lattice and the tile's
+// index within it.  Workgroup b reads position xcd_tile(b): the workgroups
+// dealt to XCD x read the x-th contiguous run of positions, in order.  The
+// tiles are laid out lattice by lattice (strips side by side, so that
+// neighbouring strips, which read each other's halo columns, share the
+// XCD's L2), and each XCD's run is then ordered by decreasing sweep length
+// (rows of the tile: a lattice's last row block may be short), ties in
+// lattice order: the short tiles fill the tail of the launch
+// (longest-processing-time-first list scheduling on every XCD).
+std::vector<int2> batch_tile_map(const vanse_batch* b) {
+  struct Item { int rows, k, local; };
+  std::vector<Item> items;
+  items.reserve((size_t)b->total_tiles);
+  const int out_w = batch_out_w(b->threads, b->fuse);
+  for (size_t k = 0; k < b->lats.size(); ++k) {
+    const vanse_desc& d = b->lats[k]->d;
+    const int r = b->rows[k];
+    const int strips = (d.nx + out_w - 1) / out_w;
+    const int nby = (d.ny + r - 1) / r;
+    for (int local = 0; local < strips * nby; ++local) {
+      const int by = local / strips;
+      items.push_back({std::min(r, d.ny - by * r), (int)k, local});
+    }
+  }
+  const int nb = b->total_tiles, q = nb >> 3, rem = nb & 7;
+  for (int x = 0; x < 8; ++x) {  // the run of XCD x, as in xcd_tile
+    const int s0 = x * q + std::min(x, rem), s1 = s0 + q + (x < rem ? 1 : 0);
+    std::stable_sort(items.begin() + s0, items.begin() + s1,
+                     [](const Item& a, const Item& c) { return a.rows > c.rows; });
+  }
+  std::vector<int2> map((size_t)nb);
+  for (int i = 0; i < nb; ++i) map[(size_t)i] = make_int2(items[(size_t)i].k, items[(size_t)i].local);
+  return map;
+}
+
+// Upload the lattice table and the tile map (host pageable copies,
 // synchronized: only when parameters or buffer parity change).
 int batch_upload(vanse_batch* b, hipStream_t st) {
   std::vector<char> blob;
   if (b->lats[0]->d.precision == VANSE_F64) fill_entries<double>(b, &blob);
   else fill_entries<float>(b, &blob);
-  std::vector<int> tl((size_t)b->total_tiles);
-  for (size_t k = 0; k < b->lats.size(); ++k) {
-    const int end = (k + 1 < b->lats.size()) ? b->first[k + 1] : b->total_tiles;
-    for (int i = b->first[k]; i < end; ++i) tl[(size_t)i] = (int)k;
-  }
+  const std::vector<int2> tl = batch_tile_map(b);
   HIP_TRY(hipMemcpyAsync(b->ws + b->entries_off, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(b->ws + b->tiles_off, tl.data(), tl.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b->ws + b->tiles_off, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   b->versions.resize(b->lats.size());
   b->cur0.resize(b->lats.size());
@@ -1026,7 +1151,7 @@ int batch_upload(vanse_batch* b, hipStream_t st) {
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
 void batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
   const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
-  const int* TL = reinterpret_cast<const int*>(b->ws + b->tiles_off);
+  const int2* TL = reinterpret_cast<const int2*>(b->ws + b->tiles_off);
   if constexpr ((FEAT & ~(FEAT_FORCE | FEAT_DRAG)) == 0) {
     if (b->fuse == 2) {
       if constexpr (sizeof(T) == 8) {  // halves of 64 or 128 lanes (batch_layout)
@@ -1188,8 +1313,14 @@ int vanse_batch_step(vanse_batch* b, int64_t nsteps, void* stream) {
     if (!b->graph && left >= glaunch) {
       hipGraph_t graph;
       HIP_TRY(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
-      for (int s = 0; s < glaunch; ++s) batch_launch(b, s, b->own);
-      HIP_TRY(hipStreamEndCapture(b->own, &graph));
+      int lrc = VANSE_OK;
+      for (int s = 0; s < glaunch && lrc == VANSE_OK; ++s) lrc = batch_launch(b, s, b->own);
+      const hipError_t ce = hipStreamEndCapture(b->own, &graph);
+      if (lrc != VANSE_OK) {
+        if (ce == hipSuccess) (void)hipGraphDestroy(graph);
+        return lrc;
+      }
+      if (ce != hipSuccess) return fail(VANSE_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ce));
       const hipError_t e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e != hipSuccess) return fail(VANSE_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));

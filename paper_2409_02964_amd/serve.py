@@ -173,5 +173,6 @@ def summarize(done, wall):
             "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
             "mean_latency_s": round(float(lat.mean()), 4),
             "converged": int(sum(s.converged for s in done)),
+            "mean_steps": round(float(np.mean([s.steps for s in done])), 1),
             "mlups": round(nodes_steps / wall / 1e6, 1),
             "wall_s": round(wall, 3)}

@@ -29,11 +29,13 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "workspace", -3: "HIP error", -4:
 
 EXPORTS = [
     "vanse_workspace_bytes", "vanse_create", "vanse_destroy", "vanse_set_params",
-    "vanse_set_scheme", "vanse_set_wall_velocity", "vanse_set_body_force",
+    "vanse_set_scheme", "vanse_set_wall_velocity", "vanse_set_velocity_rows",
+    "vanse_set_body_force",
     "vanse_set_void_fraction",
     "vanse_set_void_fraction_next",
     "vanse_set_mask", "vanse_set_force_field", "vanse_set_drag",
-    "vanse_init_equilibrium", "vanse_set_populations", "vanse_step", "vanse_read_moments",
+    "vanse_init_equilibrium", "vanse_set_populations", "vanse_step",
+    "vanse_set_check_interval", "vanse_read_moments",
     "vanse_read_populations", "vanse_observe", "vanse_residual", "vanse_set_tiling",
     "vanse_get_tiling", "vanse_set_steps_per_pass", "vanse_get_fused_tiling",
     "vanse_set_storage_exponent", "vanse_stream_copy", "vanse_time", "vanse_error_string",
@@ -86,6 +88,7 @@ def lib():
                 "vanse_set_body_force": [vp, d, d, i32],
                 "vanse_set_scheme": [vp, i32, i32],
                 "vanse_set_wall_velocity": [vp, d, d],
+                "vanse_set_velocity_rows": [vp, i32, d, d],
                 "vanse_set_void_fraction": [vp, vp, vp],
                 "vanse_set_void_fraction_next": [vp, vp, vp],
                 "vanse_set_mask": [vp, vp, vp],
@@ -94,6 +97,7 @@ def lib():
                 "vanse_init_equilibrium": [vp, d, d, d, vp],
                 "vanse_set_populations": [vp, vp, d, vp],
                 "vanse_step": [vp, i64, vp],
+                "vanse_set_check_interval": [vp, i64],
                 "vanse_read_moments": [vp, vp, vp, vp, vp, vp],
                 "vanse_read_populations": [vp, vp, vp],
                 "vanse_observe": [vp, pd, vp],
@@ -213,6 +217,15 @@ class Lattice:
         check(lib().vanse_set_wall_velocity(self.handle, float(u_lo), float(u_hi)))
         return self
 
+    def set_velocity_rows(self, u_lo=None, u_hi=None):
+        """Velocity boundary rows by non-equilibrium extrapolation (Couette
+        flow, Sec. 3.1): x velocity of the first / last row, None for an
+        ordinary row (before the populations); see vanse_set_velocity_rows."""
+        faces = (1 if u_lo is not None else 0) | (2 if u_hi is not None else 0)
+        check(lib().vanse_set_velocity_rows(self.handle, faces, float(u_lo or 0.0),
+                                            float(u_hi or 0.0)))
+        return self
+
     def set_body_force(self, gx, gy=0.0, scale_by_phi=True):
         check(lib().vanse_set_body_force(self.handle, float(gx), float(gy),
                                          1 if scale_by_phi else 0))
@@ -294,6 +307,12 @@ class Lattice:
     # ---- stepping ----
     def step(self, n=1, stream=None):
         check(lib().vanse_step(self.handle, int(n), _stream(stream)))
+        return self
+
+    def set_check_interval(self, k):
+        """Run the FP64 observables inside step() at every multiple k of t and
+        raise Diverged when one saw a non-finite node (0: off); see vanse.h."""
+        check(lib().vanse_set_check_interval(self.handle, int(k)))
         return self
 
     def stream_copy(self, n=1, stream=None):

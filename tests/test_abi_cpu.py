@@ -200,3 +200,38 @@ def test_tallest_lattice():
     assert V.workspace_bytes(64, 65535, "f16s", "wall") > 0
     with pytest.raises(V.VanseError, match="too tall"):
         V.workspace_bytes(64, 65536, "f16s", "wall")
+
+
+def test_velocity_rows_validation_on_the_host():
+    L = V.lib()
+    per = _fake_handle()
+    assert L.vanse_set_velocity_rows(per, 2, 0.0, 1e-3) == -4        # no walls
+    box = _fake_handle(bcy=1, bcx=1)
+    assert L.vanse_set_velocity_rows(box, 2, 0.0, 1e-3) == -6        # walls in x
+    solid = _fake_handle(bcy=1, mask=1)
+    assert L.vanse_set_velocity_rows(solid, 2, 0.0, 1e-3) == -6      # solid nodes
+    thin = _fake_handle(ny=2, bcy=1)
+    assert L.vanse_set_velocity_rows(thin, 1, 1e-3, 0.0) == -1       # no fluid row
+    h = _fake_handle(bcy=1)
+    assert L.vanse_set_velocity_rows(h, 4, 0.0, 1e-3) == -1          # unknown face bit
+    assert L.vanse_set_velocity_rows(h, 2, 0.0, float("inf")) == -1
+    assert L.vanse_set_wall_velocity(h, 1e-3, 0.0) == 0
+    assert L.vanse_set_velocity_rows(h, 1, 1e-3, 0.0) == -1          # the half-way wall moves
+    assert L.vanse_set_velocity_rows(h, 2, 0.0, 1e-3) == 0
+    assert L.vanse_set_wall_velocity(h, 1e-3, 2e-3) == -1            # face is a velocity row
+    other = _fake_handle(bcy=1)
+    arr = (C.c_void_p * 2)(h.value, other.value)
+    n = C.c_size_t()
+    assert L.vanse_batch_workspace_bytes(arr, 1, 128, 0, C.byref(n)) == -6   # not batched
+    for x in (per, box, solid, thin, h, other):
+        assert L.vanse_destroy(x) == 0
+
+
+def test_check_interval_validation_on_the_host():
+    L = V.lib()
+    h = _fake_handle()
+    assert L.vanse_set_check_interval(h, -1) == -1
+    assert L.vanse_set_check_interval(h, 0) == 0
+    assert L.vanse_set_check_interval(h, 100) == 0
+    assert L.vanse_step(h, 10, None) == -4                          # still no state: no GPU work
+    assert L.vanse_destroy(h) == 0

@@ -230,3 +230,36 @@ def test_non_finite_state_is_reported():
         lat.observe()
     with pytest.raises(Diverged):  # the residual reports it too
         lat.residual()
+
+
+def test_step_check_interval_reports_divergence():
+    """With a check interval the observables run inside vanse_step, and a
+    non-finite node (injected as data) makes the call report divergence at
+    the first checked time; the steps still run to the end of the call."""
+    _torch()
+    from paper_2409_02964_amd.vanse import Diverged
+    lat = lattice(64, 48, "f32s", "periodic")
+    f = start_state(lat, 5)
+    f[3, 20, 30] = np.nan
+    lat.set_populations(f).set_check_interval(4)
+    lat.step(2)                       # no multiple of 4 reached: not checked
+    with pytest.raises(Diverged, match="t = 4"):
+        lat.step(7)
+    assert lat.t == 9
+
+
+@pytest.mark.parametrize("prec,spp", [("f32s", 1), ("f32s", 2), ("f64", 2)])
+def test_step_check_interval_changes_nothing(prec, spp):
+    """Checked and unchecked runs of a finite state are bitwise equal, and
+    the check's last record is what vanse_observe reports at that time."""
+    _torch()
+    a = lattice(70, 33, prec, "wall", drag=True)
+    b = lattice(70, 33, prec, "wall", drag=True)
+    for lat in (a, b):
+        lat.set_steps_per_pass(spp).set_populations(start_state(lat, 8))
+    a.set_check_interval(3)
+    a.step(7).step(5)
+    b.step(12)
+    assert a.t == b.t == 12
+    assert np.array_equal(a.read_populations().cpu().numpy(), b.read_populations().cpu().numpy())
+    assert a.observe() == b.observe()
