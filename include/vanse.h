@@ -212,9 +212,12 @@ int vanse_step(vanse_lattice *h, int64_t nsteps, void *stream);
 /* Divergence check inside vanse_step: with k > 0, every time t that is a
  * multiple of k reached during a vanse_step call is followed by the FP64
  * observables of vanse_observe (enqueued between the launches; the record
- * of the last one is what vanse_observe would return at that t), and the
+ * of the last one is what vanse_observe would return at that time), and the
  * call ends with one synchronizing read: VANSE_ERR_DIVERGED, with the first
- * such t in vanse_last_error(), when one of them counted a non-finite node.
+ * checked time in vanse_last_error(), when one of them counted a non-finite
+ * node.  With two steps per launch a check follows the launch that reaches
+ * the multiple of k (at t or t + 1), so the launches, and the results, are
+ * those of the unchecked call.
  * The steps run to the end of the call either way (t advances by nsteps).
  * k = 0 (the default) turns the check off.  Batches do not run it. */
 int vanse_set_check_interval(vanse_lattice *h, int64_t k);

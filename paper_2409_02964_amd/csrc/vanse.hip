@@ -740,12 +740,18 @@ int vanse_step(vanse_lattice* h, int64_t nsteps, void* stream) {
   // holds the first time it was seen; one synchronizing read at the end.
   long long* flag = reinterpret_cast<long long*>(h->ws + h->L.check);
   bool checked = false;
+  // With two steps per launch a check waits for the end of the launch that
+  // reaches the multiple of k (t or t + 1), so that the launches of the call
+  // are those of an unchecked call: pairs, and one single step at the end
+  // when nsteps is odd.
+  const bool pairs = fused_ok(h);
   while (nsteps > 0) {
     const int64_t k = h->check_every;
-    const int64_t m = std::min<int64_t>(nsteps, k - h->t % k);
+    int64_t m = std::min<int64_t>(nsteps, k - h->t % k);
+    if (pairs && (m & 1) && m < nsteps) m += 1;
     if (int rc = advance(h, m, st)) return rc;
     nsteps -= m;
-    if (h->t % k == 0) {
+    if (h->t % k == 0 || (pairs && (h->t - 1) % k == 0 && m > 1)) {
       if (!checked) {
         hipLaunchKernelGGL(set_flag, dim3(1), dim3(64), 0, st, flag, -1LL);
         checked = true;
