@@ -239,6 +239,21 @@ int vanse_read_populations(vanse_lattice *h, double *f, void *stream);
  * VANSE_ERR_DIVERGED (after filling out) when out[3] > 0. */
 int vanse_observe(vanse_lattice *h, double *out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * observables of vanse_observe, bitwise the same values, computed without
+ * the lattice workspace's scratch -- the density of every node and of its
+ * neighbours is formed again from the populations, and the FP64 block
+ * partials and the reduction records live in a static device array of the
+ * library (about 5.3 MB, held by every device the library runs on until the
+ * process ends).  Allocates nothing.  Limit: ceil(nx/256) * ny <= 131072
+ * (for example 4096 x 8192 or 8192 x 4096); larger lattices get
+ * VANSE_ERR_INVALID_ARG before any device work.  Calls that overlap on one
+ * device share the array and race: serialize them (one stream, or events).
+ * `out` is HOST memory (4 doubles); synchronizes the stream; returns
+ * VANSE_ERR_DIVERGED (after filling out) when out[3] > 0. */
+int vanse_observe_noalloc(vanse_lattice *h, double *out, void *stream);
+
 /* Steady-state residual support: out[0] = sum_x |u(t) - u(t')|^2 where t'
  * is the time of the previous vanse_residual call on this lattice (-1 on
  * the first call after initialisation), out[1] = sum_x |u(t)|^2, out[2] =

@@ -242,15 +242,12 @@ __global__ void read_pops(Geo G, const S* __restrict__ buf, const T* __restrict_
         (nb & 1u) ? 0.0 : pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, y, i, nb);
 }
 
-// Pass 1 of the macroscopic read-out: delta rho (in T) to a scratch plane.
+// delta rho = sum_i (f_i - rest_i) / phi of node (x, y), in T; a velocity
+// row takes the density of the fluid row next to it; 0 on a solid node.
 template <typename S, typename T, bool SHIFT>
-__global__ void moments_rho(Geo G, const S* __restrict__ buf, const T* __restrict__ phi,
-                            StepPhys<T> ph, T* __restrict__ drho_out,
-                            const uint16_t* __restrict__ nbr) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
-  if (x >= G.nx || y >= G.ny) return;
-  // a velocity row takes the density of the fluid row next to it
+__device__ __forceinline__ T node_drho(const Geo& G, const S* __restrict__ buf,
+                                       const T* __restrict__ phi, const StepPhys<T>& ph, int x,
+                                       int y, const uint16_t* __restrict__ nbr) {
   const int kind = vel_row_kind(G, y);
   const int ys = kind == 1 ? 1 : (kind == 2 ? G.ny - 2 : y);
   const T ph_x = phi[ys * G.pitch + x];
@@ -260,12 +257,26 @@ __global__ void moments_rho(Geo G, const S* __restrict__ buf, const T* __restric
     const double f = pull_one<S, T, SHIFT>(G, buf, ph_x, ph, x, ys, i, nb);
     dm0 += static_cast<T>(f - double(rest_pop(i, ph_x, ph)));
   }
-  drho_out[y * G.pitch + x] = (nb & 1u) ? T(0) : dm0 / ph_x;
+  return (nb & 1u) ? T(0) : dm0 / ph_x;
+}
+
+// Pass 1 of the macroscopic read-out: delta rho (in T) to a scratch plane.
+template <typename S, typename T, bool SHIFT>
+__global__ void moments_rho(Geo G, const S* __restrict__ buf, const T* __restrict__ phi,
+                            StepPhys<T> ph, T* __restrict__ drho_out,
+                            const uint16_t* __restrict__ nbr) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= G.nx || y >= G.ny) return;
+  drho_out[y * G.pitch + x] = node_drho<S, T, SHIFT>(G, buf, phi, ph, x, y, nbr);
 }
 
 // Pass 2: grad rho (Eq. 10 with mirror images at walls and centre values for
 // solid neighbours), F, u, p; optional FP64 block partials of the
 // observables.  Solid nodes report zeros and are left out of the partials.
+// delta rho of the node and its neighbours comes from the plane of pass 1,
+// or (drho = null) is formed again from their populations, so that the
+// observables need no scratch plane.
 template <typename S, typename T, bool SHIFT, int FEAT>
 __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restrict__ phi,
                             StepPhys<T> ph, const T* __restrict__ drho, const T* __restrict__ fxf,
@@ -290,7 +301,8 @@ __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restric
     // velocity row: the wall velocity and the fluid neighbour's density; not
     // a fluid node, so left out of the observables
     const long long o = (long long)y * G.nx + x;
-    const double rho = double(ph.rho0 + drho[y * G.pitch + x]);
+    const double rho = double(ph.rho0 + (drho ? drho[y * G.pitch + x]
+                                               : node_drho<S, T, SHIFT>(G, buf, phi, ph, x, y, nbr)));
     if (rho_o) rho_o[o] = rho;
     if (ux_o) ux_o[o] = vkind == 1 ? G.un_lo : G.un_hi;
     if (uy_o) uy_o[o] = 0.0;
@@ -311,7 +323,10 @@ __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restric
     jx = tjx; jy = tjy;
     // neighbours of delta-rho (direction i of Eq. 5); mirror image across
     // walls, the centre value for a solid neighbour
-    const T rc = drho[y * G.pitch + x];
+    auto drho_at = [&](int xq, int yq) -> T {
+      return drho ? drho[yq * G.pitch + xq] : node_drho<S, T, SHIFT>(G, buf, phi, ph, xq, yq, nbr);
+    };
+    const T rc = drho_at(x, y);
     auto R = [&](int i) -> T {
       if (solid_bit(nb, i)) return rc;
       int xn = x + kEX[i], yn = y + kEY[i];
@@ -322,7 +337,7 @@ __global__ void moments_out(Geo G, const S* __restrict__ buf, const T* __restric
       } else {
         yn = yn < 0 ? yn + G.ny : (yn >= G.ny ? yn - G.ny : yn);
       }
-      return drho[yn * G.pitch + xn];
+      return drho_at(xn, yn);
     };
     const T grx = stencil_dx(R(1), R(3), R(5), R(8), R(6), R(7));
     const T gry = stencil_dy(R(2), R(4), R(5), R(6), R(8), R(7));

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -443,6 +444,40 @@ dim3 field_grid(const vanse_lattice* h) { return dim3((h->d.nx + 255) / 256, h->
 
 }  // namespace
 
+// Scratch of vanse_observe_noalloc: the FP64 block partials of one read-out
+// (one record per 256-column block of a row, at most kScratchBlocks), the
+// chunk records of the first reduction level and the final record.  Each
+// device holds its own copy for the life of the process; every call on a
+// device overwrites it, so calls that overlap on one device race.
+constexpr long long kScratchBlocks = 1LL << 17;
+static __device__ __align__(256) double scratch[(kScratchBlocks + 1024 + 1) * NOBS];
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per
+// device (the array's name in host code is a host-side stand-in, not a
+// device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
+
+int scratch_of_device(double** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(VANSE_ERR_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(VANSE_ERR_HIP, "hipGetSymbolAddress returned no address");
+    g_scratch_addr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return VANSE_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int vanse_workspace_bytes(const vanse_desc* d, size_t* bytes) {
@@ -780,11 +815,14 @@ int vanse_set_check_interval(vanse_lattice* h, int64_t k) {
   return VANSE_OK;
 }
 
-static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double* p, bool partials,
-                   void* stream, bool keep_u) {
+// Macroscopic read-out (rho, u, p; any may be null) and, with `part`, the
+// FP64 block partials of the observables into part.  plane: delta rho goes
+// through the workspace's scratch plane (two passes), else the second pass
+// forms every node's delta rho from its populations (no scratch plane).
+static int moments_into(vanse_lattice* h, double* rho, double* ux, double* uy, double* p,
+                        double* part, bool plane, hipStream_t st, bool keep_u) {
   if (int rc = check_ready(h)) return rc;
   if (!h->state_set) return fail(VANSE_ERR_STATE, "populations not initialised");
-  hipStream_t st = static_cast<hipStream_t>(stream);
   const Geo G = make_geo(h);
   const int rc = by_precision(h, [&](auto* s_tag, auto* t_tag, auto shift) -> int {
     using S = std::remove_pointer_t<decltype(s_tag)>;
@@ -793,10 +831,10 @@ static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double
     const StepPhys<T> ph = make_phys<T>(h);
     const S* buf = (const S*)(h->ws + h->L.pop[h->cur]);
     const T* phi = (const T*)(h->ws + h->L.phi);
-    T* drho = (T*)(h->ws + h->L.drho);
+    T* drho = plane ? (T*)(h->ws + h->L.drho) : nullptr;
     const uint16_t* nbr = h->d.has_mask ? (const uint16_t*)(h->ws + h->L.nbr) : nullptr;
-    hipLaunchKernelGGL((moments_rho<S, T, SH>), field_grid(h), dim3(256), 0, st, G, buf, phi, ph, drho, nbr);
-    double* part = partials ? (double*)(h->ws + h->L.partials) : nullptr;
+    if (plane)
+      hipLaunchKernelGGL((moments_rho<S, T, SH>), field_grid(h), dim3(256), 0, st, G, buf, phi, ph, drho, nbr);
     const T* fx = h->d.has_force_field ? (const T*)(h->ws + h->L.fx) : nullptr;
     const T* fy = h->d.has_force_field ? (const T*)(h->ws + h->L.fy) : nullptr;
     const T* beta = h->d.has_drag ? (const T*)(h->ws + h->L.beta) : nullptr;
@@ -812,6 +850,12 @@ static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double
   if (rc) return rc;
   HIP_TRY(hipGetLastError());
   return VANSE_OK;
+}
+
+static int moments(vanse_lattice* h, double* rho, double* ux, double* uy, double* p, bool partials,
+                   void* stream, bool keep_u) {
+  double* part = partials ? (double*)(h ? h->ws + h->L.partials : nullptr) : nullptr;
+  return moments_into(h, rho, ux, uy, p, part, true, static_cast<hipStream_t>(stream), keep_u);
 }
 
 int vanse_read_moments(vanse_lattice* h, double* rho, double* ux, double* uy, double* p, void* stream) {
@@ -840,13 +884,9 @@ int vanse_read_populations(vanse_lattice* h, double* f, void* stream) {
   return VANSE_OK;
 }
 
-// Reduce the block partials of the last moments pass to one record in the
-// workspace (enqueued only).
-static int reduce_on_device(vanse_lattice* h, hipStream_t st) {
-  long long n = (long long)((h->d.nx + 255) / 256) * h->d.ny;
-  const double* in = (const double*)(h->ws + h->L.partials);
-  double* mid = (double*)(h->ws + h->L.partials2);
-  double* res = (double*)(h->ws + h->L.result);
+// Fixed-order reduction of n block partials (in) to one record (res), through
+// at most 1024 chunk records (mid); enqueued only.
+static int reduce_blocks(const double* in, long long n, double* mid, double* res, hipStream_t st) {
   // level 1: at most 1024 chunks; level 2: one workgroup
   const long long chunk = (n + 1023) / 1024;
   const long long nchunks = (n + chunk - 1) / chunk;
@@ -854,6 +894,14 @@ static int reduce_on_device(vanse_lattice* h, hipStream_t st) {
   hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, (const double*)mid, nchunks, nchunks, res);
   HIP_TRY(hipGetLastError());
   return VANSE_OK;
+}
+
+// Reduce the block partials of the last moments pass to one record in the
+// workspace (enqueued only).
+static int reduce_on_device(vanse_lattice* h, hipStream_t st) {
+  const long long n = (long long)((h->d.nx + 255) / 256) * h->d.ny;
+  return reduce_blocks((const double*)(h->ws + h->L.partials), n, (double*)(h->ws + h->L.partials2),
+                       (double*)(h->ws + h->L.result), st);
 }
 
 // The same, copied to the host (synchronizes the stream).
@@ -871,6 +919,32 @@ int vanse_observe(vanse_lattice* h, double* out, void* stream) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   double rec[NOBS];
   if (int rc = reduce_to_host(h, rec, st)) return rc;
+  for (int q = 0; q < 4; ++q) out[q] = rec[q];
+  if (out[3] > 0) return fail(VANSE_ERR_DIVERGED, "%.0f nodes hold non-finite values at t = %lld", out[3], (long long)h->t);
+  return VANSE_OK;
+}
+
+int vanse_observe_noalloc(vanse_lattice* h, double* out, void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!out) return fail(VANSE_ERR_INVALID_ARG, "out is NULL");
+  const long long nblk = (long long)((h->d.nx + 255) / 256) * h->d.ny;
+  if (nblk > kScratchBlocks)
+    return fail(VANSE_ERR_INVALID_ARG,
+                "lattice too large for the static scratch: %lld read-out blocks of 256 columns > %lld",
+                nblk, kScratchBlocks);
+  if (int rc = check_ready(h)) return rc;
+  if (!h->state_set) return fail(VANSE_ERR_STATE, "populations not initialised");
+  double* sp = nullptr;
+  if (int rc = scratch_of_device(&sp)) return rc;
+  double* part = sp;
+  double* mid = sp + kScratchBlocks * NOBS;
+  double* res = mid + 1024 * NOBS;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc = moments_into(h, nullptr, nullptr, nullptr, nullptr, part, false, st, false)) return rc;
+  if (int rc = reduce_blocks(part, nblk, mid, res, st)) return rc;
+  double rec[NOBS];
+  HIP_TRY(hipMemcpyAsync(rec, res, NOBS * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   for (int q = 0; q < 4; ++q) out[q] = rec[q];
   if (out[3] > 0) return fail(VANSE_ERR_DIVERGED, "%.0f nodes hold non-finite values at t = %lld", out[3], (long long)h->t);
   return VANSE_OK;

@@ -36,7 +36,8 @@ EXPORTS = [
     "vanse_set_mask", "vanse_set_force_field", "vanse_set_drag",
     "vanse_init_equilibrium", "vanse_set_populations", "vanse_step",
     "vanse_set_check_interval", "vanse_read_moments",
-    "vanse_read_populations", "vanse_observe", "vanse_residual", "vanse_set_tiling",
+    "vanse_read_populations", "vanse_observe", "vanse_observe_noalloc", "vanse_residual",
+    "vanse_set_tiling",
     "vanse_get_tiling", "vanse_set_steps_per_pass", "vanse_get_fused_tiling",
     "vanse_set_storage_exponent", "vanse_stream_copy", "vanse_time", "vanse_error_string",
     "vanse_last_error", "vanse_batch_workspace_bytes", "vanse_batch_create", "vanse_batch_destroy",
@@ -101,6 +102,7 @@ def lib():
                 "vanse_read_moments": [vp, vp, vp, vp, vp, vp],
                 "vanse_read_populations": [vp, vp, vp],
                 "vanse_observe": [vp, pd, vp],
+                "vanse_observe_noalloc": [vp, pd, vp],
                 "vanse_residual": [vp, pd, vp],
                 "vanse_set_tiling": [vp, i32, i32],
                 "vanse_get_tiling": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
@@ -349,10 +351,13 @@ class Lattice:
         check(lib().vanse_residual(self.handle, buf, _stream(stream)))
         return (None if buf[0] < 0 else buf[0]), buf[1], int(buf[2])
 
-    def observe(self, stream=None, raise_on_diverged=True):
-        """dict(mass, u2, umax, nonfinite) reduced in FP64 on the device."""
+    def observe(self, stream=None, raise_on_diverged=True, noalloc=False):
+        """dict(mass, u2, umax, nonfinite) reduced in FP64 on the device;
+        noalloc=True: the entry point that uses no workspace scratch and
+        allocates nothing (vanse_observe_noalloc)."""
         buf = (C.c_double * 4)()
-        rc = lib().vanse_observe(self.handle, buf, _stream(stream))
+        fn = lib().vanse_observe_noalloc if noalloc else lib().vanse_observe
+        rc = fn(self.handle, buf, _stream(stream))
         res = dict(mass=buf[0], u2=buf[1], umax=buf[2], nonfinite=int(buf[3]))
         if rc == -5 and not raise_on_diverged:
             return res

@@ -235,3 +235,19 @@ def test_check_interval_validation_on_the_host():
     assert L.vanse_set_check_interval(h, 100) == 0
     assert L.vanse_step(h, 10, None) == -4                          # still no state: no GPU work
     assert L.vanse_destroy(h) == 0
+
+
+def test_noalloc_observe_limit_on_the_host():
+    """vanse_observe_noalloc keeps its partials in a static array of 131072
+    records (one per 256-column block of a row): a larger lattice is refused
+    before any device work."""
+    L = V.lib()
+    big = _fake_handle(nx=513, ny=43691)       # 3 blocks per row: 131073 records
+    out = (C.c_double * 4)()
+    assert L.vanse_observe_noalloc(big, out, None) == -1
+    assert "static scratch" in L.vanse_last_error().decode()
+    fits = _fake_handle(nx=512, ny=65535)      # 2 blocks per row: 131070 records
+    assert L.vanse_observe_noalloc(fits, out, None) == -4   # fits; no state yet
+    assert L.vanse_observe_noalloc(fits, None, None) == -1
+    for h in (big, fits):
+        assert L.vanse_destroy(h) == 0
