@@ -339,8 +339,10 @@ def precision_ladder(n: int, steps: int, out_md: str):
 
 def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
     """Turn rocprofv3 CSV output (a kernel-trace --stats run in prof_dir/trace,
-    --pmc FETCH_SIZE in prof_dir/fetch, --pmc WRITE_SIZE in prof_dir/write)
-    into a short text summary and the traffic record this benchmark reports.
+    --pmc FETCH_SIZE in prof_dir/fetch, --pmc WRITE_SIZE in prof_dir/write,
+    optionally request counts by size in prof_dir/ea_rd and prof_dir/ea_wr and
+    SQ instruction counters in prof_dir/sq) into a short text summary and the
+    traffic record this benchmark reports.
 
     The counters are scaled by what they read for the same-pattern copy
     kernel, whose bytes are known exactly (9 planes read, 9 written)."""
@@ -385,7 +387,6 @@ def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
            "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4),
            "algorithmic_bytes": alg, "steps_per_launch": STEPS_PER_PASS, "kernel": kname,
            "step_avg_ns": step_ns, "copy_avg_ns": copy_ns}
-    json.dump(rec, open(prefix + "_traffic.json", "w"), indent=1)
     lines = [f"# rocprofv3: {kname} ({STEPS_PER_PASS} time steps per launch), {NX}x{NY} "
              f"{PRECISION} channel (walls)", "",
              "Commands (from the repository root; outputs under gpurun_out/prof):", "",
@@ -401,14 +402,65 @@ def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
         if "step_kernel" in k or "step2_kernel" in k or "stream_copy" in k:
             lines.append(f"| {k[:90]} | {counters['FETCH_SIZE'][k]:.0f} | "
                          f"{counters['WRITE_SIZE'].get(k, float('nan')):.0f} |")
+    comp = BYTES_PER_NODE[PRECISION] * nodes
     lines += ["", f"Calibration with the same-pattern copy ({copy_bytes} B read and written per "
               f"dispatch): FETCH x {f_scale:.4f}, WRITE x {w_scale:.4f}.", "",
               f"Step kernel ({STEPS_PER_PASS} node updates per node per launch): "
               f"{f_step / 1e6:.1f} MB read + {w_step / 1e6:.1f} MB written = "
-              f"{(f_step + w_step) / 1e6:.1f} MB per launch; algorithmic {alg / 1e6:.1f} MB "
-              f"({(f_step + w_step) / alg:.3f}x).  Average duration {step_ns / 1e3:.1f} us -> "
-              f"{alg / step_ns:.0f} GB/s algorithmic, {(f_step + w_step) / step_ns:.0f} GB/s "
-              f"measured; copy {copy_bytes * 2 / copy_ns:.0f} GB/s."]
+              f"{(f_step + w_step) / 1e6:.1f} MB per launch; the launch must move {comp / 1e6:.1f} MB "
+              f"(each population read and written once, phi read once: "
+              f"{(f_step + w_step) / comp:.3f}x); the node updates' algorithmic bytes are "
+              f"{alg / 1e6:.1f} MB.  Average duration {step_ns / 1e3:.1f} us -> "
+              f"{comp / step_ns:.0f} GB/s of required bytes ({comp / step_ns / HBM_PEAK_GBS:.3f} of "
+              f"the peak), {(f_step + w_step) / step_ns:.0f} GB/s measured, "
+              f"{alg / step_ns:.0f} GB/s over both updates; copy {copy_bytes * 2 / copy_ns:.0f} GB/s."]
+
+    def pmc(kind):
+        per = defaultdict(lambda: defaultdict(list))
+        hits = glob.glob(os.path.join(prof_dir, f"{kind}/**/*counter_collection.csv"), recursive=True)
+        if not hits:
+            return None
+        for r in csv.DictReader(open(hits[0])):
+            per[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in per.items()}
+
+    # Cross-check of the calibration: HBM read and write requests by size
+    ea_rd, ea_wr = pmc("ea_rd"), pmc("ea_wr")
+    if ea_rd and ea_wr:
+        lines += ["", "## Cross-check: memory requests by size (--pmc TCC_EA0_RDREQ_32B_sum "
+                  "TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_sum, then "
+                  "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum)", "",
+                  "| kernel | read requests 32/64/128 B (all) | bytes read | write requests "
+                  "(64 B) | bytes written | expected |", "|---|---|---|---|---|---|"]
+        for key, expect in (("stream_copy", copy_bytes), (kname, None)):
+            r = pick(ea_rd, key)
+            w = pick(ea_wr, key)
+            rd = (32 * r["TCC_EA0_RDREQ_32B_sum"] + 64 * r["TCC_EA0_RDREQ_64B_sum"]
+                  + 128 * r["TCC_EA0_RDREQ_128B_sum"])
+            # a write request carries 64 B, or 32 B when it is not a 64-byte one
+            wb = 64 * w["TCC_EA0_WRREQ_64B_sum"] + 32 * (w["TCC_EA0_WRREQ_sum"] - w["TCC_EA0_WRREQ_64B_sum"])
+            rec["ea_read_bytes" if key == kname else "copy_ea_read_bytes"] = int(rd)
+            rec["ea_write_bytes" if key == kname else "copy_ea_write_bytes"] = int(wb)
+            lines.append(f"| {key} | {r['TCC_EA0_RDREQ_32B_sum']:.0f} / {r['TCC_EA0_RDREQ_64B_sum']:.0f}"
+                         f" / {r['TCC_EA0_RDREQ_128B_sum']:.0f} ({r['TCC_EA0_RDREQ_sum']:.0f}) | "
+                         f"{rd / 1e6:.1f} MB | {w['TCC_EA0_WRREQ_sum']:.0f} "
+                         f"({w['TCC_EA0_WRREQ_64B_sum']:.0f}) | {wb / 1e6:.1f} MB | "
+                         + (f"{expect / 1e6:.1f} MB each way |" if expect else "— |"))
+        lines += ["", f"Step kernel by request sizes: {rec['ea_read_bytes'] / 1e6:.1f} MB read + "
+                  f"{rec['ea_write_bytes'] / 1e6:.1f} MB written = "
+                  f"{(rec['ea_read_bytes'] + rec['ea_write_bytes']) / 1e6:.1f} MB, against "
+                  f"{(f_step + w_step) / 1e6:.1f} MB from the calibrated FETCH_SIZE + WRITE_SIZE."]
+    # Instruction mix and wave states
+    sq = pmc("sq")
+    if sq:
+        q = pick(sq, kname)
+        waves = q.get("SQ_WAVES", float("nan"))
+        lines += ["", "## Instruction mix of the step kernel (--pmc " + " ".join(sorted(q)) + ")", "",
+                  "| counter | per dispatch | per wave |", "|---|---|---|"]
+        for c in sorted(q):
+            lines.append(f"| {c} | {q[c]:.4g} | {q[c] / waves:.4g} |")
+        rec["sq"] = {c: q[c] for c in sorted(q)}
+    json.dump(rec, open(prefix + "_traffic.json", "w"), indent=1)
     open(prefix + "_rocprof.md", "w").write("\n".join(lines) + "\n")
     print(json.dumps(rec))
 
