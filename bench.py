@@ -88,6 +88,8 @@ def gpu_clocks():
     """Clock, power and temperature readings of the GPU from rocm-smi (a
     short dict; the error text if the tool is not usable)."""
     import subprocess
+    if "rocprofiler" in os.environ.get("LD_PRELOAD", ""):
+        return {"skipped": "under a profiler"}
     try:
         out = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--showtemp", "--json"],
                              capture_output=True, text=True, timeout=20)
@@ -446,10 +448,14 @@ def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
                          f"{rd / 1e6:.1f} MB | {w['TCC_EA0_WRREQ_sum']:.0f} "
                          f"({w['TCC_EA0_WRREQ_64B_sum']:.0f}) | {wb / 1e6:.1f} MB | "
                          + (f"{expect / 1e6:.1f} MB each way |" if expect else "— |"))
+        rd_scale = copy_bytes / rec["copy_ea_read_bytes"]
         lines += ["", f"Step kernel by request sizes: {rec['ea_read_bytes'] / 1e6:.1f} MB read + "
                   f"{rec['ea_write_bytes'] / 1e6:.1f} MB written = "
-                  f"{(rec['ea_read_bytes'] + rec['ea_write_bytes']) / 1e6:.1f} MB, against "
-                  f"{(f_step + w_step) / 1e6:.1f} MB from the calibrated FETCH_SIZE + WRITE_SIZE."]
+                  f"{(rec['ea_read_bytes'] + rec['ea_write_bytes']) / 1e6:.1f} MB.  The copy's reads "
+                  f"count x {1 / rd_scale:.3f} of its bytes by request size; scaled the same way "
+                  f"the step kernel reads {rec['ea_read_bytes'] * rd_scale / 1e6:.1f} MB, against "
+                  f"{f_step / 1e6:.1f} MB from the calibrated FETCH_SIZE (writes: "
+                  f"{rec['ea_write_bytes'] / 1e6:.1f} against {w_step / 1e6:.1f} MB)."]
     # Instruction mix and wave states
     sq = pmc("sq")
     if sq:
