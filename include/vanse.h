@@ -351,6 +351,14 @@ int vanse_batch_set_graph(vanse_batch *b, int steps_per_graph);
 /* Advance every member nsteps time steps.  Enqueued on `stream`. */
 int vanse_batch_step(vanse_batch *b, int64_t nsteps, void *stream);
 
+/* vanse_residual of every member, with one copy to the host and one
+ * synchronization for the whole batch: out is HOST memory of 3 doubles per
+ * member, in member order (sum |u(t) - u(t')|^2 or -1 on a member's first
+ * call, sum |u(t)|^2, non-finite count); each member keeps u(t) for its next
+ * vanse_residual or vanse_batch_residual call.  VANSE_ERR_DIVERGED (after
+ * filling out) when a member holds a non-finite node. */
+int vanse_batch_residual(vanse_batch *b, double *out, void *stream);
+
 /* Tiles (workgroups per launch) and rows per workgroup of the batch. */
 int vanse_batch_tiles(const vanse_batch *b, int *tiles, int *rows);
 

@@ -1137,7 +1137,8 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
                                                                             : sizeof(BatchEntry<float>);
   *entries_off = 0;
   *tiles_off = align256((size_t)n * esz);
-  *bytes = align256(*tiles_off + (size_t)tiles * sizeof(int2));
+  // then one FP64 observables record per member (vanse_batch_residual)
+  *bytes = align256(align256(*tiles_off + (size_t)tiles * sizeof(int2)) + (size_t)n * NOBS * sizeof(double));
   return VANSE_OK;
 }
 
@@ -1426,6 +1427,40 @@ int vanse_batch_step(vanse_batch* b, int64_t nsteps, void* stream) {
   }
   for (size_t k = 0; rem && k < b->lats.size(); ++k)
     if (int rc = vanse_step(b->lats[k], rem, stream)) return rc;
+  return VANSE_OK;
+}
+
+int vanse_batch_residual(vanse_batch* b, double* out, void* stream) {
+  if (!b) return fail(VANSE_ERR_INVALID_ARG, "batch is NULL");
+  if (!out) return fail(VANSE_ERR_INVALID_ARG, "out is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t n = b->lats.size();
+  double* recs = reinterpret_cast<double*>(
+      b->ws + align256(b->tiles_off + (size_t)b->total_tiles * sizeof(int2)));
+  std::vector<char> had(n);
+  // each member's read-out and reduction as vanse_residual, the final record
+  // into the batch's record array; one copy and one synchronization for all
+  for (size_t k = 0; k < n; ++k) {
+    vanse_lattice* h = b->lats[k];
+    had[k] = h->uprev_valid;
+    if (int rc = moments(h, nullptr, nullptr, nullptr, nullptr, true, stream, true)) return rc;
+    const long long nblk = (long long)((h->d.nx + 255) / 256) * h->d.ny;
+    if (int rc = reduce_blocks((const double*)(h->ws + h->L.partials), nblk, (double*)(h->ws + h->L.partials2),
+                               recs + k * NOBS, st))
+      return rc;
+  }
+  std::vector<double> rec(n * NOBS);
+  HIP_TRY(hipMemcpyAsync(rec.data(), recs, rec.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double bad = 0.0;
+  for (size_t k = 0; k < n; ++k) {
+    b->lats[k]->uprev_valid = true;
+    out[3 * k + 0] = had[k] ? rec[k * NOBS + 4] : -1.0;
+    out[3 * k + 1] = rec[k * NOBS + 1];
+    out[3 * k + 2] = rec[k * NOBS + 3];
+    bad += rec[k * NOBS + 3];
+  }
+  if (bad > 0) return fail(VANSE_ERR_DIVERGED, "%.0f nodes of the batch hold non-finite values", bad);
   return VANSE_OK;
 }
 

@@ -132,13 +132,12 @@ class SolveServer:
                 batch = Batch([s.lattice for s in active], threads=self.threads, rows=self.rows,
                               steps_per_pass=self.steps_per_pass)
             # one chunk: chunk-1 steps, keep u, one step, residual of that step
+            # (each a single synchronization for all resident requests)
             batch.step(self.chunk - 1)
-            for s in active:
-                s.lattice.residual()
+            batch.residual()
             batch.step(1)
             finished = []
-            for s in active:
-                du2, u2, bad = s.lattice.residual()
+            for s, (du2, u2, bad) in zip(list(active), batch.residual()):
                 s.steps += self.chunk
                 s.residual = math.sqrt(du2 / u2) if (du2 is not None and u2 > 0) else math.inf
                 s.history.append(s.residual)

@@ -42,7 +42,7 @@ EXPORTS = [
     "vanse_set_storage_exponent", "vanse_stream_copy", "vanse_time", "vanse_error_string",
     "vanse_last_error", "vanse_batch_workspace_bytes", "vanse_batch_create", "vanse_batch_destroy",
     "vanse_batch_workspace_bytes_ex", "vanse_batch_create_ex",
-    "vanse_batch_set_graph", "vanse_batch_step", "vanse_batch_tiles",
+    "vanse_batch_set_graph", "vanse_batch_step", "vanse_batch_residual", "vanse_batch_tiles",
 ]
 
 
@@ -122,6 +122,7 @@ def lib():
                 "vanse_batch_destroy": [vp],
                 "vanse_batch_set_graph": [vp, i32],
                 "vanse_batch_step": [vp, i64, vp],
+                "vanse_batch_residual": [vp, pd, vp],
                 "vanse_batch_tiles": [vp, C.POINTER(i32), C.POINTER(i32)],
                 "vanse_error_string": [i32],
                 "vanse_last_error": [],
@@ -402,6 +403,17 @@ class Batch:
     def step(self, n=1, stream=None):
         check(lib().vanse_batch_step(self.handle, int(n), _stream(stream)))
         return self
+
+    def residual(self, stream=None):
+        """Lattice.residual() of every member with one synchronization: a
+        list of (sum |u - u_prev|^2 or None, sum |u|^2, nonfinite)."""
+        n = len(self.lattices)
+        buf = (C.c_double * (3 * n))()
+        rc = lib().vanse_batch_residual(self.handle, buf, _stream(stream))
+        if rc not in (0, -5):
+            check(rc)
+        return [((None if buf[3 * k] < 0 else buf[3 * k]), buf[3 * k + 1], int(buf[3 * k + 2]))
+                for k in range(n)]
 
     def tiles(self):
         a, b = C.c_int(), C.c_int()

@@ -264,3 +264,30 @@ def test_batch_masks_and_scheme_variants(variant, precision):
         assert a.t == r.t == 11
         assert np.array_equal(a.read_populations().cpu().numpy(),
                               r.read_populations().cpu().numpy())
+
+
+def test_batch_residual_equals_member_residuals():
+    """vanse_batch_residual gives, bitwise, what vanse_residual gives for
+    each member (first call: no previous velocity), and keeps each member's
+    velocity for its next call of either kind."""
+    _torch()
+    from paper_2409_02964_amd.vanse import Batch
+    mem = [make(nx, ny, k)[0] for k, (nx, ny) in enumerate(SIZES)]
+    ref = [make(nx, ny, k)[0] for k, (nx, ny) in enumerate(SIZES)]
+    b = Batch(mem, threads=128)
+    b.step(5)
+    for r in ref:
+        r.step(5)
+    first = b.residual()
+    assert first == [r.residual() for r in ref]
+    assert all(du2 is None for du2, _, _ in first)
+    b.step(1)
+    for r in ref:
+        r.step(1)
+    second = b.residual()
+    assert second == [r.residual() for r in ref]
+    assert all(du2 is not None and du2 > 0 for du2, _, _ in second)
+    b.step(2)
+    for r in ref:
+        r.step(2)
+    assert [m.residual() for m in mem] == [r.residual() for r in ref]
