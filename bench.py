@@ -269,11 +269,12 @@ def served_bench(count: int, rate: float, budget_gib: float, precision: str = "f
     return out
 
 
-def precision_ladder(n: int, steps: int, out_md: str):
+def precision_ladder(n: int, steps: int, out_md: str = None, quiet: bool = False):
     """Precision ladder on an n x n channel (the benchmark channel's
     generator: walls, tanh phi step + noise, seed 2409, G = 1e-7): the FP64
     oracle against the GPU in FP64, FP32, FP32-shifted and FP16-shifted
-    storage after `steps` steps; writes a short report to `out_md`."""
+    storage after `steps` steps; writes a short report to `out_md` (if
+    given) and returns the rows.  quiet: no progress lines."""
     import math
     import numpy as np
     import torch
@@ -293,7 +294,8 @@ def precision_ladder(n: int, steps: int, out_md: str):
         k = min(chunk, steps - done)
         o.step(k)
         done += k
-        print(f"oracle {n}x{n}: {done}/{steps} steps, {time.perf_counter() - t0:.0f} s", flush=True)
+        if not quiet:
+            print(f"oracle {n}x{n}: {done}/{steps} steps, {time.perf_counter() - t0:.0f} s", flush=True)
     t_oracle = time.perf_counter() - t0
     ref = o.macroscopic()
     rows = []
@@ -315,8 +317,11 @@ def precision_ladder(n: int, steps: int, out_md: str):
         rows.append((prec, spp, BYTES_PER_NODE[prec], eu, rel(m["p"], ref["p"]),
                      rel(m["p"] - m["p"].mean(), ref["p"] - ref["p"].mean()),
                      n * n * steps / dt / 1e6))
-        print(f"{prec}, {spp} step(s) per launch: rel-L2 u {eu:.3e}", flush=True)
+        if not quiet:
+            print(f"{prec}, {spp} step(s) per launch: rel-L2 u {eu:.3e}", flush=True)
         lat.close()
+    if out_md is None:
+        return rows, t_oracle
     threads = os.environ.get("OMP_NUM_THREADS", str(os.cpu_count()))
     lines = [f"# Precision ladder: {n}x{n} channel, {steps} steps", "",
              "Command (from the repository root):", "", "```",
@@ -337,7 +342,7 @@ def precision_ladder(n: int, steps: int, out_md: str):
               "of this size (the populations of the smaller formats fit in the 256 MB "
               "last-level cache)."]
     open(out_md, "w").write("\n".join(lines) + "\n")
-    return rows
+    return rows, t_oracle
 
 
 def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
@@ -472,6 +477,46 @@ def summarize_profile(prof_dir: str, prefix: str, commands: str) -> None:
     print(json.dumps(rec))
 
 
+def summarize_variants(prof_dir: str, out_md: str) -> None:
+    """profiles/ summary of a `rocprofv3 --kernel-trace --stats` run of
+    `bench.py --variants`: the step kernels' statistics from prof_dir's
+    kernel_stats CSV and the HIP-event timings the run printed (prof_dir/
+    variants.log)."""
+    import csv
+    import glob
+    hits = glob.glob(os.path.join(prof_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not hits:
+        raise SystemExit(f"no kernel_stats.csv under {prof_dir}")
+    stats = [r for r in csv.DictReader(open(hits[0])) if "step" in r["Name"] and "kernel" in r["Name"]]
+    recs = []
+    for ln in open(os.path.join(prof_dir, "variants.log")):
+        if ln.startswith("{"):
+            recs.append(json.loads(ln))
+    cmd = open(os.path.join(prof_dir, "commands.txt")).read().strip()
+    lines = ["# rocprofv3: every step-kernel variant, 4096x4096 channel (walls)", "",
+             "Command (from the repository root; outputs under gpurun_out/prof_var):", "",
+             "```", cmd, "```", "",
+             "The benchmark channel's field, forcing and rates, with: a cylinder-and-grain solid "
+             "mask (`solid_mask`, seed 5), a force field 1e-7 N(0,1) smoothed over 8 cells, a drag "
+             "beta = 1e-3 + 1e-2 (1 - phi), a moving phi without phi(t+1) (d_t phi = 0), model B, "
+             "an upper wall at u = 1e-3, and an upper velocity row at u = 1e-3.  Per variant: 4 "
+             "untimed steps, half a second of untimed stepping (the shader clock rises under "
+             "load), then the timed steps.", "",
+             "## Kernel statistics (--kernel-trace --stats)", "",
+             "| kernel | calls | average µs | min µs | max µs |", "|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: float(r["AverageNs"])):
+        lines.append(f"| {r['Name'][:110]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} |")
+    lines += ["", "## The same runs timed with HIP events (bench.py --variants)", "",
+              "| variant | storage | steps/launch | µs per step | GLUPS |", "|---|---|---|---|---|"]
+    for r in recs:
+        lines.append(f"| {r['variant']} | {r['storage']} | {r['steps_per_launch']} | "
+                     f"{r['us_per_step']} | {r['glups']} |")
+    lines += ["", "Calls include the untimed settling steps; the kernel trace adds a little to "
+              "each launch."]
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
 # Kernel variants timed by --variants: (name, storage, steps per launch, options)
 VARIANTS = [
     ("plain", "f32s", 1, {}),
@@ -492,13 +537,15 @@ VARIANTS = [
     ("model B", "f32s", 1, {"model_b": True}),
     ("moving walls, drag", "f32s", 1, {"wall_u": 1e-3, "drag": True}),
     ("model B, solid nodes", "f32s", 1, {"model_b": True, "mask": True}),
+    ("velocity rows (Couette), drag", "f32s", 1, {"vel_rows": 1e-3, "drag": True}),
 ]
 
 
-def variants_bench(steps: int):
+def variants_bench(steps: int, settle_s: float = 0.5):
     """Every kernel variant on the 4096 x 4096 benchmark channel: `steps`
-    steps each (after 4 untimed), timed with HIP events on the launch stream;
-    prints one JSON line per variant and a markdown table."""
+    steps each (after 4 untimed, and untimed stepping for `settle_s` seconds
+    so that the shader clock has risen), timed with HIP events on the launch
+    stream; prints one JSON line per variant and a markdown table."""
     import numpy as np
     import torch
     from paper_2409_02964_amd import workloads as W
@@ -520,6 +567,8 @@ def variants_bench(steps: int):
             lat.set_scheme("B", 3)
         if o.get("wall_u"):
             lat.set_wall_velocity(0.0, o["wall_u"])
+        if o.get("vel_rows"):
+            lat.set_velocity_rows(None, o["vel_rows"])
         lat.set_void_fraction(phi)
         if o.get("force"):
             lat.set_force_field(fx, np.zeros_like(fx))
@@ -529,6 +578,10 @@ def variants_bench(steps: int):
         stream = torch.cuda.current_stream()
         lat.step(4, stream)
         torch.cuda.synchronize()
+        t_s = time.perf_counter()
+        while time.perf_counter() - t_s < settle_s:
+            lat.step(10, stream)
+            torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -577,16 +630,26 @@ def main():
     ap.add_argument("--small-steps", type=int, default=1000,
                     help="steps of the 64x64 FP64 workload, plain and graph-captured (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=2.0)
+    ap.add_argument("--summarize-variants", metavar="DIR",
+                    help="summarize a rocprofv3 kernel trace of --variants in DIR into profiles/")
     ap.add_argument("--summarize-profile", metavar="DIR",
                     help="summarize rocprofv3 CSVs in DIR/{trace,fetch,write} into profiles/")
     ap.add_argument("--precision-ladder", type=int, metavar="N", default=0,
                     help="run the precision ladder on an N x N channel and write profiles/")
     ap.add_argument("--ladder-steps", type=int, default=5000)
+    ap.add_argument("--ladder-n", type=int, default=1024,
+                    help="side of the precision ladder in the benchmark line (0: skip)")
+    ap.add_argument("--bench-ladder-steps", type=int, default=2000,
+                    help="steps of the precision ladder in the benchmark line")
     ap.add_argument("--variants", type=int, metavar="STEPS", default=0,
                     help="time every kernel variant on the benchmark channel (STEPS steps each)")
     args = ap.parse_args()
     if args.variants:
         variants_bench(args.variants)
+        return
+    if args.summarize_variants:
+        summarize_variants(args.summarize_variants,
+                           os.path.join(ROOT, "profiles", "variants_channel4096_rocprof.md"))
         return
     if args.precision_ladder:
         n = args.precision_ladder
@@ -742,6 +805,21 @@ def main():
         if extra:
             line["served_sweep"] = {str(r): served_bench(args.serve_requests, r, args.serve_budget_gib)
                                     for r in extra}
+    if args.ladder_n > 0:
+        # the precision ladder of the 2048^2, 5000-step channel workload at a
+        # quarter of its nodes and 2000 steps, so that the oracle's reference
+        # run takes about half a minute (the full size: --precision-ladder 2048)
+        from oracle import oracle as O
+        O.set_threads(max(1, min(16, len(os.sched_getaffinity(0)))))
+        rows, t_or = precision_ladder(args.ladder_n, args.bench_ladder_steps, quiet=True)
+        line["precision_ladder"] = {
+            "workload": f"channel {args.ladder_n}x{args.ladder_n} (the benchmark channel's "
+                        f"generator), {args.bench_ladder_steps} steps from rest, against the FP64 oracle "
+                        f"({t_or:.0f} s)",
+            "rows": [{"storage": p, "steps_per_launch": spp, "bytes_per_node": b,
+                      "rel_l2_u": float(f"{eu:.3e}"), "rel_l2_p": float(f"{ep:.3e}"),
+                      "rel_l2_p_minus_mean": float(f"{epd:.3e}")}
+                     for p, spp, b, eu, ep, epd, _ in rows]}
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(line), flush=True)

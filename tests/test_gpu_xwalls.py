@@ -273,3 +273,51 @@ def test_x_walls_batch_bitwise():
         assert np.array_equal(a.read_populations().cpu().numpy(), r.read_populations().cpu().numpy())
     with pytest.raises(VanseError):
         Batch([member(0, 40, 30), member(1, 40, 30, bc_x="periodic")])
+
+
+@pytest.mark.parametrize("mask", [False, True])
+def test_x_walls_batch_force_drag_bitwise(mask):
+    """Walls in x with a force field and a drag take the moving-phi instance
+    (with or without solid nodes); batched, they are bitwise the results of
+    stepping each member alone."""
+    _torch()
+    from paper_2409_02964_amd.vanse import Batch, Lattice
+    sizes = [(64, 48), (37, 53), (130, 20)]
+
+    def member(k, nx, ny):
+        lat = Lattice(nx, ny, precision="f32s", bc_x="wall", bc_y="wall", mask=mask,
+                      force_field=True, drag=True)
+        phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 3.0, seed=k + 7) ** 2
+        lat.set_params(0.5, C1_RATES).set_body_force(1e-6 * (k + 1), 2e-7)
+        if mask:
+            lat.set_mask(W.solid_mask(nx, ny, seed=k))
+        lat.set_void_fraction(phi)
+        lat.set_force_field(1e-6 * W.smoothed_noise(nx, ny, 3.0, seed=k + 20),
+                            -1e-6 * W.smoothed_noise(nx, ny, 3.0, seed=k + 30))
+        lat.set_drag(1e-3 + 1e-2 * (1 - phi), (1e-4, 0.0))
+        return lat.init_equilibrium(1.0, 1e-3, 0.0)
+
+    ref = [member(k, nx, ny) for k, (nx, ny) in enumerate(sizes)]
+    for lat in ref:
+        lat.step(9)
+    mem = [member(k, nx, ny) for k, (nx, ny) in enumerate(sizes)]
+    Batch(mem, threads=64, rows=6, graph_steps=0).step(9)
+    for a, r in zip(mem, ref):
+        assert np.array_equal(a.read_populations().cpu().numpy(), r.read_populations().cpu().numpy())
+
+
+@pytest.mark.parametrize("prec,bound", [("f16s", 2e-2), ("f32", 2e-3)])
+def test_x_walls_reduced_storage(oracle, prec, bound):
+    """A closed box in FP16-shifted and plain FP32 storage against the FP64
+    oracle: the error is the storage rounding's, reported."""
+    _torch()
+    nx, ny, steps = 96, 40, 300
+    phi = 0.55 + 0.4 * W.smoothed_noise(nx, ny, 4.0, seed=81) ** 2
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=C1_RATES, g=(2e-6, 1e-6), bc_x="wall",
+                        bc_y="wall").init_equilibrium()
+    ora.step(steps)
+    lat = xlattice(nx, ny, phi, prec, "wall", g=(2e-6, 1e-6))
+    lat.init_equilibrium(1.0).step(steps)
+    e = rel_l2_u(to_np(lat.read_moments()), ora.macroscopic())
+    _say(f"x-walls {prec} {steps} steps: rel-L2(u) {e:.3e}")
+    assert e <= bound
