@@ -362,7 +362,8 @@ __device__ inline void step2_tile(
       rA.mpxx = (q[1] + q[3]) - (q[2] + q[4]);
       rA.mpxy = (q[5] + q[7]) - (q[6] + q[8]);
       rA.phi = phi;
-      rA.drho = rA.dm0 * recip(phi);
+      rA.rphi = recip(phi);
+      rA.drho = rA.dm0 * rA.rphi;
     };
     // half 0: the staged row yA has landed once at most one batch (row
     // yA + 1: one load per staged word row) is still in flight
@@ -404,19 +405,28 @@ __device__ inline void step2_tile(
         // pull from half 0's ring: f_i(x) = f+_i(x - e_i); at a wall the
         // image rows hold the bounced-back populations.  phi of the row came
         // with it.
+        // One address per ring row (the lane's column in plane 0); the planes
+        // and the column shifts are immediate offsets.  At lanes 0 and NT - 1
+        // the shifted reads fall on the edge of a neighbouring ring row, still
+        // inside the ring (no shifted plane is the ring's first or last); the
+        // moments of those lanes are not valid for half 1 and never used.
         T q[9];
-        const int j0 = jr(yA), jm = j0 - 1, jp = j0 + 1;
-        const T phi = L.pop[pop_slot(9, j0)][t];
-        if (DRAG) rA.beta = L.pop[pop_slot(10, j0)][t];
-        q[0] = L.pop[pop_slot(0, j0)][t];
-        q[1] = L.pop[pop_slot(1, j0)][tl];
-        q[3] = L.pop[pop_slot(3, j0)][tr];
-        q[2] = L.pop[pop_slot(2, jm)][t];
-        q[5] = L.pop[pop_slot(5, jm)][tl];
-        q[6] = L.pop[pop_slot(6, jm)][tr];
-        q[4] = L.pop[pop_slot(4, jp)][t];
-        q[7] = L.pop[pop_slot(7, jp)][tr];
-        q[8] = L.pop[pop_slot(8, jp)][tl];
+        const int j0 = jr(yA);
+        const auto* r0 = &L.pop[0][0] + (j0 & 3) * NT + t;
+        const auto* rm = &L.pop[0][0] + ((j0 - 1) & 3) * NT + t;
+        const auto* rp = &L.pop[0][0] + ((j0 + 1) & 3) * NT + t;
+        constexpr int P = 4 * NT;  // elements per plane of the ring
+        const T phi = r0[9 * P];
+        if (DRAG) rA.beta = r0[10 * P];
+        q[0] = r0[0];
+        q[1] = r0[1 * P - 1];
+        q[3] = r0[3 * P + 1];
+        q[2] = rm[2 * P];
+        q[5] = rm[5 * P - 1];
+        q[6] = rm[6 * P + 1];
+        q[4] = rp[4 * P];
+        q[7] = rp[7 * P + 1];
+        q[8] = rp[8 * P - 1];
         moments(q, phi);
       }
       s_rho[t] = rA.drho;
@@ -550,7 +560,7 @@ __device__ inline void step2_tile(
 
         const T phi = rC.phi;
         const T rho = rho0 + rC.drho;
-        const T X = kappa * recip(phi);
+        const T X = kappa * rC.rphi;
         const T kr = (kappa - phi) * rho;
         const T ux = vc.ux, uy = vc.uy, Fx = bOld[0], Fy = bOld[1];
 
@@ -591,14 +601,21 @@ __device__ inline void step2_tile(
         const T pjx = rC.jx + Fx;
         const T pjy = rC.jy + Fy;
 
-        // back-transform f+ = M^-1 m+ (Eq. A1)
-        const T a = (T(4) * pm0 - pe - T(2) * pep) * T(1.0 / 36.0);
-        const T b = (T(4) * pm0 + T(2) * pe + pep) * T(1.0 / 36.0);
-        const T X1 = (pjx - pqx) * T(1.0 / 6.0), Y1 = (pjy - pqy) * T(1.0 / 6.0);
-        const T X2 = (T(2) * pjx + pqx) * T(1.0 / 12.0), Y2 = (T(2) * pjy + pqy) * T(1.0 / 12.0);
-        const T Pd = ppxx * T(0.25), Qd = ppxy * T(0.25);
+        // back-transform f+ = M^-1 m+ (Eq. A1).  Half 1 with shifted storage
+        // takes the coefficients times the storage scale (a power of two, so
+        // the products are the scaled values exactly, as a multiply at the
+        // store would give them).
+        const bool scaled = SHIFT && half != 0;
+        const T c36 = scaled ? ph.bt36 : T(1.0 / 36.0), c6 = scaled ? ph.bt6 : T(1.0 / 6.0);
+        const T c12 = scaled ? ph.bt12 : T(1.0 / 12.0), c4 = scaled ? ph.bt4 : T(0.25);
+        const T c9 = scaled ? ph.bt9 : T(1.0 / 9.0);
+        const T a = (T(4) * pm0 - pe - T(2) * pep) * c36;
+        const T b = (T(4) * pm0 + T(2) * pe + pep) * c36;
+        const T X1 = (pjx - pqx) * c6, Y1 = (pjy - pqy) * c6;
+        const T X2 = (T(2) * pjx + pqx) * c12, Y2 = (T(2) * pjy + pqy) * c12;
+        const T Pd = ppxx * c4, Qd = ppxy * c4;
         T o9[9];
-        o9[0] = (pm0 - pe + pep) * T(1.0 / 9.0);
+        o9[0] = (pm0 - pe + pep) * c9;
         o9[1] = a + X1 + Pd;
         o9[2] = a + Y1 - Pd;
         o9[3] = a - X1 + Pd;
@@ -614,10 +631,9 @@ __device__ inline void step2_tile(
           for (int i = 0; i < 9; ++i) L.pop[pop_slot(i, jo)][t] = o9[i];
           L.pop[pop_slot(9, jo)][t] = phi;
           if (DRAG) L.pop[pop_slot(10, jo)][t] = rC.beta;
-        } else if (SHIFT) {
+        } else if (SHIFT) {  // already scaled
 #pragma unroll
-          for (int i = 0; i < 9; ++i)
-            bstore(static_cast<S>(sizeof(S) == 2 ? o9[i] * ph.scale : o9[i]), dstr, xcb, poff(i, yo));
+          for (int i = 0; i < 9; ++i) bstore(static_cast<S>(o9[i]), dstr, xcb, poff(i, yo));
         } else {
           bstore(static_cast<S>(o9[0] + (phi * rho0 - ph.rest0_k)), dstr, xcb, poff(0, yo));
 #pragma unroll

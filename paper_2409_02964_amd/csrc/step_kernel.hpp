@@ -68,6 +68,7 @@ struct StepPhys {
   // floating-point ALU, so a kernel would hold them in vector registers.
   T k2, k3, k12;            // 2 kappa, 3 kappa, kappa / 12
   T he, hep, hq, hn;        // 1 - s/2 for s_e, s_eps, s_q, s_nu (Eq. 16)
+  T bt9, bt36, bt6, bt12, bt4;  // 1/9, 1/36, 1/6, 1/12, 1/4 of Eq. (A1) times `scale`
   // Velocity boundary rows (Sec. 3.1, Couette flow; FEAT_ALL with walls):
   // the first (nee_lo) or last (nee_hi) row lies on a wall moving with x
   // velocity un_lo / un_hi and is set by non-equilibrium extrapolation from
@@ -185,6 +186,7 @@ __device__ __forceinline__ T stencil_dy(T n, T s, T ne, T nw, T se, T sw) {
 template <typename T>
 struct RowState {
   T dm0, jx, jy, me, mep, mqx, mqy, mpxx, mpxy, phi, drho, beta, dphi;
+  T rphi;  // 1/phi (the two-step kernel keeps it from stage A for stage C)
   unsigned nb;
 };
 

@@ -207,6 +207,11 @@ StepPhys<T> make_phys(const vanse_lattice* h) {
   p.hep = T(1) - T(0.5) * p.s_eps;
   p.hq = T(1) - T(0.5) * p.s_q;
   p.hn = T(1) - T(0.5) * p.s_nu;
+  p.bt9 = p.scale * T(1.0 / 9.0);
+  p.bt36 = p.scale * T(1.0 / 36.0);
+  p.bt6 = p.scale * T(1.0 / 6.0);
+  p.bt12 = p.scale * T(1.0 / 12.0);
+  p.bt4 = p.scale * T(0.25);
   p.nee_lo = h->nee_lo;
   p.nee_hi = h->nee_hi;
   p.un_lo = T(h->un_lo);
