@@ -24,6 +24,10 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a multiply and an add into an FMA only within one expression:
+    # the same source then rounds the same way in every unrolled copy of a
+    # sweep loop, so a node's result does not depend on its tile
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 

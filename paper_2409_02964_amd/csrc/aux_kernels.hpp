@@ -111,8 +111,10 @@ __device__ __forceinline__ bool receiver(const Geo& G, int x, int y, int i, unsi
 
 // Solid flags (FEAT_MASK layout) from a dense uint8 mask, nonzero = solid:
 // bit 0 the node, bit i the node standing in for x + e_i, which across a wall
-// is its mirror image in the first or last row (or column).  Counts solid
-// nodes.
+// is its mirror image in the first or last row (or column).  A solid node
+// keeps bit 0 alone: nothing it computes is used, and without neighbour bits
+// the step's bounce-back and stand-in paths pass over solid regions.  Counts
+// solid nodes.
 __global__ void build_nbr(Geo G, const uint8_t* __restrict__ mask, uint16_t* __restrict__ nbr,
                           unsigned long long* __restrict__ nsolid) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -127,6 +129,7 @@ __global__ void build_nbr(Geo G, const uint8_t* __restrict__ mask, uint16_t* __r
     else yn = yn < 0 ? yn + G.ny : (yn >= G.ny ? yn - G.ny : yn);
     if (mask[(long long)yn * G.nx + xn]) b |= 1u << i;
   }
+  if (b & 1u) b = 1u;
   nbr[(long long)y * G.pitch + x] = (uint16_t)b;
   if (b & 1u) atomicAdd(nsolid, 1ull);
 }

@@ -46,6 +46,21 @@
 // those rings above the upper wall and formed in registers from the D and S
 // of row 0 below the lower wall.
 //
+// Solid nodes (FEAT_MASK; the uint16 flags of the single step: bit 0 the
+// node is solid, bit i its neighbour x + e_i is):
+//   - Half-way bounce-back: a fluid node pulls f_i from its own slot opp(i)
+//     when bit opp(i) is set.  Half 0's staged row then takes per-lane
+//     offsets, so the flags of a row must be known when its loads are
+//     issued: each staged row also carries the flags of the row two ahead,
+//     which the sweep keeps in registers until that row is staged.  Half 1
+//     takes the own-slot value from the ring (the flags ride with the row).
+//   - Eq. (10): a solid neighbour stands in with the centre value (negated
+//     for the velocity-like fields).  Solid nodes write zeros into the
+//     single-row rings, so the separable sums leave them out, and the centre
+//     value times Kx = sum of c_i e_ix over the flagged neighbours (c_i = 4
+//     on the axes, 1 on the diagonals; Ky alike) restores the stand-ins.
+//   - Solid nodes keep the rest state (zero deviations).
+//
 // Columns: lane t of either half is column x0 - 5 + t.  Half 0 forms moments
 // on lanes [0, w+10), velocities on [1, w+9), collisions on [2, w+8); half 1
 // on [3, w+7), [4, w+6), [5, w+5), the last being the strip's w <= NT - 10
@@ -60,7 +75,7 @@
 namespace vanse_dev {
 
 // NP: planes of the population ring -- the nine populations, phi and, with
-// the linear drag, its coefficient beta
+// the linear drag, its coefficient beta, and with solid nodes their flags
 template <typename T, int NT, int NP>
 struct Step2Lds {
   T rho[2][NT];      // per half: delta-rho of the row of stage A (read by B)
@@ -69,8 +84,9 @@ struct Step2Lds {
   T pop[4 * NP][NT];  // half 0's post-collision deviations, phi, beta (see pop_slot)
 };
 
-// Half 0's staging of a pulled row: the nine populations, phi and (with the
-// drag) beta, as NW rows of 4-byte words, each lane's word at its own
+// Half 0's staging of a pulled row: the nine populations, phi, (with the
+// drag) beta and (with solid nodes, last) the flags of the row two ahead, as
+// NW rows of 4-byte words, each lane's word at its own
 // position.  A 2-byte load with LDS destination fills its lane's word,
 // zero-extended; an 8-byte value takes two words, its low half in row 2i
 // and its high half in row 2i + 1.  Two slots, each its own LDS object,
@@ -183,35 +199,98 @@ __device__ __forceinline__ VelDS<T> mirrored(const VelDS<T>& v) {
   return r;
 }
 
-// Ring row of population plane i (i = 9: phi of the row, i = 10: beta, for
-// half 1) for the sweep-relative row index j >= 0
+// Ring row of population plane i (i = 9: phi of the row, i = 10: beta or the
+// solid flags, 11: the flags after beta, for half 1) for the sweep-relative
+// row index j >= 0
 __device__ __forceinline__ int pop_slot(int i, int j) { return 4 * i + (j & 3); }
 
 // Planes a row carries: nine populations and phi, plus beta with the drag
+// and the solid flags with a mask
 template <int FEAT>
-constexpr int step2_planes() { return (FEAT & FEAT_DRAG) ? 11 : 10; }
+constexpr int step2_planes() { return 10 + ((FEAT & FEAT_DRAG) ? 1 : 0) + ((FEAT & FEAT_MASK) ? 1 : 0); }
 
-// 4-byte words of a staged row: one per plane, two for 8-byte values
+// 4-byte words of a staged row: one per plane, two for 8-byte values; the
+// flags (of the row two ahead) take one
 template <typename S, int FEAT>
-constexpr int step2_words() { return step2_planes<FEAT>() * (sizeof(S) == 8 ? 2 : 1); }
+constexpr int step2_words() {
+  return (10 + ((FEAT & FEAT_DRAG) ? 1 : 0)) * (sizeof(S) == 8 ? 2 : 1) + ((FEAT & FEAT_MASK) ? 1 : 0);
+}
 
 // Waves per SIMD of the two-step kernels: four in FP32 arithmetic (128
-// registers), two in FP64 (256)
+// registers), two in FP64 (256); three with solid nodes and the drag in FP32
+// (168: at 128 they would spill, and a spill reloaded in the sweep waits for
+// the row staged ahead as well)
+constexpr int step2_waves_of(int tbytes, int feat) {
+  return tbytes == 8 ? 2 : (((feat & FEAT_MASK) && (feat & FEAT_DRAG)) ? 3 : 4);
+}
+template <typename T, int FEAT>
+constexpr int step2_waves() { return step2_waves_of(int(sizeof(T)), FEAT); }
+
+// Lanes per half: 256 in FP32 arithmetic and 128 in FP64 (whose rings take
+// twice the bytes per lane); with solid nodes and the drag, whose two extra
+// planes take LDS, 128 in FP32 (three workgroups per CU) and 64 in FP64.
+constexpr int step2_nt_of(int tbytes, int feat) {
+  const bool md = (feat & FEAT_MASK) && (feat & FEAT_DRAG);
+  if (tbytes == 8) return md ? 64 : 128;
+  return md ? 128 : 256;
+}
+
+// LDS bytes of one two-step workgroup
+template <typename S, typename T, int FEAT, int NT>
+constexpr unsigned step2_lds_bytes() {
+  return unsigned(sizeof(Step2Lds<T, NT, step2_planes<FEAT>()>) + 2 * sizeof(Step2Stage<NT, step2_words<S, FEAT>()>));
+}
+
+// Flagged-neighbour sums of the Eq. (10) stencils: sum over the neighbours
+// flagged in nb (bits 1..8) of c_i e_ix and c_i e_iy, with c_i = 4 on the
+// axes and 1 on the diagonals (each 12 times the stencil's weight)
+__device__ __forceinline__ int solid_kx(unsigned nb) {
+  const int b = int(nb);
+  return 4 * (((b >> 1) & 1) - ((b >> 3) & 1)) + ((((b >> 5) & 1) + ((b >> 8) & 1)) - (((b >> 6) & 1) + ((b >> 7) & 1)));
+}
+__device__ __forceinline__ int solid_ky(unsigned nb) {
+  const int b = int(nb);
+  return 4 * (((b >> 2) & 1) - ((b >> 4) & 1)) + ((((b >> 5) & 1) + ((b >> 6) & 1)) - (((b >> 7) & 1) + ((b >> 8) & 1)));
+}
+
+// Solid flags of the rows in flight (see the sweep)
+struct FlagRows {
+  unsigned lo, hi;
+};
+
+// true on every lane if any lane of the wave has cond
+__device__ __forceinline__ bool wave_any(bool cond) { return __builtin_amdgcn_ballot_w64(cond) != 0; }
+
+// The solid flags as a value of the ring's type and back (bit copies)
 template <typename T>
-constexpr int step2_waves() { return sizeof(T) == 8 ? 2 : 4; }
+__device__ __forceinline__ T flags_as(unsigned nb) {
+  if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, (unsigned long long)nb);
+  else return __builtin_bit_cast(T, nb);
+}
+template <typename T>
+__device__ __forceinline__ unsigned flags_of(T v) {
+  if constexpr (sizeof(T) == 8) return unsigned(__builtin_bit_cast(unsigned long long, v));
+  else return __builtin_bit_cast(unsigned, v);
+}
 
 // FEAT: the plain step plus any of FEAT_FORCE (a per-node force field added
-// to F^B) and FEAT_DRAG (the linear drag, u solved in closed form as in the
-// single step)
+// to F^B), FEAT_DRAG (the linear drag, u solved in closed form as in the
+// single step) and FEAT_MASK (solid nodes; no walls in x).  Absent force,
+// drag and flag planes read as zero.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __device__ inline void step2_tile(
     const StepGeom& g, const StepPhys<T>& ph, int strip, int by,
     lds_t<Step2Lds<T, NT, step2_planes<FEAT>()>>* __restrict__ Lp,
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st0,
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st1) {
-  static_assert((FEAT & ~(FEAT_FORCE | FEAT_DRAG)) == 0, "force field and linear drag only");
+  static_assert((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK)) == 0,
+                "force field, linear drag and solid nodes only");
   constexpr bool DRAG = (FEAT & FEAT_DRAG) != 0;
   constexpr bool FORCE = (FEAT & FEAT_FORCE) != 0;
+  constexpr bool MASK = (FEAT & FEAT_MASK) != 0;
+  constexpr int PL_NB = DRAG ? 11 : 10;                  // ring plane of the flags
+  constexpr int NW = step2_words<S, FEAT>();
+  constexpr unsigned BOUNCE = 0x1FEu;                    // neighbour bits of the flags
   auto& L = *Lp;
   static_assert(((sizeof(S) == 4 || sizeof(S) == 2) && sizeof(T) == 4) ||
                     (sizeof(S) == 8 && sizeof(T) == 8),
@@ -222,6 +301,7 @@ __device__ inline void step2_tile(
   const int half = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / NT);
   const int t = int(threadIdx.x) - half * NT;
   const int nx = g.nx, ny = g.ny, pitch = g.pitch;
+  const int yoff = 5 + 4 * half;
   const int x0 = strip * g.out_w;
   const int w = min(g.out_w, nx - x0);
   const int h = 3 * half;
@@ -232,6 +312,9 @@ __device__ inline void step2_tile(
   // lane mask, which would cost a copy of each carried value per row.
   // Values of the other lanes are never used.
   const bool olane = t >= h + 2 && t < w + 8 - h;
+  auto* s_rho = L.rho[half];
+  auto* s_u4 = L.u4[half];
+  auto* s_u2 = L.u2[half];
   const int c = wrap_index(x0 - 5 + t, nx);
   const int cm = (c == 0) ? nx - 1 : c - 1;
   const int cp = (c == nx - 1) ? 0 : c + 1;
@@ -239,24 +322,25 @@ __device__ inline void step2_tile(
   constexpr unsigned SB = sizeof(S);
   constexpr unsigned TB = sizeof(T);
 
-  auto* s_rho = L.rho[half];
-  auto* s_u4 = L.u4[half];
-  auto* s_u2 = L.u2[half];
 
   const unsigned plane_bytes = unsigned(g.plane) * SB;
   const unsigned row_bytes = unsigned(pitch) * SB;
   const rsrc_t srcr = make_rsrc(g.src, 9u * plane_bytes);
   const rsrc_t dstr = make_rsrc(g.dst, 9u * plane_bytes);
   const rsrc_t phir = make_rsrc(g.phi, unsigned(g.plane) * TB);
-  const rsrc_t betar = make_rsrc(g.beta, DRAG ? unsigned(g.plane) * TB : 0u);
-  const rsrc_t fxr = make_rsrc(g.fxf, FORCE ? unsigned(g.plane) * TB : 0u);
-  const rsrc_t fyr = make_rsrc(g.fyf, FORCE ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t betar = make_rsrc(g.beta, (DRAG && g.beta) ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t fxr = make_rsrc(g.fxf, (FORCE && g.fxf) ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t fyr = make_rsrc(g.fyf, (FORCE && g.fyf) ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t nbrr = make_rsrc(g.nbr, (MASK && g.nbr) ? unsigned(g.plane) * 2u : 0u);
   auto poff = [&](int i, int r) { return unsigned(i) * plane_bytes + unsigned(r) * row_bytes; };
+  // row of the flags a staged row yn carries (those of row yn + 2)
+  auto flag_row = [&](int yn) {
+    return unsigned(WALLS ? min(max(yn + 2, 0), ny - 1) : wrap_index(yn + 2, ny)) * unsigned(pitch) * 2u;
+  };
 
   const int y0 = by * g.rows;
   const int y1 = min(y0 + g.rows, ny);
   const int nit = (y1 - y0) + 11;
-  const int yoff = 5 + 4 * half;
   // sweep-relative row index of the population ring (>= 0 for every row it
   // holds)
   auto jr = [&](int y) { return y - y0 + 12; };
@@ -266,9 +350,10 @@ __device__ inline void step2_tile(
   const unsigned xcT = unsigned(c) * TB;
 
   // The pull of row yn from HBM: ld(i, buffer, lane offset, row offset) for
-  // the nine populations (i = 0..8) and phi (i = 9).  Rows are clamped
-  // inside walls, so every load is in bounds.
-  auto pull_row = [&](int yn, auto&& ld) {
+  // the nine populations (i = 0..8), phi (i = 9), beta (i = 10) and the
+  // flags of row yn + 2 (i = -1).  Rows are clamped inside walls, so every
+  // load is in bounds.  fl: the flags of row yn.
+  auto pull_row = [&](int yn, unsigned fl, auto&& ld) {
     int r, rs, rn;
     bool bl = false, bh = false;
     if (WALLS) {
@@ -284,7 +369,29 @@ __device__ inline void step2_tile(
     }
     ld(9, phir, xcT, unsigned(r) * unsigned(pitch) * TB);
     if (DRAG) ld(10, betar, xcT, unsigned(r) * unsigned(pitch) * TB);
+    if (MASK) ld(-1, nbrr, unsigned(c) * 2u, flag_row(yn));
     ld(0, srcr, xcb, poff(0, r));
+    if (MASK && wave_any((fl & BOUNCE) != 0)) {
+      // a wave next to a solid node: per lane the pulled slot, or the own
+      // node's opposite slot when the source is solid (whole byte offsets
+      // in the per-lane operand); wall rows as below
+      auto pick = [&](int i, unsigned vcol, unsigned soff, int opp) {
+        // the uniform parts kept opaque: folded into the per-lane columns
+        // they would become loop-invariant registers
+        unsigned so = poff(opp, r), sp = soff;
+        __asm__ volatile("" : "+s"(so), "+s"(sp));
+        ld(i, srcr, solid_bit(fl, opp) ? so + xcb : sp + vcol, 0u);
+      };
+      pick(1, xmb, poff(1, r), 3);
+      pick(3, xpb, poff(3, r), 1);
+      pick(2, xcb, bl ? poff(4, r) : poff(2, rs), 4);
+      pick(5, bl ? xcb : xmb, bl ? poff(7, r) : poff(5, rs), 7);
+      pick(6, bl ? xcb : xpb, bl ? poff(8, r) : poff(6, rs), 8);
+      pick(4, xcb, bh ? poff(2, r) : poff(4, rn), 2);
+      pick(7, bh ? xcb : xpb, bh ? poff(5, r) : poff(7, rn), 5);
+      pick(8, bh ? xcb : xmb, bh ? poff(6, r) : poff(8, rn), 6);
+      return;
+    }
     ld(1, srcr, xmb, poff(1, r));
     ld(3, srcr, xpb, poff(3, r));
     if (WALLS && (bl || bh)) {
@@ -308,9 +415,13 @@ __device__ inline void step2_tile(
   // Half 0's loads of row yn into staging slot sl; each wave's 64 lanes
   // fill 64 consecutive words from the wave's base.
   const int wb = __builtin_amdgcn_readfirstlane(t & ~63);
-  auto stage_row = [&](int yn, int sl) {
-    pull_row(yn, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
+  auto stage_row = [&](int yn, int sl, unsigned fl) {
+    pull_row(yn, fl, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
       auto* st = sl ? st1 : st0;
+      if (i < 0) {  // the flags of row yn + 2: the last word
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_t<void>*)&st->v[NW - 1][wb], 2, v, so, 0, 0);
+        return;
+      }
       if constexpr (sizeof(S) == 8) {
         // low and high words (phi and beta are FP64 too); the high word's 4
         // bytes go into the uniform offset: an immediate offset would move
@@ -334,8 +445,12 @@ __device__ inline void step2_tile(
   // and stage B write the image of row ny - 1 into the single-row rings;
   // below the lower wall the image of row 0 replaces the carried D and S of
   // row -1 before the stage that needs it.
+  // With solid nodes the flags of the rows in flight sit in 10-bit fields of
+  // two registers, shifted by one field per iteration: fl.hi holds those of
+  // rows yA, yA - 1 and yA - 2 (stages A, B and C), and half 0's fl.lo those
+  // of rows yA + 2 and yA + 1 (staged with row yA and yA - 1).
   auto body = [&](int k, int sl, RowState<T>& rA, const RowState<T>& rB,
-                  const RowState<T>& rC, T (&bNew)[2], const T (&bOld)[2]) {
+                  const RowState<T>& rC, T (&bNew)[2], const T (&bOld)[2], FlagRows& fl) {
     const int yA = y0 - yoff + k;
     if (WALLS && (yA == 1 || yA == 2)) {
       // a branch taken once per sweep (the asm statement keeps the compiler
@@ -362,12 +477,27 @@ __device__ inline void step2_tile(
       rA.mpxx = (q[1] + q[3]) - (q[2] + q[4]);
       rA.mpxy = (q[5] + q[7]) - (q[6] + q[8]);
       rA.phi = phi;
-      rA.rphi = recip(phi);
-      rA.drho = rA.dm0 * rA.rphi;
+      const T rp = recip(phi);
+      if constexpr (!MASK) rA.rphi = rp;  // (recomputed with solid nodes: registers)
+      rA.drho = rA.dm0 * rp;
     };
     // half 0: the staged row yA has landed once at most one batch (row
     // yA + 1: one load per staged word row) is still in flight
-    if (half == 0) wait_vm<step2_words<S, FEAT>()>();
+    if (half == 0) wait_vm<NW>();
+    // the flags shift by one row on every iteration, whether or not the row
+    // of stage A exists (stages B and C still do)
+    if (MASK && half == 0) {
+      // the flags of row yA + 2, staged with row yA
+      const unsigned fnew = __builtin_bit_cast(unsigned, float((sl ? st1 : st0)->v[NW - 1][t]));
+      __asm__ volatile("" ::: "memory");
+      fl.hi = ((fl.hi << 10) | (fl.lo >> 10)) & 0x3FFFFFFFu;
+      fl.lo = ((fl.lo << 10) | fnew) & 0xFFFFFu;
+    } else if (MASK) {
+      // those of row yA, with the row in half 0's ring (in bounds for every
+      // row of the sweep; rows that do not exist give values never used)
+      const unsigned nb = flags_of(L.pop[pop_slot(PL_NB, jr(yA))][t]);
+      fl.hi = ((fl.hi << 10) | nb) & 0x3FFFFFFFu;
+    }
     // the force field of stage B's row, loaded into registers here so that
     // the loads land while stage A runs (they take no LDS)
     T fex = T(0), fey = T(0);
@@ -427,17 +557,33 @@ __device__ inline void step2_tile(
         q[4] = rp[4 * P];
         q[7] = rp[7 * P + 1];
         q[8] = rp[8 * P - 1];
+        if constexpr (MASK) {
+          // a solid source: the own node's opposite population of the ring row
+          const unsigned nb = fl.hi & 0x3FFu;
+          if (wave_any((nb & BOUNCE) != 0)) {
+            q[1] = solid_bit(nb, 3) ? r0[3 * P] : q[1];
+            q[3] = solid_bit(nb, 1) ? r0[1 * P] : q[3];
+            q[2] = solid_bit(nb, 4) ? r0[4 * P] : q[2];
+            q[4] = solid_bit(nb, 2) ? r0[2 * P] : q[4];
+            q[5] = solid_bit(nb, 7) ? r0[7 * P] : q[5];
+            q[7] = solid_bit(nb, 5) ? r0[5 * P] : q[7];
+            q[6] = solid_bit(nb, 8) ? r0[8 * P] : q[6];
+            q[8] = solid_bit(nb, 6) ? r0[6 * P] : q[8];
+          }
+        }
         moments(q, phi);
       }
-      s_rho[t] = rA.drho;
+      // solid nodes: zero, left out of the separable sums
+      s_rho[t] = (MASK && solid_bit(fl.hi, 0)) ? T(0) : rA.drho;
     } else if (WALLS && yA == ny) {
-      s_rho[t] = rB.drho;  // above the upper wall: row ny - 1 itself
+      // above the upper wall: row ny - 1 itself
+      s_rho[t] = (MASK && solid_bit(fl.hi, 10)) ? T(0) : rB.drho;
     }
     lds_barrier();
 
     // The staging slot of row yA has been read (the barrier above waited for
     // this wave's LDS reads): it takes row yA + 2.
-    if (half == 0) stage_row(yA + 2, sl);
+    if (half == 0) stage_row(yA + 2, sl, fl.lo & 0x3FFu);
 
     // ---------------- stage B: velocity of row yA - 1 ----------------
     // D and S of delta-rho on row yA, then grad rho on row yA - 1.  D and S
@@ -452,8 +598,15 @@ __device__ inline void step2_tile(
         rn.s = (rE + rW) + T(4) * r0;
       }
       if (rowB) {
-        const T grx = T(4) * rc.d + (rm.d + rn.d);  // 12 d_x rho (Eq. 10)
-        const T gry = rn.s - rm.s;                  // 12 d_y rho
+        T grx = T(4) * rc.d + (rm.d + rn.d);  // 12 d_x rho (Eq. 10)
+        T gry = rn.s - rm.s;                  // 12 d_y rho
+        if constexpr (MASK) {
+          const unsigned nbB = (fl.hi >> 10) & 0x3FFu;
+          if (wave_any((nbB & BOUNCE) != 0)) {  // solid neighbours: the centre value
+            grx += T(solid_kx(nbB)) * rB.drho;
+            gry += T(solid_ky(nbB)) * rB.drho;
+          }
+        }
         const T phi = rB.phi;
         const T kp = (kappa - phi) * T(1.0 / 36.0);     // Eq. (13), with the 1/12
         const T sg = ph.scale_by_phi ? phi : T(1);
@@ -483,6 +636,10 @@ __device__ inline void step2_tile(
         U2<T> b;
         a.ux = ux; a.uy = uy; a.mux = m0 * ux; a.rux = rho * ux;
         b.muy = m0 * uy; b.ruy = rho * uy;
+        if (MASK && solid_bit(fl.hi, 10)) {  // solid node: zero, left out of the sums
+          a.ux = a.uy = a.mux = a.rux = T(0);
+          b.muy = b.ruy = T(0);
+        }
         lds_put(s_u4[t], a);
         lds_put(s_u2[t], b);
         bNew[0] = Fx;
@@ -560,20 +717,34 @@ __device__ inline void step2_tile(
 
         const T phi = rC.phi;
         const T rho = rho0 + rC.drho;
-        const T X = kappa * rC.rphi;
+        const T m0 = phi * rho0 + rC.dm0;
+        const T X = kappa * (MASK ? recip(phi) : rC.rphi);
         const T kr = (kappa - phi) * rho;
         const T ux = vc.ux, uy = vc.uy, Fx = bOld[0], Fy = bOld[1];
 
         // penalty source (Eq. 20), static void fraction; the 1/12 of the
         // derivatives is folded into the coefficients
-        const T Ca = -ph.k12 * (dx_rux + dy_ruy) + (kr * T(1.0 / 6.0)) * (dx_ux + dy_uy) +
-                     (T(0.25) - X * T(1.0 / 6.0)) * (dx_mux + dy_muy);
-        const T Cb = -ph.k12 * (dx_rux - dy_ruy) + (kr * T(1.0 / 18.0)) * (dx_ux - dy_uy) +
-                     T(1.0 / 12.0) * (dx_mux - dy_muy);
-        const T Cc = (kr * T(1.0 / 36.0)) * (dx_uy + dy_ux);
+        T Ca = -ph.k12 * (dx_rux + dy_ruy) + (kr * T(1.0 / 6.0)) * (dx_ux + dy_uy) +
+               (T(0.25) - X * T(1.0 / 6.0)) * (dx_mux + dy_muy);
+        T Cb = -ph.k12 * (dx_rux - dy_ruy) + (kr * T(1.0 / 18.0)) * (dx_ux - dy_uy) +
+               T(1.0 / 12.0) * (dx_mux - dy_muy);
+        T Cc = (kr * T(1.0 / 36.0)) * (dx_uy + dy_ux);
+        if constexpr (MASK) {
+          const unsigned nbC = (fl.hi >> 20) & 0x3FFu;
+          if (wave_any((nbC & BOUNCE) != 0)) {
+            // Solid neighbours stand in with the centre's velocity-like
+            // fields negated: each derivative gains -Kx (or -Ky) times the
+            // centre's rho u, u or (phi rho) u, here gathered into the three
+            // sums (rho u = rho (u), (phi rho) u = m0 (u))
+            const T kx = T(solid_kx(nbC)), ky = T(solid_ky(nbC));
+            const T sp = kx * ux + ky * uy, sm = kx * ux - ky * uy, sc = kx * uy + ky * ux;
+            Ca -= sp * ((kr * T(1.0 / 6.0) - ph.k12 * rho) + (T(0.25) - X * T(1.0 / 6.0)) * m0);
+            Cb -= sm * ((kr * T(1.0 / 18.0) - ph.k12 * rho) + T(1.0 / 12.0) * m0);
+            Cc -= sc * (kr * T(1.0 / 36.0));
+          }
+        }
 
         // equilibria (Eq. 18) minus those of the rest state
-        const T m0 = phi * rho0 + rC.dm0;
         const T drho = rC.drho;
         const T uu = ux * ux + uy * uy;
         const T eq_e = (ph.k2 - T(4) * phi) * drho + T(3) * m0 * uu;
@@ -624,6 +795,10 @@ __device__ inline void step2_tile(
         o9[6] = b - X2 + Y2 - Qd;
         o9[7] = b - X2 - Y2 + Qd;
         o9[8] = b + X2 - Y2 - Qd;
+        if (MASK && solid_bit(fl.hi, 20)) {  // solid node: keep the rest state
+#pragma unroll
+          for (int i = 0; i < 9; ++i) o9[i] = T(0);
+        }
 
         if (half == 0) {  // into the ring for the second step
           const int jo = jr(yo);
@@ -631,6 +806,7 @@ __device__ inline void step2_tile(
           for (int i = 0; i < 9; ++i) L.pop[pop_slot(i, jo)][t] = o9[i];
           L.pop[pop_slot(9, jo)][t] = phi;
           if (DRAG) L.pop[pop_slot(10, jo)][t] = rC.beta;
+          if (MASK) L.pop[pop_slot(PL_NB, jo)][t] = flags_as<T>((fl.hi >> 20) & 0x3FFu);
         } else if (SHIFT) {  // already scaled
 #pragma unroll
           for (int i = 0; i < 9; ++i) bstore(static_cast<S>(o9[i]), dstr, xcb, poff(i, yo));
@@ -652,25 +828,33 @@ __device__ inline void step2_tile(
 
   // Software pipeline: half 0 stages rows two ahead (see stage_row); the
   // loop is unrolled by six (a multiple of the three-row period of the
-  // states and of the two staging slots) so nothing is copied.
+  // states and of the two staging slots) so nothing is copied.  With solid
+  // nodes the flags of the first two rows are loaded here.
   RowState<T> R0{}, R1{}, R2{};
   T b0[2] = {0, 0}, b1[2] = {0, 0};
+  FlagRows fl{0u, 0u};
   if (half == 0) {
-    stage_row(y0 - yoff, 0);
-    stage_row(y0 - yoff + 1, 1);
+    unsigned fa = 0, fb = 0;
+    if (MASK) {
+      fa = bload_u16(nbrr, unsigned(c) * 2u, flag_row(y0 - 7));
+      fb = bload_u16(nbrr, unsigned(c) * 2u, flag_row(y0 - 6));
+      fl.lo = fb | (fa << 10);
+    }
+    stage_row(y0 - 5, 0, fa);
+    stage_row(y0 - 4, 1, fb);
   }
   for (int k = 0; k < nit; k += 6) {
-    body(k + 0, 0, R0, R2, R1, b0, b1);
+    body(k + 0, 0, R0, R2, R1, b0, b1, fl);
     if (k + 1 >= nit) break;
-    body(k + 1, 1, R1, R0, R2, b1, b0);
+    body(k + 1, 1, R1, R0, R2, b1, b0, fl);
     if (k + 2 >= nit) break;
-    body(k + 2, 0, R2, R1, R0, b0, b1);
+    body(k + 2, 0, R2, R1, R0, b0, b1, fl);
     if (k + 3 >= nit) break;
-    body(k + 3, 1, R0, R2, R1, b1, b0);
+    body(k + 3, 1, R0, R2, R1, b1, b0, fl);
     if (k + 4 >= nit) break;
-    body(k + 4, 0, R1, R0, R2, b0, b1);
+    body(k + 4, 0, R1, R0, R2, b0, b1, fl);
     if (k + 5 >= nit) break;
-    body(k + 5, 1, R2, R1, R0, b1, b0);
+    body(k + 5, 1, R2, R1, R0, b1, b0, fl);
   }
   // no load into LDS may outlive the workgroup
   wait_vm<0>();
@@ -680,7 +864,7 @@ __device__ inline void step2_tile(
 // tile % strips, row block tile / strips); 2 NT lanes (two halves of NT),
 // four waves per SIMD.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(step2_waves<T>())))
+__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(step2_waves<T, FEAT>())))
 vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
   __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;
   __shared__ Step2Stage<NT, step2_words<S, FEAT>()> stage0, stage1;
@@ -695,7 +879,7 @@ vanse_step2_kernel(StepGeom g, StepPhys<T> ph) {
 // as in the one-lattice kernel); each member's two buffers alternate with
 // the launch parity as in the one-step batch.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(step2_waves<T>())))
+__global__ void __launch_bounds__(2 * NT) __attribute__((amdgpu_waves_per_eu(step2_waves<T, FEAT>())))
 vanse_batch_step2_kernel(const BatchEntry<T>* __restrict__ entries,
                          const int2* __restrict__ tile_map, int launch) {
   __shared__ Step2Lds<T, NT, step2_planes<FEAT>()> lds;

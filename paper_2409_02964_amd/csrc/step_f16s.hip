@@ -2,6 +2,4 @@
 #define VANSE_S _Float16
 #define VANSE_T float
 #define VANSE_SHIFT true
-#define VANSE_FUSED2_NT 256
-#define VANSE_FUSED2_BATCH_MAX 256
 #include "step_inst.hpp"

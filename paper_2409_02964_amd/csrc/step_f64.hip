@@ -2,6 +2,4 @@
 #define VANSE_S double
 #define VANSE_T double
 #define VANSE_SHIFT false
-#define VANSE_FUSED2_NT 128
-#define VANSE_FUSED2_BATCH_MAX 128
 #include "step_inst.hpp"

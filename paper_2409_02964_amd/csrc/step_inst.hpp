@@ -7,10 +7,12 @@
 // solid nodes alone or with all of those, the scheme variants with all of
 // those, FEAT_ALL), 512 for the plain
 // step; the batched kernel for all but the last two (a moving phi is not
-// batched); the two-step kernel of the
-// first four with halves of VANSE_FUSED2_NT lanes
-// (256 in FP32 arithmetic, 128 in FP64, whose rings take twice the LDS), and
-// its batched form with halves of 64 lanes up to VANSE_FUSED2_BATCH_MAX.
+// batched); the two-step kernel of the first four and of solid nodes alone,
+// with the drag, or with the force field and drag, with halves of
+// step2_nt_of lanes, and its batched form with halves of 64 lanes up to
+// that width.
+#include <type_traits>
+
 #include "step_launch.hpp"
 
 namespace vanse_dev {
@@ -20,10 +22,40 @@ void launch_step_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStr
   hipLaunchKernelGGL((vanse_step_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(blocks), dim3(NT), 0, st, g, ph);
 }
 
-template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-void launch_step2_nt(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st) {
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
+void launch_step2(const StepGeom& g, const StepPhys<T>& ph, int blocks, hipStream_t st) {
+  constexpr int NT = step2_nt_of(int(sizeof(T)), FEAT);
+  static_assert(2 * step2_lds_bytes<S, T, FEAT, NT>() <= 160u * 1024u, "two workgroups per CU");
   hipLaunchKernelGGL((vanse_step2_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(blocks), dim3(2 * NT), 0,
                      st, g, ph);
+}
+
+template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
+bool launch_batch2(int threads, const BatchEntry<T>* entries, const int2* tile_map, int launch, int tiles,
+                   hipStream_t st) {
+  constexpr int MAXNT = step2_nt_of(int(sizeof(T)), FEAT);
+  auto go = [&](auto nt) {
+    constexpr int NT = decltype(nt)::value;
+    hipLaunchKernelGGL((vanse_batch_step2_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(tiles), dim3(2 * NT),
+                       0, st, entries, tile_map, launch);
+  };
+  if (threads == 64) {
+    go(std::integral_constant<int, 64>{});
+    return true;
+  }
+  if constexpr (MAXNT >= 128) {
+    if (threads == 128) {
+      go(std::integral_constant<int, 128>{});
+      return true;
+    }
+  }
+  if constexpr (MAXNT >= 256) {
+    if (threads == 256) {
+      go(std::integral_constant<int, 256>{});
+      return true;
+    }
+  }
+  return false;
 }
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
@@ -31,13 +63,6 @@ void launch_batch_nt(const BatchEntry<T>* entries, const int2* tile_map, int lau
                      hipStream_t st) {
   hipLaunchKernelGGL((vanse_batch_step_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(tiles), dim3(NT), 0,
                      st, entries, tile_map, launch);
-}
-
-template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
-void launch_batch2_nt(const BatchEntry<T>* entries, const int2* tile_map, int launch, int tiles,
-                      hipStream_t st) {
-  hipLaunchKernelGGL((vanse_batch_step2_kernel<S, T, SHIFT, WALLS, FEAT, NT>), dim3(tiles), dim3(2 * NT),
-                     0, st, entries, tile_map, launch);
 }
 
 #define VANSE_STEP_ONE(W, F, NT) \
@@ -73,24 +98,18 @@ VANSE_WALLS(VANSE_BATCH_ONE, FEAT_SCHEME | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
 
 // two steps per pass
 #define VANSE_STEP2_ONE(W, F) \
-  template void launch_step2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, VANSE_FUSED2_NT>( \
-      const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
-#define VANSE_STEP2_FEATS(M, W) M(W, 0) M(W, FEAT_DRAG) M(W, FEAT_FORCE) M(W, FEAT_FORCE | FEAT_DRAG)
-VANSE_STEP2_FEATS(VANSE_STEP2_ONE, false) VANSE_STEP2_FEATS(VANSE_STEP2_ONE, true)
-#undef VANSE_STEP2_ONE
-#define VANSE_BATCH2_ONE(W, F, NT) \
-  template void launch_batch2_nt<VANSE_S, VANSE_T, VANSE_SHIFT, W, F, NT>( \
-      const BatchEntry<VANSE_T>*, const int2*, int, int, hipStream_t);
-#if VANSE_FUSED2_BATCH_MAX >= 256
-#define VANSE_BATCH2_WIDTHS(W, F) VANSE_BATCH2_ONE(W, F, 64) VANSE_BATCH2_ONE(W, F, 128) \
-  VANSE_BATCH2_ONE(W, F, 256)
-#else
-#define VANSE_BATCH2_WIDTHS(W, F) VANSE_BATCH2_ONE(W, F, 64) VANSE_BATCH2_ONE(W, F, 128)
-#endif
-VANSE_STEP2_FEATS(VANSE_BATCH2_WIDTHS, false) VANSE_STEP2_FEATS(VANSE_BATCH2_WIDTHS, true)
+  template void launch_step2<VANSE_S, VANSE_T, VANSE_SHIFT, W, F>( \
+      const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t); \
+  template bool launch_batch2<VANSE_S, VANSE_T, VANSE_SHIFT, W, F>( \
+      int, const BatchEntry<VANSE_T>*, const int2*, int, int, hipStream_t);
+#define VANSE_STEP2_FEATS(W) VANSE_STEP2_ONE(W, 0) VANSE_STEP2_ONE(W, FEAT_DRAG) \
+  VANSE_STEP2_ONE(W, FEAT_FORCE) VANSE_STEP2_ONE(W, FEAT_FORCE | FEAT_DRAG) \
+  VANSE_STEP2_ONE(W, FEAT_MASK) VANSE_STEP2_ONE(W, FEAT_MASK | FEAT_DRAG) \
+  VANSE_STEP2_ONE(W, FEAT_MASK | FEAT_FORCE | FEAT_DRAG)
+VANSE_STEP2_FEATS(false)
+VANSE_STEP2_FEATS(true)
 #undef VANSE_STEP2_FEATS
-#undef VANSE_BATCH2_WIDTHS
-#undef VANSE_BATCH2_ONE
+#undef VANSE_STEP2_ONE
 
 #undef VANSE_STEP_ONE
 #undef VANSE_BATCH_ONE

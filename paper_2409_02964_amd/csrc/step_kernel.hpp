@@ -210,8 +210,8 @@ enum : int {
 };
 
 // Solid flags of FEAT_MASK, one uint16 per node: bit 0 -- the node itself is
-// solid; bit i (1..8) -- the node standing in for x + e_i (after reflection
-// across a wall) is solid.  A fluid node pulls f_i from its own slot opp(i)
+// solid (and then its only bit); bit i (1..8) -- the node standing in for
+// x + e_i (after reflection across a wall) is solid.  A fluid node pulls f_i from its own slot opp(i)
 // when bit opp(i) is set (half-way bounce-back on the solid face), and the
 // Eq. (10) stencils replace a flagged neighbour by the centre value, negated
 // for velocity-like fields.

@@ -277,8 +277,9 @@ int feat_of(const vanse_lattice* h) {
   return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0);
 }
 
-// Variants the two-step kernel takes: the force field and the drag
-bool batch_feat(int feat) { return (feat & ~(FEAT_FORCE | FEAT_DRAG)) == 0; }
+// Variants the two-step kernel takes: the force field, the drag and solid
+// nodes
+bool batch_feat(int feat) { return (feat & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK)) == 0; }
 
 // Lattices batches take: any variant with an instance of its own (not
 // FEAT_ALL) and no moving phi (its phi(t+1) is given step by step)
@@ -302,26 +303,66 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
   }
 }
 
-// Two-step launches of the plain step with or without the force field and
-// the linear drag (no other optional input or scheme variant).  Halves of
-// 256 lanes in FP32 arithmetic and of 128 in FP64 (whose LDS rings take
-// twice the bytes per lane); each outputs its half's width less 10 columns.
-// Rows per workgroup default to one full round of resident workgroups (two
-// per CU in either precision).
-template <typename T>
-constexpr int fused_nt() { return sizeof(T) == 8 ? 128 : 256; }
-int fused_out_w(const vanse_lattice* h) { return (h->d.precision == VANSE_F64 ? 128 : 256) - 10; }
+// Two-step launches of the plain step with any of the force field, the
+// linear drag and solid nodes (no walls in x, moving phi or scheme variant).
+// Halves of step2_nt_of lanes (256 in FP32 arithmetic and 128 in FP64, fewer
+// with solid nodes); each outputs its half's width less 10 columns.  Rows per
+// workgroup default to one full round of resident workgroups.
+int arith_bytes(const vanse_lattice* h) { return h->d.precision == VANSE_F64 ? 8 : 4; }
+// The two-step instance of a lattice: its single-step variant, except that
+// solid nodes without a force field take an instance without the force
+// planes (FEAT_MASK, or FEAT_MASK | FEAT_DRAG with the drag): the per-row
+// loads of the force field into registers make the sweep wait for the rows
+// staged ahead as well.
+int fused_inst(const vanse_lattice* h) {
+  const int f = feat_of(h);
+  if ((f & FEAT_MASK) && !h->d.has_force_field) return h->d.has_drag ? (FEAT_MASK | FEAT_DRAG) : FEAT_MASK;
+  return f;
+}
+int fused_nt_of(const vanse_lattice* h) { return step2_nt_of(arith_bytes(h), fused_inst(h)); }
+int fused_out_w(const vanse_lattice* h) { return fused_nt_of(h) - 10; }
 
-// Variants the two-step kernel is built for: the plain step with or without
-// the force field and the linear drag (no mask, moving phi or scheme variant)
-bool fused_feat(const vanse_lattice* h) { return batch_feat(feat_of(h)); }
+bool fused_feat(const vanse_lattice* h) { return batch_feat(feat_of(h)) && h->d.bc_x != VANSE_WALL; }
 
 bool fused_ok(const vanse_lattice* h) { return h->fuse == 2 && fused_feat(h); }
+
+// LDS bytes of a two-step workgroup of the variant feat
+template <typename S, typename T>
+unsigned fused_lds_bytes(int feat) {
+  auto of = [](auto f) {
+    constexpr int F = decltype(f)::value;
+    return step2_lds_bytes<S, T, F, step2_nt_of(int(sizeof(T)), F)>();
+  };
+  switch (feat) {
+    case FEAT_DRAG: return of(std::integral_constant<int, FEAT_DRAG>{});
+    case FEAT_FORCE: return of(std::integral_constant<int, FEAT_FORCE>{});
+    case FEAT_FORCE | FEAT_DRAG: return of(std::integral_constant<int, FEAT_FORCE | FEAT_DRAG>{});
+    case FEAT_MASK: return of(std::integral_constant<int, FEAT_MASK>{});
+    case FEAT_MASK | FEAT_DRAG: return of(std::integral_constant<int, FEAT_MASK | FEAT_DRAG>{});
+    case FEAT_MASK | FEAT_FORCE | FEAT_DRAG:
+      return of(std::integral_constant<int, FEAT_MASK | FEAT_FORCE | FEAT_DRAG>{});
+    default: return of(std::integral_constant<int, 0>{});
+  }
+}
+
+// Two-step workgroups resident per CU: by waves (step2_waves_of per SIMD)
+// and by the CU's 160 KB of LDS
+int fused_per_cu(const vanse_lattice* h) {
+  const int feat = fused_inst(h);
+  unsigned lds = 0;
+  switch (h->d.precision) {
+    case VANSE_F64: lds = fused_lds_bytes<double, double>(feat); break;
+    case VANSE_F16_SHIFTED: lds = fused_lds_bytes<_Float16, float>(feat); break;
+    default: lds = fused_lds_bytes<float, float>(feat);
+  }
+  const int waves = 4 * step2_waves_of(arith_bytes(h), feat) / (2 * fused_nt_of(h) / 64);
+  return std::max(1, std::min(waves, int(160u * 1024u / lds)));
+}
 
 int fused_rows(const vanse_lattice* h) {
   if (h->rows2 > 0) return h->rows2;
   const int strips = (h->d.nx + fused_out_w(h) - 1) / fused_out_w(h);
-  long long nby = (long long)device_cus() * 2 / strips;
+  long long nby = (long long)device_cus() * fused_per_cu(h) / strips;
   if (nby < 1) nby = 1;
   long long r = (h->d.ny + nby - 1) / nby;
   if (r < 4) r = 4;
@@ -330,38 +371,42 @@ int fused_rows(const vanse_lattice* h) {
 
 template <typename S, typename T, bool SHIFT>
 int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
-  constexpr int NT = fused_nt<T>();
   const StepPhys<T> ph = make_phys<T>(h);
+  const int feat = fused_inst(h);
   StepGeom g{};
   g.phi = h->ws + h->L.phi;
   g.phin = g.phi;
+  g.nbr = h->d.has_mask ? h->ws + h->L.nbr : nullptr;
+  g.xwalls = 0;
   g.plane = h->L.plane;
   g.nx = h->d.nx;
   g.ny = h->d.ny;
   g.pitch = h->L.pitch;
-  g.out_w = NT - 10;
+  g.out_w = fused_out_w(h);
   g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
   g.rows = fused_rows(h);
-  const int feat = feat_of(h);
-  g.beta = (feat & FEAT_DRAG) ? h->ws + h->L.beta : nullptr;
-  g.fxf = (feat & FEAT_FORCE) ? h->ws + h->L.fx : nullptr;
-  g.fyf = (feat & FEAT_FORCE) ? h->ws + h->L.fy : nullptr;
+  g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
+  g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
+  g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
   const int blocks = g.strips * ((h->d.ny + g.rows - 1) / g.rows);
   const bool walls = h->d.bc_y == VANSE_WALL;
   for (int64_t s = 0; s < pairs; ++s) {
     g.src = h->ws + h->L.pop[h->cur];
     g.dst = h->ws + h->L.pop[h->cur ^ 1];
-    auto go = [&](auto walls_c, auto feat_c) {
-      launch_step2_nt<S, T, SHIFT, decltype(walls_c)::value, decltype(feat_c)::value, NT>(g, ph, blocks, st);
-    };
     auto with_walls = [&](auto feat_c) {
-      if (walls) go(std::true_type{}, feat_c);
-      else go(std::false_type{}, feat_c);
+      constexpr int F = decltype(feat_c)::value;
+      if (walls) launch_step2<S, T, SHIFT, true, F>(g, ph, blocks, st);
+      else launch_step2<S, T, SHIFT, false, F>(g, ph, blocks, st);
     };
     switch (feat) {
       case FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_DRAG>{}); break;
       case FEAT_FORCE: with_walls(std::integral_constant<int, FEAT_FORCE>{}); break;
       case FEAT_FORCE | FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_FORCE | FEAT_DRAG>{}); break;
+      case FEAT_MASK: with_walls(std::integral_constant<int, FEAT_MASK>{}); break;
+      case FEAT_MASK | FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_MASK | FEAT_DRAG>{}); break;
+      case FEAT_MASK | FEAT_FORCE | FEAT_DRAG:
+        with_walls(std::integral_constant<int, FEAT_MASK | FEAT_FORCE | FEAT_DRAG>{});
+        break;
       default: with_walls(std::integral_constant<int, 0>{});
     }
     h->cur ^= 1;
@@ -1094,9 +1139,11 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
   if (rows < 0) return fail(VANSE_ERR_INVALID_ARG, "rows must be >= 0");
   if (fuse != 1 && fuse != 2) return fail(VANSE_ERR_INVALID_ARG, "steps per pass must be 1 or 2 (got %d)", fuse);
   const vanse_desc& d0 = lats[0] ? lats[0]->d : vanse_desc{};
-  // FP64 rings take twice the LDS per lane: halves of at most 128 lanes
-  if (fuse == 2 && lats[0] && d0.precision == VANSE_F64 && threads == 256)
-    return fail(VANSE_ERR_UNSUPPORTED, "FP64 batches with two steps per launch take 64 or 128 threads");
+  // two-step halves of at most step2_nt_of lanes (FP64 rings take twice the
+  // LDS per lane; solid nodes with the drag two more planes)
+  if (fuse == 2 && lats[0] && threads > fused_nt_of(lats[0]))
+    return fail(VANSE_ERR_UNSUPPORTED, "%s batches with two steps per launch take at most %d threads",
+                d0.precision == VANSE_F64 ? "FP64" : "these", fused_nt_of(lats[0]));
   const int out_w = batch_out_w(threads, fuse);
   long long strip_rows = 0;
   for (int k = 0; k < n; ++k) {
@@ -1113,7 +1160,8 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
                   "lattice %d differs in precision, boundary, force field, drag, mask or scheme variant", k);
     if (fuse == 2 && !fused_feat(lats[k]))
       return fail(VANSE_ERR_UNSUPPORTED,
-                  "lattice %d: two steps per launch take the force field and the drag only", k);
+                  "lattice %d: two steps per launch take the force field, the drag and solid nodes only "
+                  "(no walls in x)", k);
     strip_rows += (long long)((d.nx + out_w - 1) / out_w) * d.ny;
   }
   int r = rows;
@@ -1235,22 +1283,15 @@ int batch_upload(vanse_batch* b, hipStream_t st) {
 }
 
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
-void batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
+int batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
   const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
   const int2* TL = reinterpret_cast<const int2*>(b->ws + b->tiles_off);
-  if constexpr ((FEAT & ~(FEAT_FORCE | FEAT_DRAG)) == 0) {
+  if constexpr ((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK)) == 0) {
     if (b->fuse == 2) {
-      if constexpr (sizeof(T) == 8) {  // halves of 64 or 128 lanes (batch_layout)
-        if (b->threads == 64) launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st);
-        else launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st);
-      } else {
-        switch (b->threads) {
-          case 64: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st); break;
-          case 128: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st); break;
-          default: launch_batch2_nt<S, T, SHIFT, WALLS, FEAT, 256>(E, TL, launch, b->total_tiles, st);
-        }
-      }
-      return;
+      // halves of 64 up to step2_nt_of lanes (batch_layout)
+      if (!launch_batch2<S, T, SHIFT, WALLS, FEAT>(b->threads, E, TL, launch, b->total_tiles, st))
+        return fail(VANSE_ERR_UNSUPPORTED, "no two-step batch kernel with halves of %d lanes", b->threads);
+      return VANSE_OK;
     }
   }
   switch (b->threads) {
@@ -1258,6 +1299,7 @@ void batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
     case 128: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st); break;
     default: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 256>(E, TL, launch, b->total_tiles, st);
   }
+  return VANSE_OK;
 }
 
 int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
@@ -1265,12 +1307,16 @@ int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
     using S = std::remove_pointer_t<decltype(s_tag)>;
     using T = std::remove_pointer_t<decltype(t_tag)>;
     constexpr bool SH = decltype(shift)::value;
+    if (b->fuse == 2 && fused_inst(b->lats[0]) == (FEAT_MASK | FEAT_DRAG)) {  // see fused_inst
+      constexpr int F = FEAT_MASK | FEAT_DRAG;
+      return b->lats[0]->d.bc_y == VANSE_WALL ? batch_launch_t<S, T, SH, true, F>(b, launch, st)
+                                              : batch_launch_t<S, T, SH, false, F>(b, launch, st);
+    }
     return by_variant(b->lats[0], [&](auto walls, auto feat) -> int {
       if constexpr (decltype(feat)::value == FEAT_ALL || decltype(feat)::value == FEAT_MOVING) {
         return fail(VANSE_ERR_UNSUPPORTED, "batches take no time-varying phi, nor a scheme variant with solid nodes");
       } else {
-        batch_launch_t<S, T, SH, decltype(walls)::value, decltype(feat)::value>(b, launch, st);
-        return VANSE_OK;
+        return batch_launch_t<S, T, SH, decltype(walls)::value, decltype(feat)::value>(b, launch, st);
       }
     });
   });
