@@ -171,6 +171,25 @@ int vanse_set_void_fraction(vanse_lattice *h, const double *phi, void *stream);
 int vanse_set_void_fraction_next(vanse_lattice *h, const double *phi_next,
                                  void *stream);
 
+/* Time-varying void fraction over the next two steps (Sec. 2.3, Eq. 20;
+ * the moving particles of Eq. 23), for two steps per launch
+ * (vanse_set_steps_per_pass): phi(x, t+1) and phi(x, t+2), device float64
+ * [ny][nx] each in (0, 1].  The second step's drag coefficient beta_next
+ * (needs has_drag) and force field fx_next, fy_next (both or neither; needs
+ * has_force_field) are optional, device float64 [ny][nx]: without them the
+ * current ones serve both steps; the current ones serve the first step.
+ * The next vanse_step calls advance these two steps (one call of two steps,
+ * or two calls of one); the first takes d_t phi = phi(t+1) - phi(t), the
+ * second phi(t+2) - phi(t+1).  Afterwards phi(t+2) and the second step's
+ * force field and drag coefficient are the current ones.  The caller keeps
+ * ownership of the inputs (copied before the call returns).  Needs
+ * dynamic_phi and no pending void fraction (VANSE_ERR_STATE); synchronizes
+ * the stream. */
+int vanse_set_void_fraction_next2(vanse_lattice *h, const double *phi_next,
+                                  const double *phi_next2, const double *beta_next,
+                                  const double *fx_next, const double *fy_next,
+                                  void *stream);
+
 /* Solid nodes (Sec. 2.3 and Sec. 3.1: half-way bounce-back on their faces):
  * device uint8 [ny][nx], nonzero = solid.  A fluid node pulls the opposite
  * population of its own post-collision state from a solid neighbour's

@@ -199,40 +199,52 @@ __device__ __forceinline__ VelDS<T> mirrored(const VelDS<T>& v) {
   return r;
 }
 
-// Ring row of population plane i (i = 9: phi of the row, i = 10: beta or the
-// solid flags, 11: the flags after beta, for half 1) for the sweep-relative
-// row index j >= 0
+// Ring row of population plane i (after the nine populations: phi, beta,
+// phi(t+2) and the solid flags, see step2_planes) for the sweep-relative row
+// index j >= 0
 __device__ __forceinline__ int pop_slot(int i, int j) { return 4 * i + (j & 3); }
 
-// Planes a row carries: nine populations and phi, plus beta with the drag
-// and the solid flags with a mask
+// Planes a row carries to half 1: nine populations and phi of its step,
+// plus beta with the drag, phi(t+2) with a moving phi and the solid flags
+// with a mask (in this order)
 template <int FEAT>
-constexpr int step2_planes() { return 10 + ((FEAT & FEAT_DRAG) ? 1 : 0) + ((FEAT & FEAT_MASK) ? 1 : 0); }
+constexpr int step2_planes() {
+  return 10 + ((FEAT & FEAT_DRAG) ? 1 : 0) + ((FEAT & FEAT_DYNPHI) ? 1 : 0) + ((FEAT & FEAT_MASK) ? 1 : 0);
+}
 
-// 4-byte words of a staged row: one per plane, two for 8-byte values; the
+// Values of a staged row: nine populations, phi and beta (with the drag) of
+// the first step, and with a moving phi phi(t+1), phi(t+2) and the second
+// step's beta (with the drag)
+template <int FEAT>
+constexpr int step2_values() {
+  constexpr int D = (FEAT & FEAT_DRAG) ? 1 : 0;
+  return 10 + D + ((FEAT & FEAT_DYNPHI) ? 2 + D : 0);
+}
+
+// 4-byte words of a staged row: one per value, two for 8-byte values; the
 // flags (of the row two ahead) take one
 template <typename S, int FEAT>
 constexpr int step2_words() {
-  return (10 + ((FEAT & FEAT_DRAG) ? 1 : 0)) * (sizeof(S) == 8 ? 2 : 1) + ((FEAT & FEAT_MASK) ? 1 : 0);
+  return step2_values<FEAT>() * (sizeof(S) == 8 ? 2 : 1) + ((FEAT & FEAT_MASK) ? 1 : 0);
 }
 
+// The variants whose extra planes take so much LDS that their halves are
+// narrower (solid nodes with the drag; a moving phi)
+constexpr bool step2_wide_rows(int feat) { return ((feat & FEAT_MASK) && (feat & FEAT_DRAG)) || (feat & FEAT_DYNPHI); }
+
 // Waves per SIMD of the two-step kernels: four in FP32 arithmetic (128
-// registers), two in FP64 (256); three with solid nodes and the drag in FP32
+// registers), two in FP64 (256); three for the narrow-half variants in FP32
 // (168: at 128 they would spill, and a spill reloaded in the sweep waits for
 // the row staged ahead as well)
-constexpr int step2_waves_of(int tbytes, int feat) {
-  return tbytes == 8 ? 2 : (((feat & FEAT_MASK) && (feat & FEAT_DRAG)) ? 3 : 4);
-}
+constexpr int step2_waves_of(int tbytes, int feat) { return tbytes == 8 ? 2 : (step2_wide_rows(feat) ? 3 : 4); }
 template <typename T, int FEAT>
 constexpr int step2_waves() { return step2_waves_of(int(sizeof(T)), FEAT); }
 
 // Lanes per half: 256 in FP32 arithmetic and 128 in FP64 (whose rings take
-// twice the bytes per lane); with solid nodes and the drag, whose two extra
-// planes take LDS, 128 in FP32 (three workgroups per CU) and 64 in FP64.
+// twice the bytes per lane); half that for the variants with wide rows
+// (three workgroups per CU in FP32).
 constexpr int step2_nt_of(int tbytes, int feat) {
-  const bool md = (feat & FEAT_MASK) && (feat & FEAT_DRAG);
-  if (tbytes == 8) return md ? 64 : 128;
-  return md ? 128 : 256;
+  return (tbytes == 8 ? 128 : 256) >> (step2_wide_rows(feat) ? 1 : 0);
 }
 
 // LDS bytes of one two-step workgroup
@@ -283,12 +295,18 @@ __device__ inline void step2_tile(
     lds_t<Step2Lds<T, NT, step2_planes<FEAT>()>>* __restrict__ Lp,
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st0,
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st1) {
-  static_assert((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK)) == 0,
-                "force field, linear drag and solid nodes only");
+  static_assert((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK | FEAT_DYNPHI)) == 0,
+                "force field, linear drag, solid nodes and a moving phi only");
+  static_assert(!((FEAT & FEAT_MASK) && (FEAT & FEAT_DYNPHI)), "solid nodes or a moving phi");
   constexpr bool DRAG = (FEAT & FEAT_DRAG) != 0;
   constexpr bool FORCE = (FEAT & FEAT_FORCE) != 0;
   constexpr bool MASK = (FEAT & FEAT_MASK) != 0;
-  constexpr int PL_NB = DRAG ? 11 : 10;                  // ring plane of the flags
+  constexpr bool DYN = (FEAT & FEAT_DYNPHI) != 0;
+  // ring planes after the populations and phi, and staged values after the
+  // populations, phi and beta (see step2_planes and step2_values)
+  constexpr int PL_PHIN2 = DRAG ? 11 : 10;               // phi(t+2)
+  constexpr int PL_NB = DRAG ? 11 : 10;                  // the solid flags
+  constexpr int V_PHIN = DRAG ? 11 : 10, V_PHIN2 = V_PHIN + 1, V_BETA2 = V_PHIN + 2;
   constexpr int NW = step2_words<S, FEAT>();
   constexpr unsigned BOUNCE = 0x1FEu;                    // neighbour bits of the flags
   auto& L = *Lp;
@@ -331,6 +349,12 @@ __device__ inline void step2_tile(
   const rsrc_t betar = make_rsrc(g.beta, (DRAG && g.beta) ? unsigned(g.plane) * TB : 0u);
   const rsrc_t fxr = make_rsrc(g.fxf, (FORCE && g.fxf) ? unsigned(g.plane) * TB : 0u);
   const rsrc_t fyr = make_rsrc(g.fyf, (FORCE && g.fyf) ? unsigned(g.plane) * TB : 0u);
+  // a moving phi: phi(t+1) and the second step's phi(t+2), beta and force
+  const rsrc_t phinr = make_rsrc(g.phin, DYN ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t phin2r = make_rsrc(g.phin2, DYN ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t beta2r = make_rsrc(g.beta2, (DYN && DRAG && g.beta2) ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t fx2r = make_rsrc(g.fxf2, (DYN && FORCE && g.fxf2) ? unsigned(g.plane) * TB : 0u);
+  const rsrc_t fy2r = make_rsrc(g.fyf2, (DYN && FORCE && g.fyf2) ? unsigned(g.plane) * TB : 0u);
   const rsrc_t nbrr = make_rsrc(g.nbr, (MASK && g.nbr) ? unsigned(g.plane) * 2u : 0u);
   auto poff = [&](int i, int r) { return unsigned(i) * plane_bytes + unsigned(r) * row_bytes; };
   // row of the flags a staged row yn carries (those of row yn + 2)
@@ -369,6 +393,11 @@ __device__ inline void step2_tile(
     }
     ld(9, phir, xcT, unsigned(r) * unsigned(pitch) * TB);
     if (DRAG) ld(10, betar, xcT, unsigned(r) * unsigned(pitch) * TB);
+    if (DYN) {
+      ld(V_PHIN, phinr, xcT, unsigned(r) * unsigned(pitch) * TB);
+      ld(V_PHIN2, phin2r, xcT, unsigned(r) * unsigned(pitch) * TB);
+      if (DRAG) ld(V_BETA2, beta2r, xcT, unsigned(r) * unsigned(pitch) * TB);
+    }
     if (MASK) ld(-1, nbrr, unsigned(c) * 2u, flag_row(yn));
     ld(0, srcr, xcb, poff(0, r));
     if (MASK && wave_any((fl & BOUNCE) != 0)) {
@@ -498,14 +527,27 @@ __device__ inline void step2_tile(
       const unsigned nb = flags_of(L.pop[pop_slot(PL_NB, jr(yA))][t]);
       fl.hi = ((fl.hi << 10) | nb) & 0x3FFFFFFFu;
     }
+    // A moving phi: half 0 takes the second step's phi(t+1), phi(t+2) and
+    // beta of row yA from its staged row here and puts them into the ring
+    // after the first barrier (the ring row of yA then holds row yA - 4,
+    // which half 1 reads before that barrier).
+    T dyn_phi1 = T(0), dyn_phi2 = T(0), dyn_beta2 = T(0);
+    if (DYN && half == 0) {
+      const auto* st = sl ? st1 : st0;
+      dyn_phi1 = staged<T>(st, V_PHIN, t);
+      dyn_phi2 = staged<T>(st, V_PHIN2, t);
+      if (DRAG) dyn_beta2 = staged<T>(st, V_BETA2, t);
+      __asm__ volatile("" ::: "memory");
+    }
     // the force field of stage B's row, loaded into registers here so that
     // the loads land while stage A runs (they take no LDS)
     T fex = T(0), fey = T(0);
     if (FORCE) {
       const int yf = yA - 1;
       const unsigned ro = unsigned(WALLS ? min(max(yf, 0), ny - 1) : wrap_index(yf, ny)) * unsigned(pitch) * TB;
-      fex = bload<T>(fxr, xcT, ro);
-      fey = bload<T>(fyr, xcT, ro);
+      // with a moving phi the second step (half 1) has a force field of its own
+      fex = bload<T>((DYN && half) ? fx2r : fxr, xcT, ro);
+      fey = bload<T>((DYN && half) ? fy2r : fyr, xcT, ro);
     }
     if (rowA) {
       if (half == 0) {
@@ -515,6 +557,7 @@ __device__ inline void step2_tile(
         for (int i = 0; i < 9; ++i) f[i] = staged<S>(st, i, t);
         const T phi = staged<T>(st, 9, t);
         if (DRAG) rA.beta = staged<T>(st, 10, t);
+        if (DYN) rA.dphi = dyn_phi1 - phi;  // d_t phi of the first step
         // keeps these reads here, next to the wait that orders them: merged
         // with half 1's read of phi they would wait for the row ahead too
         __asm__ volatile("" ::: "memory");
@@ -548,6 +591,7 @@ __device__ inline void step2_tile(
         constexpr int P = 4 * NT;  // elements per plane of the ring
         const T phi = r0[9 * P];
         if (DRAG) rA.beta = r0[10 * P];
+        if (DYN) rA.dphi = r0[PL_PHIN2 * P] - phi;  // d_t phi of the second step
         q[0] = r0[0];
         q[1] = r0[1 * P - 1];
         q[3] = r0[3 * P + 1];
@@ -584,6 +628,12 @@ __device__ inline void step2_tile(
     // The staging slot of row yA has been read (the barrier above waited for
     // this wave's LDS reads): it takes row yA + 2.
     if (half == 0) stage_row(yA + 2, sl, fl.lo & 0x3FFu);
+    if (DYN && half == 0) {
+      const int ja = jr(yA);
+      L.pop[pop_slot(9, ja)][t] = dyn_phi1;
+      L.pop[pop_slot(PL_PHIN2, ja)][t] = dyn_phi2;
+      if (DRAG) L.pop[pop_slot(10, ja)][t] = dyn_beta2;
+    }
 
     // ---------------- stage B: velocity of row yA - 1 ----------------
     // D and S of delta-rho on row yA, then grad rho on row yA - 1.  D and S
@@ -729,6 +779,7 @@ __device__ inline void step2_tile(
         T Cb = -ph.k12 * (dx_rux - dy_ruy) + (kr * T(1.0 / 18.0)) * (dx_ux - dy_uy) +
                T(1.0 / 12.0) * (dx_mux - dy_muy);
         T Cc = (kr * T(1.0 / 36.0)) * (dx_uy + dy_ux);
+        if (DYN) Ca -= T(2) * X * rho * rC.dphi;  // moving phi (Eq. 20)
         if constexpr (MASK) {
           const unsigned nbC = (fl.hi >> 20) & 0x3FFu;
           if (wave_any((nbC & BOUNCE) != 0)) {
@@ -799,13 +850,19 @@ __device__ inline void step2_tile(
 #pragma unroll
           for (int i = 0; i < 9; ++i) o9[i] = T(0);
         }
+        // a moving phi: the ring and shifted storage hold deviations from the
+        // rest state of the void fraction the next pull runs at, whose rest_0
+        // is rho0 d_t phi higher (times the storage scale for half 1's stores)
+        if (DYN && (half == 0 || SHIFT)) o9[0] -= (scaled ? ph.scale : T(1)) * (rho0 * rC.dphi);
 
         if (half == 0) {  // into the ring for the second step
           const int jo = jr(yo);
 #pragma unroll
           for (int i = 0; i < 9; ++i) L.pop[pop_slot(i, jo)][t] = o9[i];
-          L.pop[pop_slot(9, jo)][t] = phi;
-          if (DRAG) L.pop[pop_slot(10, jo)][t] = rC.beta;
+          if (!DYN) {  // (with a moving phi, written with the row's staging)
+            L.pop[pop_slot(9, jo)][t] = phi;
+            if (DRAG) L.pop[pop_slot(10, jo)][t] = rC.beta;
+          }
           if (MASK) L.pop[pop_slot(PL_NB, jo)][t] = flags_as<T>((fl.hi >> 20) & 0x3FFu);
         } else if (SHIFT) {  // already scaled
 #pragma unroll

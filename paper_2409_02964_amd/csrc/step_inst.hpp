@@ -7,10 +7,11 @@
 // solid nodes alone or with all of those, the scheme variants with all of
 // those, FEAT_ALL), 512 for the plain
 // step; the batched kernel for all but the last two (a moving phi is not
-// batched); the two-step kernel of the first four and of solid nodes alone,
-// with the drag, or with the force field and drag, with halves of
-// step2_nt_of lanes, and its batched form with halves of 64 lanes up to
-// that width.
+// batched); the two-step kernel of the first four, of solid nodes alone,
+// with the drag, or with the force field and drag, and of a moving phi
+// alone, with the drag, or with the force field and drag, with halves of
+// step2_nt_of lanes, and its batched form (all but a moving phi) with halves
+// of 64 lanes up to that width.
 #include <type_traits>
 
 #include "step_launch.hpp"
@@ -108,6 +109,16 @@ VANSE_WALLS(VANSE_BATCH_ONE, FEAT_SCHEME | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
   VANSE_STEP2_ONE(W, FEAT_MASK | FEAT_FORCE | FEAT_DRAG)
 VANSE_STEP2_FEATS(false)
 VANSE_STEP2_FEATS(true)
+// a moving phi: one lattice at a time (not batched)
+#define VANSE_STEP2_DYN(W, F) \
+  template void launch_step2<VANSE_S, VANSE_T, VANSE_SHIFT, W, F>( \
+      const StepGeom&, const StepPhys<VANSE_T>&, int, hipStream_t);
+#define VANSE_STEP2_DYNS(W) VANSE_STEP2_DYN(W, FEAT_DYNPHI) VANSE_STEP2_DYN(W, FEAT_DYNPHI | FEAT_DRAG) \
+  VANSE_STEP2_DYN(W, FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
+VANSE_STEP2_DYNS(false)
+VANSE_STEP2_DYNS(true)
+#undef VANSE_STEP2_DYNS
+#undef VANSE_STEP2_DYN
 #undef VANSE_STEP2_FEATS
 #undef VANSE_STEP2_ONE
 

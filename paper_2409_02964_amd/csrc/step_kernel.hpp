@@ -106,6 +106,12 @@ struct StepGeom {
   const void* beta;  // per-node drag coefficient (F^B -= phi beta (u - u_s))
   const void* phin;  // phi(t+1) (time-varying void fraction; = phi when static)
   const void* nbr;   // uint16 solid flags per node (see FEAT_MASK), or null
+  // the second step's inputs of a two-step launch with a moving phi:
+  // phi(t+2), and the drag coefficient and force field of that step
+  const void* phin2;
+  const void* beta2;
+  const void* fxf2;
+  const void* fyf2;
   long long plane;  // elements per population plane (= pitch * ny)
   int nx, ny, pitch;
   int xwalls;       // half-way walls at x = -1/2 and x = nx - 1/2 (FEAT_MASK instances)

@@ -62,6 +62,9 @@ int pitch_of(int nx) { return (nx + 63) / 64 * 64; }
 struct Layout {
   size_t pop[2], phi, phin, nbr, fx, fy, beta, drho, uprev, partials, partials2, result, badcount,
       check, total;
+  // a moving phi: phi(t+2) and the second step's force field and drag
+  // coefficient of a two-step hand-over (vanse_set_void_fraction_next2)
+  size_t phin2, fx2, fy2, beta2;
   long long plane;
   int pitch;
   long long max_partials;
@@ -92,8 +95,16 @@ int make_layout(const vanse_desc* d, Layout* L) {
   L->plane = plane;
   for (int b = 0; b < 2; ++b) { L->pop[b] = off; off = align256(off + 9 * plane * sb); }
   L->phi = off; off = align256(off + plane * cb);
-  L->phin = 0;
-  if (d->dynamic_phi) { L->phin = off; off = align256(off + plane * cb); }
+  L->phin = L->phin2 = L->fx2 = L->fy2 = L->beta2 = 0;
+  if (d->dynamic_phi) {
+    L->phin = off; off = align256(off + plane * cb);
+    L->phin2 = off; off = align256(off + plane * cb);
+    if (d->has_force_field) {
+      L->fx2 = off; off = align256(off + plane * cb);
+      L->fy2 = off; off = align256(off + plane * cb);
+    }
+    if (d->has_drag) { L->beta2 = off; off = align256(off + plane * cb); }
+  }
   L->nbr = 0;
   if (d->has_mask) { L->nbr = off; off = align256(off + plane * sizeof(uint16_t)); }
   if (d->has_force_field) {
@@ -125,6 +136,10 @@ struct vanse_lattice {
   int cur;  // buffer holding the current state
   int64_t t;
   bool phi_set, params_set, state_set, ff_set, drag_set, uprev_valid, mask_set, phin_set;
+  // two steps' void fractions pending (phi(t+1) in L.phin, phi(t+2) in
+  // L.phin2), and whether the second step brings its own force field
+  // (L.fx2, L.fy2) and drag coefficient (L.beta2)
+  bool phin2_set = false, f2_set = false, beta2_set = false;
   double usx, usy;  // solid velocity of the linear drag
   double kappa, rho0, gx, gy;
   int scale_by_phi;
@@ -309,20 +324,29 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
 // with solid nodes); each outputs its half's width less 10 columns.  Rows per
 // workgroup default to one full round of resident workgroups.
 int arith_bytes(const vanse_lattice* h) { return h->d.precision == VANSE_F64 ? 8 : 4; }
-// The two-step instance of a lattice: its single-step variant, except that
-// solid nodes without a force field take an instance without the force
-// planes (FEAT_MASK, or FEAT_MASK | FEAT_DRAG with the drag): the per-row
-// loads of the force field into registers make the sweep wait for the rows
-// staged ahead as well.
+// The two-step instance of a lattice, or -1 for a variant the two-step
+// kernel does not take (walls in x, a scheme variant, velocity rows, solid
+// nodes with a moving phi): its single-step variant, except that solid nodes
+// without a force field take an instance without the force planes
+// (FEAT_MASK, or FEAT_MASK | FEAT_DRAG with the drag; the per-row loads of
+// the force field into registers make the sweep wait for the rows staged
+// ahead as well), and a moving phi takes FEAT_DYNPHI with the drag and the
+// force field it has.
 int fused_inst(const vanse_lattice* h) {
   const int f = feat_of(h);
+  if (h->d.bc_x == VANSE_WALL) return -1;
+  if (h->d.dynamic_phi) {
+    if (f != FEAT_MOVING) return -1;
+    return FEAT_DYNPHI | (h->d.has_force_field ? (FEAT_FORCE | FEAT_DRAG) : (h->d.has_drag ? FEAT_DRAG : 0));
+  }
+  if ((f & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK)) != 0) return -1;
   if ((f & FEAT_MASK) && !h->d.has_force_field) return h->d.has_drag ? (FEAT_MASK | FEAT_DRAG) : FEAT_MASK;
   return f;
 }
-int fused_nt_of(const vanse_lattice* h) { return step2_nt_of(arith_bytes(h), fused_inst(h)); }
+int fused_nt_of(const vanse_lattice* h) { return step2_nt_of(arith_bytes(h), std::max(fused_inst(h), 0)); }
 int fused_out_w(const vanse_lattice* h) { return fused_nt_of(h) - 10; }
 
-bool fused_feat(const vanse_lattice* h) { return batch_feat(feat_of(h)) && h->d.bc_x != VANSE_WALL; }
+bool fused_feat(const vanse_lattice* h) { return fused_inst(h) >= 0; }
 
 bool fused_ok(const vanse_lattice* h) { return h->fuse == 2 && fused_feat(h); }
 
@@ -341,6 +365,10 @@ unsigned fused_lds_bytes(int feat) {
     case FEAT_MASK | FEAT_DRAG: return of(std::integral_constant<int, FEAT_MASK | FEAT_DRAG>{});
     case FEAT_MASK | FEAT_FORCE | FEAT_DRAG:
       return of(std::integral_constant<int, FEAT_MASK | FEAT_FORCE | FEAT_DRAG>{});
+    case FEAT_DYNPHI: return of(std::integral_constant<int, FEAT_DYNPHI>{});
+    case FEAT_DYNPHI | FEAT_DRAG: return of(std::integral_constant<int, FEAT_DYNPHI | FEAT_DRAG>{});
+    case FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG:
+      return of(std::integral_constant<int, FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG>{});
     default: return of(std::integral_constant<int, 0>{});
   }
 }
@@ -348,7 +376,7 @@ unsigned fused_lds_bytes(int feat) {
 // Two-step workgroups resident per CU: by waves (step2_waves_of per SIMD)
 // and by the CU's 160 KB of LDS
 int fused_per_cu(const vanse_lattice* h) {
-  const int feat = fused_inst(h);
+  const int feat = std::max(fused_inst(h), 0);
   unsigned lds = 0;
   switch (h->d.precision) {
     case VANSE_F64: lds = fused_lds_bytes<double, double>(feat); break;
@@ -385,14 +413,22 @@ int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
   g.out_w = fused_out_w(h);
   g.strips = (h->d.nx + g.out_w - 1) / g.out_w;
   g.rows = fused_rows(h);
-  g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
-  g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
-  g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
   const int blocks = g.strips * ((h->d.ny + g.rows - 1) / g.rows);
   const bool walls = h->d.bc_y == VANSE_WALL;
   for (int64_t s = 0; s < pairs; ++s) {
     g.src = h->ws + h->L.pop[h->cur];
     g.dst = h->ws + h->L.pop[h->cur ^ 1];
+    g.phi = h->ws + h->L.phi;
+    g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
+    g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
+    g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
+    // a moving phi: the two pending void fractions, or phi held constant;
+    // the second step's force field and drag, or the first step's
+    g.phin = h->phin2_set ? h->ws + h->L.phin : g.phi;
+    g.phin2 = h->phin2_set ? h->ws + h->L.phin2 : g.phi;
+    g.beta2 = (h->phin2_set && h->beta2_set) ? h->ws + h->L.beta2 : g.beta;
+    g.fxf2 = (h->phin2_set && h->f2_set) ? h->ws + h->L.fx2 : g.fxf;
+    g.fyf2 = (h->phin2_set && h->f2_set) ? h->ws + h->L.fy2 : g.fyf;
     auto with_walls = [&](auto feat_c) {
       constexpr int F = decltype(feat_c)::value;
       if (walls) launch_step2<S, T, SHIFT, true, F>(g, ph, blocks, st);
@@ -407,10 +443,25 @@ int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
       case FEAT_MASK | FEAT_FORCE | FEAT_DRAG:
         with_walls(std::integral_constant<int, FEAT_MASK | FEAT_FORCE | FEAT_DRAG>{});
         break;
+      case FEAT_DYNPHI: with_walls(std::integral_constant<int, FEAT_DYNPHI>{}); break;
+      case FEAT_DYNPHI | FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_DYNPHI | FEAT_DRAG>{}); break;
+      case FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG:
+        with_walls(std::integral_constant<int, FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG>{});
+        break;
       default: with_walls(std::integral_constant<int, 0>{});
     }
     h->cur ^= 1;
     h->t += 2;
+    if (h->phin2_set) {  // the second step's inputs become the current ones
+      std::swap(h->L.phi, h->L.phin2);
+      if (h->beta2_set) std::swap(h->L.beta, h->L.beta2);
+      if (h->f2_set) {
+        std::swap(h->L.fx, h->L.fx2);
+        std::swap(h->L.fy, h->L.fy2);
+      }
+      h->phin2_set = h->beta2_set = h->f2_set = false;
+      h->version += 1;
+    }
     if (s == 0) HIP_TRY(hipGetLastError());
   }
   return VANSE_OK;
@@ -418,22 +469,25 @@ int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
 
 template <typename S, typename T, bool SHIFT>
 int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
-  if (fused_ok(h) && n >= 2) {
+  if (h->phin_set && n > 1)
+    return fail(VANSE_ERR_INVALID_ARG, "with phi(t+1) set, a call advances one step (asked for %lld)", (long long)n);
+  if (h->phin2_set && n > 2)
+    return fail(VANSE_ERR_INVALID_ARG, "with phi(t+1) and phi(t+2) set, a call advances at most two steps "
+                "(asked for %lld)", (long long)n);
+  if (fused_ok(h) && n >= 2 && !h->phin_set) {
     if (int rc = run_fused_pairs<S, T, SHIFT>(h, n / 2, st)) return rc;
     n &= 1;
     if (n == 0) return VANSE_OK;
   }
+  if (h->phin2_set) {
+    // one step at a time: phi(t+1) takes the one-step path of a pending
+    // void fraction, and the second step's inputs follow it (below)
+    h->phin_set = true;
+  }
   const StepPhys<T> ph = make_phys<T>(h);
-  if (h->phin_set && n > 1)
-    return fail(VANSE_ERR_INVALID_ARG, "with phi(t+1) set, a call advances one step (asked for %lld)", (long long)n);
-  StepGeom g;
-  g.phi = h->ws + h->L.phi;
-  g.phin = h->phin_set ? h->ws + h->L.phin : g.phi;
+  StepGeom g{};
   g.nbr = h->d.has_mask ? h->ws + h->L.nbr : nullptr;
   g.xwalls = h->d.bc_x == VANSE_WALL;
-  g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
-  g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
-  g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
   g.plane = h->L.plane;
   g.nx = h->d.nx;
   g.ny = h->d.ny;
@@ -446,6 +500,11 @@ int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
   for (int64_t s = 0; s < n; ++s) {
     g.src = h->ws + h->L.pop[h->cur];
     g.dst = h->ws + h->L.pop[h->cur ^ 1];
+    g.phi = h->ws + h->L.phi;
+    g.phin = h->phin_set ? h->ws + h->L.phin : g.phi;
+    g.fxf = h->d.has_force_field ? h->ws + h->L.fx : nullptr;
+    g.fyf = h->d.has_force_field ? h->ws + h->L.fy : nullptr;
+    g.beta = h->d.has_drag ? h->ws + h->L.beta : nullptr;
     const int rc = by_variant(h, [&](auto walls, auto feat) -> int {
       return launch_step_w<S, T, SHIFT, decltype(walls)::value, decltype(feat)::value>(h, g, ph, blocks, st);
     });
@@ -456,6 +515,18 @@ int run_steps(vanse_lattice* h, int64_t n, hipStream_t st) {
       std::swap(h->L.phi, h->L.phin);
       h->phin_set = false;
       h->version += 1;
+    }
+    if (h->phin2_set) {
+      // the first of two pending steps is done: phi(t+2) is pending as the
+      // next phi(t+1), with the second step's force field and drag
+      std::swap(h->L.phin, h->L.phin2);
+      if (h->beta2_set) std::swap(h->L.beta, h->L.beta2);
+      if (h->f2_set) {
+        std::swap(h->L.fx, h->L.fx2);
+        std::swap(h->L.fy, h->L.fy2);
+      }
+      h->phin2_set = h->beta2_set = h->f2_set = false;
+      h->phin_set = true;
     }
     if (s == 0) HIP_TRY(hipGetLastError());
   }
@@ -555,6 +626,7 @@ int vanse_create(const vanse_desc* d, void* workspace, size_t bytes, vanse_latti
   h->t = 0;
   h->phi_set = h->params_set = h->state_set = h->ff_set = h->drag_set = h->uprev_valid = false;
   h->mask_set = h->phin_set = false;
+  h->phin2_set = h->f2_set = h->beta2_set = false;
   h->usx = h->usy = 0.0;
   h->kappa = 0.5;
   h->rho0 = 1.0;
@@ -681,7 +753,7 @@ static int upload_phi(vanse_lattice* h, const double* phi, size_t off, hipStream
 int vanse_set_void_fraction(vanse_lattice* h, const double* phi, void* stream) {
   if (int rc = check_handle(h)) return rc;
   if (!phi) return fail(VANSE_ERR_INVALID_ARG, "phi is NULL");
-  if (h->phin_set) return fail(VANSE_ERR_STATE, "phi(t+1) is pending; step first");
+  if (h->phin_set || h->phin2_set) return fail(VANSE_ERR_STATE, "phi(t+1) is pending; step first");
   if (int rc = upload_phi(h, phi, h->L.phi, static_cast<hipStream_t>(stream))) return rc;
   h->phi_set = true;
   h->version += 1;
@@ -693,8 +765,42 @@ int vanse_set_void_fraction_next(vanse_lattice* h, const double* phi_next, void*
   if (!h->d.dynamic_phi) return fail(VANSE_ERR_STATE, "lattice was created without dynamic_phi");
   if (!phi_next) return fail(VANSE_ERR_INVALID_ARG, "phi_next is NULL");
   if (!h->phi_set) return fail(VANSE_ERR_STATE, "void fraction not set");
+  if (h->phin2_set) return fail(VANSE_ERR_STATE, "phi(t+1) and phi(t+2) are pending; step first");
   if (int rc = upload_phi(h, phi_next, h->L.phin, static_cast<hipStream_t>(stream))) return rc;
   h->phin_set = true;
+  h->version += 1;
+  return VANSE_OK;
+}
+
+int vanse_set_void_fraction_next2(vanse_lattice* h, const double* phi_next, const double* phi_next2,
+                                  const double* beta_next, const double* fx_next, const double* fy_next,
+                                  void* stream) {
+  if (int rc = check_handle(h)) return rc;
+  if (!h->d.dynamic_phi) return fail(VANSE_ERR_STATE, "lattice was created without dynamic_phi");
+  if (!phi_next || !phi_next2) return fail(VANSE_ERR_INVALID_ARG, "phi_next or phi_next2 is NULL");
+  if (!h->phi_set) return fail(VANSE_ERR_STATE, "void fraction not set");
+  if (h->phin_set || h->phin2_set) return fail(VANSE_ERR_STATE, "a void fraction is pending; step first");
+  if (beta_next && !h->d.has_drag) return fail(VANSE_ERR_STATE, "lattice was created without drag");
+  if ((fx_next != nullptr) != (fy_next != nullptr))
+    return fail(VANSE_ERR_INVALID_ARG, "give both force planes of the second step, or neither");
+  if (fx_next && !h->d.has_force_field) return fail(VANSE_ERR_STATE, "lattice was created without a force field");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc = upload_phi(h, phi_next, h->L.phin, st)) return rc;
+  if (int rc = upload_phi(h, phi_next2, h->L.phin2, st)) return rc;
+  const double* in[3] = {beta_next, fx_next, fy_next};
+  const size_t off[3] = {h->L.beta2, h->L.fx2, h->L.fy2};
+  for (int k = 0; k < 3; ++k) {
+    if (!in[k]) continue;
+    void* dst = h->ws + off[k];
+    if (h->d.precision == VANSE_F64)
+      hipLaunchKernelGGL(convert_field<double>, field_grid(h), dim3(256), 0, st, in[k], (double*)dst, h->d.nx, h->d.ny, h->L.pitch);
+    else
+      hipLaunchKernelGGL(convert_field<float>, field_grid(h), dim3(256), 0, st, in[k], (float*)dst, h->d.nx, h->d.ny, h->L.pitch);
+  }
+  HIP_TRY(hipGetLastError());
+  h->phin2_set = true;
+  h->beta2_set = beta_next != nullptr;
+  h->f2_set = fx_next != nullptr;
   h->version += 1;
   return VANSE_OK;
 }

@@ -33,6 +33,7 @@ EXPORTS = [
     "vanse_set_body_force",
     "vanse_set_void_fraction",
     "vanse_set_void_fraction_next",
+    "vanse_set_void_fraction_next2",
     "vanse_set_mask", "vanse_set_force_field", "vanse_set_drag",
     "vanse_init_equilibrium", "vanse_set_populations", "vanse_step",
     "vanse_set_check_interval", "vanse_read_moments",
@@ -92,6 +93,7 @@ def lib():
                 "vanse_set_velocity_rows": [vp, i32, d, d],
                 "vanse_set_void_fraction": [vp, vp, vp],
                 "vanse_set_void_fraction_next": [vp, vp, vp],
+                "vanse_set_void_fraction_next2": [vp, vp, vp, vp, vp, vp, vp],
                 "vanse_set_mask": [vp, vp, vp],
                 "vanse_set_force_field": [vp, vp, vp, vp],
                 "vanse_set_drag": [vp, vp, d, d, vp],
@@ -245,6 +247,22 @@ class Lattice:
         t = self._field(phi_next, (self.ny, self.nx))
         check(lib().vanse_set_void_fraction_next(self.handle, C.c_void_p(t.data_ptr()),
                                                  _stream(stream)))
+        return self
+
+    def set_void_fraction_next2(self, phi_next, phi_next2, beta_next=None, force_next=None, stream=None):
+        """phi(t+1) and phi(t+2) for the next two steps, with the second
+        step's drag coefficient and force field (fx, fy) when they change;
+        see vanse_set_void_fraction_next2."""
+        shape = (self.ny, self.nx)
+        keep = [self._field(phi_next, shape), self._field(phi_next2, shape)]
+        ptrs = [C.c_void_p(keep[0].data_ptr()), C.c_void_p(keep[1].data_ptr())]
+        for f in ([beta_next] + ([None, None] if force_next is None else list(force_next))):
+            if f is None:
+                ptrs.append(C.c_void_p(None))
+            else:
+                keep.append(self._field(f, shape))
+                ptrs.append(C.c_void_p(keep[-1].data_ptr()))
+        check(lib().vanse_set_void_fraction_next2(self.handle, *ptrs, _stream(stream)))
         return self
 
     def set_mask(self, mask, stream=None):
