@@ -54,7 +54,8 @@ METRIC = "MLUPS + %HBM peak (D2Q9 MRT-VANSE); batched solves/s + p99 latency"
 BYTES_PER_NODE = {"f64": 9 * 8 * 2 + 8, "f32": 9 * 4 * 2 + 4, "f32s": 9 * 4 * 2 + 4,
                   "f16s": 9 * 2 * 2 + 4}
 KERNEL_SOURCES = ["paper_2409_02964_amd/csrc/step_kernel.hpp",
-                  "paper_2409_02964_amd/csrc/step2_kernel.hpp"]
+                  "paper_2409_02964_amd/csrc/step2_kernel.hpp",
+                  "paper_2409_02964_amd/build.py"]  # (its compiler flags)
 PROFILE_PREFIX = os.path.join(ROOT, "profiles", "step2_f32s_channel4096")
 TRAFFIC_FILE = PROFILE_PREFIX + "_traffic.json"
 
@@ -529,9 +530,17 @@ VARIANTS = [
     ("force field", "f32s", 2, {"force": True}),
     ("drag", "f32s", 2, {"drag": True}),
     ("moving phi, force field, drag", "f32s", 1, {"dynamic": True, "force": True, "drag": True}),
+    ("moving phi, drag", "f32s", 2, {"dynamic": True, "drag": True}),
+    ("moving phi, force field, drag", "f32s", 2, {"dynamic": True, "force": True, "drag": True}),
     ("solid nodes", "f32s", 1, {"mask": True}),
+    ("solid nodes", "f32s", 2, {"mask": True}),
     ("solid nodes", "f64", 1, {"mask": True}),
+    ("solid nodes", "f64", 2, {"mask": True}),
+    ("a solid disc of radius 256", "f32s", 1, {"mask": "disc"}),
+    ("a solid disc of radius 256", "f32s", 2, {"mask": "disc"}),
+    ("a solid disc of radius 256, drag", "f32s", 2, {"mask": "disc", "drag": True}),
     ("solid nodes, force field, drag", "f32s", 1, {"mask": True, "force": True, "drag": True}),
+    ("solid nodes, force field, drag", "f32s", 2, {"mask": True, "force": True, "drag": True}),
     ("solid nodes, moving phi", "f32s", 1, {"mask": True, "dynamic": True}),
     ("walls in x (a closed box)", "f32s", 1, {"xwalls": True}),
     ("model B", "f32s", 1, {"model_b": True}),
@@ -551,18 +560,18 @@ def variants_bench(steps: int, settle_s: float = 0.5):
     from paper_2409_02964_amd import workloads as W
     from paper_2409_02964_amd.vanse import Lattice
     phi = W.channel_phi(NX, NY, seed=2409)
-    mask = W.solid_mask(NX, NY, seed=5)
+    masks = {True: W.solid_mask(NX, NY, seed=5), "disc": W.cylinder_channel(NX, NY, radius=256.0)}
     fx = 1e-7 * W.smoothed_noise(NX, NY, 8.0, seed=1)
     beta = 1e-3 + 1e-2 * (1 - phi)
     rows = []
     for name, prec, spp, o in VARIANTS:
-        lat = Lattice(NX, NY, precision=prec, bc_y="wall", mask=o.get("mask", False),
+        lat = Lattice(NX, NY, precision=prec, bc_y="wall", mask=bool(o.get("mask", False)),
                       bc_x="wall" if o.get("xwalls") else "periodic",
                       dynamic_phi=o.get("dynamic", False), force_field=o.get("force", False),
                       drag=o.get("drag", False))
         lat.set_params(KAPPA, RATES).set_body_force(G, 0.0, True)
         if o.get("mask"):
-            lat.set_mask(mask)
+            lat.set_mask(masks[o["mask"]])
         if o.get("model_b"):
             lat.set_scheme("B", 3)
         if o.get("wall_u"):

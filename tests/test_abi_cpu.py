@@ -147,6 +147,21 @@ def test_feature_state_checks_on_the_host():
     assert L.vanse_destroy(h) == 0 and L.vanse_destroy(plain) == 0
 
 
+def test_two_step_void_fraction_checks_on_the_host():
+    """vanse_set_void_fraction_next2 rejects, before any GPU work: a lattice
+    without dynamic_phi (-4), a missing phi (-1), a void fraction not set yet
+    (-4)."""
+    L = V.lib()
+    p = C.c_void_p(1 << 40)
+    plain = _fake_handle()
+    assert L.vanse_set_void_fraction_next2(plain, p, p, None, None, None, None) == -4
+    dyn = _fake_handle(dynamic=1)
+    assert L.vanse_set_void_fraction_next2(dyn, p, None, None, None, None, None) == -1
+    assert L.vanse_set_void_fraction_next2(dyn, None, p, None, None, None, None) == -1
+    assert L.vanse_set_void_fraction_next2(dyn, p, p, None, None, None, None) == -4
+    assert L.vanse_destroy(plain) == 0 and L.vanse_destroy(dyn) == 0
+
+
 @pytest.mark.parametrize("first,second,code", [
     (dict(), dict(mask=1), -1),               # members differ in their variant
     (dict(), dict(dynamic=1), -6),            # a moving phi is not batched
