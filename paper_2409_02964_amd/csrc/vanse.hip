@@ -1400,12 +1400,18 @@ int batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
       return VANSE_OK;
     }
   }
-  switch (b->threads) {
-    case 64: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st); break;
-    case 128: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st); break;
-    default: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 256>(E, TL, launch, b->total_tiles, st);
+  if constexpr (FEAT == (FEAT_MASK | FEAT_DRAG)) {
+    // a two-step instance only (one step per launch takes FEAT_MASK |
+    // FEAT_FORCE | FEAT_DRAG): no one-step batch kernel is built for it
+    return fail(VANSE_ERR_UNSUPPORTED, "no one-step batch kernel of this variant");
+  } else {
+    switch (b->threads) {
+      case 64: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 64>(E, TL, launch, b->total_tiles, st); break;
+      case 128: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 128>(E, TL, launch, b->total_tiles, st); break;
+      default: launch_batch_nt<S, T, SHIFT, WALLS, FEAT, 256>(E, TL, launch, b->total_tiles, st);
+    }
+    return VANSE_OK;
   }
-  return VANSE_OK;
 }
 
 int batch_launch(vanse_batch* b, int launch, hipStream_t st) {

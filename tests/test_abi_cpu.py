@@ -27,6 +27,18 @@ def test_library_exports_every_declared_symbol():
     assert sorted(V.EXPORTS) == names
 
 
+def test_library_binds_every_symbol_at_load():
+    """Loaded with immediate binding in a fresh process, the library
+    resolves every symbol: no launcher is referenced that no translation
+    unit instantiates (lazy binding would hide one until it is called)."""
+    import subprocess
+    import sys
+    code = ("import ctypes, os, sys; sys.path.insert(0, %r); from paper_2409_02964_amd import vanse as V; "
+            "ctypes.CDLL(V.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+
+
 def test_workspace_bytes_scales_with_precision():
     b64 = V.workspace_bytes(4096, 4096, "f64", "wall")
     b32 = V.workspace_bytes(4096, 4096, "f32", "wall")
