@@ -142,6 +142,73 @@ def test_two_step_determinism(precision, drag):
     assert np.array_equal(res[0], res[1])
 
 
+def variant_lattice(nx, ny, precision, bc, variant, seed=3):
+    """Lattices of the two-step variants beyond the plain step: solid nodes
+    (a seeded mask), with the drag, or a moving phi with the drag."""
+    from paper_2409_02964_amd.vanse import Lattice
+    phi = W.channel_phi(nx, ny, seed=seed) if ny > 2 else np.full((ny, nx), 0.7)
+    mask = variant.startswith("mask")
+    drag = variant.endswith("drag")
+    lat = Lattice(nx, ny, precision=precision, bc_y=bc, mask=mask, drag=drag,
+                  dynamic_phi=variant.startswith("dyn"))
+    lat.set_params(0.5, RATES).set_body_force(2e-5, -1e-5)
+    if mask:
+        lat.set_mask(W.solid_mask(nx, ny, seed=seed))
+    lat.set_void_fraction(phi)
+    if drag:
+        lat.set_drag(1e-3 + 2e-2 * (1 - phi), (1e-4, 0.0))
+    return lat, phi
+
+
+@pytest.mark.parametrize("nx,ny,bc", [(300, 70, "periodic"), (253, 130, "wall"), (97, 3, "wall"),
+                                      (1000, 37, "wall"), (7, 6, "periodic")])
+@pytest.mark.parametrize("precision,variant", [("f32s", "mask"), ("f16s", "mask"), ("f64", "mask"),
+                                               ("f32s", "mask_drag"), ("f64", "mask_drag"),
+                                               ("f32s", "dyn_drag"), ("f64", "dyn_drag"), ("f16s", "dyn")])
+def test_two_step_variants_write_every_node(nx, ny, bc, precision, variant):
+    """The two-step instances of solid nodes and of a moving phi leave no
+    fluid node of the destination unwritten (a moving phi handed over for
+    the two steps; solid nodes always read back as the rest state)."""
+    _torch()
+    lat, phi = variant_lattice(nx, ny, precision, bc, variant, seed=nx + ny)
+    f0 = start_state(lat, nx + 3 * ny)
+    fluid = np.ones((ny, nx), bool)
+    if variant.startswith("mask"):
+        fluid = W.solid_mask(nx, ny, seed=nx + ny) == 0
+    lat.set_populations(np.full((9, ny, nx), np.nan)).step(1)
+    assert np.isnan(lat.read_populations().cpu().numpy()[:, fluid]).all()
+    lat.set_populations(f0)
+    lat.set_steps_per_pass(2)
+    assert lat.fused_tiling()["active"]
+    if variant.startswith("dyn"):
+        lat.set_void_fraction_next2(np.clip(phi * 0.999, 0.3, 1.0), np.clip(phi * 0.998, 0.3, 1.0))
+    lat.step(2)
+    f = lat.read_populations().cpu().numpy()
+    _say(f"two steps {variant} {precision} {nx}x{ny} {bc}: {np.isnan(f).sum()} NaN")
+    assert np.isfinite(f).all()
+
+
+@pytest.mark.parametrize("precision,variant", [("f32s", "mask"), ("f32s", "mask_drag"), ("f32s", "dyn_drag"),
+                                               ("f16s", "mask")])
+def test_two_step_variant_determinism(precision, variant):
+    """Two runs of 40 steps of the solid-node and moving-phi instances on a
+    lattice of many tiles agree bitwise."""
+    _torch()
+    nx, ny = 1500, 700
+    res = []
+    for _ in range(2):
+        lat, phi = variant_lattice(nx, ny, precision, "wall", variant, seed=11)
+        lat.set_steps_per_pass(2).init_equilibrium(1.0)
+        assert lat.fused_tiling()["active"]
+        for k in range(20):
+            if variant.startswith("dyn"):
+                lat.set_void_fraction_next2(np.clip(phi * (1 - 1e-3 * (2 * k + 1)), 0.3, 1.0),
+                                            np.clip(phi * (1 - 1e-3 * (2 * k + 2)), 0.3, 1.0))
+            lat.step(2)
+        res.append(lat.read_populations().cpu().numpy())
+    assert np.array_equal(res[0], res[1])
+
+
 def test_two_step_batch_determinism():
     _torch()
     from paper_2409_02964_amd.vanse import Batch, Lattice
