@@ -288,9 +288,10 @@ int vanse_set_tiling(vanse_lattice *h, int threads, int rows);
 int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
                      int *workgroups);
 
-/* Time steps per launch of the plain step, with or without the force field
- * and the linear drag (no mask, walls in x, moving phi, scheme variant or
- * wall velocity): 1 (the default) or 2.  With 2, vanse_step advances pairs of steps with one
+/* Time steps per launch of the step with any of the force field, the linear
+ * drag, and solid nodes or a moving phi (vanse_set_void_fraction_next2; no
+ * walls in x, scheme variant, wall velocity or velocity rows): 1 (the
+ * default) or 2.  With 2, vanse_step advances pairs of steps with one
  * launch each: a workgroup's first half runs step t -> t+1 into an LDS ring
  * and its second half step t+1 -> t+2 from it, so the populations cross HBM
  * once per two steps; an odd step count ends with one single step.  Each
@@ -299,8 +300,9 @@ int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
  * state stays in deviations of the arithmetic type (FP32, or FP64 for
  * VANSE_F64), so FP32-shifted and FP64 storage match the single-step
  * results to rounding and the other storage formats skip one storage
- * rounding.  Halves of 256 lanes in FP32 arithmetic and of 128 in FP64.
- * Other lattices keep one step per launch.  rows: rows per workgroup of the
+ * rounding.  Halves of 256 lanes in FP32 arithmetic and of 128 in FP64
+ * (half that for solid nodes with the drag and for a moving phi).  Other
+ * lattices keep one step per launch.  rows: rows per workgroup of the
  * two-step kernel (0: one full round of resident workgroups). */
 int vanse_set_steps_per_pass(vanse_lattice *h, int steps, int rows);
 /* Whether the two-step launch is in use (*active), and its rows per

@@ -61,6 +61,13 @@
 //     on the axes, 1 on the diagonals; Ky alike) restores the stand-ins.
 //   - Solid nodes keep the rest state (zero deviations).
 //
+// A moving phi (FEAT_DYNPHI; the d_t phi term of Eq. 20): half 0 stages
+// phi(t), phi(t+1) and phi(t+2) (and, with the drag, both steps' beta) with
+// each row, and writes the second step's phi and beta into the ring as soon
+// as the row has landed; half 1 takes its d_t phi from there.  The ring and
+// shifted storage hold deviations from the rest state of the phi of the next
+// pull.
+//
 // Columns: lane t of either half is column x0 - 5 + t.  Half 0 forms moments
 // on lanes [0, w+10), velocities on [1, w+9), collisions on [2, w+8); half 1
 // on [3, w+7), [4, w+6), [5, w+5), the last being the strip's w <= NT - 10
@@ -287,8 +294,8 @@ __device__ __forceinline__ unsigned flags_of(T v) {
 
 // FEAT: the plain step plus any of FEAT_FORCE (a per-node force field added
 // to F^B), FEAT_DRAG (the linear drag, u solved in closed form as in the
-// single step) and FEAT_MASK (solid nodes; no walls in x).  Absent force,
-// drag and flag planes read as zero.
+// single step), and FEAT_MASK (solid nodes; no walls in x) or FEAT_DYNPHI
+// (a moving phi).  Absent force, drag and flag planes read as zero.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __device__ inline void step2_tile(
     const StepGeom& g, const StepPhys<T>& ph, int strip, int by,
@@ -374,9 +381,10 @@ __device__ inline void step2_tile(
   const unsigned xcT = unsigned(c) * TB;
 
   // The pull of row yn from HBM: ld(i, buffer, lane offset, row offset) for
-  // the nine populations (i = 0..8), phi (i = 9), beta (i = 10) and the
-  // flags of row yn + 2 (i = -1).  Rows are clamped inside walls, so every
-  // load is in bounds.  fl: the flags of row yn.
+  // the nine populations (i = 0..8), phi (i = 9), beta (i = 10), the moving
+  // phi's values (V_PHIN, V_PHIN2, V_BETA2) and the flags of row yn + 2
+  // (i = -1).  Rows are clamped inside walls, so every load is in bounds.
+  // fl: the flags of row yn.
   auto pull_row = [&](int yn, unsigned fl, auto&& ld) {
     int r, rs, rn;
     bool bl = false, bh = false;

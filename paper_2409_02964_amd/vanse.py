@@ -312,7 +312,8 @@ class Lattice:
         return dict(threads=a.value, rows=b.value, workgroups=c.value)
 
     def set_steps_per_pass(self, steps=2, rows=0):
-        """Time steps per launch of the plain step or the linear drag (1 or 2); see vanse.h."""
+        """Time steps per launch (1 or 2) of the step with the force field,
+        the drag, solid nodes or a moving phi; see vanse.h."""
         check(lib().vanse_set_steps_per_pass(self.handle, int(steps), int(rows)))
         return self
 
