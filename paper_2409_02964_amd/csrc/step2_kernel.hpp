@@ -7,7 +7,7 @@
 //   half 0 advances rows from t to t+1: pulls from HBM, moments, velocity,
 //          collision -- and writes the post-collision deviations into an LDS
 //          ring instead of HBM;
-//   half 1 advances the same columns from t+1 to t+2 four rows behind: it
+//   half 1 advances the same columns from t+1 to t+2 five rows behind: it
 //          pulls from the LDS ring (the x and y shifts of streaming become
 //          ring indices), and stores to HBM.
 // Each half computes the plain single step's scheme (Sec. 2.3: Eq. 7, 10,
@@ -18,11 +18,13 @@
 // stores with FP32-shifted storage; FP64 keeps it in FP64 (halves of 128
 // lanes then, as the rings take twice the bytes per lane).
 //
-// Per iteration k each half runs three stages on rows yA = y0 - 5 - 4 half
-// + k (A: moments), yA - 1 (B: velocity), yA - 2 (C: collision), with three
-// workgroup barriers.  Half 0's collision row P feeds half 1's pull of row
-// P - 1 one iteration later, and rows P - 2 and P - 3 two and three
-// iterations later; the ring keeps four rows of each plane.  Half-way
+// Per iteration k each half runs three stages on rows yA = y0 - 5 - 5 half
+// + k (A: moments), yA - 1 (B: velocity), yA - 2 (C: collision), with two
+// workgroup barriers (after stages A and B).  Half 0's collision row P feeds
+// half 1's pull of row P - 1 two iterations later, and rows P - 2 and P - 3
+// three and four iterations later; the ring keeps four rows of each plane,
+// row P taking the slot of row P - 4 after half 1's last read of it (see the
+// end of the sweep iteration).  Half-way
 // bounce-back at a wall enters half 1's pull through image rows of the ring
 // (row -1 of planes 2, 5, 6 and row ny of planes 4, 7, 8), which half 0
 // fills from the wall row once per sweep, so the pull itself never tests
@@ -277,6 +279,13 @@ struct FlagRows {
   unsigned lo, hi;
 };
 
+// A moving phi: the second step's phi(t+1), phi(t+2) and beta of the row
+// staged one iteration before
+template <typename T>
+struct DynRow {
+  T phi1, phi2, beta2;
+};
+
 // true on every lane if any lane of the wave has cond
 __device__ __forceinline__ bool wave_any(bool cond) { return __builtin_amdgcn_ballot_w64(cond) != 0; }
 
@@ -326,7 +335,9 @@ __device__ inline void step2_tile(
   const int half = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / NT);
   const int t = int(threadIdx.x) - half * NT;
   const int nx = g.nx, ny = g.ny, pitch = g.pitch;
-  const int yoff = 5 + 4 * half;
+  // Half 1 runs LAG = 5 rows behind half 0 (see the end of the body)
+  constexpr int LAG = 5;
+  const int yoff = 5 + LAG * half;
   const int x0 = strip * g.out_w;
   const int w = min(g.out_w, nx - x0);
   const int h = 3 * half;
@@ -371,7 +382,7 @@ __device__ inline void step2_tile(
 
   const int y0 = by * g.rows;
   const int y1 = min(y0 + g.rows, ny);
-  const int nit = (y1 - y0) + 11;
+  const int nit = (y1 - y0) + 7 + LAG;
   // sweep-relative row index of the population ring (>= 0 for every row it
   // holds)
   auto jr = [&](int y) { return y - y0 + 12; };
@@ -487,7 +498,8 @@ __device__ inline void step2_tile(
   // rows yA, yA - 1 and yA - 2 (stages A, B and C), and half 0's fl.lo those
   // of rows yA + 2 and yA + 1 (staged with row yA and yA - 1).
   auto body = [&](int k, int sl, RowState<T>& rA, const RowState<T>& rB,
-                  const RowState<T>& rC, T (&bNew)[2], const T (&bOld)[2], FlagRows& fl) {
+                  const RowState<T>& rC, T (&bNew)[2], const T (&bOld)[2], FlagRows& fl,
+                  DynRow<T>& dc) {
     const int yA = y0 - yoff + k;
     if (WALLS && (yA == 1 || yA == 2)) {
       // a branch taken once per sweep (the asm statement keeps the compiler
@@ -536,9 +548,10 @@ __device__ inline void step2_tile(
       fl.hi = ((fl.hi << 10) | nb) & 0x3FFFFFFFu;
     }
     // A moving phi: half 0 takes the second step's phi(t+1), phi(t+2) and
-    // beta of row yA from its staged row here and puts them into the ring
-    // after the first barrier (the ring row of yA then holds row yA - 4,
-    // which half 1 reads before that barrier).
+    // beta of row yA from its staged row here, and after the first barrier
+    // puts those of row yA - 1 (kept from the last iteration) into the ring:
+    // the ring row of yA - 1 then holds row yA - 5, half 1's row of this
+    // iteration, which it read before that barrier.
     T dyn_phi1 = T(0), dyn_phi2 = T(0), dyn_beta2 = T(0);
     if (DYN && half == 0) {
       const auto* st = sl ? st1 : st0;
@@ -637,10 +650,13 @@ __device__ inline void step2_tile(
     // this wave's LDS reads): it takes row yA + 2.
     if (half == 0) stage_row(yA + 2, sl, fl.lo & 0x3FFu);
     if (DYN && half == 0) {
-      const int ja = jr(yA);
-      L.pop[pop_slot(9, ja)][t] = dyn_phi1;
-      L.pop[pop_slot(PL_PHIN2, ja)][t] = dyn_phi2;
-      if (DRAG) L.pop[pop_slot(10, ja)][t] = dyn_beta2;
+      const int ja = jr(yA - 1);
+      L.pop[pop_slot(9, ja)][t] = dc.phi1;
+      L.pop[pop_slot(PL_PHIN2, ja)][t] = dc.phi2;
+      if (DRAG) L.pop[pop_slot(10, ja)][t] = dc.beta2;
+      dc.phi1 = dyn_phi1;
+      dc.phi2 = dyn_phi2;
+      dc.beta2 = dyn_beta2;
     }
 
     // ---------------- stage B: velocity of row yA - 1 ----------------
@@ -886,9 +902,14 @@ __device__ inline void step2_tile(
       vm = vc;
       vc = vn;
     }
-    // the ring rows written here are pulled in the next iteration, and the
-    // single-row rings are rewritten
-    lds_barrier();
+    // The end of the iteration: no barrier.  Half 0's collision row yo is
+    // pulled by half 1 LAG - 3 = two iterations later, behind the next
+    // iteration's barriers, and its ring slot is that of row yo - 4, which
+    // half 1 read before this iteration's first barrier.  The next
+    // iteration's stage A writes the delta-rho row after every wave has
+    // passed this iteration's second barrier (its stage B reads done), and
+    // its stage B writes the velocity row after its first barrier (this
+    // stage C's reads done).
   };
 
   // Software pipeline: half 0 stages rows two ahead (see stage_row); the
@@ -898,6 +919,7 @@ __device__ inline void step2_tile(
   RowState<T> R0{}, R1{}, R2{};
   T b0[2] = {0, 0}, b1[2] = {0, 0};
   FlagRows fl{0u, 0u};
+  DynRow<T> dc{T(0), T(0), T(0)};
   if (half == 0) {
     unsigned fa = 0, fb = 0;
     if (MASK) {
@@ -909,17 +931,17 @@ __device__ inline void step2_tile(
     stage_row(y0 - 4, 1, fb);
   }
   for (int k = 0; k < nit; k += 6) {
-    body(k + 0, 0, R0, R2, R1, b0, b1, fl);
+    body(k + 0, 0, R0, R2, R1, b0, b1, fl, dc);
     if (k + 1 >= nit) break;
-    body(k + 1, 1, R1, R0, R2, b1, b0, fl);
+    body(k + 1, 1, R1, R0, R2, b1, b0, fl, dc);
     if (k + 2 >= nit) break;
-    body(k + 2, 0, R2, R1, R0, b0, b1, fl);
+    body(k + 2, 0, R2, R1, R0, b0, b1, fl, dc);
     if (k + 3 >= nit) break;
-    body(k + 3, 1, R0, R2, R1, b1, b0, fl);
+    body(k + 3, 1, R0, R2, R1, b1, b0, fl, dc);
     if (k + 4 >= nit) break;
-    body(k + 4, 0, R1, R0, R2, b0, b1, fl);
+    body(k + 4, 0, R1, R0, R2, b0, b1, fl, dc);
     if (k + 5 >= nit) break;
-    body(k + 5, 1, R2, R1, R0, b1, b0, fl);
+    body(k + 5, 1, R2, R1, R0, b1, b0, fl, dc);
   }
   // no load into LDS may outlive the workgroup
   wait_vm<0>();
