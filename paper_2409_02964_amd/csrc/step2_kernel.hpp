@@ -586,8 +586,13 @@ __device__ inline void step2_tile(
         T q[9];
         if (SHIFT) {
 #pragma unroll
-          for (int i = 0; i < 9; ++i)
-            q[i] = sizeof(S) == 2 ? static_cast<T>(f[i]) * ph.inv_scale : static_cast<T>(f[i]);
+          for (int i = 0; i < 9; ++i) {
+            // FP16: widened and scaled in one mixed-precision FMA (the product
+            // of the exact widening rounds once, as a multiply would; only an
+            // exact zero takes the sign of + 0)
+            if constexpr (sizeof(S) == 2) q[i] = __builtin_fmaf(static_cast<float>(f[i]), ph.inv_scale, 0.0f);
+            else q[i] = static_cast<T>(f[i]);
+          }
         } else {
           q[0] = static_cast<T>(f[0]) - (phi * rho0 - ph.rest0_k);
 #pragma unroll
