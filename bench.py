@@ -544,6 +544,8 @@ VARIANTS = [
     ("solid nodes, moving phi", "f32s", 1, {"mask": True, "dynamic": True}),
     ("walls in x (a closed box)", "f32s", 1, {"xwalls": True}),
     ("model B", "f32s", 1, {"model_b": True}),
+    ("model B", "f32s", 2, {"model_b": True}),
+    ("model B, drag", "f32s", 2, {"model_b": True, "drag": True}),
     ("moving walls, drag", "f32s", 1, {"wall_u": 1e-3, "drag": True}),
     ("model B, solid nodes", "f32s", 1, {"model_b": True, "mask": True}),
     ("velocity rows (Couette), drag", "f32s", 1, {"vel_rows": 1e-3, "drag": True}),

@@ -304,20 +304,26 @@ __device__ __forceinline__ unsigned flags_of(T v) {
 // FEAT: the plain step plus any of FEAT_FORCE (a per-node force field added
 // to F^B), FEAT_DRAG (the linear drag, u solved in closed form as in the
 // single step), and FEAT_MASK (solid nodes; no walls in x) or FEAT_DYNPHI
-// (a moving phi).  Absent force, drag and flag planes read as zero.
+// (a moving phi) or FEAT_SCHEME (model B alone).  Absent force, drag and
+// flag planes read as zero.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __device__ inline void step2_tile(
     const StepGeom& g, const StepPhys<T>& ph, int strip, int by,
     lds_t<Step2Lds<T, NT, step2_planes<FEAT>()>>* __restrict__ Lp,
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st0,
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st1) {
-  static_assert((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK | FEAT_DYNPHI)) == 0,
-                "force field, linear drag, solid nodes and a moving phi only");
+  static_assert((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK | FEAT_DYNPHI | FEAT_SCHEME)) == 0,
+                "force field, linear drag, solid nodes, a moving phi and model B only");
   static_assert(!((FEAT & FEAT_MASK) && (FEAT & FEAT_DYNPHI)), "solid nodes or a moving phi");
+  static_assert(!((FEAT & FEAT_SCHEME) && (FEAT & (FEAT_MASK | FEAT_DYNPHI))),
+                "model B without solid nodes or a moving phi");
   constexpr bool DRAG = (FEAT & FEAT_DRAG) != 0;
   constexpr bool FORCE = (FEAT & FEAT_FORCE) != 0;
   constexpr bool MASK = (FEAT & FEAT_MASK) != 0;
   constexpr bool DYN = (FEAT & FEAT_DYNPHI) != 0;
+  // FEAT_SCHEME here is model B alone (Sec. 2.3): kappa - 1 in place of
+  // kappa - phi in F^p (Eq. 13) and in the kappa - phi factors of Eq. (20)
+  constexpr bool MODEL_B = (FEAT & FEAT_SCHEME) != 0;
   // ring planes after the populations and phi, and staged values after the
   // populations, phi and beta (see step2_planes and step2_values)
   constexpr int PL_PHIN2 = DRAG ? 11 : 10;               // phi(t+2)
@@ -688,7 +694,7 @@ __device__ inline void step2_tile(
           }
         }
         const T phi = rB.phi;
-        const T kp = (kappa - phi) * T(1.0 / 36.0);     // Eq. (13), with the 1/12
+        const T kp = (kappa - (MODEL_B ? T(1) : phi)) * T(1.0 / 36.0);  // Eq. (13), with the 1/12
         const T sg = ph.scale_by_phi ? phi : T(1);
         T Fx = kp * grx + sg * ph.gx;
         T Fy = kp * gry + sg * ph.gy;
@@ -799,7 +805,7 @@ __device__ inline void step2_tile(
         const T rho = rho0 + rC.drho;
         const T m0 = phi * rho0 + rC.dm0;
         const T X = kappa * (MASK ? recip(phi) : rC.rphi);
-        const T kr = (kappa - phi) * rho;
+        const T kr = (kappa - (MODEL_B ? T(1) : phi)) * rho;
         const T ux = vc.ux, uy = vc.uy, Fx = bOld[0], Fy = bOld[1];
 
         // penalty source (Eq. 20), static void fraction; the 1/12 of the

@@ -292,10 +292,6 @@ int feat_of(const vanse_lattice* h) {
   return (d.has_force_field ? FEAT_FORCE : 0) | (d.has_drag ? FEAT_DRAG : 0);
 }
 
-// Variants the two-step kernel takes: the force field, the drag and solid
-// nodes
-bool batch_feat(int feat) { return (feat & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK)) == 0; }
-
 // Lattices batches take: any variant with an instance of its own (not
 // FEAT_ALL) and no moving phi (its phi(t+1) is given step by step)
 bool batch_ok(const vanse_lattice* h) { return !h->d.dynamic_phi && feat_of(h) != FEAT_ALL; }
@@ -325,16 +321,23 @@ int by_variant(const vanse_lattice* h, Fn&& fn) {
 // workgroup default to one full round of resident workgroups.
 int arith_bytes(const vanse_lattice* h) { return h->d.precision == VANSE_F64 ? 8 : 4; }
 // The two-step instance of a lattice, or -1 for a variant the two-step
-// kernel does not take (walls in x, a scheme variant, velocity rows, solid
-// nodes with a moving phi): its single-step variant, except that solid nodes
-// without a force field take an instance without the force planes
-// (FEAT_MASK, or FEAT_MASK | FEAT_DRAG with the drag; the per-row loads of
-// the force field into registers make the sweep wait for the rows staged
-// ahead as well), and a moving phi takes FEAT_DYNPHI with the drag and the
-// force field it has.
+// kernel does not take (walls in x, the Appendix B equilibrium, wall
+// velocities, velocity rows, solid nodes with a moving phi or a scheme
+// variant): its single-step variant, except that solid nodes without a force
+// field take an instance without the force planes (FEAT_MASK, or FEAT_MASK |
+// FEAT_DRAG with the drag; the per-row loads of the force field into
+// registers make the sweep wait for the rows staged ahead as well), a moving
+// phi takes FEAT_DYNPHI with the drag and the force field it has, and model
+// B alone takes FEAT_SCHEME, with FEAT_DRAG for the drag alone and
+// FEAT_FORCE | FEAT_DRAG with the force field.
 int fused_inst(const vanse_lattice* h) {
   const int f = feat_of(h);
   if (h->d.bc_x == VANSE_WALL) return -1;
+  if (f == (FEAT_SCHEME | FEAT_MOVING)) {
+    if (!h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0 || h->d.dynamic_phi) return -1;
+    if (h->d.has_force_field) return FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG;
+    return h->d.has_drag ? (FEAT_SCHEME | FEAT_DRAG) : FEAT_SCHEME;
+  }
   if (h->d.dynamic_phi) {
     if (f != FEAT_MOVING) return -1;
     return FEAT_DYNPHI | (h->d.has_force_field ? (FEAT_FORCE | FEAT_DRAG) : (h->d.has_drag ? FEAT_DRAG : 0));
@@ -369,6 +372,10 @@ unsigned fused_lds_bytes(int feat) {
     case FEAT_DYNPHI | FEAT_DRAG: return of(std::integral_constant<int, FEAT_DYNPHI | FEAT_DRAG>{});
     case FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG:
       return of(std::integral_constant<int, FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG>{});
+    case FEAT_SCHEME: return of(std::integral_constant<int, FEAT_SCHEME>{});
+    case FEAT_SCHEME | FEAT_DRAG: return of(std::integral_constant<int, FEAT_SCHEME | FEAT_DRAG>{});
+    case FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG:
+      return of(std::integral_constant<int, FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG>{});
     default: return of(std::integral_constant<int, 0>{});
   }
 }
@@ -447,6 +454,11 @@ int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
       case FEAT_DYNPHI | FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_DYNPHI | FEAT_DRAG>{}); break;
       case FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG:
         with_walls(std::integral_constant<int, FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG>{});
+        break;
+      case FEAT_SCHEME: with_walls(std::integral_constant<int, FEAT_SCHEME>{}); break;
+      case FEAT_SCHEME | FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_SCHEME | FEAT_DRAG>{}); break;
+      case FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG:
+        with_walls(std::integral_constant<int, FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG>{});
         break;
       default: with_walls(std::integral_constant<int, 0>{});
     }
@@ -1266,8 +1278,8 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
                   "lattice %d differs in precision, boundary, force field, drag, mask or scheme variant", k);
     if (fuse == 2 && !fused_feat(lats[k]))
       return fail(VANSE_ERR_UNSUPPORTED,
-                  "lattice %d: two steps per launch take the force field, the drag and solid nodes only "
-                  "(no walls in x)", k);
+                  "lattice %d: two steps per launch take the force field, the drag, solid nodes and "
+                  "model B only (no walls in x)", k);
     strip_rows += (long long)((d.nx + out_w - 1) / out_w) * d.ny;
   }
   int r = rows;
@@ -1392,7 +1404,7 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
 int batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
   const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
   const int2* TL = reinterpret_cast<const int2*>(b->ws + b->tiles_off);
-  if constexpr ((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK)) == 0) {
+  if constexpr ((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK | FEAT_SCHEME)) == 0) {
     if (b->fuse == 2) {
       // halves of 64 up to step2_nt_of lanes (batch_layout)
       if (!launch_batch2<S, T, SHIFT, WALLS, FEAT>(b->threads, E, TL, launch, b->total_tiles, st))
@@ -1400,9 +1412,11 @@ int batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
       return VANSE_OK;
     }
   }
-  if constexpr (FEAT == (FEAT_MASK | FEAT_DRAG)) {
+  if constexpr (FEAT == (FEAT_MASK | FEAT_DRAG) || FEAT == FEAT_SCHEME || FEAT == (FEAT_SCHEME | FEAT_DRAG) ||
+                FEAT == (FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG)) {
     // a two-step instance only (one step per launch takes FEAT_MASK |
-    // FEAT_FORCE | FEAT_DRAG): no one-step batch kernel is built for it
+    // FEAT_FORCE | FEAT_DRAG, or FEAT_SCHEME | FEAT_MOVING): no one-step
+    // batch kernel is built for it
     return fail(VANSE_ERR_UNSUPPORTED, "no one-step batch kernel of this variant");
   } else {
     switch (b->threads) {
@@ -1419,10 +1433,21 @@ int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
     using S = std::remove_pointer_t<decltype(s_tag)>;
     using T = std::remove_pointer_t<decltype(t_tag)>;
     constexpr bool SH = decltype(shift)::value;
-    if (b->fuse == 2 && fused_inst(b->lats[0]) == (FEAT_MASK | FEAT_DRAG)) {  // see fused_inst
-      constexpr int F = FEAT_MASK | FEAT_DRAG;
-      return b->lats[0]->d.bc_y == VANSE_WALL ? batch_launch_t<S, T, SH, true, F>(b, launch, st)
-                                              : batch_launch_t<S, T, SH, false, F>(b, launch, st);
+    if (b->fuse == 2) {  // the two-step instances that are no one-step variant (see fused_inst)
+      const bool walls = b->lats[0]->d.bc_y == VANSE_WALL;
+      auto go = [&](auto feat) -> int {
+        constexpr int F = decltype(feat)::value;
+        return walls ? batch_launch_t<S, T, SH, true, F>(b, launch, st)
+                     : batch_launch_t<S, T, SH, false, F>(b, launch, st);
+      };
+      switch (fused_inst(b->lats[0])) {
+        case FEAT_MASK | FEAT_DRAG: return go(std::integral_constant<int, FEAT_MASK | FEAT_DRAG>{});
+        case FEAT_SCHEME: return go(std::integral_constant<int, FEAT_SCHEME>{});
+        case FEAT_SCHEME | FEAT_DRAG: return go(std::integral_constant<int, FEAT_SCHEME | FEAT_DRAG>{});
+        case FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG:
+          return go(std::integral_constant<int, FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG>{});
+        default: break;
+      }
     }
     return by_variant(b->lats[0], [&](auto walls, auto feat) -> int {
       if constexpr (decltype(feat)::value == FEAT_ALL || decltype(feat)::value == FEAT_MOVING) {

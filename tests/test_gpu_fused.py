@@ -188,9 +188,9 @@ def test_fused_falls_back_for_variants():
     b = Lattice(n, n, "f32")
     for lat in (a, b):
         lat.set_params(0.5, RATES).set_body_force(1e-6, 0).set_void_fraction(phi)
-        lat.set_scheme("B", 3)
+        lat.set_scheme("B", 2)
     b.set_steps_per_pass(2)
-    assert not b.fused_tiling()["active"]  # a scheme variant: one step per launch
+    assert not b.fused_tiling()["active"]  # the Appendix B equilibrium: one step per launch
     for lat in (a, b):
         lat.init_equilibrium(1.0)
         lat.step(7)

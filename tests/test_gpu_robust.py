@@ -144,7 +144,8 @@ def test_two_step_determinism(precision, drag):
 
 def variant_lattice(nx, ny, precision, bc, variant, seed=3):
     """Lattices of the two-step variants beyond the plain step: solid nodes
-    (a seeded mask), with the drag, or a moving phi with the drag."""
+    (a seeded mask), with the drag, a moving phi with the drag, or model B
+    (with the drag)."""
     from paper_2409_02964_amd.vanse import Lattice
     phi = W.channel_phi(nx, ny, seed=seed) if ny > 2 else np.full((ny, nx), 0.7)
     mask = variant.startswith("mask")
@@ -154,6 +155,8 @@ def variant_lattice(nx, ny, precision, bc, variant, seed=3):
     lat.set_params(0.5, RATES).set_body_force(2e-5, -1e-5)
     if mask:
         lat.set_mask(W.solid_mask(nx, ny, seed=seed))
+    if variant.startswith("model_b"):
+        lat.set_scheme("B", 3)
     lat.set_void_fraction(phi)
     if drag:
         lat.set_drag(1e-3 + 2e-2 * (1 - phi), (1e-4, 0.0))
@@ -164,7 +167,8 @@ def variant_lattice(nx, ny, precision, bc, variant, seed=3):
                                       (1000, 37, "wall"), (7, 6, "periodic")])
 @pytest.mark.parametrize("precision,variant", [("f32s", "mask"), ("f16s", "mask"), ("f64", "mask"),
                                                ("f32s", "mask_drag"), ("f64", "mask_drag"),
-                                               ("f32s", "dyn_drag"), ("f64", "dyn_drag"), ("f16s", "dyn")])
+                                               ("f32s", "dyn_drag"), ("f64", "dyn_drag"), ("f16s", "dyn"),
+                                               ("f32s", "model_b"), ("f16s", "model_b_drag"), ("f64", "model_b")])
 def test_two_step_variants_write_every_node(nx, ny, bc, precision, variant):
     """The two-step instances of solid nodes and of a moving phi leave no
     fluid node of the destination unwritten (a moving phi handed over for
@@ -189,7 +193,7 @@ def test_two_step_variants_write_every_node(nx, ny, bc, precision, variant):
 
 
 @pytest.mark.parametrize("precision,variant", [("f32s", "mask"), ("f32s", "mask_drag"), ("f32s", "dyn_drag"),
-                                               ("f16s", "mask")])
+                                               ("f16s", "mask"), ("f32s", "model_b_drag")])
 def test_two_step_variant_determinism(precision, variant):
     """Two runs of 40 steps of the solid-node and moving-phi instances on a
     lattice of many tiles agree bitwise."""
