@@ -402,7 +402,10 @@ __device__ inline void step2_tile(
   // phi's values (V_PHIN, V_PHIN2, V_BETA2) and the flags of row yn + 2
   // (i = -1).  Rows are clamped inside walls, so every load is in bounds.
   // fl: the flags of row yn.
-  auto pull_row = [&](int yn, unsigned fl, auto&& ld) {
+  // part: 0 every load; 1 phi and the other node values, the flags and the
+  // populations of the row itself (0, 1, 3); 2 those of the rows below and
+  // above (2, 5, 6, 4, 7, 8)
+  auto pull_row = [&](int yn, unsigned fl, auto&& ld, int part = 0) {
     int r, rs, rn;
     bool bl = false, bh = false;
     if (WALLS) {
@@ -416,15 +419,17 @@ __device__ inline void step2_tile(
       rs = (r == 0) ? ny - 1 : r - 1;
       rn = (r == ny - 1) ? 0 : r + 1;
     }
-    ld(9, phir, xcT, unsigned(r) * unsigned(pitch) * TB);
-    if (DRAG) ld(10, betar, xcT, unsigned(r) * unsigned(pitch) * TB);
-    if (DYN) {
-      ld(V_PHIN, phinr, xcT, unsigned(r) * unsigned(pitch) * TB);
-      ld(V_PHIN2, phin2r, xcT, unsigned(r) * unsigned(pitch) * TB);
-      if (DRAG) ld(V_BETA2, beta2r, xcT, unsigned(r) * unsigned(pitch) * TB);
+    if (part != 2) {
+      ld(9, phir, xcT, unsigned(r) * unsigned(pitch) * TB);
+      if (DRAG) ld(10, betar, xcT, unsigned(r) * unsigned(pitch) * TB);
+      if (DYN) {
+        ld(V_PHIN, phinr, xcT, unsigned(r) * unsigned(pitch) * TB);
+        ld(V_PHIN2, phin2r, xcT, unsigned(r) * unsigned(pitch) * TB);
+        if (DRAG) ld(V_BETA2, beta2r, xcT, unsigned(r) * unsigned(pitch) * TB);
+      }
+      if (MASK) ld(-1, nbrr, unsigned(c) * 2u, flag_row(yn));
+      ld(0, srcr, xcb, poff(0, r));
     }
-    if (MASK) ld(-1, nbrr, unsigned(c) * 2u, flag_row(yn));
-    ld(0, srcr, xcb, poff(0, r));
     if (MASK && wave_any((fl & BOUNCE) != 0)) {
       // a wave next to a solid node: per lane the pulled slot, or the own
       // node's opposite slot when the source is solid (whole byte offsets
@@ -446,8 +451,11 @@ __device__ inline void step2_tile(
       pick(8, bh ? xcb : xmb, bh ? poff(6, r) : poff(8, rn), 6);
       return;
     }
-    ld(1, srcr, xmb, poff(1, r));
-    ld(3, srcr, xpb, poff(3, r));
+    if (part != 2) {
+      ld(1, srcr, xmb, poff(1, r));
+      ld(3, srcr, xpb, poff(3, r));
+    }
+    if (part == 1) return;
     if (WALLS && (bl || bh)) {
       // a wall row (taken on two rows per sweep, so the others need no
       // per-lane selects of their column offsets)
@@ -469,7 +477,7 @@ __device__ inline void step2_tile(
   // Half 0's loads of row yn into staging slot sl; each wave's 64 lanes
   // fill 64 consecutive words from the wave's base.
   const int wb = __builtin_amdgcn_readfirstlane(t & ~63);
-  auto stage_row = [&](int yn, int sl, unsigned fl) {
+  auto stage_row = [&](int yn, int sl, unsigned fl, int part = 0) {
     pull_row(yn, fl, [&](int i, rsrc_t rs, unsigned v, unsigned so) {
       auto* st = sl ? st1 : st0;
       if (i < 0) {  // the flags of row yn + 2: the last word
@@ -487,7 +495,7 @@ __device__ inline void step2_tile(
         if (i >= 9 || sizeof(S) == 4) __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 4, v, so, 0, 0);
         else __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, d, 2, v, so, 0, 0);
       }
-    });
+    }, part);
   };
 
   // D and S of the two rows below the one that stage B (rm, rc) and stage C
@@ -660,7 +668,13 @@ __device__ inline void step2_tile(
 
     // The staging slot of row yA has been read (the barrier above waited for
     // this wave's LDS reads): it takes row yA + 2.
-    if (half == 0) stage_row(yA + 2, sl, fl.lo & 0x3FFu);
+    // With FP16 storage (the pipeline, not HBM, bounds it) the loads of the
+    // rows below and above follow the second barrier: the phase between the
+    // barriers is the short one.  (With 4-byte storage the later half loses
+    // more to the shorter time in flight; with the force field its register
+    // loads' wait would cover those loads too.)
+    constexpr bool SPLIT = sizeof(S) == 2 && !MASK && !FORCE;
+    if (half == 0) stage_row(yA + 2, sl, fl.lo & 0x3FFu, SPLIT ? 1 : 0);
     if (DYN && half == 0) {
       const int ja = jr(yA - 1);
       L.pop[pop_slot(9, ja)][t] = dc.phi1;
@@ -742,6 +756,8 @@ __device__ inline void step2_tile(
       rc = rn;
     }
     lds_barrier();
+
+    if (SPLIT && half == 0) stage_row(yA + 2, sl, 0u, 2);
 
     // ---------------- stage C: collide row yA - 2 ----------------
     const int yo = yA - 2;
