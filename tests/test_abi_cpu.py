@@ -278,3 +278,41 @@ def test_noalloc_observe_limit_on_the_host():
     assert L.vanse_observe_noalloc(fits, None, None) == -1
     for h in (big, fits):
         assert L.vanse_destroy(h) == 0
+
+
+def test_two_step_routing_on_the_host():
+    """Which lattices take two steps per launch when asked (a host-side
+    choice): the plain step and model B do; the Appendix B equilibrium, wall
+    velocities, walls in x and a scheme variant with solid nodes keep one.
+    Batches with two steps per launch follow the same rule."""
+    L = V.lib()
+
+    def active(h):
+        a, r, w = C.c_int(), C.c_int(), C.c_int()
+        V.check(L.vanse_get_fused_tiling(h, C.byref(a), C.byref(r), C.byref(w)))
+        return a.value
+
+    def lattice(scheme=None, wall_u=None, **kw):
+        h = _fake_handle(**kw)
+        if scheme is not None:
+            assert L.vanse_set_scheme(h, *scheme) == 0
+        if wall_u is not None:
+            assert L.vanse_set_wall_velocity(h, 0.0, wall_u) == 0
+        assert L.vanse_set_steps_per_pass(h, 2, 0) == 0
+        return h
+
+    cases = [(dict(bcy=1), 1), (dict(bcy=1, scheme=(1, 3)), 1), (dict(scheme=(1, 3)), 1),
+             (dict(bcy=1, scheme=(1, 2)), 0), (dict(bcy=1, scheme=(0, 2)), 0),
+             (dict(bcy=1, scheme=(1, 3), wall_u=1e-3), 0), (dict(bcx=1), 0),
+             (dict(bcy=1, mask=1, scheme=(1, 3)), 0), (dict(bcy=1, mask=1), 1)]
+    for kw, want in cases:
+        h = lattice(**kw)
+        assert active(h) == want, kw
+        assert L.vanse_destroy(h) == 0
+    n = C.c_size_t()
+    for scheme, code in (((1, 3), 0), ((1, 2), -6)):
+        hs = [lattice(bcy=1, scheme=scheme), lattice(bcy=1, scheme=scheme)]
+        arr = (C.c_void_p * 2)(hs[0].value, hs[1].value)
+        assert L.vanse_batch_workspace_bytes_ex(arr, 2, 128, 0, 2, C.byref(n)) == code, scheme
+        for h in hs:
+            assert L.vanse_destroy(h) == 0
