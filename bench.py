@@ -546,6 +546,8 @@ VARIANTS = [
     ("model B", "f32s", 1, {"model_b": True}),
     ("model B", "f32s", 2, {"model_b": True}),
     ("model B, drag", "f32s", 2, {"model_b": True, "drag": True}),
+    ("Appendix B equilibrium", "f32s", 1, {"eq2": True}),
+    ("Appendix B equilibrium", "f32s", 2, {"eq2": True}),
     ("moving walls, drag", "f32s", 1, {"wall_u": 1e-3, "drag": True}),
     ("model B, solid nodes", "f32s", 1, {"model_b": True, "mask": True}),
     ("velocity rows (Couette), drag", "f32s", 1, {"vel_rows": 1e-3, "drag": True}),
@@ -576,6 +578,8 @@ def variants_bench(steps: int, settle_s: float = 0.5):
             lat.set_mask(masks[o["mask"]])
         if o.get("model_b"):
             lat.set_scheme("B", 3)
+        if o.get("eq2"):
+            lat.set_scheme("A", 2)
         if o.get("wall_u"):
             lat.set_wall_velocity(0.0, o["wall_u"])
         if o.get("vel_rows"):

@@ -290,8 +290,8 @@ int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
 
 /* Time steps per launch of the step with any of the force field, the linear
  * drag, and solid nodes or a moving phi (vanse_set_void_fraction_next2) or
- * model B (no walls in x, Appendix B equilibrium, wall velocity or velocity
- * rows): 1 (the
+ * a scheme variant (model B, the Appendix B equilibrium, or both; not with
+ * solid nodes), with no walls in x, wall velocity or velocity rows: 1 (the
  * default) or 2.  With 2, vanse_step advances pairs of steps with one
  * launch each: a workgroup's first half runs step t -> t+1 into an LDS ring
  * and its second half step t+1 -> t+2 from it, so the populations cross HBM
@@ -302,7 +302,8 @@ int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
  * VANSE_F64), so FP32-shifted and FP64 storage match the single-step
  * results to rounding and the other storage formats skip one storage
  * rounding.  Halves of 256 lanes in FP32 arithmetic and of 128 in FP64
- * (half that for solid nodes with the drag and for a moving phi).  Other
+ * (half that for solid nodes with the drag, a moving phi and the Appendix B
+ * equilibrium).  Other
  * lattices keep one step per launch.  rows: rows per workgroup of the
  * two-step kernel (0: one full round of resident workgroups). */
 int vanse_set_steps_per_pass(vanse_lattice *h, int steps, int rows);

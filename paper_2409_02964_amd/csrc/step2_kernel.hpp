@@ -196,6 +196,9 @@ struct VelDS {
   T d_rux, d_ux, d_uy, d_mux;
   T s_ruy, s_uy, s_ux, s_muy;
   T ux, uy;
+  // the Appendix B penalty's four more: D of rho u_y and phi rho u_y, S of
+  // rho u_x and phi rho u_x (formed only there)
+  T d_ruy, d_muy, s_rux, s_mux;
 };
 
 // the image row beyond a wall: velocity-like fields negated
@@ -205,6 +208,7 @@ __device__ __forceinline__ VelDS<T> mirrored(const VelDS<T>& v) {
   r.d_rux = -v.d_rux; r.d_ux = -v.d_ux; r.d_uy = -v.d_uy; r.d_mux = -v.d_mux;
   r.s_ruy = -v.s_ruy; r.s_uy = -v.s_uy; r.s_ux = -v.s_ux; r.s_muy = -v.s_muy;
   r.ux = -v.ux; r.uy = -v.uy;
+  r.d_ruy = -v.d_ruy; r.d_muy = -v.d_muy; r.s_rux = -v.s_rux; r.s_mux = -v.s_mux;
   return r;
 }
 
@@ -237,9 +241,12 @@ constexpr int step2_words() {
   return step2_values<FEAT>() * (sizeof(S) == 8 ? 2 : 1) + ((FEAT & FEAT_MASK) ? 1 : 0);
 }
 
-// The variants whose extra planes take so much LDS that their halves are
-// narrower (solid nodes with the drag; a moving phi)
-constexpr bool step2_wide_rows(int feat) { return ((feat & FEAT_MASK) && (feat & FEAT_DRAG)) || (feat & FEAT_DYNPHI); }
+// The variants whose extra planes take so much LDS, or extra carried sums so
+// many registers, that their halves are narrower (solid nodes with the drag;
+// a moving phi; the Appendix B penalty)
+constexpr bool step2_wide_rows(int feat) {
+  return ((feat & FEAT_MASK) && (feat & FEAT_DRAG)) || (feat & FEAT_DYNPHI) || (feat & FEAT_EQ2);
+}
 
 // Waves per SIMD of the two-step kernels: four in FP32 arithmetic (128
 // registers), two in FP64 (256); three for the narrow-half variants in FP32
@@ -304,16 +311,18 @@ __device__ __forceinline__ unsigned flags_of(T v) {
 // FEAT: the plain step plus any of FEAT_FORCE (a per-node force field added
 // to F^B), FEAT_DRAG (the linear drag, u solved in closed form as in the
 // single step), and FEAT_MASK (solid nodes; no walls in x) or FEAT_DYNPHI
-// (a moving phi) or FEAT_SCHEME (model B alone).  Absent force, drag and
-// flag planes read as zero.
+// (a moving phi) or FEAT_SCHEME (model B alone) or FEAT_EQ2 (the Appendix B
+// equilibrium).  Absent force, drag and flag planes read as zero.
 template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT, int NT>
 __device__ inline void step2_tile(
     const StepGeom& g, const StepPhys<T>& ph, int strip, int by,
     lds_t<Step2Lds<T, NT, step2_planes<FEAT>()>>* __restrict__ Lp,
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st0,
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st1) {
-  static_assert((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK | FEAT_DYNPHI | FEAT_SCHEME)) == 0,
-                "force field, linear drag, solid nodes, a moving phi and model B only");
+  static_assert((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK | FEAT_DYNPHI | FEAT_SCHEME | FEAT_EQ2)) == 0,
+                "force field, linear drag, solid nodes, a moving phi, model B and Appendix B only");
+  static_assert(!((FEAT & FEAT_EQ2) && (FEAT & (FEAT_MASK | FEAT_DYNPHI | FEAT_SCHEME))),
+                "the Appendix B equilibrium without solid nodes or a moving phi");
   static_assert(!((FEAT & FEAT_MASK) && (FEAT & FEAT_DYNPHI)), "solid nodes or a moving phi");
   static_assert(!((FEAT & FEAT_SCHEME) && (FEAT & (FEAT_MASK | FEAT_DYNPHI))),
                 "model B without solid nodes or a moving phi");
@@ -324,6 +333,10 @@ __device__ inline void step2_tile(
   // FEAT_SCHEME here is model B alone (Sec. 2.3): kappa - 1 in place of
   // kappa - phi in F^p (Eq. 13) and in the kappa - phi factors of Eq. (20)
   constexpr bool MODEL_B = (FEAT & FEAT_SCHEME) != 0;
+  // FEAT_EQ2: the Appendix B equilibrium (B2 moments, the twelve-derivative
+  // penalty of Eq. B3), model B then a run-time flag
+  constexpr bool EQ2 = (FEAT & FEAT_EQ2) != 0;
+  const bool kappa_less_one = MODEL_B || (EQ2 && ph.model_b != 0);
   // ring planes after the populations and phi, and staged values after the
   // populations, phi and beta (see step2_planes and step2_values)
   constexpr int PL_PHIN2 = DRAG ? 11 : 10;               // phi(t+2)
@@ -708,7 +721,7 @@ __device__ inline void step2_tile(
           }
         }
         const T phi = rB.phi;
-        const T kp = (kappa - (MODEL_B ? T(1) : phi)) * T(1.0 / 36.0);  // Eq. (13), with the 1/12
+        const T kp = (kappa - (kappa_less_one ? T(1) : phi)) * T(1.0 / 36.0);  // Eq. (13), with the 1/12
         const T sg = ph.scale_by_phi ? phi : T(1);
         T Fx = kp * grx + sg * ph.gx;
         T Fy = kp * gry + sg * ph.gy;
@@ -805,6 +818,12 @@ __device__ inline void step2_tile(
         vn.s_muy = (bE.muy + bW.muy) + T(4) * b0.muy;
         vn.ux = a0.ux;
         vn.uy = a0.uy;
+        if constexpr (EQ2) {
+          vn.d_ruy = bE.ruy - bW.ruy;
+          vn.d_muy = bE.muy - bW.muy;
+          vn.s_rux = (aE.rux + aW.rux) + T(4) * a0.rux;
+          vn.s_mux = (aE.mux + aW.mux) + T(4) * a0.mux;
+        }
       }
       if (rowC && olane) {
         // the eight derivatives of Eq. (20), each 12 times its Eq. (10) value
@@ -821,16 +840,32 @@ __device__ inline void step2_tile(
         const T rho = rho0 + rC.drho;
         const T m0 = phi * rho0 + rC.dm0;
         const T X = kappa * (MASK ? recip(phi) : rC.rphi);
-        const T kr = (kappa - (MODEL_B ? T(1) : phi)) * rho;
+        const T kr = (kappa - (kappa_less_one ? T(1) : phi)) * rho;
         const T ux = vc.ux, uy = vc.uy, Fx = bOld[0], Fy = bOld[1];
 
         // penalty source (Eq. 20), static void fraction; the 1/12 of the
         // derivatives is folded into the coefficients
-        T Ca = -ph.k12 * (dx_rux + dy_ruy) + (kr * T(1.0 / 6.0)) * (dx_ux + dy_uy) +
+        T Ca, Cb, Cc;
+        if constexpr (EQ2) {
+          // Eq. (B3): twice the kappa and the phi rho u terms of Ca, two
+          // thirds of those of Cb, and Cc with all three kinds of term
+          const T dx_ruy = T(4) * vc.d_ruy + (vm.d_ruy + vn.d_ruy);
+          const T dx_muy = T(4) * vc.d_muy + (vm.d_muy + vn.d_muy);
+          const T dy_rux = vn.s_rux - vm.s_rux;
+          const T dy_mux = vn.s_mux - vm.s_mux;
+          Ca = T(-2) * ph.k12 * (dx_rux + dy_ruy) + (kr * T(1.0 / 6.0)) * (dx_ux + dy_uy) +
+               (T(1.0 / 3.0) - X * T(1.0 / 6.0)) * (dx_mux + dy_muy);
+          Cb = T(-2.0 / 3.0) * ph.k12 * (dx_rux - dy_ruy) + (kr * T(1.0 / 18.0)) * (dx_ux - dy_uy) +
+               T(1.0 / 18.0) * (dx_mux - dy_muy);
+          Cc = T(-1.0 / 3.0) * ph.k12 * (dx_ruy + dy_rux) + (kr * T(1.0 / 36.0)) * (dx_uy + dy_ux) +
+               T(1.0 / 36.0) * (dx_muy + dy_mux);
+        } else {
+          Ca = -ph.k12 * (dx_rux + dy_ruy) + (kr * T(1.0 / 6.0)) * (dx_ux + dy_uy) +
                (T(0.25) - X * T(1.0 / 6.0)) * (dx_mux + dy_muy);
-        T Cb = -ph.k12 * (dx_rux - dy_ruy) + (kr * T(1.0 / 18.0)) * (dx_ux - dy_uy) +
+          Cb = -ph.k12 * (dx_rux - dy_ruy) + (kr * T(1.0 / 18.0)) * (dx_ux - dy_uy) +
                T(1.0 / 12.0) * (dx_mux - dy_muy);
-        T Cc = (kr * T(1.0 / 36.0)) * (dx_uy + dy_ux);
+          Cc = (kr * T(1.0 / 36.0)) * (dx_uy + dy_ux);
+        }
         if (DYN) Ca -= T(2) * X * rho * rC.dphi;  // moving phi (Eq. 20)
         if constexpr (MASK) {
           const unsigned nbC = (fl.hi >> 20) & 0x3FFu;
@@ -852,7 +887,7 @@ __device__ inline void step2_tile(
         const T uu = ux * ux + uy * uy;
         const T eq_e = (ph.k2 - T(4) * phi) * drho + T(3) * m0 * uu;
         const T eq_ep = (T(4) * phi - ph.k3) * drho - T(3) * m0 * uu;
-        const T qfac = (kappa - T(2) * phi) * rho;
+        const T qfac = EQ2 ? -m0 : (kappa - T(2) * phi) * rho;  // phi rho (X - 2), or -phi rho (B2)
         const T eq_qx = qfac * ux, eq_qy = qfac * uy;
         const T eq_pxx = m0 * (ux * ux - uy * uy);
         const T eq_pxy = m0 * (ux * uy);

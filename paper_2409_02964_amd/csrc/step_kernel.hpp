@@ -212,7 +212,10 @@ struct RowIn {
 // force, drag and flag planes read as 0 through zero-length buffer
 // descriptors; phin = phi when static).
 enum : int {
-  FEAT_FORCE = 1, FEAT_DRAG = 2, FEAT_DYNPHI = 4, FEAT_MASK = 8, FEAT_SCHEME = 16, FEAT_ALL = 31
+  FEAT_FORCE = 1, FEAT_DRAG = 2, FEAT_DYNPHI = 4, FEAT_MASK = 8, FEAT_SCHEME = 16, FEAT_ALL = 31,
+  // the two-step kernel only: the Appendix B equilibrium (B1, B2) and the
+  // penalty of Eq. (B3), with model B as the run-time flag
+  FEAT_EQ2 = 32
 };
 
 // Solid flags of FEAT_MASK, one uint16 per node: bit 0 -- the node itself is

@@ -327,14 +327,18 @@ int arith_bytes(const vanse_lattice* h) { return h->d.precision == VANSE_F64 ? 8
 // field take an instance without the force planes (FEAT_MASK, or FEAT_MASK |
 // FEAT_DRAG with the drag; the per-row loads of the force field into
 // registers make the sweep wait for the rows staged ahead as well), a moving
-// phi takes FEAT_DYNPHI with the drag and the force field it has, and model
-// B alone takes FEAT_SCHEME, with FEAT_DRAG for the drag alone and
-// FEAT_FORCE | FEAT_DRAG with the force field.
+// phi takes FEAT_DYNPHI with the drag and the force field it has, model B
+// alone takes FEAT_SCHEME, with FEAT_DRAG for the drag alone and FEAT_FORCE
+// | FEAT_DRAG with the force field, and the Appendix B equilibrium (with or
+// without model B) FEAT_EQ2, with FEAT_FORCE | FEAT_DRAG when it has either.
 int fused_inst(const vanse_lattice* h) {
   const int f = feat_of(h);
   if (h->d.bc_x == VANSE_WALL) return -1;
   if (f == (FEAT_SCHEME | FEAT_MOVING)) {
-    if (!h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0 || h->d.dynamic_phi) return -1;
+    if (h->uw_lo != 0.0 || h->uw_hi != 0.0 || h->d.dynamic_phi) return -1;
+    const bool fd = h->d.has_force_field || h->d.has_drag;
+    if (h->eq2) return fd ? (FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG) : FEAT_EQ2;
+    if (!h->model_b) return -1;
     if (h->d.has_force_field) return FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG;
     return h->d.has_drag ? (FEAT_SCHEME | FEAT_DRAG) : FEAT_SCHEME;
   }
@@ -376,6 +380,9 @@ unsigned fused_lds_bytes(int feat) {
     case FEAT_SCHEME | FEAT_DRAG: return of(std::integral_constant<int, FEAT_SCHEME | FEAT_DRAG>{});
     case FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG:
       return of(std::integral_constant<int, FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG>{});
+    case FEAT_EQ2: return of(std::integral_constant<int, FEAT_EQ2>{});
+    case FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG:
+      return of(std::integral_constant<int, FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG>{});
     default: return of(std::integral_constant<int, 0>{});
   }
 }
@@ -459,6 +466,10 @@ int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
       case FEAT_SCHEME | FEAT_DRAG: with_walls(std::integral_constant<int, FEAT_SCHEME | FEAT_DRAG>{}); break;
       case FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG:
         with_walls(std::integral_constant<int, FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG>{});
+        break;
+      case FEAT_EQ2: with_walls(std::integral_constant<int, FEAT_EQ2>{}); break;
+      case FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG:
+        with_walls(std::integral_constant<int, FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG>{});
         break;
       default: with_walls(std::integral_constant<int, 0>{});
     }
@@ -1279,7 +1290,12 @@ int batch_layout(vanse_lattice* const* lats, int n, int threads, int rows, int f
     if (fuse == 2 && !fused_feat(lats[k]))
       return fail(VANSE_ERR_UNSUPPORTED,
                   "lattice %d: two steps per launch take the force field, the drag, solid nodes and "
-                  "model B only (no walls in x)", k);
+                  "the scheme variants only (no walls in x or wall velocities)", k);
+    // (the one-step instance of the scheme variants serves model B and the
+    // Appendix B equilibrium alike through run-time flags; the two-step
+    // instances do not)
+    if (fuse == 2 && fused_inst(lats[k]) != fused_inst(lats[0]))
+      return fail(VANSE_ERR_INVALID_ARG, "lattice %d differs in its two-step instance (scheme variant)", k);
     strip_rows += (long long)((d.nx + out_w - 1) / out_w) * d.ny;
   }
   int r = rows;
@@ -1404,7 +1420,7 @@ template <typename S, typename T, bool SHIFT, bool WALLS, int FEAT>
 int batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
   const BatchEntry<T>* E = reinterpret_cast<const BatchEntry<T>*>(b->ws + b->entries_off);
   const int2* TL = reinterpret_cast<const int2*>(b->ws + b->tiles_off);
-  if constexpr ((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK | FEAT_SCHEME)) == 0) {
+  if constexpr ((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK | FEAT_SCHEME | FEAT_EQ2)) == 0) {
     if (b->fuse == 2) {
       // halves of 64 up to step2_nt_of lanes (batch_layout)
       if (!launch_batch2<S, T, SHIFT, WALLS, FEAT>(b->threads, E, TL, launch, b->total_tiles, st))
@@ -1413,7 +1429,7 @@ int batch_launch_t(vanse_batch* b, int launch, hipStream_t st) {
     }
   }
   if constexpr (FEAT == (FEAT_MASK | FEAT_DRAG) || FEAT == FEAT_SCHEME || FEAT == (FEAT_SCHEME | FEAT_DRAG) ||
-                FEAT == (FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG)) {
+                FEAT == (FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG) || (FEAT & FEAT_EQ2) != 0) {
     // a two-step instance only (one step per launch takes FEAT_MASK |
     // FEAT_FORCE | FEAT_DRAG, or FEAT_SCHEME | FEAT_MOVING): no one-step
     // batch kernel is built for it
@@ -1446,6 +1462,9 @@ int batch_launch(vanse_batch* b, int launch, hipStream_t st) {
         case FEAT_SCHEME | FEAT_DRAG: return go(std::integral_constant<int, FEAT_SCHEME | FEAT_DRAG>{});
         case FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG:
           return go(std::integral_constant<int, FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG>{});
+        case FEAT_EQ2: return go(std::integral_constant<int, FEAT_EQ2>{});
+        case FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG:
+          return go(std::integral_constant<int, FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG>{});
         default: break;
       }
     }

@@ -313,7 +313,7 @@ class Lattice:
 
     def set_steps_per_pass(self, steps=2, rows=0):
         """Time steps per launch (1 or 2) of the step with the force field,
-        the drag, solid nodes or a moving phi; see vanse.h."""
+        the drag, solid nodes, a moving phi or a scheme variant; see vanse.h."""
         check(lib().vanse_set_steps_per_pass(self.handle, int(steps), int(rows)))
         return self
 

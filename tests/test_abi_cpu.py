@@ -282,9 +282,10 @@ def test_noalloc_observe_limit_on_the_host():
 
 def test_two_step_routing_on_the_host():
     """Which lattices take two steps per launch when asked (a host-side
-    choice): the plain step and model B do; the Appendix B equilibrium, wall
+    choice): the plain step, model B and the Appendix B equilibrium do; wall
     velocities, walls in x and a scheme variant with solid nodes keep one.
-    Batches with two steps per launch follow the same rule."""
+    Batches with two steps per launch follow the same rule, and their members
+    must share the two-step instance."""
     L = V.lib()
 
     def active(h):
@@ -302,7 +303,7 @@ def test_two_step_routing_on_the_host():
         return h
 
     cases = [(dict(bcy=1), 1), (dict(bcy=1, scheme=(1, 3)), 1), (dict(scheme=(1, 3)), 1),
-             (dict(bcy=1, scheme=(1, 2)), 0), (dict(bcy=1, scheme=(0, 2)), 0),
+             (dict(bcy=1, scheme=(1, 2)), 1), (dict(bcy=1, scheme=(0, 2)), 1),
              (dict(bcy=1, scheme=(1, 3), wall_u=1e-3), 0), (dict(bcx=1), 0),
              (dict(bcy=1, mask=1, scheme=(1, 3)), 0), (dict(bcy=1, mask=1), 1)]
     for kw, want in cases:
@@ -310,9 +311,12 @@ def test_two_step_routing_on_the_host():
         assert active(h) == want, kw
         assert L.vanse_destroy(h) == 0
     n = C.c_size_t()
-    for scheme, code in (((1, 3), 0), ((1, 2), -6)):
-        hs = [lattice(bcy=1, scheme=scheme), lattice(bcy=1, scheme=scheme)]
+    for schemes, code in ((((1, 3), (1, 3)), 0), (((0, 2), (0, 2)), 0), (((1, 3), (0, 2)), -1),
+                          (((1, 2), (1, 3)), -1)):
+        hs = [lattice(bcy=1, scheme=sc) for sc in schemes]
         arr = (C.c_void_p * 2)(hs[0].value, hs[1].value)
-        assert L.vanse_batch_workspace_bytes_ex(arr, 2, 128, 0, 2, C.byref(n)) == code, scheme
+        # (FP64 handles: the Appendix B instance takes halves of at most 64 lanes)
+        assert L.vanse_batch_workspace_bytes_ex(arr, 2, 64, 0, 2, C.byref(n)) == code, schemes
+        assert L.vanse_batch_workspace_bytes_ex(arr, 2, 64, 0, 1, C.byref(n)) == 0  # one step: alike
         for h in hs:
             assert L.vanse_destroy(h) == 0

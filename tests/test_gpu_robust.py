@@ -157,6 +157,8 @@ def variant_lattice(nx, ny, precision, bc, variant, seed=3):
         lat.set_mask(W.solid_mask(nx, ny, seed=seed))
     if variant.startswith("model_b"):
         lat.set_scheme("B", 3)
+    if variant.startswith("appb"):
+        lat.set_scheme("A", 2)
     lat.set_void_fraction(phi)
     if drag:
         lat.set_drag(1e-3 + 2e-2 * (1 - phi), (1e-4, 0.0))
@@ -168,7 +170,8 @@ def variant_lattice(nx, ny, precision, bc, variant, seed=3):
 @pytest.mark.parametrize("precision,variant", [("f32s", "mask"), ("f16s", "mask"), ("f64", "mask"),
                                                ("f32s", "mask_drag"), ("f64", "mask_drag"),
                                                ("f32s", "dyn_drag"), ("f64", "dyn_drag"), ("f16s", "dyn"),
-                                               ("f32s", "model_b"), ("f16s", "model_b_drag"), ("f64", "model_b")])
+                                               ("f32s", "model_b"), ("f16s", "model_b_drag"), ("f64", "model_b"),
+                                               ("f32s", "appb"), ("f16s", "appb_drag"), ("f64", "appb")])
 def test_two_step_variants_write_every_node(nx, ny, bc, precision, variant):
     """The two-step instances of solid nodes and of a moving phi leave no
     fluid node of the destination unwritten (a moving phi handed over for
@@ -193,7 +196,7 @@ def test_two_step_variants_write_every_node(nx, ny, bc, precision, variant):
 
 
 @pytest.mark.parametrize("precision,variant", [("f32s", "mask"), ("f32s", "mask_drag"), ("f32s", "dyn_drag"),
-                                               ("f16s", "mask"), ("f32s", "model_b_drag")])
+                                               ("f16s", "mask"), ("f32s", "model_b_drag"), ("f32s", "appb_drag")])
 def test_two_step_variant_determinism(precision, variant):
     """Two runs of 40 steps of the solid-node and moving-phi instances on a
     lattice of many tiles agree bitwise."""
