@@ -352,13 +352,16 @@ int vanse_batch_destroy(vanse_batch *b);
 
 /* As the two calls above, with steps_per_pass time steps per launch (1 or
  * 2).  With 2 every launch applies the two-step kernel of
- * vanse_set_steps_per_pass to all members (threads 64 or 128 in FP64,
- * else VANSE_ERR_UNSUPPORTED): threads is then the
- * width of each half of a workgroup of 2 x threads lanes, a tile is a strip
- * of threads-10 columns, and rows = 0 gives about four rounds of resident
- * workgroups.  Each member's results are bitwise those of stepping it alone
- * with two steps per launch; an odd step count ends with one step of each
- * member on its own. */
+ * vanse_set_steps_per_pass to all members, which must share its instance
+ * (VANSE_ERR_INVALID_ARG otherwise; model B alone and the Appendix B
+ * equilibrium do not): threads is then the width of each half of a
+ * workgroup of 2 x threads lanes, at most the half width of that instance
+ * (256 in FP32 arithmetic, 128 in FP64, half that for solid nodes with the
+ * drag and for the Appendix B equilibrium; VANSE_ERR_UNSUPPORTED beyond), a
+ * tile is a strip of threads-10 columns, and rows = 0 gives about four
+ * rounds of resident workgroups.  Each member's results are bitwise those
+ * of stepping it alone with two steps per launch; an odd step count ends
+ * with one step of each member on its own. */
 int vanse_batch_workspace_bytes_ex(vanse_lattice *const *lats, int n, int threads,
                                    int rows, int steps_per_pass, size_t *bytes);
 int vanse_batch_create_ex(vanse_lattice *const *lats, int n, int threads, int rows,
