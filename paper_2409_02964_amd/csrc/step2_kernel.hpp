@@ -70,6 +70,16 @@
 // shifted storage hold deviations from the rest state of the phi of the next
 // pull.
 //
+// The scheme variants (Sec. 2.3 and Appendix B): model B (FEAT_SCHEME here)
+// takes kappa - 1 for kappa - phi in F^p and the source term; the Appendix
+// B equilibrium (FEAT_EQ2) its q moments and the penalty of Eq. (B3), whose
+// four extra derivatives come from the same velocity records (their D and S
+// carried as the others are).
+//
+// Half 0 issues its staging loads after the first barrier; with FP16
+// storage (bound by the pipeline rather than HBM) those of the rows below
+// and above follow the second barrier, in the longer phase.
+//
 // Columns: lane t of either half is column x0 - 5 + t.  Half 0 forms moments
 // on lanes [0, w+10), velocities on [1, w+9), collisions on [2, w+8); half 1
 // on [3, w+7), [4, w+6), [5, w+5), the last being the strip's w <= NT - 10
