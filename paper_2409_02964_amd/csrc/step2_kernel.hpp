@@ -70,9 +70,10 @@
 // shifted storage hold deviations from the rest state of the phi of the next
 // pull.
 //
-// The scheme variants (Sec. 2.3 and Appendix B): model B (FEAT_SCHEME here)
-// takes kappa - 1 for kappa - phi in F^p and the source term; the Appendix
-// B equilibrium (FEAT_EQ2) its q moments and the penalty of Eq. (B3), whose
+// The scheme variants (Sec. 2.3 and Appendix B): model B (FEAT_SCHEME here,
+// also with solid nodes) takes kappa - 1 for kappa - phi in F^p and the
+// source term, the solid-neighbour terms included; the Appendix B
+// equilibrium (FEAT_EQ2) its q moments and the penalty of Eq. (B3), whose
 // four extra derivatives come from the same velocity records (their D and S
 // carried as the others are).
 //
@@ -334,8 +335,7 @@ __device__ inline void step2_tile(
   static_assert(!((FEAT & FEAT_EQ2) && (FEAT & (FEAT_MASK | FEAT_DYNPHI | FEAT_SCHEME))),
                 "the Appendix B equilibrium without solid nodes or a moving phi");
   static_assert(!((FEAT & FEAT_MASK) && (FEAT & FEAT_DYNPHI)), "solid nodes or a moving phi");
-  static_assert(!((FEAT & FEAT_SCHEME) && (FEAT & (FEAT_MASK | FEAT_DYNPHI))),
-                "model B without solid nodes or a moving phi");
+  static_assert(!((FEAT & FEAT_SCHEME) && (FEAT & FEAT_DYNPHI)), "model B without a moving phi");
   constexpr bool DRAG = (FEAT & FEAT_DRAG) != 0;
   constexpr bool FORCE = (FEAT & FEAT_FORCE) != 0;
   constexpr bool MASK = (FEAT & FEAT_MASK) != 0;

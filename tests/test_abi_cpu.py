@@ -282,8 +282,9 @@ def test_noalloc_observe_limit_on_the_host():
 
 def test_two_step_routing_on_the_host():
     """Which lattices take two steps per launch when asked (a host-side
-    choice): the plain step, model B and the Appendix B equilibrium do; wall
-    velocities, walls in x and a scheme variant with solid nodes keep one.
+    choice): the plain step, model B (also with solid nodes) and the Appendix
+    B equilibrium do; wall velocities, walls in x and the Appendix B
+    equilibrium with solid nodes keep one.
     Batches with two steps per launch follow the same rule, and their members
     must share the two-step instance."""
     L = V.lib()
@@ -305,7 +306,8 @@ def test_two_step_routing_on_the_host():
     cases = [(dict(bcy=1), 1), (dict(bcy=1, scheme=(1, 3)), 1), (dict(scheme=(1, 3)), 1),
              (dict(bcy=1, scheme=(1, 2)), 1), (dict(bcy=1, scheme=(0, 2)), 1),
              (dict(bcy=1, scheme=(1, 3), wall_u=1e-3), 0), (dict(bcx=1), 0),
-             (dict(bcy=1, mask=1, scheme=(1, 3)), 0), (dict(bcy=1, mask=1), 1)]
+             (dict(bcy=1, mask=1, scheme=(1, 3)), 1), (dict(bcy=1, mask=1, scheme=(0, 2)), 0),
+             (dict(bcy=1, mask=1), 1)]
     for kw, want in cases:
         h = lattice(**kw)
         assert active(h) == want, kw

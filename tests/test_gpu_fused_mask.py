@@ -280,3 +280,62 @@ def test_two_step_mask_widths_and_fallbacks():
         lat.init_equilibrium(1.0)
         lat.step(7)
     assert torch.equal(a.read_populations(), b.read_populations())
+
+
+# ---- model B with solid nodes (Sec. 2.3: kappa - 1 for kappa - phi, the
+# solid-neighbour terms of the penalty included) ------------------------------
+
+@pytest.mark.parametrize("nx,ny,bc,rows,force,drag", [
+    (61, 37, "wall", 0, False, False), (64, 48, "periodic", 3, False, False),
+    (130, 40, "wall", 0, True, True), (50, 44, "periodic", 1, False, True)])
+def test_fused_mask_model_b_fp64_vs_oracle(oracle, nx, ny, bc, rows, force, drag):
+    """Model B with solid nodes, two steps per launch in FP64 (with the force
+    field and drag or not), node by node against the FP64 oracle's model B."""
+    torch = _torch()
+    _say(f"fused mask model B fp64 vs oracle {nx}x{ny} {bc} rows={rows} force={force} drag={drag}")
+    phi = field(nx, ny, nx + 5 * ny)
+    mask = W.solid_mask(nx, ny, seed=nx * ny + 3)
+    fluid = mask == 0
+    f0 = W.random_populations(nx, ny, seed=23 + nx)
+    g = (2e-5, -1e-5)
+    fc = (1e-5 * W.smoothed_noise(nx, ny, 3.0, seed=1), -1e-5 * W.smoothed_noise(nx, ny, 3.0, seed=2)) if force else None
+    dr = (1e-3 + 0.1 * W.smoothed_noise(nx, ny, 2.0, seed=ny) ** 2, (1e-4, 0.0)) if drag else None
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=RATES, g=g, bc_y=bc, mask=mask, model_b=True,
+                        force=fc, drag=dr)
+    ora.set_populations(f0)
+    lat = lattice(nx, ny, phi, mask, "f64", bc, rows=rows, g=g, force=fc, drag=dr)
+    lat.set_scheme("B", 3)
+    assert lat.fused_tiling()["active"]
+    lat.set_populations(torch.from_numpy(f0))
+    for n, bound in ((2, 1e-14), (5, 1e-13)):
+        ora.step(n)
+        lat.step(n)
+        fg = lat.read_populations().cpu().numpy()
+        err = np.max(np.abs(fg[:, fluid] - ora.f[:, fluid])) / np.max(np.abs(ora.f))
+        _say(f"   t={lat.t}: max rel err {err:.3e}")
+        assert err <= bound
+        assert np.all(fg[:, ~fluid] == 0.0)
+
+
+def test_fused_mask_model_b_matches_single_steps():
+    """Model B with solid nodes in FP32-shifted storage: two steps per launch
+    against one (the instance with every input), to FP32 rounding."""
+    torch = _torch()
+    nx, ny = 253, 130
+    phi = field(nx, ny, 11)
+    mask = W.solid_mask(nx, ny, seed=17)
+    fluid = mask == 0
+    f0 = W.random_populations(nx, ny, seed=29)
+    f0[:, ~fluid] = 0.0
+    a = lattice(nx, ny, phi, mask, "f32s", "wall", fused=False)
+    b = lattice(nx, ny, phi, mask, "f32s", "wall", fused=True)
+    for lat in (a, b):
+        lat.set_scheme("B", 3)
+        lat.set_populations(torch.from_numpy(f0))
+    assert b.fused_tiling()["active"] and not a.fused_tiling()["active"]
+    for n in (2, 5, 4):
+        a.step(n)
+        b.step(n)
+    rel = fluid_rel_diff(a.read_populations().cpu().numpy(), b.read_populations().cpu().numpy(), f0, fluid)
+    _say(f"model B with solid nodes, two steps vs one: relative difference {rel:.3e}")
+    assert rel <= 1e-5

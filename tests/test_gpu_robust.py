@@ -155,7 +155,7 @@ def variant_lattice(nx, ny, precision, bc, variant, seed=3):
     lat.set_params(0.5, RATES).set_body_force(2e-5, -1e-5)
     if mask:
         lat.set_mask(W.solid_mask(nx, ny, seed=seed))
-    if variant.startswith("model_b"):
+    if "model_b" in variant:
         lat.set_scheme("B", 3)
     if variant.startswith("appb"):
         lat.set_scheme("A", 2)
@@ -171,7 +171,8 @@ def variant_lattice(nx, ny, precision, bc, variant, seed=3):
                                                ("f32s", "mask_drag"), ("f64", "mask_drag"),
                                                ("f32s", "dyn_drag"), ("f64", "dyn_drag"), ("f16s", "dyn"),
                                                ("f32s", "model_b"), ("f16s", "model_b_drag"), ("f64", "model_b"),
-                                               ("f32s", "appb"), ("f16s", "appb_drag"), ("f64", "appb")])
+                                               ("f32s", "appb"), ("f16s", "appb_drag"), ("f64", "appb"),
+                                               ("f32s", "mask_model_b"), ("f32s", "mask_model_b_drag")])
 def test_two_step_variants_write_every_node(nx, ny, bc, precision, variant):
     """The two-step instances of solid nodes and of a moving phi leave no
     fluid node of the destination unwritten (a moving phi handed over for
