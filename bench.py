@@ -551,6 +551,7 @@ VARIANTS = [
     ("moving walls, drag", "f32s", 1, {"wall_u": 1e-3, "drag": True}),
     ("model B, solid nodes", "f32s", 1, {"model_b": True, "mask": True}),
     ("model B, solid nodes", "f32s", 2, {"model_b": True, "mask": True}),
+    ("Appendix B equilibrium, solid nodes", "f32s", 2, {"eq2": True, "mask": True}),
     ("velocity rows (Couette), drag", "f32s", 1, {"vel_rows": 1e-3, "drag": True}),
 ]
 

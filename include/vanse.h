@@ -290,9 +290,9 @@ int vanse_get_tiling(const vanse_lattice *h, int *threads, int *rows,
 
 /* Time steps per launch of the step with any of the force field, the linear
  * drag, and solid nodes or a moving phi (vanse_set_void_fraction_next2) or
- * a scheme variant (model B, the Appendix B equilibrium, or both; with
- * solid nodes model B only), with no walls in x, wall velocity or velocity
- * rows: 1 (the
+ * a scheme variant (model B, the Appendix B equilibrium, or both; also
+ * with solid nodes), with no walls in x, wall velocity or velocity rows: 1
+ * (the
  * default) or 2.  With 2, vanse_step advances pairs of steps with one
  * launch each: a workgroup's first half runs step t -> t+1 into an LDS ring
  * and its second half step t+1 -> t+2 from it, so the populations cross HBM

@@ -70,12 +70,13 @@
 // shifted storage hold deviations from the rest state of the phi of the next
 // pull.
 //
-// The scheme variants (Sec. 2.3 and Appendix B): model B (FEAT_SCHEME here,
-// also with solid nodes) takes kappa - 1 for kappa - phi in F^p and the
+// The scheme variants (Sec. 2.3 and Appendix B), also with solid nodes:
+// model B (FEAT_SCHEME here) takes kappa - 1 for kappa - phi in F^p and the
 // source term, the solid-neighbour terms included; the Appendix B
 // equilibrium (FEAT_EQ2) its q moments and the penalty of Eq. (B3), whose
 // four extra derivatives come from the same velocity records (their D and S
-// carried as the others are).
+// carried as the others are, their solid-neighbour terms gathered with the
+// others').
 //
 // Half 0 issues its staging loads after the first barrier; with FP16
 // storage (bound by the pipeline rather than HBM) those of the rows below
@@ -332,8 +333,8 @@ __device__ inline void step2_tile(
     lds_t<Step2Stage<NT, step2_words<S, FEAT>()>>* __restrict__ st1) {
   static_assert((FEAT & ~(FEAT_FORCE | FEAT_DRAG | FEAT_MASK | FEAT_DYNPHI | FEAT_SCHEME | FEAT_EQ2)) == 0,
                 "force field, linear drag, solid nodes, a moving phi, model B and Appendix B only");
-  static_assert(!((FEAT & FEAT_EQ2) && (FEAT & (FEAT_MASK | FEAT_DYNPHI | FEAT_SCHEME))),
-                "the Appendix B equilibrium without solid nodes or a moving phi");
+  static_assert(!((FEAT & FEAT_EQ2) && (FEAT & (FEAT_DYNPHI | FEAT_SCHEME))),
+                "the Appendix B equilibrium without a moving phi");
   static_assert(!((FEAT & FEAT_MASK) && (FEAT & FEAT_DYNPHI)), "solid nodes or a moving phi");
   static_assert(!((FEAT & FEAT_SCHEME) && (FEAT & FEAT_DYNPHI)), "model B without a moving phi");
   constexpr bool DRAG = (FEAT & FEAT_DRAG) != 0;
@@ -886,9 +887,15 @@ __device__ inline void step2_tile(
             // sums (rho u = rho (u), (phi rho) u = m0 (u))
             const T kx = T(solid_kx(nbC)), ky = T(solid_ky(nbC));
             const T sp = kx * ux + ky * uy, sm = kx * ux - ky * uy, sc = kx * uy + ky * ux;
-            Ca -= sp * ((kr * T(1.0 / 6.0) - ph.k12 * rho) + (T(0.25) - X * T(1.0 / 6.0)) * m0);
-            Cb -= sm * ((kr * T(1.0 / 18.0) - ph.k12 * rho) + T(1.0 / 12.0) * m0);
-            Cc -= sc * (kr * T(1.0 / 36.0));
+            if constexpr (EQ2) {  // the same with the coefficients of Eq. (B3)
+              Ca -= sp * ((kr * T(1.0 / 6.0) - T(2) * ph.k12 * rho) + (T(1.0 / 3.0) - X * T(1.0 / 6.0)) * m0);
+              Cb -= sm * ((kr * T(1.0 / 18.0) - T(2.0 / 3.0) * ph.k12 * rho) + T(1.0 / 18.0) * m0);
+              Cc -= sc * ((kr * T(1.0 / 36.0) - T(1.0 / 3.0) * ph.k12 * rho) + T(1.0 / 36.0) * m0);
+            } else {
+              Ca -= sp * ((kr * T(1.0 / 6.0) - ph.k12 * rho) + (T(0.25) - X * T(1.0 / 6.0)) * m0);
+              Cb -= sm * ((kr * T(1.0 / 18.0) - ph.k12 * rho) + T(1.0 / 12.0) * m0);
+              Cc -= sc * (kr * T(1.0 / 36.0));
+            }
           }
         }
 

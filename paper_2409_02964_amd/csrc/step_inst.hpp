@@ -9,9 +9,9 @@
 // step; the batched kernel for all but the last two (a moving phi is not
 // batched); the two-step kernel of the first four, of solid nodes alone,
 // with the drag, or with the force field and drag, of model B alone, with
-// the drag, or with the force field and drag, of model B with solid nodes
-// alone or with the force field and drag, of the Appendix B equilibrium
-// alone or with the force field and drag, and of a moving phi alone, with the drag, or
+// the drag, or with the force field and drag, of model B and of the Appendix
+// B equilibrium, each with or without solid nodes, alone or with the force
+// field and drag, and of a moving phi alone, with the drag, or
 // with the force field and drag, with halves of step2_nt_of lanes, and its
 // batched form (all but a moving phi) with halves of 64 lanes up to that
 // width.
@@ -113,7 +113,8 @@ VANSE_WALLS(VANSE_BATCH_ONE, FEAT_SCHEME | FEAT_DYNPHI | FEAT_FORCE | FEAT_DRAG)
   VANSE_STEP2_ONE(W, FEAT_SCHEME) VANSE_STEP2_ONE(W, FEAT_SCHEME | FEAT_DRAG) \
   VANSE_STEP2_ONE(W, FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG) \
   VANSE_STEP2_ONE(W, FEAT_EQ2) VANSE_STEP2_ONE(W, FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG) \
-  VANSE_STEP2_ONE(W, FEAT_MASK | FEAT_SCHEME) VANSE_STEP2_ONE(W, FEAT_MASK | FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG)
+  VANSE_STEP2_ONE(W, FEAT_MASK | FEAT_SCHEME) VANSE_STEP2_ONE(W, FEAT_MASK | FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG) \
+  VANSE_STEP2_ONE(W, FEAT_MASK | FEAT_EQ2) VANSE_STEP2_ONE(W, FEAT_MASK | FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG)
 VANSE_STEP2_FEATS(false)
 VANSE_STEP2_FEATS(true)
 // a moving phi: one lattice at a time (not batched)

@@ -331,17 +331,19 @@ int arith_bytes(const vanse_lattice* h) { return h->d.precision == VANSE_F64 ? 8
 // alone takes FEAT_SCHEME, with FEAT_DRAG for the drag alone and FEAT_FORCE
 // | FEAT_DRAG with the force field, and the Appendix B equilibrium (with or
 // without model B) FEAT_EQ2, with FEAT_FORCE | FEAT_DRAG when it has either.
-// Model B with solid nodes (FEAT_ALL in one step per launch) takes FEAT_MASK
-// | FEAT_SCHEME, with FEAT_FORCE | FEAT_DRAG when it has either.
+// The scheme variants with solid nodes (FEAT_ALL in one step per launch)
+// take FEAT_MASK with FEAT_EQ2 (the Appendix B equilibrium, with or without
+// model B) or FEAT_SCHEME (model B alone), with FEAT_FORCE | FEAT_DRAG when
+// they have either.
 int fused_inst(const vanse_lattice* h) {
   const int f = feat_of(h);
   if (h->d.bc_x == VANSE_WALL) return -1;
   if (f == FEAT_ALL) {
-    if (!h->d.has_mask || !h->model_b || h->eq2 || h->uw_lo != 0.0 || h->uw_hi != 0.0 || h->nee_lo ||
+    if (!h->d.has_mask || !(h->model_b || h->eq2) || h->uw_lo != 0.0 || h->uw_hi != 0.0 || h->nee_lo ||
         h->nee_hi || h->d.dynamic_phi)
       return -1;
-    return (h->d.has_force_field || h->d.has_drag) ? (FEAT_MASK | FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG)
-                                                     : (FEAT_MASK | FEAT_SCHEME);
+    const int fd = (h->d.has_force_field || h->d.has_drag) ? (FEAT_FORCE | FEAT_DRAG) : 0;
+    return FEAT_MASK | (h->eq2 ? FEAT_EQ2 : FEAT_SCHEME) | fd;
   }
   if (f == (FEAT_SCHEME | FEAT_MOVING)) {
     if (h->uw_lo != 0.0 || h->uw_hi != 0.0 || h->d.dynamic_phi) return -1;
@@ -395,6 +397,9 @@ unsigned fused_lds_bytes(int feat) {
     case FEAT_MASK | FEAT_SCHEME: return of(std::integral_constant<int, FEAT_MASK | FEAT_SCHEME>{});
     case FEAT_MASK | FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG:
       return of(std::integral_constant<int, FEAT_MASK | FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG>{});
+    case FEAT_MASK | FEAT_EQ2: return of(std::integral_constant<int, FEAT_MASK | FEAT_EQ2>{});
+    case FEAT_MASK | FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG:
+      return of(std::integral_constant<int, FEAT_MASK | FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG>{});
     default: return of(std::integral_constant<int, 0>{});
   }
 }
@@ -486,6 +491,10 @@ int run_fused_pairs(vanse_lattice* h, int64_t pairs, hipStream_t st) {
       case FEAT_MASK | FEAT_SCHEME: with_walls(std::integral_constant<int, FEAT_MASK | FEAT_SCHEME>{}); break;
       case FEAT_MASK | FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG:
         with_walls(std::integral_constant<int, FEAT_MASK | FEAT_SCHEME | FEAT_FORCE | FEAT_DRAG>{});
+        break;
+      case FEAT_MASK | FEAT_EQ2: with_walls(std::integral_constant<int, FEAT_MASK | FEAT_EQ2>{}); break;
+      case FEAT_MASK | FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG:
+        with_walls(std::integral_constant<int, FEAT_MASK | FEAT_EQ2 | FEAT_FORCE | FEAT_DRAG>{});
         break;
       default: with_walls(std::integral_constant<int, 0>{});
     }

@@ -282,9 +282,8 @@ def test_noalloc_observe_limit_on_the_host():
 
 def test_two_step_routing_on_the_host():
     """Which lattices take two steps per launch when asked (a host-side
-    choice): the plain step, model B (also with solid nodes) and the Appendix
-    B equilibrium do; wall velocities, walls in x and the Appendix B
-    equilibrium with solid nodes keep one.
+    choice): the plain step and the scheme variants (also with solid nodes)
+    do; wall velocities and walls in x keep one.
     Batches with two steps per launch follow the same rule, and their members
     must share the two-step instance."""
     L = V.lib()
@@ -306,7 +305,8 @@ def test_two_step_routing_on_the_host():
     cases = [(dict(bcy=1), 1), (dict(bcy=1, scheme=(1, 3)), 1), (dict(scheme=(1, 3)), 1),
              (dict(bcy=1, scheme=(1, 2)), 1), (dict(bcy=1, scheme=(0, 2)), 1),
              (dict(bcy=1, scheme=(1, 3), wall_u=1e-3), 0), (dict(bcx=1), 0),
-             (dict(bcy=1, mask=1, scheme=(1, 3)), 1), (dict(bcy=1, mask=1, scheme=(0, 2)), 0),
+             (dict(bcy=1, mask=1, scheme=(1, 3)), 1), (dict(bcy=1, mask=1, scheme=(0, 2)), 1),
+             (dict(bcy=1, mask=1, scheme=(1, 3), wall_u=1e-3), 0),
              (dict(bcy=1, mask=1), 1)]
     for kw, want in cases:
         h = lattice(**kw)

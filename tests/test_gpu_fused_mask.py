@@ -282,17 +282,23 @@ def test_two_step_mask_widths_and_fallbacks():
     assert torch.equal(a.read_populations(), b.read_populations())
 
 
-# ---- model B with solid nodes (Sec. 2.3: kappa - 1 for kappa - phi, the
-# solid-neighbour terms of the penalty included) ------------------------------
+# ---- the scheme variants with solid nodes: model B (Sec. 2.3: kappa - 1 for
+# kappa - phi, the solid-neighbour terms of the penalty included) and the
+# Appendix B equilibrium (the penalty of Eq. B3) ------------------------------
 
+SCHEMES = {"B": ("B", 3), "AppB": ("A", 2), "B+AppB": ("B", 2)}
+
+
+@pytest.mark.parametrize("scheme", ["B", "AppB", "B+AppB"])
 @pytest.mark.parametrize("nx,ny,bc,rows,force,drag", [
     (61, 37, "wall", 0, False, False), (64, 48, "periodic", 3, False, False),
     (130, 40, "wall", 0, True, True), (50, 44, "periodic", 1, False, True)])
-def test_fused_mask_model_b_fp64_vs_oracle(oracle, nx, ny, bc, rows, force, drag):
-    """Model B with solid nodes, two steps per launch in FP64 (with the force
-    field and drag or not), node by node against the FP64 oracle's model B."""
+def test_fused_mask_scheme_fp64_vs_oracle(oracle, scheme, nx, ny, bc, rows, force, drag):
+    """A scheme variant with solid nodes, two steps per launch in FP64 (with
+    the force field and drag or not), node by node against the FP64 oracle."""
     torch = _torch()
-    _say(f"fused mask model B fp64 vs oracle {nx}x{ny} {bc} rows={rows} force={force} drag={drag}")
+    model, order = SCHEMES[scheme]
+    _say(f"fused mask {scheme} fp64 vs oracle {nx}x{ny} {bc} rows={rows} force={force} drag={drag}")
     phi = field(nx, ny, nx + 5 * ny)
     mask = W.solid_mask(nx, ny, seed=nx * ny + 3)
     fluid = mask == 0
@@ -300,11 +306,11 @@ def test_fused_mask_model_b_fp64_vs_oracle(oracle, nx, ny, bc, rows, force, drag
     g = (2e-5, -1e-5)
     fc = (1e-5 * W.smoothed_noise(nx, ny, 3.0, seed=1), -1e-5 * W.smoothed_noise(nx, ny, 3.0, seed=2)) if force else None
     dr = (1e-3 + 0.1 * W.smoothed_noise(nx, ny, 2.0, seed=ny) ** 2, (1e-4, 0.0)) if drag else None
-    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=RATES, g=g, bc_y=bc, mask=mask, model_b=True,
-                        force=fc, drag=dr)
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=RATES, g=g, bc_y=bc, mask=mask, model_b=model == "B",
+                        eq2=order == 2, force=fc, drag=dr)
     ora.set_populations(f0)
     lat = lattice(nx, ny, phi, mask, "f64", bc, rows=rows, g=g, force=fc, drag=dr)
-    lat.set_scheme("B", 3)
+    lat.set_scheme(model, order)
     assert lat.fused_tiling()["active"]
     lat.set_populations(torch.from_numpy(f0))
     for n, bound in ((2, 1e-14), (5, 1e-13)):
@@ -317,10 +323,13 @@ def test_fused_mask_model_b_fp64_vs_oracle(oracle, nx, ny, bc, rows, force, drag
         assert np.all(fg[:, ~fluid] == 0.0)
 
 
-def test_fused_mask_model_b_matches_single_steps():
-    """Model B with solid nodes in FP32-shifted storage: two steps per launch
-    against one (the instance with every input), to FP32 rounding."""
+@pytest.mark.parametrize("scheme", ["B", "AppB"])
+def test_fused_mask_scheme_matches_single_steps(scheme):
+    """A scheme variant with solid nodes in FP32-shifted storage: two steps
+    per launch against one (the instance with every input), to FP32
+    rounding."""
     torch = _torch()
+    model, order = SCHEMES[scheme]
     nx, ny = 253, 130
     phi = field(nx, ny, 11)
     mask = W.solid_mask(nx, ny, seed=17)
@@ -330,12 +339,12 @@ def test_fused_mask_model_b_matches_single_steps():
     a = lattice(nx, ny, phi, mask, "f32s", "wall", fused=False)
     b = lattice(nx, ny, phi, mask, "f32s", "wall", fused=True)
     for lat in (a, b):
-        lat.set_scheme("B", 3)
+        lat.set_scheme(model, order)
         lat.set_populations(torch.from_numpy(f0))
     assert b.fused_tiling()["active"] and not a.fused_tiling()["active"]
     for n in (2, 5, 4):
         a.step(n)
         b.step(n)
     rel = fluid_rel_diff(a.read_populations().cpu().numpy(), b.read_populations().cpu().numpy(), f0, fluid)
-    _say(f"model B with solid nodes, two steps vs one: relative difference {rel:.3e}")
+    _say(f"{scheme} with solid nodes, two steps vs one: relative difference {rel:.3e}")
     assert rel <= 1e-5

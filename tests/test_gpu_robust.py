@@ -157,7 +157,7 @@ def variant_lattice(nx, ny, precision, bc, variant, seed=3):
         lat.set_mask(W.solid_mask(nx, ny, seed=seed))
     if "model_b" in variant:
         lat.set_scheme("B", 3)
-    if variant.startswith("appb"):
+    if "appb" in variant:
         lat.set_scheme("A", 2)
     lat.set_void_fraction(phi)
     if drag:
@@ -172,7 +172,8 @@ def variant_lattice(nx, ny, precision, bc, variant, seed=3):
                                                ("f32s", "dyn_drag"), ("f64", "dyn_drag"), ("f16s", "dyn"),
                                                ("f32s", "model_b"), ("f16s", "model_b_drag"), ("f64", "model_b"),
                                                ("f32s", "appb"), ("f16s", "appb_drag"), ("f64", "appb"),
-                                               ("f32s", "mask_model_b"), ("f32s", "mask_model_b_drag")])
+                                               ("f32s", "mask_model_b"), ("f32s", "mask_model_b_drag"),
+                                               ("f32s", "mask_appb"), ("f64", "mask_appb_drag")])
 def test_two_step_variants_write_every_node(nx, ny, bc, precision, variant):
     """The two-step instances of solid nodes and of a moving phi leave no
     fluid node of the destination unwritten (a moving phi handed over for
