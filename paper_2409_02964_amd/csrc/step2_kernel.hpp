@@ -364,16 +364,21 @@ __device__ inline void step2_tile(
   // slots, branches -- in scalar registers
   const int half = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / NT);
   // Wave priorities (s_setprio: the order in which a SIMD issues the
-  // instructions of its waves; the results do not change).  With 4- or
-  // 8-byte storage half 1's waves go first throughout; with FP16 storage,
-  // whose staging loads follow the second barrier, the waves between the
-  // start of a row and its second barrier (stages A and B, the short phase)
-  // go before those in stage C (see the sweep iteration).  Each was measured
-  // against no priorities on the 4096^2 channel: 146 -> 140 us per step in
-  // FP32-shifted storage, 114.5 -> 111.5 in FP16-shifted storage; the other
-  // choice gained nothing for either.
-  constexpr bool PRIO_PHASE = sizeof(S) == 2;
-  if (!PRIO_PHASE && half == 1) __builtin_amdgcn_s_setprio(1);
+  // instructions of its waves; the results do not change).  With FP32
+  // storage half 1's waves go first throughout, then half 0's waves between
+  // the start of a row and its second barrier (stages A and B, the short
+  // phase), then half 0's waves in stage C; with FP64 storage half 1's waves
+  // go first and half 0's keep one level.  With FP16 storage, whose staging
+  // loads of the shifted rows follow the second barrier, only the phase
+  // counts: stages A and B of either half before stage C.  Measured against
+  // no priorities on the 4096^2 channel: 146 -> 136.5 us per step in
+  // FP32-shifted storage, 113 -> 109 in FP16-shifted storage, 328 -> 321 in
+  // FP64; the orders tried besides (half 0 first, the phase order alone with
+  // 4-byte storage, half 1 first with FP16 storage, half 0's phase order
+  // with FP64) gained less or lost.
+  constexpr bool PRIO_PHASE = sizeof(S) == 2;       // both halves, by phase
+  constexpr bool PRIO_HALF0_PHASE = sizeof(S) == 4;  // half 0 by phase, under half 1
+  if (!PRIO_PHASE && half == 1) __builtin_amdgcn_s_setprio(2);
   const int t = int(threadIdx.x) - half * NT;
   const int nx = g.nx, ny = g.ny, pitch = g.pitch;
   // Half 1 runs LAG = 5 rows behind half 0 (see the end of the body)
@@ -550,7 +555,7 @@ __device__ inline void step2_tile(
                   const RowState<T>& rC, T (&bNew)[2], const T (&bOld)[2], FlagRows& fl,
                   DynRow<T>& dc) {
     const int yA = y0 - yoff + k;
-    if (PRIO_PHASE) __builtin_amdgcn_s_setprio(1);  // stages A and B first
+    if (PRIO_PHASE || (PRIO_HALF0_PHASE && half == 0)) __builtin_amdgcn_s_setprio(1);  // stages A and B first
     if (WALLS && (yA == 1 || yA == 2)) {
       // a branch taken once per sweep (the asm statement keeps the compiler
       // from turning it into selects on every row)
@@ -792,7 +797,7 @@ __device__ inline void step2_tile(
       rc = rn;
     }
     lds_barrier();
-    if (PRIO_PHASE) __builtin_amdgcn_s_setprio(0);  // stage C after them
+    if (PRIO_PHASE || (PRIO_HALF0_PHASE && half == 0)) __builtin_amdgcn_s_setprio(0);  // stage C after them
 
     if (SPLIT && half == 0) stage_row(yA + 2, sl, 0u, 2);
 
