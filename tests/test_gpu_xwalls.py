@@ -134,6 +134,36 @@ def test_box_many_steps_fp64(oracle):
     assert abs(obs["mass"] - obs0["mass"]) <= 1e-13 * obs0["mass"]
 
 
+def test_box_at_rest_under_force_along_walls_fp64(oracle):
+    """Hydrostatic equilibrium along the walls (the oracle's pin of the
+    Eq. 10 stand-in beyond a wall, tests/test_oracle_wall_pins.py): a closed
+    box under phi G along x, phi varying along x, stays at rest on the GPU and
+    its rho depends on x alone; the populations match the oracle's."""
+    torch = _torch()
+    from paper_2409_02964_amd.vanse import Lattice
+    nx, ny, steps, G = 24, 10, 6000, 1e-5
+    rates = dict(s_c=1.0, s_e=1.2, s_eps=1.2, s_q=1.2, s_nu=1.0)
+    x = np.arange(nx)[None, :] * np.ones((ny, 1))
+    phi = 0.6 + 0.3 * np.sin(np.pi * (x + 0.5) / nx) ** 2
+    _say(f"box at rest fp64 {nx}x{ny}, {steps} steps")
+    ora = oracle.Oracle(nx, ny, phi, kappa=0.5, rates=rates, g=(G, 0.0), bc_x="wall",
+                        bc_y="wall").init_equilibrium()
+    ora.step(steps)
+    lat = Lattice(nx, ny, precision="f64", bc_x="wall", bc_y="wall")
+    lat.set_params(0.5, rates).set_body_force(G, 0.0, True).set_void_fraction(phi)
+    lat.init_equilibrium(1.0)
+    lat.step(steps)
+    m = to_np(lat.read_moments())
+    fg = lat.read_populations().cpu().numpy()
+    err = np.max(np.abs(fg - ora.f)) / np.max(np.abs(ora.f))
+    urel = max(np.max(np.abs(m["ux"])), np.max(np.abs(m["uy"]))) / G
+    spread = np.max(np.abs(m["rho"] - m["rho"][ny // 2][None, :])) / (G * nx)
+    _say(f"box at rest fp64: max rel err {err:.3e}, max|u|/G {urel:.2e}, rho spread across y {spread:.2e}")
+    assert err <= 1e-13
+    assert urel < 1e-7
+    assert spread < 1e-9
+
+
 def test_lid_driven_cavity_fp64(oracle):
     """Walls on all four sides, the upper one moving at 0.01: 400 steps
     against the oracle (the moving-wall corrections meet the x-walls at the
