@@ -367,16 +367,16 @@ __device__ inline void step2_tile(
   // instructions of its waves; the results do not change).  With FP32
   // storage half 1's waves go first throughout, then half 0's waves between
   // the start of a row and its second barrier (stages A and B, the short
-  // phase), then half 0's waves in stage C; with FP64 storage half 1's waves
-  // go first and half 0's keep one level.  With FP16 storage, whose staging
-  // loads of the shifted rows follow the second barrier, only the phase
-  // counts: stages A and B of either half before stage C.  Measured against
-  // no priorities on the 4096^2 channel: 146 -> 136.5 us per step in
-  // FP32-shifted storage, 113 -> 109 in FP16-shifted storage, 328 -> 321 in
+  // phase), then half 0's waves in stage C.  With FP16 and FP64 storage only
+  // the phase counts: stages A and B of either half before stage C (FP16
+  // storage issues its staging loads of the shifted rows after the second
+  // barrier; FP64 halves are 128 lanes wide).  Measured against no
+  // priorities on the 4096^2 channel: 146 -> 136.5 us per step in
+  // FP32-shifted storage, 113 -> 109 in FP16-shifted storage, 328 -> 314 in
   // FP64; the orders tried besides (half 0 first, the phase order alone with
-  // 4-byte storage, half 1 first with FP16 storage, half 0's phase order
-  // with FP64) gained less or lost.
-  constexpr bool PRIO_PHASE = sizeof(S) == 2;       // both halves, by phase
+  // 4-byte storage, half 1 first with FP16 or FP64 storage, ...) gained less
+  // or lost.
+  constexpr bool PRIO_PHASE = sizeof(S) != 4;       // both halves, by phase
   constexpr bool PRIO_HALF0_PHASE = sizeof(S) == 4;  // half 0 by phase, under half 1
   if (!PRIO_PHASE && half == 1) __builtin_amdgcn_s_setprio(2);
   const int t = int(threadIdx.x) - half * NT;
