@@ -381,11 +381,12 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
                   const T (&bOld)[2]) {
     const int yn = y0 - 2 + k;
     const S (&f)[9] = in.f;
-    // FP16 storage: the waves in stages A and B (the short phase up to the
-    // second barrier) issue before the waves in stage C (s_setprio; the
-    // results do not change).  Measured on the 4096^2 channel: 186.3 ->
-    // 183.5 us per step; with 4-byte storage it gained nothing.
-    if (sizeof(S) == 2) __builtin_amdgcn_s_setprio(1);
+    // FP16 and FP64 storage: the waves in stages A and B (the short phase up
+    // to the second barrier) issue before the waves in stage C (s_setprio;
+    // the results do not change).  Measured on the 4096^2 channel: 186.3 ->
+    // 183.5 us per step in FP16-shifted storage, 612 -> 606 in FP64; with
+    // 4-byte storage it gained nothing.
+    if (sizeof(S) != 4) __builtin_amdgcn_s_setprio(1);
     const T phi_in = in.phi, beta_in = in.beta, phin_in = in.phin;
     const unsigned nb_in = in.nb;
 
@@ -545,7 +546,7 @@ __device__ __forceinline__ void step_tile(const StepGeom& g, const StepPhys<T>& 
       bNew[1] = Fy;
     }
     __syncthreads();
-    if (sizeof(S) == 2) __builtin_amdgcn_s_setprio(0);  // stage C after them
+    if (sizeof(S) != 4) __builtin_amdgcn_s_setprio(0);  // stage C after them
 
     // ---------------- stage C: collide row yn-2 ----------------
     const int yo = yn - 2;
