@@ -319,7 +319,7 @@ MMS_RUNS = [
     pytest.param("I", 0.5, 0.4, 0.1, 0.1, 1.2, 1.4, id="I-nu0.1"),
     pytest.param("I", 0.5, 0.4, 1.0, 0.1, 1.0, 1.2, id="I-nu1.0"),
     pytest.param("II", 0.5, 0.3, 1.0, 0.5, 1.2, 1.4, id="II-nu1.0"),
-    pytest.param("II", 0.5, 0.3, 0.1, 0.5, 1.2, 1.4, id="II-nu0.1", marks=pytest.mark.slow),
+    pytest.param("II", 0.5, 0.3, 0.1, 0.5, 1.2, 1.4, id="II-nu0.1"),
 ]
 
 
