@@ -365,19 +365,20 @@ __device__ inline void step2_tile(
   const int half = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / NT);
   // Wave priorities (s_setprio: the order in which a SIMD issues the
   // instructions of its waves; the results do not change).  With FP32
-  // storage half 1's waves go first throughout, then half 0's waves between
-  // the start of a row and its second barrier (stages A and B, the short
-  // phase), then half 0's waves in stage C.  With FP16 and FP64 storage only
-  // the phase counts: stages A and B of either half before stage C (FP16
-  // storage issues its staging loads of the shifted rows after the second
-  // barrier; FP64 halves are 128 lanes wide).  Measured against no
-  // priorities on the 4096^2 channel: 146 -> 136.5 us per step in
-  // FP32-shifted storage, 113 -> 109 in FP16-shifted storage, 328 -> 314 in
-  // FP64; the orders tried besides (half 0 first, the phase order alone with
-  // 4-byte storage, half 1 first with FP16 or FP64 storage, ...) gained less
-  // or lost.
-  constexpr bool PRIO_PHASE = sizeof(S) != 4;       // both halves, by phase
-  constexpr bool PRIO_HALF0_PHASE = sizeof(S) == 4;  // half 0 by phase, under half 1
+  // storage and halves of 256 lanes half 1's waves go first throughout, then
+  // half 0's waves between the start of a row and its second barrier (stages
+  // A and B, the short phase), then half 0's waves in stage C.  Otherwise
+  // (FP16 or FP64 storage, or the narrower halves of batches) only the phase
+  // counts: stages A and B of either half before stage C (FP16 storage
+  // issues its staging loads of the shifted rows after the second barrier).
+  // Measured against no priorities on the 4096^2 channel: 146 -> 136.5 us
+  // per step in FP32-shifted storage, 113 -> 109 in FP16-shifted storage,
+  // 328 -> 314 in FP64; on the 256-lattice FP32 batch with 128-lane halves
+  // the phase order gains 1% over the three levels.  The orders tried
+  // besides (half 0 first, the phase order alone with 256-lane FP32 halves,
+  // half 1 first with FP16 or FP64 storage, ...) gained less or lost.
+  constexpr bool PRIO_PHASE = sizeof(S) != 4 || NT < 256;        // both halves, by phase
+  constexpr bool PRIO_HALF0_PHASE = sizeof(S) == 4 && NT >= 256;  // half 0 by phase, under half 1
   if (!PRIO_PHASE && half == 1) __builtin_amdgcn_s_setprio(2);
   const int t = int(threadIdx.x) - half * NT;
   const int nx = g.nx, ny = g.ny, pitch = g.pitch;
