@@ -199,7 +199,7 @@ def batched_bench(steps: int, baseline_steps: int, graph_steps: int = 100):
     nodes = sum(sp["L"] ** 2 for sp in specs)
     lats = build()
     best, _ = autotune_batch(lats, candidates=[(128, 16), (256, 0), (64, 16), (128, 0, 2),
-                                               (128, 32, 2), (128, 40, 2), (128, 48, 2),
+                                               (128, 24, 2), (128, 32, 2), (128, 40, 2), (128, 48, 2),
                                                (128, 64, 2), (256, 48, 2), (64, 24, 2),
                                                (64, 32, 2), (64, 40, 2), (64, 64, 2)],
                              steps=40, repeats=3)
