@@ -368,9 +368,10 @@ __device__ inline void step2_tile(
   // storage and halves of 256 lanes half 1's waves go first throughout, then
   // half 0's waves between the start of a row and its second barrier (stages
   // A and B, the short phase), then half 0's waves in stage C.  Otherwise
-  // (FP16 or FP64 storage, or the narrower halves of batches) only the phase
-  // counts: stages A and B of either half before stage C (FP16 storage
-  // issues its staging loads of the shifted rows after the second barrier).
+  // (FP16 or FP64 storage, or halves narrower than 256 lanes: batches and
+  // the FP32 variants with wide rows) only the phase counts: stages A and B
+  // of either half before stage C (FP16 storage issues its staging loads of
+  // the shifted rows after the second barrier).
   // Measured against no priorities on the 4096^2 channel: 146 -> 136.5 us
   // per step in FP32-shifted storage, 113 -> 109 in FP16-shifted storage,
   // 328 -> 314 in FP64; on the 256-lattice FP32 batch with 128-lane halves
