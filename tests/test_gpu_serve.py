@@ -85,17 +85,19 @@ def test_served_results_equal_solo_runs(precision, steps_per_pass):
         assert s.latency >= 0 and s.finished >= s.admitted >= s.arrival - 1e-9
 
 
-@pytest.mark.parametrize("precision", ["f16s", "f32", "f32s", "f64"])
-def test_served_results_match_oracle(oracle, precision):
+@pytest.mark.parametrize("precision,steps_per_pass", [("f16s", 1), ("f32", 1), ("f32s", 1), ("f64", 1),
+                                                      ("f16s", 2), ("f64", 2)])
+def test_served_results_match_oracle(oracle, precision, steps_per_pass):
     """Every request of a served mix (run to the step cap) against the FP64
-    oracle advanced by the same number of steps from the same inputs."""
+    oracle advanced by the same number of steps from the same inputs, with
+    one or two time steps per launch."""
     _torch()
     from paper_2409_02964_amd.serve import SolveServer
     from paper_2409_02964_amd.vanse import workspace_bytes
     reqs = small_requests()
     need = sorted(workspace_bytes(r["L"], r["L"], precision, drag=True) for r in reqs)
     srv = SolveServer(need[-1] + need[-2] + need[0], precision=precision, chunk=40,
-                      max_steps=400, tol=1e-30, keep_results=True)
+                      max_steps=400, tol=1e-30, keep_results=True, steps_per_pass=steps_per_pass)
     done = {s.rid: s for s in srv.run(reqs)}
     assert max(a for _, a, _, _ in srv.log) >= 2
     for r in reqs:
